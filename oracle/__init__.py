@@ -1,0 +1,259 @@
+"""CPU checker for the closest-hit ray tracing path: TEST INFRASTRUCTURE ONLY.
+
+Thin ctypes wrapper over ``liboracle.so`` (float64 C++, built from
+``oracle.cpp`` by :func:`build`).  Only the tests, ``__graft_entry__.smoke``
+and the benchmark's CPU-baseline leg may import this package; the product
+path (``paper_2208_10008_amd``) never does.
+
+Functions and what pins them:
+
+* :func:`brute` -- closest hit by definition (every ray against every facet).
+  Pinned by hand-built cases with exact answers (``tests/golden``), by the
+  numpy linear-solve brute force in :mod:`oracle.npref`, and by closed-form
+  ground and wall distances.
+* :func:`build_tree` -- the paper's top-down build with the Eq. (2) split.
+  Pinned by tree invariants and hand-worked split choices.
+* :func:`trace_bvh` -- Sec. III-B traversal of that tree; must equal
+  :func:`brute` on every ray.
+* :func:`bounces` -- specular reflection chains; pinned by image-source
+  closed forms.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+MARGIN_CAP = 1e-3
+
+D_MODES = {"mean": 0, "sum": 1, "kweighted": 2, "parent": 3}
+D_NORMS = {"unit": 0, "raw": 1}
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.cpp into liboracle.so (g++, float64, no FMA contraction)."""
+    src = os.path.join(_HERE, "oracle.cpp")
+    if not force and os.path.exists(_LIB_PATH) and \
+            os.path.getmtime(_LIB_PATH) >= os.path.getmtime(src):
+        return _LIB_PATH
+    tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+    cmd = ["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fPIC", "-shared",
+           "-pthread", "-o", tmp, src]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("t_isect", ctypes.c_double),
+                ("t_trav", ctypes.c_double), ("src", ctypes.c_double * 3),
+                ("max_leaf", ctypes.c_int32), ("nbins", ctypes.c_int32),
+                ("d_mode", ctypes.c_int32), ("d_norm", ctypes.c_int32),
+                ("max_depth", ctypes.c_int32), ("depth_limit", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.c_void_p
+        i64, i32 = ctypes.c_int64, ctypes.c_int32
+        lib.or_brute.argtypes = [P, i64, P, i64, P, i32, P, P, P, P, P, P]
+        lib.or_eval.argtypes = [P, i64, P, i64, P, P, P, P, P]
+        lib.or_build.argtypes = [P, i64, ctypes.POINTER(_Params)]
+        lib.or_build.restype = P
+        lib.or_tree_free.argtypes = [P]
+        lib.or_tree_size.argtypes = [P]
+        lib.or_tree_size.restype = i64
+        lib.or_tree_depth.argtypes = [P]
+        lib.or_tree_depth.restype = i32
+        lib.or_tree_export.argtypes = [P] * 13
+        lib.or_trace_bvh.argtypes = [P, i64, P, P, i64, P, i32, P, P, P, P, P, P, P, P]
+        lib.or_bounces.argtypes = [P, i64, P, P, i64, i32, i32, P, P, P, P, P, P, P, P]
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f32(a, cols):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    if a.ndim != 2 or a.shape[1] != cols:
+        raise ValueError(f"expected float32 [n, {cols}]")
+    return a
+
+
+@dataclasses.dataclass
+class Hits:
+    id: np.ndarray       # int32, -1 miss
+    t: np.ndarray        # float64, +inf miss
+    u: np.ndarray
+    v: np.ndarray
+    margin: np.ndarray   # capped at MARGIN_CAP
+    t2: np.ndarray | None = None
+    nodes: np.ndarray | None = None
+    tris_tested: np.ndarray | None = None
+
+
+def _alloc(m):
+    return (np.empty(m, np.int32), np.empty(m, np.float64), np.empty(m, np.float64),
+            np.empty(m, np.float64), np.empty(m, np.float64), np.empty(m, np.float64))
+
+
+def brute(tris, rays, skip=None, nthreads=0) -> Hits:
+    tris, rays = _f32(tris, 9), _f32(rays, 8)
+    m = rays.shape[0]
+    sk = None if skip is None else np.ascontiguousarray(skip, dtype=np.int32)
+    i, t, u, v, mg, t2 = _alloc(m)
+    rc = _load().or_brute(_ptr(tris), tris.shape[0], _ptr(rays), m, _ptr(sk), nthreads,
+                          _ptr(i), _ptr(t), _ptr(u), _ptr(v), _ptr(mg), _ptr(t2))
+    if rc != 0:
+        raise RuntimeError("or_brute failed")
+    return Hits(i, t, u, v, mg, t2)
+
+
+def evaluate(tris, rays, ids):
+    """Float64 crossing (valid, t, u, v) of each ray with its given facet."""
+    tris, rays = _f32(tris, 9), _f32(rays, 8)
+    ids = np.ascontiguousarray(ids, dtype=np.int32)
+    m = rays.shape[0]
+    valid = np.empty(m, np.int32)
+    t, u, v = np.empty(m), np.empty(m), np.empty(m)
+    rc = _load().or_eval(_ptr(tris), tris.shape[0], _ptr(rays), m, _ptr(ids), _ptr(valid),
+                         _ptr(t), _ptr(u), _ptr(v))
+    if rc != 0:
+        raise RuntimeError("or_eval failed")
+    return valid.astype(bool), t, u, v
+
+
+@dataclasses.dataclass
+class SplitParams:
+    alpha: float = 1.0
+    t_isect: float = 1.0
+    t_trav: float = 1.0
+    src: tuple = (0.0, 0.0, 0.0)
+    max_leaf: int = 4
+    nbins: int = 16
+    d_mode: str = "mean"
+    d_norm: str = "unit"
+    max_depth: int = 32
+    depth_limit: int = 64
+
+    def c(self) -> _Params:
+        p = _Params()
+        # alpha and the unit costs are single precision parameters on the GPU
+        # side; both sides widen the same float32 values
+        p.alpha = float(np.float32(self.alpha))
+        p.t_isect = float(np.float32(self.t_isect))
+        p.t_trav = float(np.float32(self.t_trav))
+        for k in range(3):
+            p.src[k] = float(np.float32(self.src[k]))
+        p.max_leaf, p.nbins = self.max_leaf, self.nbins
+        p.d_mode, p.d_norm = D_MODES[self.d_mode], D_NORMS[self.d_norm]
+        p.max_depth, p.depth_limit = self.max_depth, self.depth_limit
+        return p
+
+
+@dataclasses.dataclass
+class Tree:
+    """Depth-first pre-order node arrays of a binary BVH."""
+    lo: np.ndarray
+    hi: np.ndarray
+    left: np.ndarray
+    right: np.ndarray
+    first: np.ndarray
+    count: np.ndarray
+    depth: np.ndarray
+    axis: np.ndarray
+    plane: np.ndarray
+    flags: np.ndarray
+    cost: np.ndarray
+    perm: np.ndarray
+    handle: object = None
+    tris: np.ndarray | None = None
+
+    def __del__(self):
+        if self.handle is not None and _lib is not None:
+            _lib.or_tree_free(self.handle)
+            self.handle = None
+
+    @property
+    def n_nodes(self) -> int:
+        return int(self.left.shape[0])
+
+
+def build_tree(tris, params: SplitParams) -> Tree:
+    tris = _f32(tris, 9)
+    lib = _load()
+    cp = params.c()
+    h = lib.or_build(_ptr(tris), tris.shape[0], ctypes.byref(cp))
+    if not h:
+        raise ValueError("or_build rejected its arguments")
+    nn = lib.or_tree_size(h)
+    n = tris.shape[0]
+    lo, hi = np.empty((nn, 3)), np.empty((nn, 3))
+    ints = [np.empty(nn, np.int32) for _ in range(8)]
+    cost = np.empty(nn)
+    perm = np.empty(n, np.int32)
+    lib.or_tree_export(h, _ptr(lo), _ptr(hi), *[_ptr(a) for a in ints], _ptr(cost), _ptr(perm))
+    left, right, first, count, depth, axis, plane, flags = ints
+    return Tree(lo, hi, left, right, first, count, depth, axis, plane, flags, cost, perm,
+                handle=h, tris=tris)
+
+
+def trace_bvh(tree: Tree, rays, skip=None, nthreads=0, stats=False) -> Hits:
+    tris = tree.tris
+    rays = _f32(rays, 8)
+    m = rays.shape[0]
+    sk = None if skip is None else np.ascontiguousarray(skip, dtype=np.int32)
+    i, t, u, v, mg, t2 = _alloc(m)
+    nv = np.empty(m, np.int32) if stats else None
+    nt = np.empty(m, np.int32) if stats else None
+    rc = _load().or_trace_bvh(_ptr(tris), tris.shape[0], tree.handle, _ptr(rays), m, _ptr(sk),
+                              nthreads, _ptr(i), _ptr(t), _ptr(u), _ptr(v), _ptr(mg), _ptr(t2),
+                              _ptr(nv), _ptr(nt))
+    if rc != 0:
+        raise RuntimeError("or_trace_bvh failed")
+    return Hits(i, t, u, v, mg, t2, nv, nt)
+
+
+@dataclasses.dataclass
+class Chains:
+    id: np.ndarray        # [max_b, m]
+    t: np.ndarray
+    u: np.ndarray
+    v: np.ndarray
+    margin: np.ndarray
+    seg: np.ndarray | None  # [max_b, m, 8] float64
+    path_len: np.ndarray  # [m]
+    n_hits: np.ndarray    # [m]
+
+
+def bounces(tris, rays, max_b: int, tree: Tree | None = None, nthreads=0,
+            segments=True) -> Chains:
+    tris, rays = _f32(tris, 9), _f32(rays, 8)
+    m = rays.shape[0]
+    shape = (max_b, m)
+    i = np.empty(shape, np.int32)
+    t, u, v, mg = (np.empty(shape) for _ in range(4))
+    seg = np.empty((max_b, m, 8)) if segments else None
+    pl = np.empty(m)
+    nh = np.empty(m, np.int32)
+    rc = _load().or_bounces(_ptr(tris), tris.shape[0], None if tree is None else tree.handle,
+                            _ptr(rays), m, max_b, nthreads, _ptr(i), _ptr(t), _ptr(u),
+                            _ptr(v), _ptr(mg), _ptr(seg), _ptr(pl), _ptr(nh))
+    if rc != 0:
+        raise RuntimeError("or_bounces failed")
+    return Chains(i, t, u, v, mg, seg, pl, nh)

@@ -1,0 +1,110 @@
+"""Named synthetic workloads (scene + transmitters + launched rays).
+
+* ``microcell``: 200 x 200 m, 242 triangles, Tx (0, 0, 10), level-5
+  icosphere (10,242 rays), tmin 1e-4 m, tmax 500 m, one closest-hit segment.
+* ``city24k``: 2 x 2 km, 2,000 buildings (about 24k triangles), Tx (0, 0, 25),
+  level-9 icosphere (2,621,442 rays), tmin 1e-4 m, tmax 2 km per segment, up to
+  6 segments (bounces).
+* ``dense200k``: 3 x 3 km, tessellated facades (>= 200k triangles), 4 Tx at
+  (+-750, +-750, 25), level 9 per Tx (10,485,768 rays), up to 6 segments.
+* ``multiscene``: 8 city scenes of uneven size with 8 Tx each.
+
+The split parameters carry the paper's spatial-distance source point: the
+transmitter the BVH is built for (Eq. 2).
+"""
+from __future__ import annotations
+
+import dataclasses
+import functools
+import math
+
+import numpy as np
+
+from . import icosphere, scenes
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    tris: np.ndarray            # float32 [n, 9]
+    rays: np.ndarray            # float32 [m, 8]
+    tx: tuple                   # source point used for the distance term
+    max_bounces: int
+    tmin: float
+    tmax: float
+    level: int
+
+    @property
+    def n_tris(self) -> int:
+        return int(self.tris.shape[0])
+
+    @property
+    def n_rays(self) -> int:
+        return int(self.rays.shape[0])
+
+
+@functools.lru_cache(maxsize=2)
+def _city24k_tris(seed: int) -> np.ndarray:
+    return scenes.city(seed=seed)
+
+
+@functools.lru_cache(maxsize=1)
+def _dense_tris(seed: int) -> np.ndarray:
+    return scenes.dense_city(seed=seed)
+
+
+def microcell(seed: int = 0) -> Workload:
+    tx = (0.0, 0.0, 10.0)
+    tris = scenes.microcell(seed=seed, tx=tx)
+    rays = icosphere.make_rays(tx, icosphere.directions(5), 1e-4, 500.0)
+    return Workload("microcell-242tri-L5", tris, rays, tx, 1, 1e-4, 500.0, 5)
+
+
+def city24k(seed: int = 0, level: int = 9, max_bounces: int = 6) -> Workload:
+    tx = (0.0, 0.0, 25.0)
+    tris = _city24k_tris(seed)
+    rays = icosphere.make_rays(tx, icosphere.directions(level), 1e-4, 2000.0)
+    return Workload(f"city-{tris.shape[0]}tri-L{level}-b{max_bounces}", tris, rays,
+                    tx, max_bounces, 1e-4, 2000.0, level)
+
+
+DENSE_TX = ((-750.0, -750.0, 25.0), (750.0, -750.0, 25.0),
+            (-750.0, 750.0, 25.0), (750.0, 750.0, 25.0))
+
+
+def dense200k(seed: int = 0, level: int = 9, max_bounces: int = 6) -> Workload:
+    """Rays of the 4 transmitters concatenated; the distance term uses the
+    centre of the four (the BVH serves all of them at once)."""
+    tris = _dense_tris(seed)
+    d = icosphere.directions(level)
+    rays = np.concatenate([icosphere.make_rays(t, d, 1e-4, 2000.0) for t in DENSE_TX])
+    centre = tuple(float(np.mean([t[i] for t in DENSE_TX])) for i in range(3))
+    return Workload(f"dense-{tris.shape[0]}tri-4xL{level}-b{max_bounces}", tris, rays,
+                    centre, max_bounces, 1e-4, 2000.0, level)
+
+
+MULTI_TARGETS = (1_000, 4_000, 12_000, 24_000, 50_000, 90_000, 140_000, 200_000)
+
+
+def multiscene_scene(i: int) -> tuple[np.ndarray, float]:
+    """Scene i of the uneven multi-scene set: ``target / 12`` buildings on a
+    square of side 2 km * sqrt(target / 24k), seed i; returns (tris, half)."""
+    target = MULTI_TARGETS[i]
+    nb = max(1, target // 12)
+    half = 1000.0 * math.sqrt(target / 24_000)
+    return scenes.city(seed=i, n_buildings=nb, half=half, tx=None), half
+
+
+def multiscene_queries(seed: int = 0, per_scene: int = 8, levels=(6, 9), bounces=(1, 6)):
+    """Transmitters spread over the 8 scenes: per query (scene, tx, level,
+    max_bounces); Tx uniform outside buildings at 25 m."""
+    rng = np.random.default_rng(1000 + seed)
+    out = []
+    for s in range(len(MULTI_TARGETS)):
+        tris, half = multiscene_scene(s)
+        for _ in range(per_scene):
+            tx = scenes.free_point(rng, half, tris, 25.0)
+            lv = int(rng.integers(levels[0], levels[1] + 1))
+            nb = int(rng.integers(bounces[0], bounces[1] + 1))
+            out.append((s, tx, lv, nb))
+    return out
