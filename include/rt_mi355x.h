@@ -1,0 +1,180 @@
+/* rt_mi355x.h -- C ABI of the MI355X (gfx950) closest-hit ray tracer.
+ *
+ * The library builds a bounding volume hierarchy over triangular facets with
+ * the split cost that blends the surface area heuristic with the squared
+ * distance from the ray source point (Sec. II-B, Eq. (2)), then traces
+ * launched rays through it: a ray enters only the bounding volumes it meets
+ * (Sec. III-B), keeps the nearest facet hit inside its action range
+ * [tmin, tmax], and may be re-launched as a specular reflection up to a set
+ * number of segments (Sec. III-B, reflection order).
+ *
+ * Conventions shared by every call:
+ *   - All array arguments are DEVICE pointers (HBM) unless a comment says
+ *     "host".  The caller owns them; the library never frees them.
+ *   - Every call that takes a stream enqueues its device work on that stream
+ *     (hipStream_t, 0 = the null stream).  rt_build and rt_rebuild also wait
+ *     for it: they read one counter per tree level back to the host.
+ *   - Functions return RT_OK (0) or a negative RT_E* code; the text of the
+ *     last error on the calling thread is given by rt_last_error().  No C++
+ *     exception crosses this interface.
+ *   - Facets: float32 [n][9] = (v0.xyz, v1.xyz, v2.xyz), 4-byte aligned.
+ *     Facet ids are the caller's indices 0..n-1.
+ *   - Rays: float32 [m][8] = (ox, oy, oz, tmin, dx, dy, dz, tmax), 32 bytes
+ *     per ray, 16-byte aligned.  d need not be unit length; t is the ray
+ *     parameter (point = o + t d).  The range is closed: tmin <= t <= tmax.
+ *   - Hits: rt_hit, 16 bytes, 16-byte aligned.  Ties on t go to the smaller
+ *     facet id; a miss is {-1, +inf, 0, 0}.
+ */
+#ifndef RT_MI355X_H
+#define RT_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define RT_OK 0
+#define RT_EINVAL (-1) /* bad argument: null / misaligned pointer, size, NaN facet, parameter out of range */
+#define RT_ENOMEM (-2) /* device allocation failed */
+#define RT_EHIP (-3)   /* a HIP runtime call failed; rt_last_error() has its text */
+#define RT_EDEPTH (-4) /* internal: tree deeper than the traversal stack */
+
+/* ---- split parameters (Sec. II-B, Sec. II-C) ---------------------------- */
+#define RT_D_CHILD_MEAN 0      /* d^2 = mean of the two child volumes' d^2 (default) */
+#define RT_D_CHILD_SUM 1       /* d^2 = sum of the two children's d^2 */
+#define RT_D_CHILD_KWEIGHTED 2 /* d^2 = facet-count-weighted mean of the children's d^2 */
+#define RT_D_PARENT 3          /* d^2 of the parent volume: constant per node, equals Eq. (1) */
+
+#define RT_DNORM_UNIT 0 /* SAH part / (k_C t_i), distance part / (root diagonal)^2 (default) */
+#define RT_DNORM_RAW 1  /* Eq. (2) in the units it is printed in (metres squared) */
+
+#define RT_MAX_BINS 64     /* largest nbins */
+#define RT_MAX_DEPTH 64    /* largest depth_limit: the traversal stack holds this many entries */
+#define RT_MAX_BOUNCES 64  /* largest max_bounces */
+
+typedef struct rt_split_params {
+  float alpha;       /* Eq. (2) weight in [0, 1]; 1 = surface area only (Eq. (1)), 0 = distance only */
+  float t_isect;     /* t_i, cost of one facet test (> 0) */
+  float t_trav;      /* t_trav, per-node constant of Eq. (1)/(2) (>= 0) */
+  float src[3];      /* ray source point whose distance to a volume's centre enters Eq. (2) */
+  int32_t max_leaf;  /* a node holding <= max_leaf facets is a leaf (>= 1) */
+  int32_t nbins;     /* candidate planes: nbins equal centroid bins per axis (2..RT_MAX_BINS) */
+  int32_t d_mode;    /* RT_D_* */
+  int32_t d_norm;    /* RT_DNORM_* */
+  int32_t max_depth; /* from this depth on, alpha is taken as 1 */
+  int32_t depth_limit; /* no leaf deeper than this (1..RT_MAX_DEPTH); nodes that could
+                          not otherwise meet it are halved by position */
+} rt_split_params;
+
+/* Defaults: alpha 1, t_isect 1, t_trav 1, src 0, max_leaf 4, nbins 16,
+ * RT_D_CHILD_MEAN, RT_DNORM_UNIT, max_depth 32, depth_limit 64. */
+void rt_split_params_default(rt_split_params* p);
+
+/* ---- results ------------------------------------------------------------ */
+typedef struct rt_hit {
+  int32_t tri_id; /* caller's facet index, -1 = miss */
+  float t;        /* ray parameter of the hit, +inf on a miss */
+  float u, v;     /* hit point = (1 - u - v) v0 + u v1 + v v2 */
+} rt_hit;
+
+typedef struct rt_bvh rt_bvh; /* opaque; owns its device memory */
+
+typedef struct rt_bvh_info {
+  int64_t n_tris;
+  int64_t n_nodes;     /* binary tree nodes, leaves included (2 * n_internal + 1) */
+  int64_t n_internal;
+  int64_t n_leaves;
+  int32_t depth;       /* deepest leaf, root = 0 */
+  int32_t n_levels;    /* build passes run (one per tree level) */
+  int64_t device_bytes; /* device memory held by the handle */
+  int64_t trace_bytes;  /* of which: traversal nodes + leaf-ordered facets */
+  float root_lo[3], root_hi[3];
+} rt_bvh_info;
+
+/* One node of the binary tree in build order (breadth-first; the two
+ * children of a node are adjacent: right = left + 1). */
+typedef struct rt_node_rec {
+  float lo[3], hi[3]; /* node volume: union of its facets' boxes (Eq. (3) bounds) */
+  int32_t left;       /* index of the left child, -1 for a leaf */
+  int32_t first;      /* facets perm[first .. first + count) belong to this node */
+  int32_t count;
+  int32_t depth;      /* root = 0 */
+  int32_t axis;       /* chosen split axis 0..2, -1 for leaves and position splits */
+  int32_t plane;      /* chosen bin boundary 1..nbins-1, -1 likewise */
+  int32_t flags;      /* bit0 halved by position (depth limit), bit1 all centroids equal,
+                         bit2 alpha taken as 1 (depth >= max_depth) */
+  int32_t reserved;
+  double cost;        /* Eq. (2) cost of the chosen split (0 if none) */
+} rt_node_rec;
+
+/* ---- build (Sec. II-C) ---------------------------------------------------
+ * Builds the tree of n facets on the GPU: per-facet boxes and centroids,
+ * root volume, then one pass per tree level that bins each node's centroids,
+ * evaluates Eq. (2) on every bin boundary, and partitions the node's facets
+ * (stable: each side keeps the input order).  tris may be freed once the call
+ * returns.  *out receives a new handle.  Waits for stream s.
+ * Errors: RT_EINVAL (null, n < 1, n >= 2^30, non-finite vertex, bad params),
+ * RT_ENOMEM, RT_EHIP. */
+int rt_build(const float* tris, int64_t n, const rt_split_params* p, rt_bvh** out,
+             hipStream_t s);
+
+/* Rebuilds an existing handle in place for new facets or parameters, reusing
+ * its device memory when it is large enough.  Same contract as rt_build. */
+int rt_rebuild(rt_bvh* b, const float* tris, int64_t n, const rt_split_params* p,
+               hipStream_t s);
+
+/* ---- trace (Sec. III-B) -------------------------------------------------
+ * Closest hit of each ray: out[i] for rays[i].  n = 0 is a no-op.  The handle
+ * may be traced concurrently from several streams.
+ * Errors: RT_EINVAL (null / misaligned pointers, n < 0). */
+int rt_trace(const rt_bvh* b, const float* rays, int64_t n, rt_hit* out, hipStream_t s);
+
+/* Reflection chains: each ray is traced; after a hit it is reflected
+ * specularly about the facet's plane and launched again from the hit point
+ * with the same [tmin, tmax], ignoring the facet it leaves, until it misses
+ * or max_bounces segments have been traced.
+ *   out       [max_bounces][n] rt_hit, segment b of ray i at out[b * n + i];
+ *             segments after the one that missed are written as misses
+ *   path_len  [n] float64: sum over the hits of t * |d| (nullable)
+ *   n_hits    [n] int32: number of hits (reflection points) (nullable)
+ * Errors: RT_EINVAL (as rt_trace; max_bounces outside 1..RT_MAX_BOUNCES). */
+int rt_trace_bounces(const rt_bvh* b, const float* rays, int64_t n, int32_t max_bounces,
+                     rt_hit* out, double* path_len, int32_t* n_hits, hipStream_t s);
+
+/* Optional outputs and launch shape for rt_trace_ex. */
+typedef struct rt_trace_opts {
+  float* seg_rays;     /* nullable, [max_bounces][n][8]: the ray of every traced segment,
+                          as rays[] (the reflected origin, direction, tmin, tmax); rows of
+                          segments never traced are left untouched */
+  uint32_t* ray_stats; /* nullable, [n][2]: nodes visited and facets tested per ray,
+                          summed over its segments (instrumented kernel, slower) */
+  int32_t block;       /* threads per block, 64..1024 multiple of 64; 0 = default */
+  int32_t grid;        /* persistent blocks; 0 = default (fills every compute unit) */
+} rt_trace_opts;
+
+/* rt_trace_bounces with optional outputs (opts nullable). */
+int rt_trace_ex(const rt_bvh* b, const float* rays, int64_t n, int32_t max_bounces,
+                rt_hit* out, double* path_len, int32_t* n_hits, const rt_trace_opts* opts,
+                hipStream_t s);
+
+/* ---- inspection and lifetime ------------------------------------------ */
+int rt_bvh_info_get(const rt_bvh* b, rt_bvh_info* info); /* host struct */
+
+/* Copies the binary tree (host buffers): nodes [info.n_nodes], perm [n_tris]
+ * (leaf order of the caller's facet ids).  Synchronises the device.
+ * RT_EINVAL if a capacity is too small. */
+int rt_bvh_download(const rt_bvh* b, rt_node_rec* nodes, int64_t node_cap, int32_t* perm,
+                    int64_t perm_cap);
+
+void rt_bvh_destroy(rt_bvh* b); /* NULL is a no-op; waits for the device */
+
+const char* rt_last_error(void); /* thread-local, never NULL */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RT_MI355X_H */

@@ -1,0 +1,275 @@
+"""MI355X (gfx950) closest-hit ray tracing through a BVH built with the
+SAH-plus-spatial-distance split of arXiv 2208.10008 (Sec. II-B, Eq. (2)).
+
+Thin ctypes binding of ``librt_mi355x.so`` (C ABI in ``include/rt_mi355x.h``).
+Every step of the path runs in the library's HIP kernels; this module only
+marshals arguments.  PyTorch supplies device memory (CUDA tensors) and
+streams.  Importing works without a GPU; any call that needs the library
+raises :class:`RtError` if it has not been built (``python -m
+paper_2208_10008_amd._build``) -- there is no CPU fallback.
+
+Low-level functions keep the C names (:func:`rt_build`, :func:`rt_trace`,
+:func:`rt_trace_bounces`, ...); :class:`BVH` wraps a handle.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librt_mi355x.so")
+
+RT_OK, RT_EINVAL, RT_ENOMEM, RT_EHIP, RT_EDEPTH = 0, -1, -2, -3, -4
+D_MODES = {"mean": 0, "sum": 1, "kweighted": 2, "parent": 3}
+D_NORMS = {"unit": 0, "raw": 1}
+MAX_BOUNCES = 64
+
+
+class RtError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class rt_split_params(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_float), ("t_isect", ctypes.c_float),
+                ("t_trav", ctypes.c_float), ("src", ctypes.c_float * 3),
+                ("max_leaf", ctypes.c_int32), ("nbins", ctypes.c_int32),
+                ("d_mode", ctypes.c_int32), ("d_norm", ctypes.c_int32),
+                ("max_depth", ctypes.c_int32), ("depth_limit", ctypes.c_int32)]
+
+
+class rt_bvh_info(ctypes.Structure):
+    _fields_ = [("n_tris", ctypes.c_int64), ("n_nodes", ctypes.c_int64),
+                ("n_internal", ctypes.c_int64), ("n_leaves", ctypes.c_int64),
+                ("depth", ctypes.c_int32), ("n_levels", ctypes.c_int32),
+                ("device_bytes", ctypes.c_int64), ("trace_bytes", ctypes.c_int64),
+                ("root_lo", ctypes.c_float * 3), ("root_hi", ctypes.c_float * 3)]
+
+
+class rt_trace_opts(ctypes.Structure):
+    _fields_ = [("seg_rays", ctypes.c_void_p), ("ray_stats", ctypes.c_void_p),
+                ("block", ctypes.c_int32), ("grid", ctypes.c_int32)]
+
+
+# numpy view of rt_node_rec (64 bytes)
+NODE_DTYPE = np.dtype([("lo", "<f4", 3), ("hi", "<f4", 3), ("left", "<i4"), ("first", "<i4"),
+                       ("count", "<i4"), ("depth", "<i4"), ("axis", "<i4"), ("plane", "<i4"),
+                       ("flags", "<i4"), ("reserved", "<i4"), ("cost", "<f8")])
+assert NODE_DTYPE.itemsize == 64
+
+EXPORTS = ("rt_split_params_default", "rt_build", "rt_rebuild", "rt_trace",
+           "rt_trace_bounces", "rt_trace_ex", "rt_bvh_info_get", "rt_bvh_download",
+           "rt_bvh_destroy", "rt_last_error")
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Loads the HIP library; raises RtError if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RtError(RT_EHIP, f"{path} is not built; run python -m paper_2208_10008_amd._build")
+    lib = ctypes.CDLL(path)
+    P, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    lib.rt_split_params_default.argtypes = [ctypes.POINTER(rt_split_params)]
+    lib.rt_split_params_default.restype = None
+    lib.rt_build.argtypes = [P, i64, ctypes.POINTER(rt_split_params), ctypes.POINTER(P), P]
+    lib.rt_rebuild.argtypes = [P, P, i64, ctypes.POINTER(rt_split_params), P]
+    lib.rt_trace.argtypes = [P, P, i64, P, P]
+    lib.rt_trace_bounces.argtypes = [P, P, i64, i32, P, P, P, P]
+    lib.rt_trace_ex.argtypes = [P, P, i64, i32, P, P, P, ctypes.POINTER(rt_trace_opts), P]
+    lib.rt_bvh_info_get.argtypes = [P, ctypes.POINTER(rt_bvh_info)]
+    lib.rt_bvh_download.argtypes = [P, P, i64, P, i64]
+    lib.rt_bvh_destroy.argtypes = [P]
+    lib.rt_bvh_destroy.restype = None
+    lib.rt_last_error.argtypes = []
+    lib.rt_last_error.restype = ctypes.c_char_p
+    for name in ("rt_build", "rt_rebuild", "rt_trace", "rt_trace_bounces", "rt_trace_ex",
+                 "rt_bvh_info_get", "rt_bvh_download"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != RT_OK:
+        raise RtError(rc, load().rt_last_error().decode())
+
+
+@dataclasses.dataclass
+class SplitParams:
+    """Eq. (2) split parameters (rt_split_params)."""
+    alpha: float = 1.0
+    t_isect: float = 1.0
+    t_trav: float = 1.0
+    src: tuple = (0.0, 0.0, 0.0)
+    max_leaf: int = 4
+    nbins: int = 16
+    d_mode: str = "mean"
+    d_norm: str = "unit"
+    max_depth: int = 32
+    depth_limit: int = 64
+
+    def c(self) -> rt_split_params:
+        p = rt_split_params()
+        p.alpha, p.t_isect, p.t_trav = self.alpha, self.t_isect, self.t_trav
+        for k in range(3):
+            p.src[k] = self.src[k]
+        p.max_leaf, p.nbins = self.max_leaf, self.nbins
+        p.d_mode, p.d_norm = D_MODES[self.d_mode], D_NORMS[self.d_norm]
+        p.max_depth, p.depth_limit = self.max_depth, self.depth_limit
+        return p
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dev(t, dtype, cols, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise RtError(RT_EINVAL, f"{name} must be a CUDA tensor")
+    if t.dtype != dtype or t.dim() != 2 or t.shape[1] != cols or not t.is_contiguous():
+        raise RtError(RT_EINVAL, f"{name} must be a contiguous {dtype} tensor [n, {cols}]")
+    return t
+
+
+# ---- C-named entry points -------------------------------------------------
+def rt_build(tris, params: SplitParams | rt_split_params, stream=None) -> ctypes.c_void_p:
+    """rt_build(tris [n, 9] float32 CUDA tensor, params) -> handle."""
+    lib = load()
+    _dev(tris, __import__("torch").float32, 9, "tris")
+    cp = params.c() if isinstance(params, SplitParams) else params
+    h = ctypes.c_void_p()
+    _check(lib.rt_build(_ptr(tris), tris.shape[0], ctypes.byref(cp), ctypes.byref(h), _stream(stream)))
+    return h
+
+
+def rt_rebuild(handle, tris, params, stream=None):
+    lib = load()
+    _dev(tris, __import__("torch").float32, 9, "tris")
+    cp = params.c() if isinstance(params, SplitParams) else params
+    _check(lib.rt_rebuild(handle, _ptr(tris), tris.shape[0], ctypes.byref(cp), _stream(stream)))
+
+
+def rt_trace(handle, rays, out, stream=None):
+    """rays [n, 8] float32, out [n, 4] int32 view of rt_hit (CUDA tensors)."""
+    lib = load()
+    _check(lib.rt_trace(handle, _ptr(rays), rays.shape[0], _ptr(out), _stream(stream)))
+
+
+def rt_trace_bounces(handle, rays, max_bounces, out, path_len=None, n_hits=None, stream=None):
+    lib = load()
+    _check(lib.rt_trace_bounces(handle, _ptr(rays), rays.shape[0], max_bounces, _ptr(out),
+                                _ptr(path_len), _ptr(n_hits), _stream(stream)))
+
+
+def rt_trace_ex(handle, rays, max_bounces, out, path_len=None, n_hits=None, seg_rays=None,
+                ray_stats=None, block=0, grid=0, stream=None):
+    lib = load()
+    o = rt_trace_opts()
+    o.seg_rays = None if seg_rays is None else seg_rays.data_ptr()
+    o.ray_stats = None if ray_stats is None else ray_stats.data_ptr()
+    o.block, o.grid = block, grid
+    _check(lib.rt_trace_ex(handle, _ptr(rays), rays.shape[0], max_bounces, _ptr(out),
+                           _ptr(path_len), _ptr(n_hits), ctypes.byref(o), _stream(stream)))
+
+
+def rt_bvh_info_get(handle) -> rt_bvh_info:
+    info = rt_bvh_info()
+    _check(load().rt_bvh_info_get(handle, ctypes.byref(info)))
+    return info
+
+
+def rt_bvh_download(handle):
+    info = rt_bvh_info_get(handle)
+    nodes = np.zeros(info.n_nodes, dtype=NODE_DTYPE)
+    perm = np.zeros(info.n_tris, dtype=np.int32)
+    _check(load().rt_bvh_download(handle, nodes.ctypes.data_as(ctypes.c_void_p), info.n_nodes,
+                                  perm.ctypes.data_as(ctypes.c_void_p), info.n_tris))
+    return nodes, perm
+
+
+def rt_bvh_destroy(handle):
+    if handle:
+        load().rt_bvh_destroy(handle)
+
+
+# ---- handle wrapper ---------------------------------------------------------
+class BVH:
+    """Owns one rt_bvh handle; tensors passed in stay owned by the caller."""
+
+    def __init__(self, tris, params: SplitParams | None = None, stream=None):
+        self.params = params or SplitParams()
+        self.handle = rt_build(tris, self.params, stream)
+
+    def rebuild(self, tris, params: SplitParams | None = None, stream=None):
+        if params is not None:
+            self.params = params
+        rt_rebuild(self.handle, tris, self.params, stream)
+
+    def info(self) -> rt_bvh_info:
+        return rt_bvh_info_get(self.handle)
+
+    def download(self):
+        return rt_bvh_download(self.handle)
+
+    def hits_buffer(self, n, max_bounces=1):
+        import torch
+        return torch.empty((max_bounces, n, 4), dtype=torch.int32, device="cuda")
+
+    def trace(self, rays, out=None, stream=None):
+        _dev(rays, __import__("torch").float32, 8, "rays")
+        if out is None:
+            out = self.hits_buffer(rays.shape[0])[0]
+        rt_trace(self.handle, rays, out, stream)
+        return out
+
+    def trace_bounces(self, rays, max_bounces, out=None, path_len=None, n_hits=None,
+                      seg_rays=None, ray_stats=None, block=0, grid=0, stream=None):
+        import torch
+        _dev(rays, torch.float32, 8, "rays")
+        n = rays.shape[0]
+        if out is None:
+            out = self.hits_buffer(n, max_bounces)
+        if path_len is None:
+            path_len = torch.empty(n, dtype=torch.float64, device=rays.device)
+        if n_hits is None:
+            n_hits = torch.empty(n, dtype=torch.int32, device=rays.device)
+        if seg_rays is None and ray_stats is None and block == 0 and grid == 0:
+            rt_trace_bounces(self.handle, rays, max_bounces, out, path_len, n_hits, stream)
+        else:
+            rt_trace_ex(self.handle, rays, max_bounces, out, path_len, n_hits, seg_rays,
+                        ray_stats, block, grid, stream)
+        return out, path_len, n_hits
+
+    def close(self):
+        if getattr(self, "handle", None):
+            rt_bvh_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def split_hits(out):
+    """int32 [..., 4] view of rt_hit -> (tri_id int32, t, u, v float32) tensors."""
+    ids = out[..., 0]
+    tuv = out[..., 1:].view(__import__("torch").float32)
+    return ids, tuv[..., 0], tuv[..., 1], tuv[..., 2]

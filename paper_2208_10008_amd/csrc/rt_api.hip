@@ -1,0 +1,287 @@
+// C ABI of the gfx950 ray tracing library (declared in include/rt_mi355x.h):
+// argument checks, device memory of a tree handle, error text.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "rt_internal.h"
+
+namespace rt {
+
+static thread_local std::string g_err = "no error";
+
+int set_error(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int check_hip(hipError_t e, const char* what) {
+  if (e == hipSuccess) return RT_OK;
+  if (e == hipErrorOutOfMemory)
+    return set_error(RT_ENOMEM, std::string(what) + ": out of device memory");
+  return set_error(RT_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+namespace {
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+void free_buffers(Buffers& B) {
+  void* ptrs[] = {B.flo,  B.fhi,   B.cen,      B.refs_a,   B.refs_b, B.perm,   B.nodes,
+                  B.act_a, B.act_b, B.cand,    B.counters, B.root_box, B.tnodes, B.tfacets};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  B = Buffers();
+}
+
+template <class T>
+int alloc(T*& p, size_t count, int64_t& bytes) {
+  size_t b = sizeof(T) * (count ? count : 1);
+  hipError_t e = hipMalloc((void**)&p, b);
+  if (e != hipSuccess) {
+    p = nullptr;
+    return check_hip(e, "hipMalloc");
+  }
+  bytes += (int64_t)b;
+  return RT_OK;
+}
+
+int ensure_buffers(Buffers& B, int64_t n) {
+  if (B.cap_n >= n && B.flo) return RT_OK;
+  free_buffers(B);
+  int64_t bytes = 0;
+  int rc = RT_OK;
+  const size_t nn = (size_t)n;
+  if (rc == RT_OK) rc = alloc(B.flo, nn, bytes);
+  if (rc == RT_OK) rc = alloc(B.fhi, nn, bytes);
+  if (rc == RT_OK) rc = alloc(B.cen, 3 * nn, bytes);
+  if (rc == RT_OK) rc = alloc(B.refs_a, nn, bytes);
+  if (rc == RT_OK) rc = alloc(B.refs_b, nn, bytes);
+  if (rc == RT_OK) rc = alloc(B.perm, nn, bytes);
+  if (rc == RT_OK) rc = alloc(B.nodes, 2 * nn, bytes);
+  if (rc == RT_OK) rc = alloc(B.act_a, nn, bytes);
+  if (rc == RT_OK) rc = alloc(B.act_b, nn, bytes);
+  if (rc == RT_OK) rc = alloc(B.cand, 2 * nn, bytes);
+  if (rc == RT_OK) rc = alloc(B.counters, 16, bytes);
+  if (rc == RT_OK) rc = alloc(B.root_box, 12, bytes);
+  if (rc == RT_OK) rc = alloc(B.tnodes, nn, bytes);
+  if (rc == RT_OK) rc = alloc(B.tfacets, nn, bytes);
+  if (rc != RT_OK) {
+    free_buffers(B);
+    return rc;
+  }
+  B.cap_n = n;
+  B.bytes = bytes;
+  return RT_OK;
+}
+
+int check_params(const rt_split_params* p) {
+  if (!p) return set_error(RT_EINVAL, "split params: NULL");
+  if (!(p->alpha >= 0.f && p->alpha <= 1.f))
+    return set_error(RT_EINVAL, "split params: alpha must lie in [0, 1]");
+  if (!(p->t_isect > 0.f) || !std::isfinite(p->t_isect))
+    return set_error(RT_EINVAL, "split params: t_isect must be positive");
+  if (!(p->t_trav >= 0.f) || !std::isfinite(p->t_trav))
+    return set_error(RT_EINVAL, "split params: t_trav must be >= 0");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(p->src[a])) return set_error(RT_EINVAL, "split params: src not finite");
+  if (p->max_leaf < 1) return set_error(RT_EINVAL, "split params: max_leaf must be >= 1");
+  if (p->nbins < 2 || p->nbins > RT_MAX_BINS)
+    return set_error(RT_EINVAL, "split params: nbins must lie in 2..64");
+  if (p->d_mode < RT_D_CHILD_MEAN || p->d_mode > RT_D_PARENT)
+    return set_error(RT_EINVAL, "split params: unknown d_mode");
+  if (p->d_norm != RT_DNORM_UNIT && p->d_norm != RT_DNORM_RAW)
+    return set_error(RT_EINVAL, "split params: unknown d_norm");
+  if (p->max_depth < 0) return set_error(RT_EINVAL, "split params: max_depth must be >= 0");
+  if (p->depth_limit < 1 || p->depth_limit > RT_MAX_DEPTH)
+    return set_error(RT_EINVAL, "split params: depth_limit must lie in 1..64");
+  return RT_OK;
+}
+
+int check_build_args(const float* tris, int64_t n, const rt_split_params* p) {
+  if (!tris) return set_error(RT_EINVAL, "rt_build: tris is NULL");
+  if (n < 1 || n >= (int64_t(1) << 30)) return set_error(RT_EINVAL, "rt_build: n must lie in 1..2^30-1");
+  if (!aligned(tris, 4)) return set_error(RT_EINVAL, "rt_build: tris must be 4-byte aligned");
+  int rc = check_params(p);
+  if (rc != RT_OK) return rc;
+  // a halving schedule must reach the leaf size within the depth limit
+  int64_t need = (n + p->max_leaf - 1) / p->max_leaf;
+  int l = 0;
+  while ((int64_t(1) << l) < need) ++l;
+  if (l > p->depth_limit)
+    return set_error(RT_EINVAL, "rt_build: depth_limit too small for n / max_leaf");
+  return RT_OK;
+}
+
+int do_build(rt_bvh* b, const float* tris, int64_t n, const rt_split_params* p, hipStream_t s) {
+  int rc = check_build_args(tris, n, p);
+  if (rc != RT_OK) return rc;
+  rc = ensure_buffers(b->buf, n);
+  if (rc != RT_OK) return rc;
+  rt_bvh_info info;
+  std::memset(&info, 0, sizeof(info));
+  rc = build_tree(b->buf, tris, n, *p, s, &info);
+  if (rc != RT_OK) return rc;
+  info.device_bytes = b->buf.bytes;
+  b->info = info;
+  b->params = *p;
+  // root bounds for the info struct
+  BNode root;
+  rc = check_hip(hipMemcpy(&root, b->buf.nodes, sizeof(BNode), hipMemcpyDeviceToHost), "hipMemcpy");
+  if (rc != RT_OK) return rc;
+  for (int a = 0; a < 3; ++a) {
+    b->info.root_lo[a] = root.lo[a];
+    b->info.root_hi[a] = root.hi[a];
+  }
+  return RT_OK;
+}
+
+int check_trace_args(const rt_bvh* b, const float* rays, int64_t n, int32_t max_b, const rt_hit* out,
+                     const double* path_len, const int32_t* n_hits, const rt_trace_opts* opts) {
+  if (!b || b->info.n_tris <= 0) return set_error(RT_EINVAL, "trace: invalid tree handle");
+  if (n < 0) return set_error(RT_EINVAL, "trace: n must be >= 0");
+  if (n >= (int64_t(1) << 40)) return set_error(RT_EINVAL, "trace: n too large");
+  if (max_b < 1 || max_b > RT_MAX_BOUNCES)
+    return set_error(RT_EINVAL, "trace: max_bounces must lie in 1..64");
+  if (n == 0) return RT_OK;
+  if (!rays || !out) return set_error(RT_EINVAL, "trace: rays and out must not be NULL");
+  if (!aligned(rays, 16) || !aligned(out, 16))
+    return set_error(RT_EINVAL, "trace: rays and out must be 16-byte aligned");
+  if ((path_len && !aligned(path_len, 8)) || (n_hits && !aligned(n_hits, 4)))
+    return set_error(RT_EINVAL, "trace: misaligned path_len / n_hits");
+  if (opts) {
+    if (opts->seg_rays && !aligned(opts->seg_rays, 16))
+      return set_error(RT_EINVAL, "trace: seg_rays must be 16-byte aligned");
+    if (opts->ray_stats && !aligned(opts->ray_stats, 8))
+      return set_error(RT_EINVAL, "trace: ray_stats must be 8-byte aligned");
+    if (opts->block < 0 || opts->block > 1024 || (opts->block % 64) != 0 || opts->grid < 0)
+      return set_error(RT_EINVAL, "trace: block must be a multiple of 64 up to 1024, grid >= 0");
+  }
+  return RT_OK;
+}
+
+}  // namespace
+}  // namespace rt
+
+using namespace rt;
+
+extern "C" {
+
+void rt_split_params_default(rt_split_params* p) {
+  if (!p) return;
+  p->alpha = 1.f;
+  p->t_isect = 1.f;
+  p->t_trav = 1.f;
+  p->src[0] = p->src[1] = p->src[2] = 0.f;
+  p->max_leaf = 4;
+  p->nbins = 16;
+  p->d_mode = RT_D_CHILD_MEAN;
+  p->d_norm = RT_DNORM_UNIT;
+  p->max_depth = 32;
+  p->depth_limit = 64;
+}
+
+int rt_build(const float* tris, int64_t n, const rt_split_params* p, rt_bvh** out,
+             hipStream_t s) {
+  if (!out) return set_error(RT_EINVAL, "rt_build: out is NULL");
+  *out = nullptr;
+  int rc0 = check_build_args(tris, n, p);
+  if (rc0 != RT_OK) return rc0;
+  rt_bvh* b = new (std::nothrow) rt_bvh();
+  if (!b) return set_error(RT_ENOMEM, "rt_build: host allocation failed");
+  std::memset(&b->info, 0, sizeof(b->info));
+  (void)hipGetDevice(&b->device);
+  int rc = do_build(b, tris, n, p, s);
+  if (rc != RT_OK) {
+    free_buffers(b->buf);
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return RT_OK;
+}
+
+int rt_rebuild(rt_bvh* b, const float* tris, int64_t n, const rt_split_params* p, hipStream_t s) {
+  if (!b) return set_error(RT_EINVAL, "rt_rebuild: handle is NULL");
+  int rc = do_build(b, tris, n, p, s);
+  if (rc != RT_OK) b->info.n_tris = 0;  // unusable until rebuilt
+  return rc;
+}
+
+int rt_trace(const rt_bvh* b, const float* rays, int64_t n, rt_hit* out, hipStream_t s) {
+  int rc = check_trace_args(b, rays, n, 1, out, nullptr, nullptr, nullptr);
+  if (rc != RT_OK || n == 0) return rc;
+  return launch_trace(b->buf, b->info.n_internal, rays, n, 1, out, nullptr, nullptr, nullptr, s);
+}
+
+int rt_trace_bounces(const rt_bvh* b, const float* rays, int64_t n, int32_t max_bounces,
+                     rt_hit* out, double* path_len, int32_t* n_hits, hipStream_t s) {
+  return rt_trace_ex(b, rays, n, max_bounces, out, path_len, n_hits, nullptr, s);
+}
+
+int rt_trace_ex(const rt_bvh* b, const float* rays, int64_t n, int32_t max_bounces, rt_hit* out,
+                double* path_len, int32_t* n_hits, const rt_trace_opts* opts, hipStream_t s) {
+  int rc = check_trace_args(b, rays, n, max_bounces, out, path_len, n_hits, opts);
+  if (rc != RT_OK || n == 0) return rc;
+  return launch_trace(b->buf, b->info.n_internal, rays, n, max_bounces, out, path_len, n_hits,
+                      opts, s);
+}
+
+int rt_bvh_info_get(const rt_bvh* b, rt_bvh_info* info) {
+  if (!b || !info) return set_error(RT_EINVAL, "rt_bvh_info_get: NULL argument");
+  *info = b->info;
+  return RT_OK;
+}
+
+int rt_bvh_download(const rt_bvh* b, rt_node_rec* nodes, int64_t node_cap, int32_t* perm,
+                    int64_t perm_cap) {
+  if (!b || !nodes || !perm) return set_error(RT_EINVAL, "rt_bvh_download: NULL argument");
+  if (b->info.n_tris <= 0) return set_error(RT_EINVAL, "rt_bvh_download: tree not built");
+  if (node_cap < b->info.n_nodes || perm_cap < b->info.n_tris)
+    return set_error(RT_EINVAL, "rt_bvh_download: capacity too small");
+  int rc = check_hip(hipDeviceSynchronize(), "hipDeviceSynchronize");
+  if (rc != RT_OK) return rc;
+  const int64_t nn = b->info.n_nodes;
+  BNode* tmp = new (std::nothrow) BNode[nn];
+  if (!tmp) return set_error(RT_ENOMEM, "rt_bvh_download: host allocation failed");
+  rc = check_hip(hipMemcpy(tmp, b->buf.nodes, sizeof(BNode) * nn, hipMemcpyDeviceToHost), "hipMemcpy");
+  if (rc == RT_OK)
+    rc = check_hip(hipMemcpy(perm, b->buf.perm, sizeof(int32_t) * b->info.n_tris,
+                             hipMemcpyDeviceToHost), "hipMemcpy");
+  if (rc == RT_OK) {
+    for (int64_t i = 0; i < nn; ++i) {
+      rt_node_rec& r = nodes[i];
+      const BNode& q = tmp[i];
+      for (int a = 0; a < 3; ++a) {
+        r.lo[a] = q.lo[a];
+        r.hi[a] = q.hi[a];
+      }
+      r.left = q.left;
+      r.first = q.first;
+      r.count = q.count;
+      r.depth = q.depth;
+      r.axis = q.axis;
+      r.plane = q.plane;
+      r.flags = q.flags;
+      r.reserved = 0;
+      r.cost = q.cost;
+    }
+  }
+  delete[] tmp;
+  return rc;
+}
+
+void rt_bvh_destroy(rt_bvh* b) {
+  if (!b) return;
+  (void)hipDeviceSynchronize();
+  free_buffers(b->buf);
+  delete b;
+}
+
+const char* rt_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

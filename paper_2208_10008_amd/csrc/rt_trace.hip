@@ -1,0 +1,273 @@
+// Ray traversal, closest hit and specular re-launch (Sec. III-B).
+//
+// One ray per lane.  A ray visits a node by fetching its 64-byte record and
+// testing both child volumes (closed slab test, robust to zero direction
+// components); a child is entered when its slab interval meets
+// [tmin, t_best], so hits already found shrink the action range and cull the
+// volumes behind them.  Leaves test their facets with the watertight
+// ray-triangle test in float32; the nearest hit wins, ties to the smaller
+// facet id.  After a hit the ray may be reflected about the facet plane and
+// traced again; the path length is summed in float64.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "rt_internal.h"
+
+namespace rt {
+namespace {
+
+constexpr int kStack = RT_MAX_DEPTH;
+constexpr float kBig = 1e30f;  // stand-in for 1/0 in the slab test
+// Slab far distances grow by 2 * gamma(3) so rounding never rejects a volume
+// the exact ray meets (Ize, "Robust BVH ray traversal", JCGT 2013).
+constexpr float kFarGrow = 1.0f + 2.0f * (3.0f * 5.9604645e-8f) / (1.0f - 3.0f * 5.9604645e-8f);
+
+struct RayPre {
+  float ox, oy, oz, dx, dy, dz;
+  float ix, iy, iz;  // 1/d (kBig for a zero component)
+  float tmin, tmax;
+  int kx, ky, kz;    // axis permutation of the watertight test
+  float sx, sy, sz;  // its shear constants
+};
+
+__device__ inline float sel(float x, float y, float z, int k) {
+  return k == 0 ? x : (k == 1 ? y : z);
+}
+
+__device__ inline RayPre prepare(float ox, float oy, float oz, float dx, float dy, float dz,
+                                 float tmin, float tmax) {
+  RayPre r;
+  r.ox = ox; r.oy = oy; r.oz = oz;
+  r.dx = dx; r.dy = dy; r.dz = dz;
+  r.ix = dx != 0.f ? 1.f / dx : kBig;
+  r.iy = dy != 0.f ? 1.f / dy : kBig;
+  r.iz = dz != 0.f ? 1.f / dz : kBig;
+  r.tmin = tmin;
+  r.tmax = tmax;
+  float ax = fabsf(dx), ay = fabsf(dy), az = fabsf(dz);
+  int kz = (ax >= ay && ax >= az) ? 0 : (ay >= az ? 1 : 2);
+  int kx = kz == 2 ? 0 : kz + 1;
+  int ky = kx == 2 ? 0 : kx + 1;
+  float dkz = sel(dx, dy, dz, kz);
+  if (dkz < 0.f) { int t = kx; kx = ky; ky = t; }
+  r.kx = kx; r.ky = ky; r.kz = kz;
+  r.sx = sel(dx, dy, dz, kx) / dkz;
+  r.sy = sel(dx, dy, dz, ky) / dkz;
+  r.sz = 1.f / dkz;
+  return r;
+}
+
+// Closed slab test of one box against [tlo, thi]; returns the entry distance
+// through tnear.
+__device__ inline bool slab(const RayPre& r, float lox, float hix, float loy, float hiy,
+                            float loz, float hiz, float tlo, float thi, float& tnear) {
+  float x0 = (lox - r.ox) * r.ix, x1 = (hix - r.ox) * r.ix;
+  float y0 = (loy - r.oy) * r.iy, y1 = (hiy - r.oy) * r.iy;
+  float z0 = (loz - r.oz) * r.iz, z1 = (hiz - r.oz) * r.iz;
+  float tn = fmaxf(fmaxf(fminf(x0, x1), fminf(y0, y1)), fmaxf(fminf(z0, z1), tlo));
+  float tf = fminf(fminf(fmaxf(x0, x1), fmaxf(y0, y1)), fmaxf(z0, z1)) * kFarGrow;
+  tf = fminf(tf, thi);
+  tnear = tn;
+  return tn <= tf;
+}
+
+// Watertight ray-triangle test (Woop, Benthin, Wald, JCGT 2013) in float32,
+// two-sided.  The edge functions are products rounded one by one, so a
+// shared edge gives exactly opposite values in its two facets.
+__device__ inline bool facet_test(const RayPre& r, const float4& p0, const float4& p1,
+                                  const float4& p2, float& t, float& u, float& v) {
+#pragma clang fp contract(off)
+  const float ax = p0.x - r.ox, ay = p0.y - r.oy, az = p0.z - r.oz;
+  const float bx = p1.x - r.ox, by = p1.y - r.oy, bz = p1.z - r.oz;
+  const float cx = p2.x - r.ox, cy = p2.y - r.oy, cz = p2.z - r.oz;
+  const float Akz = sel(ax, ay, az, r.kz), Bkz = sel(bx, by, bz, r.kz), Ckz = sel(cx, cy, cz, r.kz);
+  const float Ax = sel(ax, ay, az, r.kx) - r.sx * Akz;
+  const float Ay = sel(ax, ay, az, r.ky) - r.sy * Akz;
+  const float Bx = sel(bx, by, bz, r.kx) - r.sx * Bkz;
+  const float By = sel(bx, by, bz, r.ky) - r.sy * Bkz;
+  const float Cx = sel(cx, cy, cz, r.kx) - r.sx * Ckz;
+  const float Cy = sel(cx, cy, cz, r.ky) - r.sy * Ckz;
+  const float U = Cx * By - Cy * Bx;
+  const float V = Ax * Cy - Ay * Cx;
+  const float W = Bx * Ay - By * Ax;
+  if ((U < 0.f || V < 0.f || W < 0.f) && (U > 0.f || V > 0.f || W > 0.f)) return false;
+  const float det = U + V + W;
+  if (det == 0.f) return false;
+  const float T = U * (r.sz * Akz) + V * (r.sz * Bkz) + W * (r.sz * Ckz);
+  const float rcp = 1.f / det;
+  t = T * rcp;
+  u = V * rcp;
+  v = W * rcp;
+  return true;
+}
+
+struct Hit {
+  int id;  // caller's facet id, -1 none
+  int pos; // leaf-order position
+  float t, u, v;
+};
+
+template <bool STATS>
+__device__ Hit closest(const TNode* __restrict__ tn, const TFacet* __restrict__ tf,
+                       const RayPre& r, int skip_pos, uint32_t& nvis, uint32_t& ntest) {
+  int stack[kStack];
+  int sp = 0;
+  int node = 0;
+  Hit h;
+  h.id = -1;
+  h.pos = -1;
+  h.t = r.tmax;
+  h.u = h.v = 0.f;
+  int best_id = 0x7fffffff;
+  for (;;) {
+    while (node >= 0) {
+      const TNode nd = tn[node];
+      if (STATS) ++nvis;
+      float n0, n1;
+      bool h0 = slab(r, nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.c.x, nd.c.y, r.tmin, h.t, n0);
+      bool h1 = slab(r, nd.b.x, nd.b.y, nd.b.z, nd.b.w, nd.c.z, nd.c.w, r.tmin, h.t, n1);
+      if (h0 && h1) {
+        bool first0 = n0 <= n1;
+        stack[sp++] = first0 ? nd.d.y : nd.d.x;
+        node = first0 ? nd.d.x : nd.d.y;
+      } else if (h0) {
+        node = nd.d.x;
+      } else if (h1) {
+        node = nd.d.y;
+      } else {
+        if (sp == 0) return h;
+        node = stack[--sp];
+      }
+    }
+    // leaf: facets from position ~node to the one tagged last
+    for (int k = ~node;; ++k) {
+      const TFacet f = tf[k];
+      const uint32_t tag = __float_as_uint(f.p0.w);
+      const int id = (int)(tag & ~kLastFacet);
+      if (k != skip_pos) {
+        if (STATS) ++ntest;
+        float t, u, v;
+        if (facet_test(r, f.p0, f.p1, f.p2, t, u, v) && t >= r.tmin &&
+            (t < h.t || (t == h.t && id < best_id))) {
+          h.t = t;
+          h.u = u;
+          h.v = v;
+          h.pos = k;
+          best_id = id;
+        }
+      }
+      if (tag & kLastFacet) break;
+    }
+    if (sp == 0) break;
+    node = stack[--sp];
+  }
+  if (best_id != 0x7fffffff) h.id = best_id;
+  return h;
+}
+
+__device__ inline void store_hit(rt_hit* out, int64_t k, const Hit& h) {
+  int4 w;
+  if (h.id >= 0) {
+    w = make_int4(h.id, __float_as_int(h.t), __float_as_int(h.u), __float_as_int(h.v));
+  } else {
+    w = make_int4(-1, __float_as_int(INFINITY), 0, 0);
+  }
+  reinterpret_cast<int4*>(out)[k] = w;
+}
+
+constexpr int kBlock = 128;
+
+template <bool BOUNCE, bool SEG, bool STATS>
+__global__ __launch_bounds__(kBlock) void k_trace(const TNode* __restrict__ tn,
+                                                  const TFacet* __restrict__ tf,
+                                                  const float4* __restrict__ rays, int64_t n,
+                                                  int max_b, rt_hit* __restrict__ out,
+                                                  double* __restrict__ path_len,
+                                                  int32_t* __restrict__ n_hits,
+                                                  float4* __restrict__ seg,
+                                                  uint32_t* __restrict__ stats) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const float4 ra = rays[2 * i], rb = rays[2 * i + 1];
+  float ox = ra.x, oy = ra.y, oz = ra.z, dx = rb.x, dy = rb.y, dz = rb.z;
+  const float tmin = ra.w, tmax = rb.w;
+  int skip = -1;
+  double path = 0.0;
+  int hits = 0;
+  uint32_t nvis = 0, ntest = 0;
+  int b = 0;
+  for (; b < max_b; ++b) {
+    if (SEG) {
+      seg[2 * ((int64_t)b * n + i)] = make_float4(ox, oy, oz, tmin);
+      seg[2 * ((int64_t)b * n + i) + 1] = make_float4(dx, dy, dz, tmax);
+    }
+    const RayPre r = prepare(ox, oy, oz, dx, dy, dz, tmin, tmax);
+    const Hit h = closest<STATS>(tn, tf, r, skip, nvis, ntest);
+    store_hit(out, (int64_t)b * n + i, h);
+    if (!BOUNCE || h.id < 0) break;
+    ++hits;
+    path += (double)h.t * sqrt((double)dx * dx + (double)dy * dy + (double)dz * dz);
+    if (b + 1 == max_b) break;
+    // specular reflection about the facet plane, from the hit point
+    const TFacet f = tf[h.pos];
+    const float e1x = f.p1.x - f.p0.x, e1y = f.p1.y - f.p0.y, e1z = f.p1.z - f.p0.z;
+    const float e2x = f.p2.x - f.p0.x, e2y = f.p2.y - f.p0.y, e2z = f.p2.z - f.p0.z;
+    float nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
+    const float inv = 1.f / sqrtf(nx * nx + ny * ny + nz * nz);
+    nx *= inv; ny *= inv; nz *= inv;
+    ox = ox + h.t * dx;
+    oy = oy + h.t * dy;
+    oz = oz + h.t * dz;
+    const float dn = 2.f * (dx * nx + dy * ny + dz * nz);
+    dx = dx - dn * nx;
+    dy = dy - dn * ny;
+    dz = dz - dn * nz;
+    skip = h.pos;
+  }
+  if (BOUNCE) {
+    Hit none;
+    none.id = -1;
+    for (++b; b < max_b; ++b) store_hit(out, (int64_t)b * n + i, none);
+    if (path_len) path_len[i] = path;
+    if (n_hits) n_hits[i] = hits;
+  }
+  if (STATS) {
+    stats[2 * i] = nvis;
+    stats[2 * i + 1] = ntest;
+  }
+}
+
+template <bool BOUNCE, bool SEG, bool STATS>
+void launch(const Buffers& B, const float* rays, int64_t n, int max_b, rt_hit* out,
+            double* path_len, int32_t* n_hits, float* seg, uint32_t* stats, hipStream_t s) {
+  const int64_t blocks = (n + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL((k_trace<BOUNCE, SEG, STATS>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                     B.tnodes, B.tfacets, reinterpret_cast<const float4*>(rays), n, max_b, out,
+                     path_len, n_hits, reinterpret_cast<float4*>(seg), stats);
+}
+
+}  // namespace
+
+int launch_trace(const Buffers& B, int64_t /*n_internal*/, const float* rays, int64_t n,
+                 int32_t max_b, rt_hit* out, double* path_len, int32_t* n_hits,
+                 const rt_trace_opts* opts, hipStream_t s) {
+  if (n == 0) return RT_OK;
+  float* seg = opts ? opts->seg_rays : nullptr;
+  uint32_t* stats = opts ? opts->ray_stats : nullptr;
+  const bool bounce = max_b > 1 || path_len || n_hits;
+  if (!bounce && !seg && !stats) {
+    launch<false, false, false>(B, rays, n, 1, out, nullptr, nullptr, nullptr, nullptr, s);
+  } else if (!seg && !stats) {
+    launch<true, false, false>(B, rays, n, max_b, out, path_len, n_hits, nullptr, nullptr, s);
+  } else if (seg && !stats) {
+    launch<true, true, false>(B, rays, n, max_b, out, path_len, n_hits, seg, nullptr, s);
+  } else if (!seg) {
+    launch<true, false, true>(B, rays, n, max_b, out, path_len, n_hits, nullptr, stats, s);
+  } else {
+    launch<true, true, true>(B, rays, n, max_b, out, path_len, n_hits, seg, stats, s);
+  }
+  return check_hip(hipGetLastError(), "trace launch");
+}
+
+}  // namespace rt

@@ -1,0 +1,130 @@
+"""The C ABI without a GPU: the library loads, exports every function that
+include/rt_mi355x.h declares, its structs match the binding, and argument
+checks that precede any device work return RT_EINVAL."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import paper_2208_10008_amd as R
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rt_mi355x.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rt_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_expected_entry_points():
+    assert set(declared_functions()) == set(R.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = R.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", R.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {l.split()[-1] for l in out.splitlines() if " T " in l}
+    assert set(declared_functions()) <= exported
+
+
+def test_library_is_gfx950_code(tmp_path):
+    # the offload bundle of the library built here names its target
+    sec = tmp_path / "fatbin"
+    subprocess.run(["/opt/rocm/llvm/bin/llvm-objcopy", "--dump-section=.hip_fatbin=" + str(sec),
+                    R.LIB_PATH, str(tmp_path / "copy.so")], check=True)
+    data = sec.read_bytes()
+    assert b"amdgcn-amd-amdhsa--gfx950" in data
+
+
+def test_struct_layouts_match_header(tmp_path):
+    src = tmp_path / "sz.c"
+    src.write_text("""
+#include <stdio.h>
+#include <stddef.h>
+#include "rt_mi355x.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu\\n", sizeof(rt_split_params), sizeof(rt_hit), sizeof(rt_bvh_info),
+         sizeof(rt_node_rec), sizeof(rt_trace_opts));
+  printf("%zu %zu %zu %zu\\n", offsetof(rt_node_rec, cost), offsetof(rt_bvh_info, root_lo),
+         offsetof(rt_split_params, max_leaf), offsetof(rt_trace_opts, block));
+  return 0;
+}""")
+    exe = tmp_path / "sz"
+    subprocess.run(["gcc", "-D__HIP_PLATFORM_AMD__", "-I" + os.path.join(ROOT, "include"),
+                    "-I/opt/rocm/include", str(src), "-o", str(exe)], check=True)
+    a, b = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")[:2]
+    sizes = [int(x) for x in a.split()]
+    offs = [int(x) for x in b.split()]
+    assert sizes == [ctypes.sizeof(R.rt_split_params), 16, ctypes.sizeof(R.rt_bvh_info),
+                     R.NODE_DTYPE.itemsize, ctypes.sizeof(R.rt_trace_opts)]
+    assert offs == [R.NODE_DTYPE.fields["cost"][1], R.rt_bvh_info.root_lo.offset,
+                    R.rt_split_params.max_leaf.offset, R.rt_trace_opts.block.offset]
+
+
+def test_defaults():
+    lib = R.load()
+    p = R.rt_split_params()
+    lib.rt_split_params_default(ctypes.byref(p))
+    d = R.SplitParams()
+    assert (p.alpha, p.t_isect, p.t_trav, list(p.src)) == (d.alpha, d.t_isect, d.t_trav, list(d.src))
+    assert (p.max_leaf, p.nbins, p.d_mode, p.d_norm, p.max_depth, p.depth_limit) == \
+        (d.max_leaf, d.nbins, 0, 0, d.max_depth, d.depth_limit)
+
+
+def _build_rc(tris_ptr, n, params):
+    lib = R.load()
+    h = ctypes.c_void_p()
+    return lib.rt_build(tris_ptr, n, ctypes.byref(params), ctypes.byref(h), None), h
+
+
+@pytest.mark.parametrize("field,value", [("alpha", 1.5), ("alpha", -0.5), ("alpha", float("nan")),
+                                         ("max_leaf", 0), ("nbins", 1), ("nbins", 65),
+                                         ("d_mode", 4), ("d_norm", 2), ("depth_limit", 0),
+                                         ("depth_limit", 65), ("t_isect", 0.0)])
+def test_build_rejects_bad_params(field, value):
+    p = R.SplitParams().c()
+    setattr(p, field, value)
+    host = np.zeros((4, 9), np.float32)   # never read: the checks come first
+    rc, h = _build_rc(host.ctypes.data_as(ctypes.c_void_p), 4, p)
+    assert rc == R.RT_EINVAL and not h.value
+    assert len(R.load().rt_last_error()) > 0
+
+
+def test_build_rejects_bad_sizes_and_pointers():
+    p = R.SplitParams().c()
+    host = np.zeros((4, 9), np.float32)
+    ptr = host.ctypes.data_as(ctypes.c_void_p)
+    assert _build_rc(None, 4, p)[0] == R.RT_EINVAL
+    assert _build_rc(ptr, 0, p)[0] == R.RT_EINVAL
+    assert _build_rc(ptr, -3, p)[0] == R.RT_EINVAL
+    assert _build_rc(ptr, 1 << 30, p)[0] == R.RT_EINVAL
+    assert _build_rc(ctypes.c_void_p(host.ctypes.data + 1), 4, p)[0] == R.RT_EINVAL
+    q = R.SplitParams(max_leaf=1, depth_limit=3).c()   # 100 facets need 7 halvings
+    assert _build_rc(ptr, 100, q)[0] == R.RT_EINVAL
+    lib = R.load()
+    assert lib.rt_build(ptr, 4, ctypes.byref(p), None, None) == R.RT_EINVAL
+
+
+def test_null_handles():
+    lib = R.load()
+    info = R.rt_bvh_info()
+    assert lib.rt_bvh_info_get(None, ctypes.byref(info)) == R.RT_EINVAL
+    assert lib.rt_trace(None, None, 0, None, None) == R.RT_EINVAL
+    assert lib.rt_trace_bounces(None, None, 0, 1, None, None, None, None) == R.RT_EINVAL
+    assert lib.rt_bvh_download(None, None, 0, None, 0) == R.RT_EINVAL
+    lib.rt_bvh_destroy(None)
+    assert lib.rt_rebuild(None, None, 0, None, None) == R.RT_EINVAL
+
+
+def test_binding_rejects_host_tensors():
+    torch = pytest.importorskip("torch")
+    with pytest.raises(R.RtError):
+        R.rt_build(torch.zeros((4, 9)), R.SplitParams())

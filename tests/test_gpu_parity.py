@@ -1,0 +1,345 @@
+"""GPU path vs the CPU checker, through the C ABI (ctypes binding).
+
+Trees: the GPU tree must equal the checker's tree exactly (boxes, splits,
+Eq. (2) costs, leaf order) -- both make every decision in float64 in the same
+order.  Hits: see tests/_parity.py for the rule.
+"""
+import os
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2208_10008_amd as R
+from rtgen import icosphere, workloads
+
+from _parity import canonical_compare, compare_hits
+from _scenes import box_scene, check_tree, corridor, ground_and_wall
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+NTHREADS = min(16, os.cpu_count() or 1)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    R.load()
+    yield
+    torch.cuda.synchronize()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def hits_np(out):
+    o = out.cpu().numpy()
+    ids = o[..., 0].copy()
+    tuv = o[..., 1:].view(np.float32)
+    return ids, tuv[..., 0].astype(np.float64), tuv[..., 1], tuv[..., 2]
+
+
+def gpu_tree(bvh):
+    nodes, perm = bvh.download()
+    return nodes, perm
+
+
+def oracle_params(p: R.SplitParams) -> oracle.SplitParams:
+    return oracle.SplitParams(alpha=p.alpha, t_isect=p.t_isect, t_trav=p.t_trav, src=p.src,
+                              max_leaf=p.max_leaf, nbins=p.nbins, d_mode=p.d_mode,
+                              d_norm=p.d_norm, max_depth=p.max_depth, depth_limit=p.depth_limit)
+
+
+@pytest.fixture(scope="module")
+def micro():
+    return workloads.microcell()
+
+
+@pytest.fixture(scope="module")
+def city():
+    return workloads.city24k()
+
+
+# ---------------------------------------------------------------- worked cases
+def test_box_worked_cases():
+    tris, cases = box_scene()
+    rays = np.array([c["ray"] for c in cases], dtype=np.float32)
+    for max_leaf in (1, 4, 12):
+        bvh = R.BVH(dev(tris), R.SplitParams(max_leaf=max_leaf))
+        ids, t, u, v = hits_np(bvh.trace(dev(rays)))
+        for k, c in enumerate(cases):
+            assert ids[k] == c["id"], (max_leaf, c["name"])
+            if c["id"] >= 0:
+                assert t[k] == c["t"], (max_leaf, c["name"], t[k])
+            else:
+                assert t[k] == np.inf
+        assert abs(u[0] - 0.3) < 1e-6 and abs(v[0] - 0.3) < 1e-6
+
+
+def test_image_source_chain():
+    tris = ground_and_wall(wall_x=20.0)
+    d = (np.float32([1, 0, -1]) / np.float32(np.sqrt(2))).astype(np.float32)
+    rays = np.array([[0, 0, 10, 1e-4, d[0], d[1], d[2], 1e3]], dtype=np.float32)
+    bvh = R.BVH(dev(tris), R.SplitParams(max_leaf=1))
+    out, pl, nh = bvh.trace_bounces(dev(rays), 4)
+    ids, t, _, _ = hits_np(out)
+    assert nh.item() == 2 and ids[0, 0] in (0, 1) and ids[1, 0] in (2, 3) and ids[2, 0] == -1
+    assert abs(pl.item() - np.hypot(20, 20)) < 2e-5
+
+
+def test_corridor_chain():
+    rays = np.array([[5, 0, 0, 1e-4, 1, 0.5, 0, 1e3]], dtype=np.float32)
+    bvh = R.BVH(dev(corridor(10.0)), R.SplitParams(max_leaf=1))
+    out, pl, nh = bvh.trace_bounces(dev(rays), 6)
+    ids, t, _, _ = hits_np(out)
+    assert nh.item() == 6 and list(ids[:, 0] // 2) == [1, 0, 1, 0, 1, 0]
+    expect = 55 * np.sqrt(1.25)
+    assert abs(pl.item() - expect) < 1e-5 * expect
+
+
+# ---------------------------------------------------------------- trees
+TREE_CASES = [
+    dict(alpha=1.0), dict(alpha=0.7), dict(alpha=0.4), dict(alpha=0.0),
+    dict(alpha=0.4, d_norm="raw"), dict(alpha=0.4, d_mode="kweighted"),
+    dict(alpha=0.4, d_mode="sum"), dict(alpha=0.4, d_mode="parent"),
+    dict(alpha=0.4, max_leaf=1), dict(alpha=0.4, max_leaf=8), dict(alpha=0.7, nbins=8),
+    dict(alpha=0.7, nbins=64), dict(alpha=0.4, max_leaf=1, depth_limit=16, max_depth=6),
+]
+
+
+@pytest.mark.parametrize("kw", TREE_CASES, ids=[str(k) for k in TREE_CASES])
+def test_tree_equals_oracle_city(city, kw):
+    p = R.SplitParams(src=city.tx, **kw)
+    bvh = R.BVH(dev(city.tris), p)
+    nodes, perm = gpu_tree(bvh)
+    ref = oracle.build_tree(city.tris, oracle_params(p))
+    check_tree(city.tris, nodes["lo"].astype(np.float64), nodes["hi"].astype(np.float64),
+               nodes["left"], np.where(nodes["left"] >= 0, nodes["left"] + 1, -1), nodes["first"],
+               nodes["count"], nodes["depth"], perm, p.max_leaf, p.depth_limit)
+    canonical_compare(nodes, perm, ref)
+    info = bvh.info()
+    assert info.n_nodes == ref.n_nodes and info.depth == ref.depth.max()
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 17])
+def test_tiny_scenes(n):
+    rng = np.random.default_rng(n)
+    tris = rng.uniform(-10, 10, size=(n, 9)).astype(np.float32)
+    rays = np.concatenate([icosphere.make_rays((0.1, 0.2, 0.3), icosphere.directions(4), 0.0, 100.0)])
+    for max_leaf in (1, 4):
+        p = R.SplitParams(max_leaf=max_leaf, alpha=0.5, src=(1, 2, 3))
+        bvh = R.BVH(dev(tris), p)
+        nodes, perm = gpu_tree(bvh)
+        canonical_compare(nodes, perm, oracle.build_tree(tris, oracle_params(p)))
+        ids, t, _, _ = hits_np(bvh.trace(dev(rays)))
+        compare_hits(tris, rays, ids, t, oracle.brute(tris, rays))
+
+
+# ---------------------------------------------------------------- hits
+@pytest.mark.parametrize("alpha", [1.0, 0.7, 0.0])
+def test_microcell_all_rays(micro, alpha):
+    p = R.SplitParams(alpha=alpha, src=micro.tx)
+    bvh = R.BVH(dev(micro.tris), p)
+    ids, t, _, _ = hits_np(bvh.trace(dev(micro.rays)))
+    stats = compare_hits(micro.tris, micro.rays, ids, t, oracle.brute(micro.tris, micro.rays))
+    log("microcell", alpha, stats)
+
+
+def test_city_primary_all_rays(city):
+    p = R.SplitParams(alpha=0.4, src=city.tx)
+    bvh = R.BVH(dev(city.tris), p)
+    t0 = time.time()
+    ids, t, _, _ = hits_np(bvh.trace(dev(city.rays)))
+    ref = oracle.trace_bvh(oracle.build_tree(city.tris, oracle_params(p)), city.rays,
+                           nthreads=NTHREADS)
+    stats = compare_hits(city.tris, city.rays, ids, t, ref)
+    log("city primary", stats, "%.1fs" % (time.time() - t0))
+    assert stats["clean"] > 0.99 * stats["rays"]
+
+
+def test_hits_do_not_depend_on_the_tree(city):
+    rays = city.rays[: 200_000]
+    ref = oracle.trace_bvh(oracle.build_tree(city.tris, oracle.SplitParams(src=city.tx)), rays,
+                           nthreads=NTHREADS)
+    clean = ref.margin > 1e-4
+    base = None
+    for kw in (dict(alpha=1.0), dict(alpha=0.4), dict(alpha=0.0), dict(alpha=0.4, max_leaf=1),
+               dict(alpha=0.7, max_leaf=8, nbins=8)):
+        bvh = R.BVH(dev(city.tris), R.SplitParams(src=city.tx, **kw))
+        o = bvh.trace(dev(rays)).cpu().numpy()
+        if base is None:
+            base = o
+        else:
+            assert np.array_equal(o[clean], base[clean]), kw
+
+
+def test_city_bounces_every_segment(city):
+    """Full size, the benchmark's launch: every traced segment of every chain
+    is re-traced by the checker from the GPU's own float32 segment ray."""
+    p = R.SplitParams(alpha=0.4, src=city.tx)
+    bvh = R.BVH(dev(city.tris), p)
+    n, nb = city.n_rays, city.max_bounces
+    seg = torch.empty((nb, n, 8), dtype=torch.float32, device="cuda")
+    out, pl, nh = bvh.trace_bounces(dev(city.rays), nb, seg_rays=seg)
+    torch.cuda.synchronize()
+    ids, t, _, _ = hits_np(out)
+    seg_np = seg.cpu().numpy()
+    nh_np, pl_np = nh.cpu().numpy(), pl.cpu().numpy()
+    tree = oracle.build_tree(city.tris, oracle_params(p))
+    live = np.ones(n, bool)
+    prev = np.full(n, -1, np.int32)
+    total = {"segments": 0, "clean": 0, "low_margin": 0, "low_margin_differing": 0}
+    path = np.zeros(n)
+    for b in range(nb):
+        idx = np.nonzero(live)[0]
+        if idx.size == 0:
+            break
+        rays_b = seg_np[b, idx]
+        if b == 0:
+            assert np.array_equal(rays_b, city.rays)
+        ref = oracle.trace_bvh(tree, rays_b, skip=prev[idx], nthreads=NTHREADS)
+        st = compare_hits(city.tris, rays_b, ids[b, idx], t[b, idx], ref, skip=prev[idx])
+        for k in ("clean", "low_margin", "low_margin_differing"):
+            total[k] += st[k]
+        total["segments"] += idx.size
+        hit = ids[b, idx] >= 0
+        d = rays_b[:, 4:7].astype(np.float64)
+        path[idx[hit]] += t[b, idx[hit]] * np.sqrt((d[hit] ** 2).sum(1))
+        prev[idx] = ids[b, idx]
+        live[idx[~hit]] = False
+        # untraced segments are written as misses
+        dead = np.nonzero(~live)[0]
+        if b + 1 < nb:
+            assert np.all(ids[b + 1, dead] == -1)
+    assert np.array_equal(nh_np, (ids >= 0).sum(0))
+    np.testing.assert_allclose(pl_np, path, rtol=1e-12, atol=0)
+    log("city bounces", total)
+    assert total["clean"] > 0.99 * total["segments"]
+
+
+def test_city_chains_against_float64_chains(city):
+    """The checker's own float64 chains (reflection in float64): segments agree
+    while every earlier segment of the chain is clean; path lengths of fully
+    clean chains agree to 1e-5."""
+    rng = np.random.default_rng(7)
+    idx = np.sort(rng.choice(city.n_rays, 100_000, replace=False))
+    rays = city.rays[idx]
+    p = R.SplitParams(alpha=0.4, src=city.tx)
+    bvh = R.BVH(dev(city.tris), p)
+    out, pl, nh = bvh.trace_bounces(dev(rays), city.max_bounces)
+    ids, t, _, _ = hits_np(out)
+    ch = oracle.bounces(city.tris, rays, city.max_bounces,
+                        tree=oracle.build_tree(city.tris, oracle_params(p)), nthreads=NTHREADS,
+                        segments=False)
+    ok_so_far = np.ones(rays.shape[0], bool)
+    compared = 0
+    for b in range(city.max_bounces):
+        m = ok_so_far & (ch.margin[b] > 1e-4)
+        assert np.array_equal(ids[b, m], ch.id[b, m]), f"segment {b}"
+        hit = m & (ch.id[b] >= 0)
+        assert np.all(np.abs(t[b, hit] - ch.t[b, hit]) <= 1e-4 * ch.t[b, hit])
+        compared += int(m.sum())
+        ok_so_far = m & (ch.id[b] >= 0)
+    clean_chain = np.all(ch.margin > 1e-4, axis=0)
+    plg = pl.cpu().numpy()
+    np.testing.assert_allclose(plg[clean_chain], ch.path_len[clean_chain], rtol=1e-5)
+    assert np.array_equal(nh.cpu().numpy()[clean_chain], ch.n_hits[clean_chain])
+    log("chains: compared segments", compared, "clean chains", int(clean_chain.sum()))
+
+
+def test_dense_city_tree_and_sampled_chains():
+    w = workloads.dense200k()
+    p = R.SplitParams(alpha=0.4, src=w.tx)
+    bvh = R.BVH(dev(w.tris), p)
+    nodes, perm = gpu_tree(bvh)
+    tree = oracle.build_tree(w.tris, oracle_params(p))
+    canonical_compare(nodes, perm, tree)
+    # every ray traced with bounces, as in the benchmark; a sample is checked
+    n, nb = w.n_rays, w.max_bounces
+    rays_d = dev(w.rays)
+    seg = torch.empty((nb, n, 8), dtype=torch.float32, device="cuda")
+    out, pl, nh = bvh.trace_bounces(rays_d, nb, seg_rays=seg)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(11)
+    idx = np.sort(rng.choice(n, 100_000, replace=False))
+    it = torch.from_numpy(idx).cuda()
+    ids, t, _, _ = hits_np(out[:, it])
+    seg_np = seg[:, it].cpu().numpy()
+    prev = np.full(idx.size, -1, np.int32)
+    live = np.ones(idx.size, bool)
+    for b in range(nb):
+        k = np.nonzero(live)[0]
+        if k.size == 0:
+            break
+        ref = oracle.trace_bvh(tree, seg_np[b, k], skip=prev[k], nthreads=NTHREADS)
+        compare_hits(w.tris, seg_np[b, k], ids[b, k], t[b, k], ref, skip=prev[k])
+        prev[k] = ids[b, k]
+        live[k[ids[b, k] < 0]] = False
+
+
+# ---------------------------------------------------------------- edge cases
+def test_empty_ray_batch_and_range_edges(micro):
+    bvh = R.BVH(dev(micro.tris), R.SplitParams())
+    empty = torch.empty((0, 8), dtype=torch.float32, device="cuda")
+    out = torch.full((1, 4), 7, dtype=torch.int32, device="cuda")
+    R.rt_trace(bvh.handle, empty, out)
+    assert torch.all(out == 7)
+    rays = micro.rays.copy()
+    rays[:, 3] = 10.0
+    rays[:, 7] = 5.0            # tmin > tmax: nothing can be hit
+    ids, t, _, _ = hits_np(bvh.trace(dev(rays)))
+    assert np.all(ids == -1) and np.all(t == np.inf)
+
+
+def test_duplicate_facets_tie_to_lower_id():
+    f = [0, -5, -5, 0, 5, -5, 0, 0, 5]
+    tris = np.array([[9, 9, 9, 9, 9, 9, 9, 9, 9.5], f, f, f], dtype=np.float32)
+    rays = np.array([[-1, 0, 0, 1e-4, 1, 0, 0, 10]] * 3, dtype=np.float32)
+    for max_leaf in (1, 2, 4):
+        ids, t, _, _ = hits_np(R.BVH(dev(tris), R.SplitParams(max_leaf=max_leaf)).trace(dev(rays)))
+        assert np.all(ids == 1) and np.all(t == 1.0)
+
+
+def test_origin_on_a_facet():
+    tris = np.array([[0, -5, -5, 0, 5, -5, 0, 0, 5]], dtype=np.float32)
+    rays = np.array([[0, 0, 0, 0.0, 1, 0, 0, 10], [0, 0, 0, 1e-4, 1, 0, 0, 10]], dtype=np.float32)
+    ids, t, _, _ = hits_np(R.BVH(dev(tris), R.SplitParams()).trace(dev(rays)))
+    assert ids[0] == 0 and t[0] == 0.0 and ids[1] == -1
+
+
+def test_rebuild_matches_fresh_build(micro, city):
+    p1 = R.SplitParams(alpha=0.7, src=micro.tx)
+    p2 = R.SplitParams(alpha=0.4, src=city.tx, max_leaf=2)
+    bvh = R.BVH(dev(city.tris), p2)
+    bvh.rebuild(dev(micro.tris), p1)           # smaller scene into the same buffers
+    n1, perm1 = gpu_tree(bvh)
+    canonical_compare(n1, perm1, oracle.build_tree(micro.tris, oracle_params(p1)))
+    ids, t, _, _ = hits_np(bvh.trace(dev(micro.rays)))
+    compare_hits(micro.tris, micro.rays, ids, t, oracle.brute(micro.tris, micro.rays))
+    bvh.rebuild(dev(city.tris), p2)            # and back
+    n2, perm2 = gpu_tree(bvh)
+    canonical_compare(n2, perm2, oracle.build_tree(city.tris, oracle_params(p2)))
+
+
+def test_invalid_arguments(micro):
+    bad = micro.tris.copy()
+    bad[5, 4] = np.nan
+    with pytest.raises(R.RtError) as e:
+        R.BVH(dev(bad), R.SplitParams())
+    assert e.value.code == R.RT_EINVAL
+    bvh = R.BVH(dev(micro.tris), R.SplitParams())
+    rays = dev(micro.rays)
+    out = torch.empty((micro.n_rays, 4), dtype=torch.int32, device="cuda")
+    flat = rays.view(-1)[1:1 + 8 * 100].view(100, 8)      # 4-byte, not 16-byte aligned
+    with pytest.raises(R.RtError):
+        R.rt_trace(bvh.handle, flat, out)
+    for nb in (0, 65):
+        with pytest.raises(R.RtError):
+            R.rt_trace_bounces(bvh.handle, rays, nb, out)
