@@ -102,6 +102,110 @@ __device__ inline bool facet_test(const RayPre& r, const float4& p0, const float
   return true;
 }
 
+// ---- compensated float32 arithmetic (value = hi + lo) ----------------------
+// Error-free sum (Knuth) and product (fused multiply-add) give each operation's
+// rounding error exactly, so a short chain of them carries about twice the
+// float32 precision without leaving float32.
+struct F2 {
+  float hi, lo;
+};
+
+__device__ inline F2 two_sum(float a, float b) {
+#pragma clang fp contract(off)
+  float s = a + b;
+  float bb = s - a;
+  float e = (a - (s - bb)) + (b - bb);
+  return {s, e};
+}
+__device__ inline F2 fast_two_sum(float a, float b) {  // |a| >= |b|
+#pragma clang fp contract(off)
+  float s = a + b;
+  return {s, b - (s - a)};
+}
+__device__ inline F2 two_prod(float a, float b) {
+#pragma clang fp contract(off)
+  float p = a * b;
+  return {p, fmaf(a, b, -p)};
+}
+__device__ inline F2 f2_add(F2 a, F2 b) {
+#pragma clang fp contract(off)
+  F2 s = two_sum(a.hi, b.hi);
+  F2 t = two_sum(a.lo, b.lo);
+  float lo = s.lo + t.hi;
+  F2 u = fast_two_sum(s.hi, lo);
+  return fast_two_sum(u.hi, u.lo + t.lo);
+}
+__device__ inline F2 f2_neg(F2 a) { return {-a.hi, -a.lo}; }
+__device__ inline F2 f2_mul(F2 a, F2 b) {
+#pragma clang fp contract(off)
+  F2 p = two_prod(a.hi, b.hi);
+  float lo = p.lo + (a.hi * b.lo + a.lo * b.hi);
+  return fast_two_sum(p.hi, lo);
+}
+__device__ inline F2 f2_mulf(F2 a, float b) {
+#pragma clang fp contract(off)
+  F2 p = two_prod(a.hi, b);
+  return fast_two_sum(p.hi, p.lo + a.lo * b);
+}
+__device__ inline float f2_div(F2 a, F2 b) {
+#pragma clang fp contract(off)
+  float q = a.hi / b.hi;
+  // one correction step: r = a - q b, q += r / b
+  F2 qb = f2_mulf(b, q);
+  F2 r = f2_add(a, f2_neg(qb));
+  return q + (r.hi + r.lo) / b.hi;
+}
+
+// Unnormalised facet normal (v1 - v0) x (v2 - v0) in compensated float32.
+struct N2 {
+  F2 x, y, z;
+};
+__device__ inline N2 facet_normal(const float4& p0, const float4& p1, const float4& p2) {
+  const F2 e1x = two_sum(p1.x, -p0.x), e1y = two_sum(p1.y, -p0.y), e1z = two_sum(p1.z, -p0.z);
+  const F2 e2x = two_sum(p2.x, -p0.x), e2y = two_sum(p2.y, -p0.y), e2z = two_sum(p2.z, -p0.z);
+  N2 n;
+  n.x = f2_add(f2_mul(e1y, e2z), f2_neg(f2_mul(e1z, e2y)));
+  n.y = f2_add(f2_mul(e1z, e2x), f2_neg(f2_mul(e1x, e2z)));
+  n.z = f2_add(f2_mul(e1x, e2y), f2_neg(f2_mul(e1y, e2x)));
+  return n;
+}
+
+__device__ inline F2 f2_div2(F2 a, F2 b) {  // quotient kept as hi + lo
+#pragma clang fp contract(off)
+  float q = a.hi / b.hi;
+  F2 r = f2_add(a, f2_neg(f2_mulf(b, q)));
+  return fast_two_sum(q, (r.hi + r.lo) / b.hi);
+}
+
+// Distance to the facet's plane along the ray, t = n.(v0 - o) / n.d, with the
+// edge vectors, the normal and both dot products carried in compensated
+// float32: the result keeps float32 relative accuracy even when the facet is
+// much larger than t (a reflected ray leaving a wall next to a km-wide
+// ground facet).
+__device__ inline float plane_t(const N2& n, const float4& p0, float ox, float oy, float oz,
+                                float dx, float dy, float dz) {
+  const F2 wx = two_sum(p0.x, -ox), wy = two_sum(p0.y, -oy), wz = two_sum(p0.z, -oz);
+  const F2 num = f2_add(f2_add(f2_mul(n.x, wx), f2_mul(n.y, wy)), f2_mul(n.z, wz));
+  const F2 den = f2_add(f2_add(f2_mulf(n.x, dx), f2_mulf(n.y, dy)), f2_mulf(n.z, dz));
+  return f2_div(num, den);
+}
+
+// Specular reflection r = d - 2 (d.n) / (n.n) n, evaluated in compensated
+// float32 and rounded once per component.
+__device__ inline void reflect(const N2& n, float& dx, float& dy, float& dz) {
+  const F2 dn = f2_add(f2_add(f2_mulf(n.x, dx), f2_mulf(n.y, dy)), f2_mulf(n.z, dz));
+  const F2 nn = f2_add(f2_add(f2_mul(n.x, n.x), f2_mul(n.y, n.y)), f2_mul(n.z, n.z));
+  F2 k = f2_div2(dn, nn);
+  k.hi *= 2.f;
+  k.lo *= 2.f;
+  const F2 rx = f2_add(F2{dx, 0.f}, f2_neg(f2_mul(k, n.x)));
+  const F2 ry = f2_add(F2{dy, 0.f}, f2_neg(f2_mul(k, n.y)));
+  const F2 rz = f2_add(F2{dz, 0.f}, f2_neg(f2_mul(k, n.z)));
+  dx = rx.hi + rx.lo;
+  dy = ry.hi + ry.lo;
+  dz = rz.hi + rz.lo;
+}
+
 struct Hit {
   int id;  // caller's facet id, -1 none
   int pos; // leaf-order position
@@ -119,7 +223,7 @@ __device__ Hit closest(const TNode* __restrict__ tn, const TFacet* __restrict__ 
   h.pos = -1;
   h.t = r.tmax;
   h.u = h.v = 0.f;
-  int best_id = 0x7fffffff;
+  int best_id = 0x7fffffff;  // h.id, or the largest id while there is no hit
   for (;;) {
     while (node >= 0) {
       const TNode nd = tn[node];
@@ -154,16 +258,15 @@ __device__ Hit closest(const TNode* __restrict__ tn, const TFacet* __restrict__ 
           h.u = u;
           h.v = v;
           h.pos = k;
+          h.id = id;
           best_id = id;
         }
       }
       if (tag & kLastFacet) break;
     }
-    if (sp == 0) break;
+    if (sp == 0) return h;
     node = stack[--sp];
   }
-  if (best_id != 0x7fffffff) h.id = best_id;
-  return h;
 }
 
 __device__ inline void store_hit(rt_hit* out, int64_t k, const Hit& h) {
@@ -203,26 +306,25 @@ __global__ __launch_bounds__(kBlock) void k_trace(const TNode* __restrict__ tn,
       seg[2 * ((int64_t)b * n + i) + 1] = make_float4(dx, dy, dz, tmax);
     }
     const RayPre r = prepare(ox, oy, oz, dx, dy, dz, tmin, tmax);
-    const Hit h = closest<STATS>(tn, tf, r, skip, nvis, ntest);
+    Hit h = closest<STATS>(tn, tf, r, skip, nvis, ntest);
+    N2 nrm;
+    if (h.id >= 0) {
+      // the facet is decided; its distance is recomputed accurately
+      const TFacet f = tf[h.pos];
+      nrm = facet_normal(f.p0, f.p1, f.p2);
+      const float tp = plane_t(nrm, f.p0, ox, oy, oz, dx, dy, dz);
+      if (isfinite(tp)) h.t = fminf(fmaxf(tp, tmin), tmax);
+    }
     store_hit(out, (int64_t)b * n + i, h);
     if (!BOUNCE || h.id < 0) break;
     ++hits;
     path += (double)h.t * sqrt((double)dx * dx + (double)dy * dy + (double)dz * dz);
     if (b + 1 == max_b) break;
-    // specular reflection about the facet plane, from the hit point
-    const TFacet f = tf[h.pos];
-    const float e1x = f.p1.x - f.p0.x, e1y = f.p1.y - f.p0.y, e1z = f.p1.z - f.p0.z;
-    const float e2x = f.p2.x - f.p0.x, e2y = f.p2.y - f.p0.y, e2z = f.p2.z - f.p0.z;
-    float nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
-    const float inv = 1.f / sqrtf(nx * nx + ny * ny + nz * nz);
-    nx *= inv; ny *= inv; nz *= inv;
-    ox = ox + h.t * dx;
-    oy = oy + h.t * dy;
-    oz = oz + h.t * dz;
-    const float dn = 2.f * (dx * nx + dy * ny + dz * nz);
-    dx = dx - dn * nx;
-    dy = dy - dn * ny;
-    dz = dz - dn * nz;
+    // specular reflection about the facet plane, launched from the hit point
+    ox = fmaf(h.t, dx, ox);
+    oy = fmaf(h.t, dy, oy);
+    oz = fmaf(h.t, dz, oz);
+    reflect(nrm, dx, dy, dz);
     skip = h.pos;
   }
   if (BOUNCE) {
