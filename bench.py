@@ -1,0 +1,242 @@
+#!/usr/bin/env python3
+"""Closest-hit ray tracing benchmark on one MI355X.
+
+A step is one pass of the whole path for one transmitter: build the BVH of
+the scene with the Eq. (2) split for that transmitter (Sec. II-B, II-C), then
+trace the launched rays with up to 6 specular bounces (Sec. III-B).  Scene and
+rays are seeded synthetic inputs already resident in HBM.  The value is
+traced segments (primary + every re-launched segment) per second of step time,
+in millions.
+
+Prints one JSON line.  Extra fields: the trace kernel's roofline (algorithmic
+bytes from the instrumented kernel's node and facet counts), the CPU checker's
+rate on the same workload, the traditional (alpha = 1) vs improved split
+comparison, facet tests and nodes per ray, per-step latency percentiles.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "closest-hit Mrays/s (24k-tri scene, ≤6 bounces); tri tests/ray; p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+TRACE_SRC = os.path.join(ROOT, "paper_2208_10008_amd", "csrc", "rt_trace.hip")
+NODE_BYTES = 64      # binary node: both child boxes + references
+FACET_BYTES = 36     # three float32 vertices
+RAY_BYTES = 32
+HIT_BYTES = 16
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="city24k", choices=["city24k", "microcell", "dense200k"])
+    ap.add_argument("--alpha", type=float, default=0.4)
+    ap.add_argument("--max-leaf", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run one plain device copy of this size (counter calibration)")
+    return ap.parse_args()
+
+
+def kernel_source_hash():
+    with open(TRACE_SRC, "rb") as f:
+        return hashlib.sha1(f.read()).hexdigest()[:12]
+
+
+def load_traffic(workload_name):
+    """HBM bytes per trace launch from committed counter runs, if they were
+    taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "trace_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_source_sha1") != kernel_source_hash() or rec.get("workload") != workload_name:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: the path has no multi-GPU mode "
+              "(rays are independent; see the sharding notes of the design)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2208_10008_amd as R
+    from rtgen import workloads
+
+    torch.cuda.set_device(0)
+    w = {"city24k": workloads.city24k, "microcell": workloads.microcell,
+         "dense200k": workloads.dense200k}[args.workload]()
+    params = R.SplitParams(alpha=args.alpha, src=w.tx, max_leaf=args.max_leaf)
+    nb = w.max_bounces
+    tris = torch.from_numpy(w.tris).cuda()
+    rays = torch.from_numpy(w.rays).cuda()
+    n = w.n_rays
+    out = torch.empty((nb, n, 4), dtype=torch.int32, device="cuda")
+    path_len = torch.empty(n, dtype=torch.float64, device="cuda")
+    n_hits = torch.empty(n, dtype=torch.int32, device="cuda")
+    bvh = R.BVH(tris, params)
+    stream = torch.cuda.current_stream()
+
+    def step(p, ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        R.rt_rebuild(bvh.handle, tris, p)
+        if ev is not None:
+            ev[1].record(stream)
+        R.rt_trace_bounces(bvh.handle, rays, nb, out, path_len, n_hits)
+        if ev is not None:
+            ev[2].record(stream)
+
+    def timed(p, steps, warmup):
+        for _ in range(warmup):
+            step(p)
+        torch.cuda.synchronize()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+        wall = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            s0 = time.perf_counter()
+            step(p, evs[k])
+            evs[k][2].synchronize()
+            wall.append(time.perf_counter() - s0)
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t0
+        build_ms = [e[0].elapsed_time(e[1]) for e in evs]
+        trace_ms = [e[1].elapsed_time(e[2]) for e in evs]
+        return total, wall, build_ms, trace_ms
+
+    total, wall, build_ms, trace_ms = timed(params, args.steps, args.warmup)
+    nh = n_hits.cpu().numpy()
+    segments = int(np.minimum(nh + 1, nb).sum())
+    ms_per_step = 1e3 * total / args.steps
+    value = segments / (total / args.steps) / 1e6
+    trace_mean_ms = float(np.mean(trace_ms))
+
+    # instrumented launch (outside the timed region): nodes and facet tests
+    stats = torch.empty((n, 2), dtype=torch.int32, device="cuda")
+    R.rt_trace_ex(bvh.handle, rays, nb, out, path_len, n_hits, ray_stats=stats)
+    st = stats.cpu().numpy().astype(np.int64)
+    nodes_total, tests_total = int(st[:, 0].sum()), int(st[:, 1].sum())
+    alg_bytes = segments * (RAY_BYTES + HIT_BYTES) + nodes_total * NODE_BYTES + tests_total * FACET_BYTES
+    achieved = alg_bytes / (trace_mean_ms * 1e-3) / 1e9
+    traffic = load_traffic(w.name)
+    info = bvh.info()
+
+    if args.copy_mib:
+        # a plain elementwise copy kernel: reads and writes copy_mib MiB each
+        a = torch.ones(args.copy_mib * 2 ** 18, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+
+    result = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "Mrays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": w.name, "tris": w.n_tris, "rays": n, "max_bounces": nb,
+            "tx": list(w.tx), "alpha": args.alpha, "max_leaf": args.max_leaf,
+            "step": "rt_rebuild (Eq. 2 BVH for this Tx) + rt_trace_bounces",
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "kernel": "k_trace<bounce>", "kernel_ms": round(trace_mean_ms, 4),
+            "alg_bytes_per_launch": alg_bytes,
+        },
+        "segments_per_step": segments,
+        "trace_only_mrays_s": round(segments / (trace_mean_ms * 1e-3) / 1e6, 2),
+        "primary_mrays_s": round(n / (total / args.steps) / 1e6, 2),
+        "build_ms": round(float(np.mean(build_ms)), 4),
+        "trace_ms": round(trace_mean_ms, 4),
+        "latency_ms_p50": round(1e3 * float(np.percentile(wall, 50)), 4),
+        "latency_ms_p99": round(1e3 * float(np.percentile(wall, 99)), 4),
+        "tri_tests_per_ray": round(tests_total / segments, 3),
+        "nodes_per_ray": round(nodes_total / segments, 3),
+        "tri_tests_per_primary_p50_p99": [int(np.percentile(st[:, 1], 50)), int(np.percentile(st[:, 1], 99))],
+        "bvh": {"nodes": info.n_nodes, "depth": info.depth, "trace_bytes": info.trace_bytes},
+    }
+
+    if not args.no_compare:
+        trad = R.SplitParams(alpha=1.0, src=w.tx, max_leaf=args.max_leaf)
+        t_tot, _, t_build, t_trace = timed(trad, max(5, args.steps // 3), 1)
+        i_tot, _, i_build, i_trace = timed(params, max(5, args.steps // 3), 1)
+        result["improved_vs_traditional"] = {
+            "alpha_improved": args.alpha, "alpha_traditional": 1.0,
+            "trace_ms_improved": round(float(np.mean(i_trace)), 4),
+            "trace_ms_traditional": round(float(np.mean(t_trace)), 4),
+            "trace_time_ratio": round(float(np.mean(i_trace) / np.mean(t_trace)), 4),
+            "step_ms_improved": round(1e3 * i_tot / max(5, args.steps // 3), 4),
+            "step_ms_traditional": round(1e3 * t_tot / max(5, args.steps // 3), 4),
+            "paper_claim": "20-35% less computation time than the traditional BVH "
+                           "(hardware not stated in the paper)",
+        }
+        step(params)  # leave the improved tree in place
+        torch.cuda.synchronize()
+
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(w, args.alpha, args.max_leaf)
+
+    print(json.dumps(result), flush=True)
+
+
+def cpu_baseline(w, alpha, max_leaf):
+    """The CPU checker (float64 C++, all of its threads) running the same
+    step: the paper's build for the transmitter, then every ray's chain with
+    the Sec. III-B traversal (with its margin bookkeeping)."""
+    import numpy as np
+
+    import oracle
+
+    threads = min(16, os.cpu_count() or 1)
+    runs = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        tree = oracle.build_tree(w.tris, oracle.SplitParams(alpha=alpha, src=w.tx, max_leaf=max_leaf))
+        t1 = time.perf_counter()
+        ch = oracle.bounces(w.tris, w.rays, w.max_bounces, tree=tree, nthreads=threads, segments=False)
+        t2 = time.perf_counter()
+        segs = int(np.minimum(ch.n_hits + 1, w.max_bounces).sum())
+        runs.append((t2 - t0, t1 - t0, segs))
+        if t2 - t0 > 10:
+            break
+    runs.sort()
+    tot, build, segs = runs[len(runs) // 2]
+    return {"value": round(segs / tot / 1e6, 3), "unit": "Mrays/s", "cores": threads,
+            "kind": "oracle", "seconds_per_step": round(tot, 3), "build_s": round(build, 3),
+            "sample": f"whole workload: {w.n_rays} rays, <= {w.max_bounces} segments each, "
+                      f"float64 build + traversal, median of {len(runs)} runs"}
+
+
+if __name__ == "__main__":
+    main()
