@@ -31,8 +31,8 @@ namespace {
 bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
 void free_buffers(Buffers& B) {
-  void* ptrs[] = {B.flo,  B.fhi,   B.cen,      B.refs_a,   B.refs_b, B.perm,   B.nodes,
-                  B.act_a, B.act_b, B.cand,    B.counters, B.root_box, B.tnodes, B.tfacets};
+  void* ptrs[] = {B.recs_a, B.recs_b, B.perm,  B.nodes,    B.act_a,    B.act_b,  B.cand,
+                  B.big,    B.small,  B.counters, B.root_box, B.tnodes, B.tfacets};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   B = Buffers();
@@ -51,22 +51,21 @@ int alloc(T*& p, size_t count, int64_t& bytes) {
 }
 
 int ensure_buffers(Buffers& B, int64_t n) {
-  if (B.cap_n >= n && B.flo) return RT_OK;
+  if (B.cap_n >= n && B.recs_a) return RT_OK;
   free_buffers(B);
   int64_t bytes = 0;
   int rc = RT_OK;
   const size_t nn = (size_t)n;
-  if (rc == RT_OK) rc = alloc(B.flo, nn, bytes);
-  if (rc == RT_OK) rc = alloc(B.fhi, nn, bytes);
-  if (rc == RT_OK) rc = alloc(B.cen, 3 * nn, bytes);
-  if (rc == RT_OK) rc = alloc(B.refs_a, nn, bytes);
-  if (rc == RT_OK) rc = alloc(B.refs_b, nn, bytes);
+  if (rc == RT_OK) rc = alloc(B.recs_a, nn, bytes);
+  if (rc == RT_OK) rc = alloc(B.recs_b, nn, bytes);
   if (rc == RT_OK) rc = alloc(B.perm, nn, bytes);
   if (rc == RT_OK) rc = alloc(B.nodes, 2 * nn, bytes);
   if (rc == RT_OK) rc = alloc(B.act_a, nn, bytes);
   if (rc == RT_OK) rc = alloc(B.act_b, nn, bytes);
   if (rc == RT_OK) rc = alloc(B.cand, 2 * nn, bytes);
-  if (rc == RT_OK) rc = alloc(B.counters, 16, bytes);
+  if (rc == RT_OK) rc = alloc(B.big, nn, bytes);
+  if (rc == RT_OK) rc = alloc(B.small, nn, bytes);
+  if (rc == RT_OK) rc = alloc(B.counters, 32, bytes);
   if (rc == RT_OK) rc = alloc(B.root_box, 12, bytes);
   if (rc == RT_OK) rc = alloc(B.tnodes, nn, bytes);
   if (rc == RT_OK) rc = alloc(B.tfacets, nn, bytes);

@@ -43,18 +43,23 @@ struct alignas(16) TFacet {
 };
 constexpr uint32_t kLastFacet = 0x80000000u;
 
+// ---- build-time facet record, kept in reference order: 32 bytes ----
+//   lo = (box lo xyz, caller's id bits), hi = (box hi xyz, 0)
+struct alignas(16) FacetRec {
+  float4 lo, hi;
+};
+
 struct Buffers {
   // build scratch
-  float4* flo = nullptr;    // [n] facet box lo
-  float4* fhi = nullptr;    // [n] facet box hi
-  double* cen = nullptr;    // [3][n] centroids (SoA)
-  int32_t* refs_a = nullptr;
-  int32_t* refs_b = nullptr;
+  FacetRec* recs_a = nullptr;  // [n] facet records, ping-pong between levels
+  FacetRec* recs_b = nullptr;
   int32_t* perm = nullptr;  // [n] final leaf order
   BNode* nodes = nullptr;   // [2n - 1]
   int32_t* act_a = nullptr; // [n] active node ids
   int32_t* act_b = nullptr;
-  int32_t* cand = nullptr;  // [2n] child is internal flag
+  int32_t* cand = nullptr;  // [2n] facet count of a child that stays internal, else 0
+  int32_t* big = nullptr;   // [n] level positions of nodes above the big-node size
+  int32_t* small = nullptr; // [n] level positions of the other nodes
   int32_t* counters = nullptr;  // small device counters
   long long* root_box = nullptr; // ordered-int root bounds (6 float + 6 double)
   // traversal data
