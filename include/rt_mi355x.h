@@ -52,6 +52,13 @@ extern "C" {
 #define RT_DNORM_UNIT 0 /* SAH part / (k_C t_i), distance part / (root diagonal)^2 (default) */
 #define RT_DNORM_RAW 1  /* Eq. (2) in the units it is printed in (metres squared) */
 
+/* Traversal node formats (Sec. II-C tree, stored for the GPU) */
+#define RT_NODE_BIN2 0 /* binary: both child volumes as float32 in the parent, 64 B per node */
+#define RT_NODE_F4 1   /* 4-wide: pairs of tree levels merged, float32 child volumes, 128 B */
+#define RT_NODE_Q4 2   /* 4-wide, child volumes as 8-bit offsets from a float32 origin with
+                          power-of-two scales per axis, rounded outward so that the decoded
+                          volume always contains the exact one, 64 B */
+
 #define RT_MAX_BINS 64     /* largest nbins */
 #define RT_MAX_DEPTH 64    /* largest depth_limit: the traversal stack holds this many entries */
 #define RT_MAX_BOUNCES 64  /* largest max_bounces */
@@ -68,10 +75,12 @@ typedef struct rt_split_params {
   int32_t max_depth; /* from this depth on, alpha is taken as 1 */
   int32_t depth_limit; /* no leaf deeper than this (1..RT_MAX_DEPTH); nodes that could
                           not otherwise meet it are halved by position */
+  int32_t node_format; /* RT_NODE_*: layout the traversal reads; never changes the tree
+                          or the hits */
 } rt_split_params;
 
 /* Defaults: alpha 1, t_isect 1, t_trav 1, src 0, max_leaf 4, nbins 16,
- * RT_D_CHILD_MEAN, RT_DNORM_UNIT, max_depth 32, depth_limit 64. */
+ * RT_D_CHILD_MEAN, RT_DNORM_UNIT, max_depth 32, depth_limit 64, RT_NODE_BIN2. */
 void rt_split_params_default(rt_split_params* p);
 
 /* ---- results ------------------------------------------------------------ */
@@ -93,6 +102,10 @@ typedef struct rt_bvh_info {
   int64_t device_bytes; /* device memory held by the handle */
   int64_t trace_bytes;  /* of which: traversal nodes + leaf-ordered facets */
   float root_lo[3], root_hi[3];
+  int32_t node_format;  /* RT_NODE_* of the traversal nodes */
+  int32_t n_trace_nodes; /* traversal node records (wide formats: one per even-depth
+                            internal node, stored at that node's breadth-first internal
+                            index, so some records are unused) */
 } rt_bvh_info;
 
 /* One node of the binary tree in build order (breadth-first; the two
@@ -169,6 +182,21 @@ int rt_bvh_info_get(const rt_bvh* b, rt_bvh_info* info); /* host struct */
  * RT_EINVAL if a capacity is too small. */
 int rt_bvh_download(const rt_bvh* b, rt_node_rec* nodes, int64_t node_cap, int32_t* perm,
                     int64_t perm_cap);
+
+/* Copies the traversal node array as the GPU reads it (host buffer of at
+ * least *bytes; call with host = NULL to get the size).  Layouts, all little
+ * endian, one record per node index:
+ *   RT_NODE_BIN2, 64 B: float c0lox, c0hix, c0loy, c0hiy; c1lox, c1hix, c1loy, c1hiy;
+ *                 c0loz, c0hiz, c1loz, c1hiz; int32 ref0, ref1, 0, 0
+ *   RT_NODE_F4, 128 B: float lox[4], hix[4], loy[4], hiy[4], loz[4], hiz[4];
+ *                 int32 ref[4]; uint32 mask (bit c: child c present), 0, 0, 0
+ *   RT_NODE_Q4, 64 B: float ox, oy, oz; uint32 meta = (ex + 127) | (ey + 127) << 8 |
+ *                 (ez + 127) << 16 | mask << 24; uint8 qlox[4], qloy[4], qloz[4], qhix[4],
+ *                 qhiy[4], qhiz[4]; 8 bytes 0; int32 ref[4].  Child c's volume is
+ *                 lo = fmaf(q_lo, 2^e, o), hi = fmaf(q_hi, 2^e, o) per axis (float32).
+ * A reference r >= 0 is a node index, r < 0 a leaf whose facets start at
+ * leaf-order position ~r.  Synchronises the device. */
+int rt_bvh_export_trace_nodes(const rt_bvh* b, void* host, int64_t* bytes);
 
 void rt_bvh_destroy(rt_bvh* b); /* NULL is a no-op; waits for the device */
 

@@ -25,6 +25,7 @@ LIB_PATH = os.path.join(_HERE, "librt_mi355x.so")
 RT_OK, RT_EINVAL, RT_ENOMEM, RT_EHIP, RT_EDEPTH = 0, -1, -2, -3, -4
 D_MODES = {"mean": 0, "sum": 1, "kweighted": 2, "parent": 3}
 D_NORMS = {"unit": 0, "raw": 1}
+NODE_FORMATS = {"bin2": 0, "f4": 1, "q4": 2}
 MAX_BOUNCES = 64
 
 
@@ -39,7 +40,8 @@ class rt_split_params(ctypes.Structure):
                 ("t_trav", ctypes.c_float), ("src", ctypes.c_float * 3),
                 ("max_leaf", ctypes.c_int32), ("nbins", ctypes.c_int32),
                 ("d_mode", ctypes.c_int32), ("d_norm", ctypes.c_int32),
-                ("max_depth", ctypes.c_int32), ("depth_limit", ctypes.c_int32)]
+                ("max_depth", ctypes.c_int32), ("depth_limit", ctypes.c_int32),
+                ("node_format", ctypes.c_int32)]
 
 
 class rt_bvh_info(ctypes.Structure):
@@ -47,7 +49,8 @@ class rt_bvh_info(ctypes.Structure):
                 ("n_internal", ctypes.c_int64), ("n_leaves", ctypes.c_int64),
                 ("depth", ctypes.c_int32), ("n_levels", ctypes.c_int32),
                 ("device_bytes", ctypes.c_int64), ("trace_bytes", ctypes.c_int64),
-                ("root_lo", ctypes.c_float * 3), ("root_hi", ctypes.c_float * 3)]
+                ("root_lo", ctypes.c_float * 3), ("root_hi", ctypes.c_float * 3),
+                ("node_format", ctypes.c_int32), ("n_trace_nodes", ctypes.c_int32)]
 
 
 class rt_trace_opts(ctypes.Structure):
@@ -63,7 +66,7 @@ assert NODE_DTYPE.itemsize == 64
 
 EXPORTS = ("rt_split_params_default", "rt_build", "rt_rebuild", "rt_trace",
            "rt_trace_bounces", "rt_trace_ex", "rt_bvh_info_get", "rt_bvh_download",
-           "rt_bvh_destroy", "rt_last_error")
+           "rt_bvh_export_trace_nodes", "rt_bvh_destroy", "rt_last_error")
 
 _lib = None
 
@@ -86,12 +89,13 @@ def load(path: str = LIB_PATH):
     lib.rt_trace_ex.argtypes = [P, P, i64, i32, P, P, P, ctypes.POINTER(rt_trace_opts), P]
     lib.rt_bvh_info_get.argtypes = [P, ctypes.POINTER(rt_bvh_info)]
     lib.rt_bvh_download.argtypes = [P, P, i64, P, i64]
+    lib.rt_bvh_export_trace_nodes.argtypes = [P, P, ctypes.POINTER(i64)]
     lib.rt_bvh_destroy.argtypes = [P]
     lib.rt_bvh_destroy.restype = None
     lib.rt_last_error.argtypes = []
     lib.rt_last_error.restype = ctypes.c_char_p
     for name in ("rt_build", "rt_rebuild", "rt_trace", "rt_trace_bounces", "rt_trace_ex",
-                 "rt_bvh_info_get", "rt_bvh_download"):
+                 "rt_bvh_info_get", "rt_bvh_download", "rt_bvh_export_trace_nodes"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -115,6 +119,7 @@ class SplitParams:
     d_norm: str = "unit"
     max_depth: int = 32
     depth_limit: int = 64
+    node_format: str = "bin2"
 
     def c(self) -> rt_split_params:
         p = rt_split_params()
@@ -124,6 +129,7 @@ class SplitParams:
         p.max_leaf, p.nbins = self.max_leaf, self.nbins
         p.d_mode, p.d_norm = D_MODES[self.d_mode], D_NORMS[self.d_norm]
         p.max_depth, p.depth_limit = self.max_depth, self.depth_limit
+        p.node_format = NODE_FORMATS[self.node_format]
         return p
 
 
@@ -203,6 +209,17 @@ def rt_bvh_download(handle):
     return nodes, perm
 
 
+def rt_bvh_export_trace_nodes(handle) -> np.ndarray:
+    """Raw traversal node records (uint8 bytes) as the GPU reads them."""
+    lib = load()
+    nbytes = ctypes.c_int64(0)
+    _check(lib.rt_bvh_export_trace_nodes(handle, None, ctypes.byref(nbytes)))
+    buf = np.zeros(nbytes.value, dtype=np.uint8)
+    _check(lib.rt_bvh_export_trace_nodes(handle, buf.ctypes.data_as(ctypes.c_void_p),
+                                         ctypes.byref(nbytes)))
+    return buf
+
+
 def rt_bvh_destroy(handle):
     if handle:
         load().rt_bvh_destroy(handle)
@@ -226,6 +243,9 @@ class BVH:
 
     def download(self):
         return rt_bvh_download(self.handle)
+
+    def trace_nodes(self) -> np.ndarray:
+        return rt_bvh_export_trace_nodes(self.handle)
 
     def hits_buffer(self, n, max_bounces=1):
         import torch

@@ -32,7 +32,7 @@ bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) %
 
 void free_buffers(Buffers& B) {
   void* ptrs[] = {B.recs_a, B.recs_b, B.perm,  B.nodes,    B.act_a,    B.act_b,  B.cand,
-                  B.big,    B.small,  B.counters, B.root_box, B.tnodes, B.tfacets};
+                  B.big,    B.small,  B.counters, B.root_box, B.tnodes, B.tfacets, B.wnodes};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   B = Buffers();
@@ -69,6 +69,7 @@ int ensure_buffers(Buffers& B, int64_t n) {
   if (rc == RT_OK) rc = alloc(B.root_box, 12, bytes);
   if (rc == RT_OK) rc = alloc(B.tnodes, nn, bytes);
   if (rc == RT_OK) rc = alloc(B.tfacets, nn, bytes);
+  if (rc == RT_OK) rc = alloc(B.wnodes, nn, bytes);
   if (rc != RT_OK) {
     free_buffers(B);
     return rc;
@@ -98,6 +99,8 @@ int check_params(const rt_split_params* p) {
   if (p->max_depth < 0) return set_error(RT_EINVAL, "split params: max_depth must be >= 0");
   if (p->depth_limit < 1 || p->depth_limit > RT_MAX_DEPTH)
     return set_error(RT_EINVAL, "split params: depth_limit must lie in 1..64");
+  if (p->node_format < RT_NODE_BIN2 || p->node_format > RT_NODE_Q4)
+    return set_error(RT_EINVAL, "split params: unknown node_format");
   return RT_OK;
 }
 
@@ -182,6 +185,7 @@ void rt_split_params_default(rt_split_params* p) {
   p->d_norm = RT_DNORM_UNIT;
   p->max_depth = 32;
   p->depth_limit = 64;
+  p->node_format = RT_NODE_BIN2;
 }
 
 int rt_build(const float* tris, int64_t n, const rt_split_params* p, rt_bvh** out,
@@ -214,7 +218,7 @@ int rt_rebuild(rt_bvh* b, const float* tris, int64_t n, const rt_split_params* p
 int rt_trace(const rt_bvh* b, const float* rays, int64_t n, rt_hit* out, hipStream_t s) {
   int rc = check_trace_args(b, rays, n, 1, out, nullptr, nullptr, nullptr);
   if (rc != RT_OK || n == 0) return rc;
-  return launch_trace(b->buf, b->info.n_internal, rays, n, 1, out, nullptr, nullptr, nullptr, s);
+  return launch_trace(b->buf, b->info.node_format, rays, n, 1, out, nullptr, nullptr, nullptr, s);
 }
 
 int rt_trace_bounces(const rt_bvh* b, const float* rays, int64_t n, int32_t max_bounces,
@@ -226,7 +230,7 @@ int rt_trace_ex(const rt_bvh* b, const float* rays, int64_t n, int32_t max_bounc
                 double* path_len, int32_t* n_hits, const rt_trace_opts* opts, hipStream_t s) {
   int rc = check_trace_args(b, rays, n, max_bounces, out, path_len, n_hits, opts);
   if (rc != RT_OK || n == 0) return rc;
-  return launch_trace(b->buf, b->info.n_internal, rays, n, max_bounces, out, path_len, n_hits,
+  return launch_trace(b->buf, b->info.node_format, rays, n, max_bounces, out, path_len, n_hits,
                       opts, s);
 }
 
@@ -271,6 +275,25 @@ int rt_bvh_download(const rt_bvh* b, rt_node_rec* nodes, int64_t node_cap, int32
     }
   }
   delete[] tmp;
+  return rc;
+}
+
+int rt_bvh_export_trace_nodes(const rt_bvh* b, void* host, int64_t* bytes) {
+  if (!b || !bytes) return set_error(RT_EINVAL, "rt_bvh_export_trace_nodes: NULL argument");
+  if (b->info.n_tris <= 0) return set_error(RT_EINVAL, "rt_bvh_export_trace_nodes: tree not built");
+  const int fmt = b->info.node_format;
+  const int64_t rec = fmt == RT_NODE_F4 ? sizeof(FNode4) : fmt == RT_NODE_Q4 ? sizeof(QNode4) : sizeof(TNode);
+  const int64_t need = rec * b->info.n_trace_nodes;
+  if (!host) {
+    *bytes = need;
+    return RT_OK;
+  }
+  if (*bytes < need) return set_error(RT_EINVAL, "rt_bvh_export_trace_nodes: buffer too small");
+  int rc = check_hip(hipDeviceSynchronize(), "hipDeviceSynchronize");
+  if (rc != RT_OK) return rc;
+  const void* src = fmt == RT_NODE_BIN2 ? (const void*)b->buf.tnodes : (const void*)b->buf.wnodes;
+  rc = check_hip(hipMemcpy(host, src, need, hipMemcpyDeviceToHost), "hipMemcpy");
+  *bytes = need;
   return rc;
 }
 

@@ -921,6 +921,113 @@ __global__ void k_emit(const BNode* __restrict__ nodes, int total, const int32_t
   tn[nd.tidx] = t;
 }
 
+// ---------------------------------------------------------------------------
+// 4-wide traversal nodes: every even-depth internal node becomes one wide
+// node whose children are its grandchildren, or its children where those are
+// leaves.  Stored at the node's breadth-first internal index.
+
+__device__ inline float pow2f(int e) { return __int_as_float((e + 127) << 23); }  // e in [-126, 127]
+
+// Per-axis exponent: smallest e with fmaf(255, 2^e, lo) >= hi, the decode
+// expression of the traversal kernel.
+__device__ inline int quant_exp(float lo, float hi) {
+  int e = -126;
+  const float ext = hi - lo;
+  if (ext > 0.f) {
+    int x;
+    frexpf(ext / 255.f, &x);  // ext / 255 < 2^x
+    e = max(-126, min(127, x - 1));
+  }
+  while (e < 127 && fmaf(255.f, pow2f(e), lo) < hi) ++e;
+  while (e > -126 && fmaf(255.f, pow2f(e - 1), lo) >= hi) --e;
+  return e;
+}
+// Largest q with decode(q) <= v (q in [0, 255]); decode(0) = lo <= v.
+__device__ inline unsigned quant_lo(float v, float lo, float sc) {
+  int q = (int)floorf((v - lo) / sc);
+  q = max(0, min(255, q));
+  while (q > 0 && fmaf((float)q, sc, lo) > v) --q;
+  while (q < 255 && fmaf((float)(q + 1), sc, lo) <= v) ++q;
+  return (unsigned)q;
+}
+// Smallest q with decode(q) >= v; decode(255) >= the parent's hi >= v.
+__device__ inline unsigned quant_hi(float v, float lo, float sc) {
+  int q = (int)ceilf((v - lo) / sc);
+  q = max(0, min(255, q));
+  while (q < 255 && fmaf((float)q, sc, lo) < v) ++q;
+  while (q > 0 && fmaf((float)(q - 1), sc, lo) >= v) --q;
+  return (unsigned)q;
+}
+
+template <int FMT>
+__global__ void k_collapse(const BNode* __restrict__ nodes, int total, FNode4* __restrict__ wn) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= total) return;
+  const BNode nd = nodes[id];
+  const bool root_leaf = id == 0 && nd.left < 0;
+  if (!root_leaf && (nd.left < 0 || (nd.depth & 1))) return;
+  // gather up to four children
+  BNode ch[4];
+  int nc = 0;
+  if (root_leaf) {
+    ch[nc++] = nd;
+  } else {
+    for (int side = 0; side < 2; ++side) {
+      const BNode c = nodes[nd.left + side];
+      if (c.left < 0) {
+        ch[nc++] = c;
+      } else {
+        ch[nc++] = nodes[c.left];
+        ch[nc++] = nodes[c.left + 1];
+      }
+    }
+  }
+  int ref[4] = {0, 0, 0, 0};
+  for (int c = 0; c < nc; ++c) ref[c] = ch[c].left < 0 ? ~ch[c].first : ch[c].tidx;
+  const unsigned mask = (1u << nc) - 1u;
+  const int slot = root_leaf ? 0 : nd.tidx;
+  if (FMT == RT_NODE_F4) {
+    FNode4 o;
+    float v[6][4];
+    for (int c = 0; c < 4; ++c)
+      for (int q = 0; q < 3; ++q) {
+        // unused slots: lo = hi = +inf (never entered; also masked out)
+        v[2 * q][c] = c < nc ? ch[c].lo[q] : INFINITY;
+        v[2 * q + 1][c] = c < nc ? ch[c].hi[q] : INFINITY;
+      }
+    o.lox = make_float4(v[0][0], v[0][1], v[0][2], v[0][3]);
+    o.hix = make_float4(v[1][0], v[1][1], v[1][2], v[1][3]);
+    o.loy = make_float4(v[2][0], v[2][1], v[2][2], v[2][3]);
+    o.hiy = make_float4(v[3][0], v[3][1], v[3][2], v[3][3]);
+    o.loz = make_float4(v[4][0], v[4][1], v[4][2], v[4][3]);
+    o.hiz = make_float4(v[5][0], v[5][1], v[5][2], v[5][3]);
+    o.ref = make_int4(ref[0], ref[1], ref[2], ref[3]);
+    o.meta = make_uint4(mask, 0u, 0u, 0u);
+    wn[slot] = o;
+  } else {
+    QNode4 o;
+    int e[3];
+    float sc[3];
+    for (int q = 0; q < 3; ++q) {
+      e[q] = quant_exp(nd.lo[q], nd.hi[q]);
+      sc[q] = pow2f(e[q]);
+    }
+    unsigned ql[3] = {0u, 0u, 0u}, qh[3] = {0u, 0u, 0u};
+    for (int c = 0; c < nc; ++c)
+      for (int q = 0; q < 3; ++q) {
+        ql[q] |= quant_lo(ch[c].lo[q], nd.lo[q], sc[q]) << (8 * c);
+        qh[q] |= quant_hi(ch[c].hi[q], nd.lo[q], sc[q]) << (8 * c);
+      }
+    const unsigned meta = (unsigned)(e[0] + 127) | ((unsigned)(e[1] + 127) << 8) |
+                          ((unsigned)(e[2] + 127) << 16) | (mask << 24);
+    o.h = make_float4(nd.lo[0], nd.lo[1], nd.lo[2], __uint_as_float(meta));
+    o.qa = make_uint4(ql[0], ql[1], ql[2], qh[0]);
+    o.qb = make_uint4(qh[1], qh[2], 0u, 0u);
+    o.ref = make_int4(ref[0], ref[1], ref[2], ref[3]);
+    reinterpret_cast<QNode4*>(wn)[slot] = o;
+  }
+}
+
 }  // namespace
 
 #define HIPCHECK(call)                                  \
@@ -1056,6 +1163,12 @@ int build_tree(Buffers& B, const float* tris, int64_t n64, const rt_split_params
   const int eb = 256;
   hipLaunchKernelGGL(k_emit, dim3((total + eb - 1) / eb), dim3(eb), 0, s, B.nodes, total, B.perm,
                      tris, B.tnodes, B.tfacets);
+  if (p.node_format == RT_NODE_F4)
+    hipLaunchKernelGGL(k_collapse<RT_NODE_F4>, dim3((total + eb - 1) / eb), dim3(eb), 0, s,
+                       B.nodes, total, B.wnodes);
+  else if (p.node_format == RT_NODE_Q4)
+    hipLaunchKernelGGL(k_collapse<RT_NODE_Q4>, dim3((total + eb - 1) / eb), dim3(eb), 0, s,
+                       B.nodes, total, B.wnodes);
   HIPCHECK(hipGetLastError());
   int32_t nonfinite = 0;
   HIPCHECK(hipMemcpyAsync(&nonfinite, B.counters + C_NONFINITE, 4, hipMemcpyDeviceToHost, s));
@@ -1068,7 +1181,11 @@ int build_tree(Buffers& B, const float* tris, int64_t n64, const rt_split_params
   info->n_leaves = total - n_internal;
   info->depth = levels;  // deepest leaf depth (root alone = 0)
   info->n_levels = levels;
-  info->trace_bytes = (int64_t)sizeof(TNode) * std::max(n_internal, 1) + (int64_t)sizeof(TFacet) * n;
+  const int64_t node_bytes = p.node_format == RT_NODE_F4 ? sizeof(FNode4)
+                             : p.node_format == RT_NODE_Q4 ? sizeof(QNode4) : sizeof(TNode);
+  info->node_format = p.node_format;
+  info->n_trace_nodes = std::max(n_internal, 1);
+  info->trace_bytes = node_bytes * std::max(n_internal, 1) + (int64_t)sizeof(TFacet) * n;
   return RT_OK;
 }
 

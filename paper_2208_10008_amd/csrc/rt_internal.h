@@ -35,6 +35,21 @@ struct alignas(64) TNode {
   int4 d;
 };
 
+// ---- 4-wide traversal nodes (one per even-depth internal node) ----
+// Children are the node's grandchildren, or its children where those are
+// leaves; `mask` marks the used slots.
+struct alignas(64) FNode4 {  // 128 bytes
+  float4 lox, hix, loy, hiy, loz, hiz;  // component c = child c
+  int4 ref;
+  uint4 meta;                           // x = mask
+};
+struct alignas(64) QNode4 {  // 64 bytes
+  float4 h;    // origin xyz, w = bits (ex + 127) | (ey + 127) << 8 | (ez + 127) << 16 | mask << 24
+  uint4 qa;    // bytes: qlo.x[4], qlo.y[4], qlo.z[4], qhi.x[4]
+  uint4 qb;    // bytes: qhi.y[4], qhi.z[4], 0, 0
+  int4 ref;
+};
+
 // ---- leaf-ordered facet: 48 bytes ----
 //   p0 = (v0.xyz, id bits), p1 = (v1.xyz, 0), p2 = (v2.xyz, 0); the top bit of
 //   the id marks the last facet of its leaf.
@@ -64,6 +79,7 @@ struct Buffers {
   long long* root_box = nullptr; // ordered-int root bounds (6 float + 6 double)
   // traversal data
   TNode* tnodes = nullptr;  // [max(n_internal, 1)]
+  FNode4* wnodes = nullptr; // [max(n_internal, 1)] wide nodes (QNode4 records use the first half)
   TFacet* tfacets = nullptr;  // [n]
   int64_t cap_n = 0;        // facets the buffers can hold
   int64_t bytes = 0;
@@ -103,7 +119,7 @@ int check_hip(hipError_t e, const char* what);
 int build_tree(Buffers& B, const float* tris, int64_t n, const rt_split_params& p,
                hipStream_t s, rt_bvh_info* info);
 // trace.hip
-int launch_trace(const Buffers& B, int64_t n_internal, const float* rays, int64_t n,
+int launch_trace(const Buffers& B, int node_format, const float* rays, int64_t n,
                  int32_t max_bounces, rt_hit* out, double* path_len, int32_t* n_hits,
                  const rt_trace_opts* opts, hipStream_t s);
 

@@ -212,11 +212,74 @@ struct Hit {
   float t, u, v;
 };
 
-template <bool STATS>
-__device__ Hit closest(const TNode* __restrict__ tn, const TFacet* __restrict__ tf,
-                       const RayPre& r, int skip_pos, uint32_t& nvis, uint32_t& ntest) {
-  int stack[kStack];
+// Stack of pending subtrees with the distance at which the ray enters them;
+// an entry behind the current nearest hit is dropped when popped.
+template <int N>
+struct Stack {
+  int ref[N];
+  float tn[N];
   int sp = 0;
+  __device__ void push(int r, float t) {
+    ref[sp] = r;
+    tn[sp] = t;
+    ++sp;
+  }
+  // next subtree entered no later than tbest; false when none is left
+  __device__ bool pop(float tbest, int& r) {
+    while (sp > 0) {
+      --sp;
+      if (tn[sp] <= tbest) {
+        r = ref[sp];
+        return true;
+      }
+    }
+    return false;
+  }
+};
+
+__device__ inline void cswap(float& ka, int& ra, float& kb, int& rb) {
+  if (kb < ka) {
+    const float k = ka;
+    ka = kb;
+    kb = k;
+    const int x = ra;
+    ra = rb;
+    rb = x;
+  }
+}
+
+__device__ inline float pow2f(int e) { return __int_as_float((e + 127) << 23); }
+__device__ inline float qbyte(unsigned w, int c) { return (float)((w >> (8 * c)) & 255u); }
+
+// Tests the facets of one leaf (positions ~node .. the one tagged last).
+template <bool STATS>
+__device__ inline void leaf_test(const TFacet* __restrict__ tf, const RayPre& r, int node,
+                                 int skip_pos, Hit& h, int& best_id, uint32_t& ntest) {
+  for (int k = ~node;; ++k) {
+    const TFacet f = tf[k];
+    const uint32_t tag = __float_as_uint(f.p0.w);
+    const int id = (int)(tag & ~kLastFacet);
+    if (k != skip_pos) {
+      if (STATS) ++ntest;
+      float t, u, v;
+      if (facet_test(r, f.p0, f.p1, f.p2, t, u, v) && t >= r.tmin &&
+          (t < h.t || (t == h.t && id < best_id))) {
+        h.t = t;
+        h.u = u;
+        h.v = v;
+        h.pos = k;
+        h.id = id;
+        best_id = id;
+      }
+    }
+    if (tag & kLastFacet) break;
+  }
+}
+
+template <int FMT, bool STATS>
+__device__ Hit closest(const void* __restrict__ nodes, const TFacet* __restrict__ tf,
+                       const RayPre& r, int skip_pos, uint32_t& nvis, uint32_t& ntest) {
+  Stack<FMT == RT_NODE_BIN2 ? kStack : kStack * 3 / 2> st;
   int node = 0;
   Hit h;
   h.id = -1;
@@ -226,46 +289,86 @@ __device__ Hit closest(const TNode* __restrict__ tn, const TFacet* __restrict__ 
   int best_id = 0x7fffffff;  // h.id, or the largest id while there is no hit
   for (;;) {
     while (node >= 0) {
-      const TNode nd = tn[node];
       if (STATS) ++nvis;
-      float n0, n1;
-      bool h0 = slab(r, nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.c.x, nd.c.y, r.tmin, h.t, n0);
-      bool h1 = slab(r, nd.b.x, nd.b.y, nd.b.z, nd.b.w, nd.c.z, nd.c.w, r.tmin, h.t, n1);
-      if (h0 && h1) {
-        bool first0 = n0 <= n1;
-        stack[sp++] = first0 ? nd.d.y : nd.d.x;
-        node = first0 ? nd.d.x : nd.d.y;
-      } else if (h0) {
-        node = nd.d.x;
-      } else if (h1) {
-        node = nd.d.y;
+      if constexpr (FMT == RT_NODE_BIN2) {
+        const TNode nd = static_cast<const TNode*>(nodes)[node];
+        float n0, n1;
+        const bool h0 = slab(r, nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.c.x, nd.c.y, r.tmin, h.t, n0);
+        const bool h1 = slab(r, nd.b.x, nd.b.y, nd.b.z, nd.b.w, nd.c.z, nd.c.w, r.tmin, h.t, n1);
+        if (h0 && h1) {
+          const bool first0 = n0 <= n1;
+          st.push(first0 ? nd.d.y : nd.d.x, first0 ? n1 : n0);
+          node = first0 ? nd.d.x : nd.d.y;
+        } else if (h0) {
+          node = nd.d.x;
+        } else if (h1) {
+          node = nd.d.y;
+        } else if (!st.pop(h.t, node)) {
+          return h;
+        }
       } else {
-        if (sp == 0) return h;
-        node = stack[--sp];
-      }
-    }
-    // leaf: facets from position ~node to the one tagged last
-    for (int k = ~node;; ++k) {
-      const TFacet f = tf[k];
-      const uint32_t tag = __float_as_uint(f.p0.w);
-      const int id = (int)(tag & ~kLastFacet);
-      if (k != skip_pos) {
-        if (STATS) ++ntest;
-        float t, u, v;
-        if (facet_test(r, f.p0, f.p1, f.p2, t, u, v) && t >= r.tmin &&
-            (t < h.t || (t == h.t && id < best_id))) {
-          h.t = t;
-          h.u = u;
-          h.v = v;
-          h.pos = k;
-          h.id = id;
-          best_id = id;
+        float key[4];
+        int ref[4];
+        unsigned mask;
+        if constexpr (FMT == RT_NODE_F4) {
+          const FNode4 nd = static_cast<const FNode4*>(nodes)[node];
+          mask = nd.meta.x;
+          const float lx[4] = {nd.lox.x, nd.lox.y, nd.lox.z, nd.lox.w};
+          const float hx[4] = {nd.hix.x, nd.hix.y, nd.hix.z, nd.hix.w};
+          const float ly[4] = {nd.loy.x, nd.loy.y, nd.loy.z, nd.loy.w};
+          const float hy[4] = {nd.hiy.x, nd.hiy.y, nd.hiy.z, nd.hiy.w};
+          const float lz[4] = {nd.loz.x, nd.loz.y, nd.loz.z, nd.loz.w};
+          const float hz[4] = {nd.hiz.x, nd.hiz.y, nd.hiz.z, nd.hiz.w};
+          const int rr[4] = {nd.ref.x, nd.ref.y, nd.ref.z, nd.ref.w};
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            float tn;
+            const bool hit = ((mask >> c) & 1u) &&
+                             slab(r, lx[c], hx[c], ly[c], hy[c], lz[c], hz[c], r.tmin, h.t, tn);
+            key[c] = hit ? tn : INFINITY;
+            ref[c] = rr[c];
+          }
+        } else {
+          const QNode4 nd = static_cast<const QNode4*>(nodes)[node];
+          const unsigned meta = __float_as_uint(nd.h.w);
+          mask = meta >> 24;
+          const float sx = pow2f((int)(meta & 255u) - 127);
+          const float sy = pow2f((int)((meta >> 8) & 255u) - 127);
+          const float sz = pow2f((int)((meta >> 16) & 255u) - 127);
+          const int rr[4] = {nd.ref.x, nd.ref.y, nd.ref.z, nd.ref.w};
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            // decode exactly as the builder verified: fmaf(q, 2^e, origin)
+            const float lx = fmaf(qbyte(nd.qa.x, c), sx, nd.h.x);
+            const float ly = fmaf(qbyte(nd.qa.y, c), sy, nd.h.y);
+            const float lz = fmaf(qbyte(nd.qa.z, c), sz, nd.h.z);
+            const float hx = fmaf(qbyte(nd.qa.w, c), sx, nd.h.x);
+            const float hy = fmaf(qbyte(nd.qb.x, c), sy, nd.h.y);
+            const float hz = fmaf(qbyte(nd.qb.y, c), sz, nd.h.z);
+            float tn;
+            const bool hit = ((mask >> c) & 1u) && slab(r, lx, hx, ly, hy, lz, hz, r.tmin, h.t, tn);
+            key[c] = hit ? tn : INFINITY;
+            ref[c] = rr[c];
+          }
+        }
+        // nearest first
+        cswap(key[0], ref[0], key[1], ref[1]);
+        cswap(key[2], ref[2], key[3], ref[3]);
+        cswap(key[0], ref[0], key[2], ref[2]);
+        cswap(key[1], ref[1], key[3], ref[3]);
+        cswap(key[1], ref[1], key[2], ref[2]);
+        if (key[0] == INFINITY) {
+          if (!st.pop(h.t, node)) return h;
+        } else {
+          if (key[3] != INFINITY) st.push(ref[3], key[3]);
+          if (key[2] != INFINITY) st.push(ref[2], key[2]);
+          if (key[1] != INFINITY) st.push(ref[1], key[1]);
+          node = ref[0];
         }
       }
-      if (tag & kLastFacet) break;
     }
-    if (sp == 0) return h;
-    node = stack[--sp];
+    leaf_test<STATS>(tf, r, node, skip_pos, h, best_id, ntest);
+    if (!st.pop(h.t, node)) return h;
   }
 }
 
@@ -281,8 +384,8 @@ __device__ inline void store_hit(rt_hit* out, int64_t k, const Hit& h) {
 
 constexpr int kBlock = 128;
 
-template <bool BOUNCE, bool SEG, bool STATS>
-__global__ __launch_bounds__(kBlock) void k_trace(const TNode* __restrict__ tn,
+template <int FMT, bool BOUNCE, bool SEG, bool STATS>
+__global__ __launch_bounds__(kBlock) void k_trace(const void* __restrict__ tn,
                                                   const TFacet* __restrict__ tf,
                                                   const float4* __restrict__ rays, int64_t n,
                                                   int max_b, rt_hit* __restrict__ out,
@@ -306,7 +409,7 @@ __global__ __launch_bounds__(kBlock) void k_trace(const TNode* __restrict__ tn,
       seg[2 * ((int64_t)b * n + i) + 1] = make_float4(dx, dy, dz, tmax);
     }
     const RayPre r = prepare(ox, oy, oz, dx, dy, dz, tmin, tmax);
-    Hit h = closest<STATS>(tn, tf, r, skip, nvis, ntest);
+    Hit h = closest<FMT, STATS>(tn, tf, r, skip, nvis, ntest);
     N2 nrm;
     if (h.id >= 0) {
       // the facet is decided; its distance is recomputed accurately
@@ -340,34 +443,51 @@ __global__ __launch_bounds__(kBlock) void k_trace(const TNode* __restrict__ tn,
   }
 }
 
-template <bool BOUNCE, bool SEG, bool STATS>
+template <int FMT, bool BOUNCE, bool SEG, bool STATS>
 void launch(const Buffers& B, const float* rays, int64_t n, int max_b, rt_hit* out,
             double* path_len, int32_t* n_hits, float* seg, uint32_t* stats, hipStream_t s) {
   const int64_t blocks = (n + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL((k_trace<BOUNCE, SEG, STATS>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
-                     B.tnodes, B.tfacets, reinterpret_cast<const float4*>(rays), n, max_b, out,
+  const void* nodes = FMT == RT_NODE_BIN2 ? (const void*)B.tnodes : (const void*)B.wnodes;
+  hipLaunchKernelGGL((k_trace<FMT, BOUNCE, SEG, STATS>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                     nodes, B.tfacets, reinterpret_cast<const float4*>(rays), n, max_b, out,
                      path_len, n_hits, reinterpret_cast<float4*>(seg), stats);
+}
+
+template <int FMT>
+void launch_fmt(const Buffers& B, const float* rays, int64_t n, int max_b, rt_hit* out,
+                double* path_len, int32_t* n_hits, float* seg, uint32_t* stats, hipStream_t s) {
+  const bool bounce = max_b > 1 || path_len || n_hits;
+  if (!bounce && !seg && !stats) {
+    launch<FMT, false, false, false>(B, rays, n, 1, out, nullptr, nullptr, nullptr, nullptr, s);
+  } else if (!seg && !stats) {
+    launch<FMT, true, false, false>(B, rays, n, max_b, out, path_len, n_hits, nullptr, nullptr, s);
+  } else if (seg && !stats) {
+    launch<FMT, true, true, false>(B, rays, n, max_b, out, path_len, n_hits, seg, nullptr, s);
+  } else if (!seg) {
+    launch<FMT, true, false, true>(B, rays, n, max_b, out, path_len, n_hits, nullptr, stats, s);
+  } else {
+    launch<FMT, true, true, true>(B, rays, n, max_b, out, path_len, n_hits, seg, stats, s);
+  }
 }
 
 }  // namespace
 
-int launch_trace(const Buffers& B, int64_t /*n_internal*/, const float* rays, int64_t n,
+int launch_trace(const Buffers& B, int node_format, const float* rays, int64_t n,
                  int32_t max_b, rt_hit* out, double* path_len, int32_t* n_hits,
                  const rt_trace_opts* opts, hipStream_t s) {
   if (n == 0) return RT_OK;
   float* seg = opts ? opts->seg_rays : nullptr;
   uint32_t* stats = opts ? opts->ray_stats : nullptr;
-  const bool bounce = max_b > 1 || path_len || n_hits;
-  if (!bounce && !seg && !stats) {
-    launch<false, false, false>(B, rays, n, 1, out, nullptr, nullptr, nullptr, nullptr, s);
-  } else if (!seg && !stats) {
-    launch<true, false, false>(B, rays, n, max_b, out, path_len, n_hits, nullptr, nullptr, s);
-  } else if (seg && !stats) {
-    launch<true, true, false>(B, rays, n, max_b, out, path_len, n_hits, seg, nullptr, s);
-  } else if (!seg) {
-    launch<true, false, true>(B, rays, n, max_b, out, path_len, n_hits, nullptr, stats, s);
-  } else {
-    launch<true, true, true>(B, rays, n, max_b, out, path_len, n_hits, seg, stats, s);
+  switch (node_format) {
+    case RT_NODE_F4:
+      launch_fmt<RT_NODE_F4>(B, rays, n, max_b, out, path_len, n_hits, seg, stats, s);
+      break;
+    case RT_NODE_Q4:
+      launch_fmt<RT_NODE_Q4>(B, rays, n, max_b, out, path_len, n_hits, seg, stats, s);
+      break;
+    default:
+      launch_fmt<RT_NODE_BIN2>(B, rays, n, max_b, out, path_len, n_hits, seg, stats, s);
+      break;
   }
   return check_hip(hipGetLastError(), "trace launch");
 }

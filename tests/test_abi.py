@@ -53,8 +53,9 @@ def test_struct_layouts_match_header(tmp_path):
 int main(void) {
   printf("%zu %zu %zu %zu %zu\\n", sizeof(rt_split_params), sizeof(rt_hit), sizeof(rt_bvh_info),
          sizeof(rt_node_rec), sizeof(rt_trace_opts));
-  printf("%zu %zu %zu %zu\\n", offsetof(rt_node_rec, cost), offsetof(rt_bvh_info, root_lo),
-         offsetof(rt_split_params, max_leaf), offsetof(rt_trace_opts, block));
+  printf("%zu %zu %zu %zu %zu %zu\\n", offsetof(rt_node_rec, cost), offsetof(rt_bvh_info, root_lo),
+         offsetof(rt_split_params, max_leaf), offsetof(rt_trace_opts, block),
+         offsetof(rt_split_params, node_format), offsetof(rt_bvh_info, n_trace_nodes));
   return 0;
 }""")
     exe = tmp_path / "sz"
@@ -66,7 +67,8 @@ int main(void) {
     assert sizes == [ctypes.sizeof(R.rt_split_params), 16, ctypes.sizeof(R.rt_bvh_info),
                      R.NODE_DTYPE.itemsize, ctypes.sizeof(R.rt_trace_opts)]
     assert offs == [R.NODE_DTYPE.fields["cost"][1], R.rt_bvh_info.root_lo.offset,
-                    R.rt_split_params.max_leaf.offset, R.rt_trace_opts.block.offset]
+                    R.rt_split_params.max_leaf.offset, R.rt_trace_opts.block.offset,
+                    R.rt_split_params.node_format.offset, R.rt_bvh_info.n_trace_nodes.offset]
 
 
 def test_defaults():
@@ -75,8 +77,8 @@ def test_defaults():
     lib.rt_split_params_default(ctypes.byref(p))
     d = R.SplitParams()
     assert (p.alpha, p.t_isect, p.t_trav, list(p.src)) == (d.alpha, d.t_isect, d.t_trav, list(d.src))
-    assert (p.max_leaf, p.nbins, p.d_mode, p.d_norm, p.max_depth, p.depth_limit) == \
-        (d.max_leaf, d.nbins, 0, 0, d.max_depth, d.depth_limit)
+    assert (p.max_leaf, p.nbins, p.d_mode, p.d_norm, p.max_depth, p.depth_limit, p.node_format) == \
+        (d.max_leaf, d.nbins, 0, 0, d.max_depth, d.depth_limit, 0)
 
 
 def _build_rc(tris_ptr, n, params):
@@ -88,7 +90,8 @@ def _build_rc(tris_ptr, n, params):
 @pytest.mark.parametrize("field,value", [("alpha", 1.5), ("alpha", -0.5), ("alpha", float("nan")),
                                          ("max_leaf", 0), ("nbins", 1), ("nbins", 65),
                                          ("d_mode", 4), ("d_norm", 2), ("depth_limit", 0),
-                                         ("depth_limit", 65), ("t_isect", 0.0)])
+                                         ("depth_limit", 65), ("t_isect", 0.0),
+                                         ("node_format", 3), ("node_format", -1)])
 def test_build_rejects_bad_params(field, value):
     p = R.SplitParams().c()
     setattr(p, field, value)
@@ -120,6 +123,7 @@ def test_null_handles():
     assert lib.rt_trace(None, None, 0, None, None) == R.RT_EINVAL
     assert lib.rt_trace_bounces(None, None, 0, 1, None, None, None, None) == R.RT_EINVAL
     assert lib.rt_bvh_download(None, None, 0, None, 0) == R.RT_EINVAL
+    assert lib.rt_bvh_export_trace_nodes(None, None, None) == R.RT_EINVAL
     lib.rt_bvh_destroy(None)
     assert lib.rt_rebuild(None, None, 0, None, None) == R.RT_EINVAL
 

@@ -180,10 +180,11 @@ def test_hits_do_not_depend_on_the_tree(city):
             assert np.array_equal(o[clean], base[clean]), kw
 
 
-def test_city_bounces_every_segment(city):
+@pytest.mark.parametrize("fmt", ["bin2", "f4", "q4"])
+def test_city_bounces_every_segment(city, fmt):
     """Full size, the benchmark's launch: every traced segment of every chain
     is re-traced by the checker from the GPU's own float32 segment ray."""
-    p = R.SplitParams(alpha=0.4, src=city.tx)
+    p = R.SplitParams(alpha=0.4, src=city.tx, node_format=fmt)
     bvh = R.BVH(dev(city.tris), p)
     n, nb = city.n_rays, city.max_bounces
     seg = torch.empty((nb, n, 8), dtype=torch.float32, device="cuda")
@@ -220,7 +221,7 @@ def test_city_bounces_every_segment(city):
             assert np.all(ids[b + 1, dead] == -1)
     assert np.array_equal(nh_np, (ids >= 0).sum(0))
     np.testing.assert_allclose(pl_np, path, rtol=1e-12, atol=0)
-    log("city bounces", total)
+    log("city bounces", fmt, total)
     assert total["clean"] > 0.99 * total["segments"]
 
 
@@ -267,9 +268,10 @@ def test_city_chains_against_float64_chains(city):
     assert np.array_equal(nh.cpu().numpy()[clean_chain], ch.n_hits[clean_chain])
 
 
-def test_dense_city_tree_and_sampled_chains():
+@pytest.mark.parametrize("fmt", ["bin2", "q4"])
+def test_dense_city_tree_and_sampled_chains(fmt):
     w = workloads.dense200k()
-    p = R.SplitParams(alpha=0.4, src=w.tx)
+    p = R.SplitParams(alpha=0.4, src=w.tx, node_format=fmt)
     bvh = R.BVH(dev(w.tris), p)
     nodes, perm = gpu_tree(bvh)
     tree = oracle.build_tree(w.tris, oracle_params(p))
@@ -356,3 +358,87 @@ def test_invalid_arguments(micro):
     for nb in (0, 65):
         with pytest.raises(R.RtError):
             R.rt_trace_bounces(bvh.handle, rays, nb, out)
+
+
+# ---------------------------------------------------------------- node formats
+def test_node_formats_give_the_same_hits(city):
+    """Wide and quantized layouts change only which volumes are tested, never
+    a facet test: chains agree bit for bit with the binary layout except where
+    a segment's checker margin is below 1e-4."""
+    rays = dev(city.rays)
+    outs = {}
+    for fmt in ("bin2", "f4", "q4"):
+        bvh = R.BVH(dev(city.tris), R.SplitParams(alpha=0.4, src=city.tx, node_format=fmt))
+        out, pl, nh = bvh.trace_bounces(rays, city.max_bounces)
+        outs[fmt] = (out.cpu().numpy(), pl.cpu().numpy())
+    base, base_pl = outs["bin2"]
+    ref = oracle.trace_bvh(oracle.build_tree(city.tris, oracle.SplitParams(src=city.tx)),
+                           city.rays, nthreads=NTHREADS)
+    clean0 = ref.margin > 1e-4
+    for fmt in ("f4", "q4"):
+        o, pl = outs[fmt]
+        same_chain = np.all(o == base, axis=(0, 2))
+        assert np.all(o[0][clean0] == base[0][clean0]), fmt
+        differ = ~same_chain
+        log(fmt, "chains differing from binary:", int(differ.sum()), "of", city.n_rays)
+        assert differ.mean() < 1e-3
+        assert np.array_equal(pl[same_chain], base_pl[same_chain])
+
+
+_FMAF_C = r"""
+#include <math.h>
+#include <stdint.h>
+void decode(const float* o, const int32_t* e, const uint8_t* q, float* out, int64_t n) {
+  for (int64_t i = 0; i < n; ++i) out[i] = fmaf((float)q[i], ldexpf(1.0f, e[i]), o[i]);
+}
+"""
+
+
+def test_quantized_bounds_are_conservative(city, tmp_path):
+    """Every decoded 8-bit child volume (float32 fmaf decode, as the kernel
+    does it) contains the exact child volume of the binary tree."""
+    import ctypes
+    import subprocess
+    src = tmp_path / "dec.c"
+    src.write_text(_FMAF_C)
+    so = tmp_path / "dec.so"
+    subprocess.run(["gcc", "-O2", "-shared", "-fPIC", str(src), "-o", str(so), "-lm"], check=True)
+    lib = ctypes.CDLL(str(so))
+    for alpha in (1.0, 0.4):
+        p = R.SplitParams(alpha=alpha, src=city.tx, node_format="q4")
+        bvh = R.BVH(dev(city.tris), p)
+        nodes, perm = bvh.download()
+        raw = bvh.trace_nodes().reshape(-1, 64)
+        f = raw.view(np.float32).reshape(-1, 16)
+        u = raw.view(np.uint32).reshape(-1, 16)
+        refs = raw.view(np.int32).reshape(-1, 16)[:, 12:16]
+        # breadth-first internal index of every internal binary node
+        internal = np.nonzero(nodes["left"] >= 0)[0]
+        tidx = np.full(nodes.shape[0], -1)
+        tidx[internal] = np.arange(internal.size)      # internal nodes are numbered in order
+        checked = 0
+        for b in internal[nodes["depth"][internal] % 2 == 0]:
+            w = tidx[b]
+            meta = u[w, 3]
+            e = np.array([(meta & 255) - 127, ((meta >> 8) & 255) - 127, ((meta >> 16) & 255) - 127])
+            mask = meta >> 24
+            kids = []
+            for c in (nodes["left"][b], nodes["left"][b] + 1):
+                if nodes["left"][c] < 0:
+                    kids.append(c)
+                else:
+                    kids += [nodes["left"][c], nodes["left"][c] + 1]
+            assert mask == (1 << len(kids)) - 1
+            qb = raw[w, 16:40].reshape(6, 4)        # qlo x y z, qhi x y z; byte c = child c
+            for c, kid in enumerate(kids):
+                o = f[w, 0:3].astype(np.float32)
+                out = np.zeros(6, np.float32)
+                qs = np.array([qb[0, c], qb[1, c], qb[2, c], qb[3, c], qb[4, c], qb[5, c]], np.uint8)
+                lib.decode(np.concatenate([o, o]).ctypes.data, np.concatenate([e, e]).astype(np.int32).ctypes.data,
+                           qs.ctypes.data, out.ctypes.data, ctypes.c_int64(6))
+                assert np.all(out[0:3] <= nodes["lo"][kid]) and np.all(out[3:6] >= nodes["hi"][kid]), (b, c)
+                ref_expect = ~nodes["first"][kid] if nodes["left"][kid] < 0 else tidx[kid]
+                assert refs[w, c] == ref_expect
+                checked += 1
+        log("q4 alpha", alpha, "child volumes checked:", checked)
+        assert checked > 1000
