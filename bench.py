@@ -42,6 +42,7 @@ def parse():
     ap.add_argument("--workload", default="city24k", choices=["city24k", "microcell", "dense200k"])
     ap.add_argument("--alpha", type=float, default=0.4)
     ap.add_argument("--max-leaf", type=int, default=4)
+    ap.add_argument("--node-format", default="bin2", choices=["bin2", "f4", "q4"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -84,7 +85,8 @@ def main():
     torch.cuda.set_device(0)
     w = {"city24k": workloads.city24k, "microcell": workloads.microcell,
          "dense200k": workloads.dense200k}[args.workload]()
-    params = R.SplitParams(alpha=args.alpha, src=w.tx, max_leaf=args.max_leaf)
+    params = R.SplitParams(alpha=args.alpha, src=w.tx, max_leaf=args.max_leaf,
+                           node_format=args.node_format)
     nb = w.max_bounces
     tris = torch.from_numpy(w.tris).cuda()
     rays = torch.from_numpy(w.rays).cuda()
@@ -165,6 +167,7 @@ def main():
         "config": {
             "workload": w.name, "tris": w.n_tris, "rays": n, "max_bounces": nb,
             "tx": list(w.tx), "alpha": args.alpha, "max_leaf": args.max_leaf,
+            "node_format": args.node_format,
             "step": "rt_rebuild (Eq. 2 BVH for this Tx) + rt_trace_bounces",
         },
         "roofline": {
@@ -188,7 +191,13 @@ def main():
     }
 
     if not args.no_compare:
-        trad = R.SplitParams(alpha=1.0, src=w.tx, max_leaf=args.max_leaf)
+        fmts = {}
+        for fmt in ("bin2", "f4", "q4"):
+            pf = R.SplitParams(alpha=args.alpha, src=w.tx, max_leaf=args.max_leaf, node_format=fmt)
+            _, _, _, f_trace = timed(pf, 10, 2)
+            fmts[fmt] = round(float(np.mean(f_trace)), 4)
+        result["trace_ms_by_node_format"] = fmts
+        trad = R.SplitParams(alpha=1.0, src=w.tx, max_leaf=args.max_leaf, node_format=args.node_format)
         t_tot, _, t_build, t_trace = timed(trad, max(5, args.steps // 3), 1)
         i_tot, _, i_build, i_trace = timed(params, max(5, args.steps // 3), 1)
         result["improved_vs_traditional"] = {

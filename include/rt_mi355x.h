@@ -165,8 +165,13 @@ typedef struct rt_trace_opts {
                           segments never traced are left untouched */
   uint32_t* ray_stats; /* nullable, [n][2]: nodes visited and facets tested per ray,
                           summed over its segments (instrumented kernel, slower) */
-  int32_t block;       /* threads per block, 64..1024 multiple of 64; 0 = default */
-  int32_t grid;        /* persistent blocks; 0 = default (fills every compute unit) */
+  int32_t block;       /* reserved, must be 0 or 64 (one wave per work-group) */
+  int32_t grid;        /* 0: one work-group (one wave) per 64 consecutive rays, scheduled by the
+                          hardware (fastest measured); > 0: this many persistent work-groups
+                          taking batches of rays from an atomic queue */
+  int32_t refill;      /* persistent mode: 0 = a wave takes 64 consecutive rays when all its
+                          chains have ended; 1 = free lanes take new rays at every segment */
+  int32_t reserved;
 } rt_trace_opts;
 
 /* rt_trace_bounces with optional outputs (opts nullable). */

@@ -55,7 +55,8 @@ class rt_bvh_info(ctypes.Structure):
 
 class rt_trace_opts(ctypes.Structure):
     _fields_ = [("seg_rays", ctypes.c_void_p), ("ray_stats", ctypes.c_void_p),
-                ("block", ctypes.c_int32), ("grid", ctypes.c_int32)]
+                ("block", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("refill", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 # numpy view of rt_node_rec (64 bytes)
@@ -184,12 +185,12 @@ def rt_trace_bounces(handle, rays, max_bounces, out, path_len=None, n_hits=None,
 
 
 def rt_trace_ex(handle, rays, max_bounces, out, path_len=None, n_hits=None, seg_rays=None,
-                ray_stats=None, block=0, grid=0, stream=None):
+                ray_stats=None, block=0, grid=0, refill=0, stream=None):
     lib = load()
     o = rt_trace_opts()
     o.seg_rays = None if seg_rays is None else seg_rays.data_ptr()
     o.ray_stats = None if ray_stats is None else ray_stats.data_ptr()
-    o.block, o.grid = block, grid
+    o.block, o.grid, o.refill = block, grid, refill
     _check(lib.rt_trace_ex(handle, _ptr(rays), rays.shape[0], max_bounces, _ptr(out),
                            _ptr(path_len), _ptr(n_hits), ctypes.byref(o), _stream(stream)))
 
@@ -259,7 +260,7 @@ class BVH:
         return out
 
     def trace_bounces(self, rays, max_bounces, out=None, path_len=None, n_hits=None,
-                      seg_rays=None, ray_stats=None, block=0, grid=0, stream=None):
+                      seg_rays=None, ray_stats=None, block=0, grid=0, refill=0, stream=None):
         import torch
         _dev(rays, torch.float32, 8, "rays")
         n = rays.shape[0]
@@ -269,11 +270,11 @@ class BVH:
             path_len = torch.empty(n, dtype=torch.float64, device=rays.device)
         if n_hits is None:
             n_hits = torch.empty(n, dtype=torch.int32, device=rays.device)
-        if seg_rays is None and ray_stats is None and block == 0 and grid == 0:
+        if seg_rays is None and ray_stats is None and block == 0 and grid == 0 and refill == 0:
             rt_trace_bounces(self.handle, rays, max_bounces, out, path_len, n_hits, stream)
         else:
             rt_trace_ex(self.handle, rays, max_bounces, out, path_len, n_hits, seg_rays,
-                        ray_stats, block, grid, stream)
+                        ray_stats, block, grid, refill, stream)
         return out, path_len, n_hits
 
     def close(self):

@@ -32,7 +32,8 @@ bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) %
 
 void free_buffers(Buffers& B) {
   void* ptrs[] = {B.recs_a, B.recs_b, B.perm,  B.nodes,    B.act_a,    B.act_b,  B.cand,
-                  B.big,    B.small,  B.counters, B.root_box, B.tnodes, B.tfacets, B.wnodes};
+                  B.big,    B.small,  B.counters, B.root_box, B.tnodes, B.tfacets, B.wnodes,
+                  B.queue};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   B = Buffers();
@@ -70,6 +71,7 @@ int ensure_buffers(Buffers& B, int64_t n) {
   if (rc == RT_OK) rc = alloc(B.tnodes, nn, bytes);
   if (rc == RT_OK) rc = alloc(B.tfacets, nn, bytes);
   if (rc == RT_OK) rc = alloc(B.wnodes, nn, bytes);
+  if (rc == RT_OK) rc = alloc(B.queue, kQueueSlots, bytes);
   if (rc != RT_OK) {
     free_buffers(B);
     return rc;
@@ -160,8 +162,9 @@ int check_trace_args(const rt_bvh* b, const float* rays, int64_t n, int32_t max_
       return set_error(RT_EINVAL, "trace: seg_rays must be 16-byte aligned");
     if (opts->ray_stats && !aligned(opts->ray_stats, 8))
       return set_error(RT_EINVAL, "trace: ray_stats must be 8-byte aligned");
-    if (opts->block < 0 || opts->block > 1024 || (opts->block % 64) != 0 || opts->grid < 0)
-      return set_error(RT_EINVAL, "trace: block must be a multiple of 64 up to 1024, grid >= 0");
+    if ((opts->block != 0 && opts->block != 64) || opts->grid < 0 ||
+        (opts->refill != 0 && opts->refill != 1))
+      return set_error(RT_EINVAL, "trace: block must be 0 or 64, grid >= 0, refill 0 or 1");
   }
   return RT_OK;
 }
@@ -218,7 +221,8 @@ int rt_rebuild(rt_bvh* b, const float* tris, int64_t n, const rt_split_params* p
 int rt_trace(const rt_bvh* b, const float* rays, int64_t n, rt_hit* out, hipStream_t s) {
   int rc = check_trace_args(b, rays, n, 1, out, nullptr, nullptr, nullptr);
   if (rc != RT_OK || n == 0) return rc;
-  return launch_trace(b->buf, b->info.node_format, rays, n, 1, out, nullptr, nullptr, nullptr, s);
+  return launch_trace(b->buf, b->info.node_format, b->info.depth, rays, n, 1, out, nullptr, nullptr,
+                      nullptr, s);
 }
 
 int rt_trace_bounces(const rt_bvh* b, const float* rays, int64_t n, int32_t max_bounces,
@@ -230,8 +234,8 @@ int rt_trace_ex(const rt_bvh* b, const float* rays, int64_t n, int32_t max_bounc
                 double* path_len, int32_t* n_hits, const rt_trace_opts* opts, hipStream_t s) {
   int rc = check_trace_args(b, rays, n, max_bounces, out, path_len, n_hits, opts);
   if (rc != RT_OK || n == 0) return rc;
-  return launch_trace(b->buf, b->info.node_format, rays, n, max_bounces, out, path_len, n_hits,
-                      opts, s);
+  return launch_trace(b->buf, b->info.node_format, b->info.depth, rays, n, max_bounces, out,
+                      path_len, n_hits, opts, s);
 }
 
 int rt_bvh_info_get(const rt_bvh* b, rt_bvh_info* info) {

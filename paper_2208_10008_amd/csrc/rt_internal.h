@@ -57,6 +57,7 @@ struct alignas(16) TFacet {
   float4 p0, p1, p2;
 };
 constexpr uint32_t kLastFacet = 0x80000000u;
+constexpr int kQueueSlots = 64;  // trace calls that may be in flight on one handle at once
 
 // ---- build-time facet record, kept in reference order: 32 bytes ----
 //   lo = (box lo xyz, caller's id bits), hi = (box hi xyz, 0)
@@ -80,6 +81,7 @@ struct Buffers {
   // traversal data
   TNode* tnodes = nullptr;  // [max(n_internal, 1)]
   FNode4* wnodes = nullptr; // [max(n_internal, 1)] wide nodes (QNode4 records use the first half)
+  unsigned long long* queue = nullptr;  // [kQueueSlots] ray queue heads, one per trace call in flight
   TFacet* tfacets = nullptr;  // [n]
   int64_t cap_n = 0;        // facets the buffers can hold
   int64_t bytes = 0;
@@ -119,7 +121,7 @@ int check_hip(hipError_t e, const char* what);
 int build_tree(Buffers& B, const float* tris, int64_t n, const rt_split_params& p,
                hipStream_t s, rt_bvh_info* info);
 // trace.hip
-int launch_trace(const Buffers& B, int node_format, const float* rays, int64_t n,
+int launch_trace(const Buffers& B, int node_format, int depth, const float* rays, int64_t n,
                  int32_t max_bounces, rt_hit* out, double* path_len, int32_t* n_hits,
                  const rt_trace_opts* opts, hipStream_t s);
 

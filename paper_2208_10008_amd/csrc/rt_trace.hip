@@ -11,13 +11,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 
 #include "rt_internal.h"
 
 namespace rt {
 namespace {
 
-constexpr int kStack = RT_MAX_DEPTH;
 constexpr float kBig = 1e30f;  // stand-in for 1/0 in the slab test
 // Slab far distances grow by 2 * gamma(3) so rounding never rejects a volume
 // the exact ray meets (Ize, "Robust BVH ray traversal", JCGT 2013).
@@ -212,28 +212,21 @@ struct Hit {
   float t, u, v;
 };
 
-// Stack of pending subtrees with the distance at which the ray enters them;
-// an entry behind the current nearest hit is dropped when popped.
-template <int N>
+// Stack of pending subtrees, all of it in LDS: lane column layout (entry i
+// of a lane at col[i * 64]) so the lanes of a wave hit distinct banks.  No
+// private (scratch) memory is used, which would cap the waves in flight.
 struct Stack {
-  int ref[N];
-  float tn[N];
+  int* col;
   int sp = 0;
-  __device__ void push(int r, float t) {
-    ref[sp] = r;
-    tn[sp] = t;
+  __device__ void push(int r) {
+    col[sp * 64] = r;
     ++sp;
   }
-  // next subtree entered no later than tbest; false when none is left
-  __device__ bool pop(float tbest, int& r) {
-    while (sp > 0) {
-      --sp;
-      if (tn[sp] <= tbest) {
-        r = ref[sp];
-        return true;
-      }
-    }
-    return false;
+  __device__ bool pop(int& r) {
+    if (sp == 0) return false;
+    --sp;
+    r = col[sp * 64];
+    return true;
   }
 };
 
@@ -278,8 +271,10 @@ __device__ inline void leaf_test(const TFacet* __restrict__ tf, const RayPre& r,
 
 template <int FMT, bool STATS>
 __device__ Hit closest(const void* __restrict__ nodes, const TFacet* __restrict__ tf,
-                       const RayPre& r, int skip_pos, uint32_t& nvis, uint32_t& ntest) {
-  Stack<FMT == RT_NODE_BIN2 ? kStack : kStack * 3 / 2> st;
+                       const RayPre& r, int skip_pos, int* stack_col, uint32_t& nvis,
+                       uint32_t& ntest) {
+  Stack st;
+  st.col = stack_col;
   int node = 0;
   Hit h;
   h.id = -1;
@@ -297,13 +292,13 @@ __device__ Hit closest(const void* __restrict__ nodes, const TFacet* __restrict_
         const bool h1 = slab(r, nd.b.x, nd.b.y, nd.b.z, nd.b.w, nd.c.z, nd.c.w, r.tmin, h.t, n1);
         if (h0 && h1) {
           const bool first0 = n0 <= n1;
-          st.push(first0 ? nd.d.y : nd.d.x, first0 ? n1 : n0);
+          st.push(first0 ? nd.d.y : nd.d.x);
           node = first0 ? nd.d.x : nd.d.y;
         } else if (h0) {
           node = nd.d.x;
         } else if (h1) {
           node = nd.d.y;
-        } else if (!st.pop(h.t, node)) {
+        } else if (!st.pop(node)) {
           return h;
         }
       } else {
@@ -358,17 +353,17 @@ __device__ Hit closest(const void* __restrict__ nodes, const TFacet* __restrict_
         cswap(key[1], ref[1], key[3], ref[3]);
         cswap(key[1], ref[1], key[2], ref[2]);
         if (key[0] == INFINITY) {
-          if (!st.pop(h.t, node)) return h;
+          if (!st.pop(node)) return h;
         } else {
-          if (key[3] != INFINITY) st.push(ref[3], key[3]);
-          if (key[2] != INFINITY) st.push(ref[2], key[2]);
-          if (key[1] != INFINITY) st.push(ref[1], key[1]);
+          if (key[3] != INFINITY) st.push(ref[3]);
+          if (key[2] != INFINITY) st.push(ref[2]);
+          if (key[1] != INFINITY) st.push(ref[1]);
           node = ref[0];
         }
       }
     }
     leaf_test<STATS>(tf, r, node, skip_pos, h, best_id, ntest);
-    if (!st.pop(h.t, node)) return h;
+    if (!st.pop(node)) return h;
   }
 }
 
@@ -382,9 +377,16 @@ __device__ inline void store_hit(rt_hit* out, int64_t k, const Hit& h) {
   reinterpret_cast<int4*>(out)[k] = w;
 }
 
-constexpr int kBlock = 128;
+constexpr int kBlock = 64;  // one wave per work-group: the LDS stack is per wave
 
-template <int FMT, bool BOUNCE, bool SEG, bool STATS>
+// Persistent wavefronts: each wave keeps one reflection chain per lane and
+// takes rays from a global queue with one atomic per wave (ballot + popcount
+// give each free lane its ray).  By default a wave takes a new batch of 64
+// consecutive rays once all its chains have ended, so a wave traces adjacent
+// launch directions together; with `refill` it tops up free lanes at every
+// segment.  A wave exits once the queue is drained and its lanes are idle; no
+// wave ever waits for another.
+template <int FMT, int SD, bool BOUNCE, bool SEG, bool STATS>
 __global__ __launch_bounds__(kBlock) void k_trace(const void* __restrict__ tn,
                                                   const TFacet* __restrict__ tf,
                                                   const float4* __restrict__ rays, int64_t n,
@@ -392,24 +394,56 @@ __global__ __launch_bounds__(kBlock) void k_trace(const void* __restrict__ tn,
                                                   double* __restrict__ path_len,
                                                   int32_t* __restrict__ n_hits,
                                                   float4* __restrict__ seg,
-                                                  uint32_t* __restrict__ stats) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  const float4 ra = rays[2 * i], rb = rays[2 * i + 1];
-  float ox = ra.x, oy = ra.y, oz = ra.z, dx = rb.x, dy = rb.y, dz = rb.z;
-  const float tmin = ra.w, tmax = rb.w;
-  int skip = -1;
+                                                  uint32_t* __restrict__ stats,
+                                                  unsigned long long* __restrict__ queue,
+                                                  int refill) {
+  __shared__ int s_stack[SD * kBlock];
+  const int lane = threadIdx.x;
+  const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  int64_t i = -1;  // ray of this lane, -1 when free
+  float ox = 0.f, oy = 0.f, oz = 0.f, dx = 0.f, dy = 0.f, dz = 0.f, tmin = 0.f, tmax = 0.f;
+  int skip = -1, b = 0, hits = 0;
   double path = 0.0;
-  int hits = 0;
   uint32_t nvis = 0, ntest = 0;
-  int b = 0;
-  for (; b < max_b; ++b) {
+  bool drained = false;
+  for (;;) {
+    const unsigned long long free_lanes = __ballot(i < 0);
+    if (!drained && (refill ? free_lanes != 0ull : free_lanes == ~0ull)) {
+      const int leader = __ffsll((long long)free_lanes) - 1;
+      unsigned long long base = 0;
+      if (queue == nullptr) {
+        // one batch per work-group: rays [64 b, 64 b + 64) of work-group b
+        base = (unsigned long long)blockIdx.x * kBlock;
+        drained = true;
+      } else {
+        if (lane == leader) base = atomicAdd(queue, (unsigned long long)__popcll(free_lanes));
+        base = __shfl(base, leader);
+      }
+      if (base >= (unsigned long long)n) drained = true;
+      if (i < 0) {
+        const unsigned long long j = base + __popcll(free_lanes & below);
+        if (j < (unsigned long long)n) {
+          i = (int64_t)j;
+          const float4 ra = rays[2 * i], rb = rays[2 * i + 1];
+          ox = ra.x; oy = ra.y; oz = ra.z; tmin = ra.w;
+          dx = rb.x; dy = rb.y; dz = rb.z; tmax = rb.w;
+          skip = -1;
+          b = 0;
+          hits = 0;
+          path = 0.0;
+          nvis = ntest = 0;
+        }
+      }
+    }
+    if (__ballot(i >= 0) == 0ull) break;
+    if (i < 0) continue;
+    // one segment of this lane's chain
     if (SEG) {
       seg[2 * ((int64_t)b * n + i)] = make_float4(ox, oy, oz, tmin);
       seg[2 * ((int64_t)b * n + i) + 1] = make_float4(dx, dy, dz, tmax);
     }
     const RayPre r = prepare(ox, oy, oz, dx, dy, dz, tmin, tmax);
-    Hit h = closest<FMT, STATS>(tn, tf, r, skip, nvis, ntest);
+    Hit h = closest<FMT, STATS>(tn, tf, r, skip, s_stack + lane, nvis, ntest);
     N2 nrm;
     if (h.id >= 0) {
       // the facet is decided; its distance is recomputed accurately
@@ -419,74 +453,127 @@ __global__ __launch_bounds__(kBlock) void k_trace(const void* __restrict__ tn,
       if (isfinite(tp)) h.t = fminf(fmaxf(tp, tmin), tmax);
     }
     store_hit(out, (int64_t)b * n + i, h);
-    if (!BOUNCE || h.id < 0) break;
-    ++hits;
-    path += (double)h.t * sqrt((double)dx * dx + (double)dy * dy + (double)dz * dz);
-    if (b + 1 == max_b) break;
-    // specular reflection about the facet plane, launched from the hit point
-    ox = fmaf(h.t, dx, ox);
-    oy = fmaf(h.t, dy, oy);
-    oz = fmaf(h.t, dz, oz);
-    reflect(nrm, dx, dy, dz);
-    skip = h.pos;
+    bool more = false;
+    if (BOUNCE && h.id >= 0) {
+      ++hits;
+      path += (double)h.t * sqrt((double)dx * dx + (double)dy * dy + (double)dz * dz);
+      if (b + 1 < max_b) {
+        // specular reflection about the facet plane, launched from the hit point
+        ox = fmaf(h.t, dx, ox);
+        oy = fmaf(h.t, dy, oy);
+        oz = fmaf(h.t, dz, oz);
+        reflect(nrm, dx, dy, dz);
+        skip = h.pos;
+        ++b;
+        more = true;
+      }
+    }
+    if (!more) {  // chain finished: segments never launched read as misses
+      if (BOUNCE) {
+        Hit none;
+        none.id = -1;
+        for (int q = b + 1; q < max_b; ++q) store_hit(out, (int64_t)q * n + i, none);
+        if (path_len) path_len[i] = path;
+        if (n_hits) n_hits[i] = hits;
+      }
+      if (STATS) {
+        stats[2 * i] = nvis;
+        stats[2 * i + 1] = ntest;
+      }
+      i = -1;
+    }
   }
-  if (BOUNCE) {
-    Hit none;
-    none.id = -1;
-    for (++b; b < max_b; ++b) store_hit(out, (int64_t)b * n + i, none);
-    if (path_len) path_len[i] = path;
-    if (n_hits) n_hits[i] = hits;
+}
+
+__global__ void k_queue_reset(unsigned long long* q) { *q = 0ull; }
+
+template <int FMT, int SD, bool BOUNCE, bool SEG, bool STATS>
+void launch_sd(const Buffers& B, const float* rays, int64_t n, int max_b, rt_hit* out,
+               double* path_len, int32_t* n_hits, float* seg, uint32_t* stats, int grid,
+               int refill, hipStream_t s) {
+  auto kern = k_trace<FMT, SD, BOUNCE, SEG, STATS>;
+  static int resident = 0;  // persistent work-groups that fit the device at once
+  if (resident == 0) {
+    int dev = 0, cus = 0, per_cu = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, 0);
+    resident = std::max(1, cus * std::max(1, per_cu));
   }
-  if (STATS) {
-    stats[2 * i] = nvis;
-    stats[2 * i + 1] = ntest;
+  const int64_t batches = (n + kBlock - 1) / kBlock;
+  const void* nodes = FMT == RT_NODE_BIN2 ? (const void*)B.tnodes : (const void*)B.wnodes;
+  unsigned long long* q = nullptr;
+  int64_t blocks = batches;  // default: one work-group per batch of 64 rays
+  if (grid > 0) {            // persistent work-groups pulling batches from a queue
+    static std::atomic<unsigned> next_slot{0};
+    q = B.queue + (next_slot.fetch_add(1) % kQueueSlots);
+    blocks = std::min<int64_t>(grid, batches);
+    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(1), 0, s, q);
   }
+  (void)resident;
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kBlock), 0, s, nodes, B.tfacets,
+                     reinterpret_cast<const float4*>(rays), n, max_b, out, path_len, n_hits,
+                     reinterpret_cast<float4*>(seg), stats, q, refill);
+}
+
+// Stack entries a ray can need: one per binary level below the root, or up
+// to three per 4-wide level.  A short LDS stack keeps more waves resident.
+constexpr int kShortStack = 32;
+template <int FMT>
+constexpr int stack_need(int depth) {
+  return FMT == RT_NODE_BIN2 ? depth : 3 * ((depth + 1) / 2);
 }
 
 template <int FMT, bool BOUNCE, bool SEG, bool STATS>
-void launch(const Buffers& B, const float* rays, int64_t n, int max_b, rt_hit* out,
-            double* path_len, int32_t* n_hits, float* seg, uint32_t* stats, hipStream_t s) {
-  const int64_t blocks = (n + kBlock - 1) / kBlock;
-  const void* nodes = FMT == RT_NODE_BIN2 ? (const void*)B.tnodes : (const void*)B.wnodes;
-  hipLaunchKernelGGL((k_trace<FMT, BOUNCE, SEG, STATS>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
-                     nodes, B.tfacets, reinterpret_cast<const float4*>(rays), n, max_b, out,
-                     path_len, n_hits, reinterpret_cast<float4*>(seg), stats);
+void launch(const Buffers& B, int depth, const float* rays, int64_t n, int max_b, rt_hit* out,
+            double* path_len, int32_t* n_hits, float* seg, uint32_t* stats, int grid,
+            int refill, hipStream_t s) {
+  if (stack_need<FMT>(depth) <= kShortStack)
+    launch_sd<FMT, kShortStack, BOUNCE, SEG, STATS>(B, rays, n, max_b, out, path_len, n_hits, seg,
+                                                    stats, grid, refill, s);
+  else
+    launch_sd<FMT, stack_need<FMT>(RT_MAX_DEPTH), BOUNCE, SEG, STATS>(B, rays, n, max_b, out,
+                                                                      path_len, n_hits, seg,
+                                                                      stats, grid, refill, s);
 }
 
 template <int FMT>
-void launch_fmt(const Buffers& B, const float* rays, int64_t n, int max_b, rt_hit* out,
-                double* path_len, int32_t* n_hits, float* seg, uint32_t* stats, hipStream_t s) {
+void launch_fmt(const Buffers& B, int depth, const float* rays, int64_t n, int max_b, rt_hit* out,
+                double* path_len, int32_t* n_hits, float* seg, uint32_t* stats, int grid,
+                int refill, hipStream_t s) {
   const bool bounce = max_b > 1 || path_len || n_hits;
   if (!bounce && !seg && !stats) {
-    launch<FMT, false, false, false>(B, rays, n, 1, out, nullptr, nullptr, nullptr, nullptr, s);
+    launch<FMT, false, false, false>(B, depth, rays, n, 1, out, nullptr, nullptr, nullptr, nullptr, grid, refill, s);
   } else if (!seg && !stats) {
-    launch<FMT, true, false, false>(B, rays, n, max_b, out, path_len, n_hits, nullptr, nullptr, s);
+    launch<FMT, true, false, false>(B, depth, rays, n, max_b, out, path_len, n_hits, nullptr, nullptr, grid, refill, s);
   } else if (seg && !stats) {
-    launch<FMT, true, true, false>(B, rays, n, max_b, out, path_len, n_hits, seg, nullptr, s);
+    launch<FMT, true, true, false>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, nullptr, grid, refill, s);
   } else if (!seg) {
-    launch<FMT, true, false, true>(B, rays, n, max_b, out, path_len, n_hits, nullptr, stats, s);
+    launch<FMT, true, false, true>(B, depth, rays, n, max_b, out, path_len, n_hits, nullptr, stats, grid, refill, s);
   } else {
-    launch<FMT, true, true, true>(B, rays, n, max_b, out, path_len, n_hits, seg, stats, s);
+    launch<FMT, true, true, true>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, stats, grid, refill, s);
   }
 }
 
 }  // namespace
 
-int launch_trace(const Buffers& B, int node_format, const float* rays, int64_t n,
+int launch_trace(const Buffers& B, int node_format, int depth, const float* rays, int64_t n,
                  int32_t max_b, rt_hit* out, double* path_len, int32_t* n_hits,
                  const rt_trace_opts* opts, hipStream_t s) {
   if (n == 0) return RT_OK;
   float* seg = opts ? opts->seg_rays : nullptr;
   uint32_t* stats = opts ? opts->ray_stats : nullptr;
+  const int grid = opts ? opts->grid : 0;
+  const int refill = opts ? opts->refill : 0;
   switch (node_format) {
     case RT_NODE_F4:
-      launch_fmt<RT_NODE_F4>(B, rays, n, max_b, out, path_len, n_hits, seg, stats, s);
+      launch_fmt<RT_NODE_F4>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, stats, grid, refill, s);
       break;
     case RT_NODE_Q4:
-      launch_fmt<RT_NODE_Q4>(B, rays, n, max_b, out, path_len, n_hits, seg, stats, s);
+      launch_fmt<RT_NODE_Q4>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, stats, grid, refill, s);
       break;
     default:
-      launch_fmt<RT_NODE_BIN2>(B, rays, n, max_b, out, path_len, n_hits, seg, stats, s);
+      launch_fmt<RT_NODE_BIN2>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, stats, grid, refill, s);
       break;
   }
   return check_hip(hipGetLastError(), "trace launch");

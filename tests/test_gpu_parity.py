@@ -404,6 +404,8 @@ def test_quantized_bounds_are_conservative(city, tmp_path):
     so = tmp_path / "dec.so"
     subprocess.run(["gcc", "-O2", "-shared", "-fPIC", str(src), "-o", str(so), "-lm"], check=True)
     lib = ctypes.CDLL(str(so))
+    lib.decode.argtypes = [ctypes.c_void_p] * 4 + [ctypes.c_int64]
+    lib.decode.restype = None
     for alpha in (1.0, 0.4):
         p = R.SplitParams(alpha=alpha, src=city.tx, node_format="q4")
         bvh = R.BVH(dev(city.tris), p)
@@ -431,11 +433,11 @@ def test_quantized_bounds_are_conservative(city, tmp_path):
             assert mask == (1 << len(kids)) - 1
             qb = raw[w, 16:40].reshape(6, 4)        # qlo x y z, qhi x y z; byte c = child c
             for c, kid in enumerate(kids):
-                o = f[w, 0:3].astype(np.float32)
+                o6 = np.ascontiguousarray(np.concatenate([f[w, 0:3], f[w, 0:3]]), dtype=np.float32)
+                e6 = np.ascontiguousarray(np.concatenate([e, e]), dtype=np.int32)
+                qs = np.ascontiguousarray(qb[:, c], dtype=np.uint8)
                 out = np.zeros(6, np.float32)
-                qs = np.array([qb[0, c], qb[1, c], qb[2, c], qb[3, c], qb[4, c], qb[5, c]], np.uint8)
-                lib.decode(np.concatenate([o, o]).ctypes.data, np.concatenate([e, e]).astype(np.int32).ctypes.data,
-                           qs.ctypes.data, out.ctypes.data, ctypes.c_int64(6))
+                lib.decode(o6.ctypes.data, e6.ctypes.data, qs.ctypes.data, out.ctypes.data, 6)
                 assert np.all(out[0:3] <= nodes["lo"][kid]) and np.all(out[3:6] >= nodes["hi"][kid]), (b, c)
                 ref_expect = ~nodes["first"][kid] if nodes["left"][kid] < 0 else tidx[kid]
                 assert refs[w, c] == ref_expect
