@@ -13,7 +13,8 @@
  *     "host".  The caller owns them; the library never frees them.
  *   - Every call that takes a stream enqueues its device work on that stream
  *     (hipStream_t, 0 = the null stream).  rt_build and rt_rebuild also wait
- *     for it: they read one counter per tree level back to the host.
+ *     for it: the whole build runs on the device and ends by writing one
+ *     record (node count, depth, errors) that the host reads.
  *   - Functions return RT_OK (0) or a negative RT_E* code; the text of the
  *     last error on the calling thread is given by rt_last_error().  No C++
  *     exception crosses this interface.
@@ -98,18 +99,20 @@ typedef struct rt_bvh_info {
   int64_t n_internal;
   int64_t n_leaves;
   int32_t depth;       /* deepest leaf, root = 0 */
-  int32_t n_levels;    /* build passes run (one per tree level) */
+  int32_t n_levels;    /* tree levels (depth + 1) */
   int64_t device_bytes; /* device memory held by the handle */
   int64_t trace_bytes;  /* of which: traversal nodes + leaf-ordered facets */
   float root_lo[3], root_hi[3];
   int32_t node_format;  /* RT_NODE_* of the traversal nodes */
-  int32_t n_trace_nodes; /* traversal node records (wide formats: one per even-depth
-                            internal node, stored at that node's breadth-first internal
-                            index, so some records are unused) */
+  int32_t n_trace_nodes; /* traversal node records; record (left - 1) / 2 belongs to the
+                            internal node whose children are left, left + 1 (wide formats:
+                            only even-depth internal nodes have one, so some records are
+                            unused) */
 } rt_bvh_info;
 
-/* One node of the binary tree in build order (breadth-first; the two
- * children of a node are adjacent: right = left + 1). */
+/* One node of the binary tree.  Node 0 is the root; the two children of a
+ * node are adjacent (right = left + 1); the order of the pairs follows the
+ * build's schedule and is not fixed. */
 typedef struct rt_node_rec {
   float lo[3], hi[3]; /* node volume: union of its facets' boxes (Eq. (3) bounds) */
   int32_t left;       /* index of the left child, -1 for a leaf */
@@ -126,10 +129,11 @@ typedef struct rt_node_rec {
 
 /* ---- build (Sec. II-C) ---------------------------------------------------
  * Builds the tree of n facets on the GPU: per-facet boxes and centroids,
- * root volume, then one pass per tree level that bins each node's centroids,
- * evaluates Eq. (2) on every bin boundary, and partitions the node's facets
- * (stable: each side keeps the input order).  tris may be freed once the call
- * returns.  *out receives a new handle.  Waits for stream s.
+ * root volume, then for every internal node: bin its centroids, evaluate
+ * Eq. (2) on every bin boundary, and partition the node's facets (stable:
+ * each side keeps the input order).  The tree does not depend on the order in
+ * which the device processes nodes.  tris may be freed once the call returns.
+ * *out receives a new handle.  Waits for stream s.
  * Errors: RT_EINVAL (null, n < 1, n >= 2^30, non-finite vertex, bad params),
  * RT_ENOMEM, RT_EHIP. */
 int rt_build(const float* tris, int64_t n, const rt_split_params* p, rt_bvh** out,

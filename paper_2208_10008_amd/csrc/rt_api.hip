@@ -31,9 +31,9 @@ namespace {
 bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
 void free_buffers(Buffers& B) {
-  void* ptrs[] = {B.recs_a, B.recs_b, B.perm,  B.nodes,    B.act_a,    B.act_b,  B.cand,
-                  B.big,    B.small,  B.counters, B.root_box, B.tnodes, B.tfacets, B.wnodes,
-                  B.queue};
+  void* ptrs[] = {B.recs_a, B.recs_b,   B.perm,     B.nodes,  B.mlist,   B.slist,
+                  B.aitems, B.accnt,    B.abins,    B.counters, B.root_box, B.tnodes,
+                  B.tfacets, B.wnodes,  B.queue};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   B = Buffers();
@@ -61,12 +61,13 @@ int ensure_buffers(Buffers& B, int64_t n) {
   if (rc == RT_OK) rc = alloc(B.recs_b, nn, bytes);
   if (rc == RT_OK) rc = alloc(B.perm, nn, bytes);
   if (rc == RT_OK) rc = alloc(B.nodes, 2 * nn, bytes);
-  if (rc == RT_OK) rc = alloc(B.act_a, nn, bytes);
-  if (rc == RT_OK) rc = alloc(B.act_b, nn, bytes);
-  if (rc == RT_OK) rc = alloc(B.cand, 2 * nn, bytes);
-  if (rc == RT_OK) rc = alloc(B.big, nn, bytes);
-  if (rc == RT_OK) rc = alloc(B.small, nn, bytes);
-  if (rc == RT_OK) rc = alloc(B.counters, 32, bytes);
+  const int64_t icap = item_capacity(n), acap = anode_capacity(n);
+  if (rc == RT_OK) rc = alloc(B.mlist, 2 * nn, bytes);
+  if (rc == RT_OK) rc = alloc(B.slist, nn, bytes);
+  if (rc == RT_OK) rc = alloc(B.aitems, 2 * (size_t)icap, bytes);
+  if (rc == RT_OK) rc = alloc(B.accnt, 2 * (size_t)icap * 3 * RT_MAX_BINS, bytes);
+  if (rc == RT_OK) rc = alloc(B.abins, 2 * (size_t)acap * bins_bytes(RT_MAX_BINS, true), bytes);
+  if (rc == RT_OK) rc = alloc(B.counters, kStateWords, bytes);
   if (rc == RT_OK) rc = alloc(B.root_box, 12, bytes);
   if (rc == RT_OK) rc = alloc(B.tnodes, nn, bytes);
   if (rc == RT_OK) rc = alloc(B.tfacets, nn, bytes);
@@ -77,6 +78,8 @@ int ensure_buffers(Buffers& B, int64_t n) {
     return rc;
   }
   B.cap_n = n;
+  B.item_cap = icap;
+  B.anode_cap = acap;
   B.bytes = bytes;
   return RT_OK;
 }
@@ -133,14 +136,6 @@ int do_build(rt_bvh* b, const float* tris, int64_t n, const rt_split_params* p, 
   info.device_bytes = b->buf.bytes;
   b->info = info;
   b->params = *p;
-  // root bounds for the info struct
-  BNode root;
-  rc = check_hip(hipMemcpy(&root, b->buf.nodes, sizeof(BNode), hipMemcpyDeviceToHost), "hipMemcpy");
-  if (rc != RT_OK) return rc;
-  for (int a = 0; a < 3; ++a) {
-    b->info.root_lo[a] = root.lo[a];
-    b->info.root_hi[a] = root.hi[a];
-  }
   return RT_OK;
 }
 

@@ -1,14 +1,20 @@
 // GPU tree build (Sec. II-C) with the Eq. (2) split cost (Sec. II-B).
 //
-// Flow, one kernel pass per tree level:
-//   k_prep     per facet: box, centroid (float64), reference list, root bounds
-//   k_root     root node from the reduced bounds
-//   k_level    one work-group per node of the level: bin the centroids on the
-//              three axes, evaluate Eq. (2) on every bin boundary, pick the
-//              cheapest (ties: lower axis, then lower boundary), partition the
-//              facet references stably into the two children
-//   k_compact  list the children that still hold more than max_leaf facets
-//   k_emit     traversal nodes and leaf-ordered facets
+// Every internal node is split the same way: bin its facets' centroids on the
+// three axes, evaluate Eq. (2) on every bin boundary, take the cheapest one
+// (ties: lower axis, then lower boundary) and partition the facet references
+// stably into the two children.  Three schedules apply that step, by node size:
+//   big nodes     (> kBigNode facets) one pass per tree level; each node is cut
+//                 into chunks of kChunk facets that separate work-groups bin
+//                 (k_a_bin) and then partition (k_a_split)
+//   medium nodes  (> kRegNode facets) one wave per node, one pass per level (k_m)
+//   subtrees      one wave finishes a whole subtree (k_s); at or below kRegNode
+//                 facets the facet records stay in the wave's registers, one
+//                 per lane, and the wave walks the subtree depth-first
+// A fixed number of passes is queued for each schedule; whatever is left over
+// moves on to the next schedule, which handles nodes of any size.  Node ids
+// come from an atomic counter (root 0, siblings adjacent), the lists between
+// passes live on the device, and the host reads a single record at the end.
 //
 // Every decision (bin index, Eq. (2) cost, argmin) is made in float64 with a
 // fixed operation order and no contraction into fused multiply-adds, so the
@@ -21,6 +27,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
+#include <string>
 #include <vector>
 
 #include "rt_internal.h"
@@ -28,14 +36,9 @@
 namespace rt {
 namespace {
 
-constexpr int kCompactThreads = 1024;
-
-// counters[] slots
-enum { C_NONFINITE = 0, C_NEXT = 1, C_BIG = 2, C_SMALL = 3 };
-
 struct BuildConst {
   double alpha, t_isect, t_trav, src[3];
-  double inv_l2;  // 1 / squared root diagonal (0 if the root is a point)
+  double inv_l2;
   int32_t max_leaf, nbins, d_mode, d_norm, max_depth, depth_limit;
 };
 
@@ -88,56 +91,16 @@ __device__ __host__ inline int halvings(int k, int max_leaf) {
   return l;
 }
 
-// centroid of a facet = centre of its box, in float64 (exact for the sum of
-// two float32 values in practice, and the same expression everywhere)
+// centroid of a facet = centre of its box, in float64
 __device__ inline double centroid(float lo, float hi) { return ((double)lo + (double)hi) * 0.5; }
 
+// bin of a centroid; the clamp at 0 only matters for values outside the node
 __device__ inline int bin_of(double c, double lo, double scale, int nb) {
-  return min(nb - 1, (int)((c - lo) * scale));
+  return max(0, min(nb - 1, (int)((c - lo) * scale)));
 }
 
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_prep(const float* __restrict__ tris, int n,
-                                              FacetRec* __restrict__ recs, int32_t* __restrict__ perm,
-                                              int32_t* __restrict__ counters,
-                                              long long* __restrict__ root);
-
-__global__ void k_root_init(long long* root) {
-  int t = threadIdx.x;
-  if (t < 3) {
-    root[t] = f2o(INFINITY);
-    root[3 + t] = f2o(-INFINITY);
-    root[6 + t] = d2o(INFINITY);
-    root[9 + t] = d2o(-INFINITY);
-  }
-}
-
-__global__ void k_root(const long long* root, int n, BNode* nodes, double* inv_l2) {
-  BNode r;
-  for (int a = 0; a < 3; ++a) {
-    r.lo[a] = o2f((int32_t)root[a]);
-    r.hi[a] = o2f((int32_t)root[3 + a]);
-    r.cblo[a] = o2d(root[6 + a]);
-    r.cbhi[a] = o2d(root[9 + a]);
-  }
-  r.left = -1;
-  r.first = 0;
-  r.count = n;
-  r.depth = 0;
-  r.axis = r.plane = -1;
-  r.flags = 0;
-  r.tidx = 0;
-  r.cost = 0.0;
-  nodes[0] = r;
-  double ex = (double)r.hi[0] - (double)r.lo[0];
-  double ey = (double)r.hi[1] - (double)r.lo[1];
-  double ez = (double)r.hi[2] - (double)r.lo[2];
-  double l2 = (ex * ex + ey * ey) + ez * ez;
-  *inv_l2 = l2 > 0.0 ? 1.0 / l2 : 0.0;
-}
-
-// ---------------------------------------------------------------------------
-// wave-wide reductions and scans (64 lanes)
+// wave-wide helpers (64 lanes)
 __device__ inline int lane_id() { return threadIdx.x & 63; }
 __device__ inline float wmin(float v) {
   for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
@@ -155,13 +118,13 @@ __device__ inline double wmax(double v) {
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
   return v;
 }
-__device__ inline int wscan_incl(int v) {
-  const int lane = lane_id();
-  for (int o = 1; o < 64; o <<= 1) {
-    int t = __shfl_up(v, o);
-    if (lane >= o) v += t;
-  }
+__device__ inline int wsum(int v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   return v;
+}
+__device__ inline unsigned long long lanes_below() {
+  const int lane = lane_id();
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 // lanes of one wave see each other's LDS writes after this
 __device__ inline void wave_sync() {
@@ -169,31 +132,452 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
+// the wave's own global stores are visible to its later loads after this
+__device__ inline void wave_global_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+__device__ inline int bcast(int v) { return __shfl(v, 0); }
 
-template <int G>
-__device__ inline void group_sync() {
-  if constexpr (G == 64) {
-    wave_sync();
-  } else {
-    __syncthreads();
+// ---------------------------------------------------------------------------
+// Bins of one node: per axis a and bin b (slot a B + b) a facet count, the
+// union of the facets' boxes (ordered ints: lo xyz, hi xyz) and, where the
+// children's centroid bounds come from the bins, the centroid bounds
+// (ordered int64: lo xyz, hi xyz).
+struct Bins {
+  int* cnt;
+  int* box;
+  long long* cb;  // null when not kept
+};
+__device__ inline Bins bins_at(char* base, int B, bool with_cb) {
+  Bins b;
+  b.cnt = (int*)base;
+  b.box = (int*)(base + align8(sizeof(int) * 3 * B));
+  b.cb = with_cb ? (long long*)(base + align8(sizeof(int) * 3 * B) + align8(sizeof(int) * 3 * B * 6))
+                 : nullptr;
+  return b;
+}
+__device__ inline void bins_clear(const Bins& S, int B, int t, int nt) {
+  for (int c = t; c < 3 * B; c += nt) {
+    S.cnt[c] = 0;
+    for (int q = 0; q < 3; ++q) {
+      S.box[6 * c + q] = f2o(INFINITY);
+      S.box[6 * c + 3 + q] = f2o(-INFINITY);
+      if (S.cb) {
+        S.cb[6 * c + q] = d2o(INFINITY);
+        S.cb[6 * c + 3 + q] = d2o(-INFINITY);
+      }
+    }
   }
 }
 
-// Level bookkeeping kept on the device, so several levels can be queued
-// without waiting for the host.
-struct LevelState {
-  int32_t active;      // nodes of the current level
-  int32_t n_big;       // of which above kBigNode facets
-  int32_t n_small;
-  int32_t child_base;  // first node id of the current level's children
-  int32_t n_internal;  // internal nodes before the current level
-  int32_t levels;      // levels with at least one node so far
-  int32_t pad[2];
+// Node constants of one split.
+struct NodeSetup {
+  double alpha;
+  int flags;       // 1 forced halving, 4 alpha taken as 1 (2 added when no plane separates)
+  bool forced;
+  bool axis_ok[3]; // nonzero centroid extent
+  double scale[3]; // B / extent
 };
+__device__ inline NodeSetup node_setup(const BuildConst& C, int depth, int k, const double cblo[3],
+                                       const double cbhi[3]) {
+  NodeSetup u;
+  u.alpha = C.alpha;
+  u.flags = 0;
+  u.forced = depth + halvings(k, C.max_leaf) >= C.depth_limit;
+  if (u.forced) {
+    u.flags = 1;
+  } else if (depth >= C.max_depth) {
+    u.alpha = 1.0;
+    u.flags = 4;
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double ext = cbhi[a] - cblo[a];
+    u.axis_ok[a] = ext > 0.0;
+    u.scale[a] = ext > 0.0 ? (double)C.nbins / ext : 0.0;
+  }
+  return u;
+}
+
+// Eq. (2) on every bin boundary of one node, any bin count: each lane holds
+// one bin; segmented prefix and suffix scans (lane shuffles) give the two
+// sides of every boundary.
+__device__ void wave_eval_any(const int* cnt, const int* box, const BuildConst& C, const NodeSetup& u,
+                          const double clo[3], const double chi[3], int k, int& axis_out,
+                          int& plane_out, double& best_out) {
+  const int B = C.nbins;
+  const int lane = lane_id();
+  double bc = INFINITY;
+  int bi = 1 << 30;
+  const bool packed = 3 * B <= 64;
+  const int passes = packed ? 1 : 3;
+  for (int pass = 0; pass < passes; ++pass) {
+    const int a = packed ? lane / B : pass;
+    const int b = packed ? lane - a * B : lane;
+    const bool valid = packed ? lane < 3 * B : lane < B;
+    int c = 0;
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    if (valid) {
+      const int slot = a * B + b;
+      c = cnt[slot];
+      if (c > 0) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          lo[q] = o2f(box[6 * slot + q]);
+          hi[q] = o2f(box[6 * slot + 3 + q]);
+        }
+      }
+    }
+    int pc = c, sc = c;
+    float pl[3], ph[3], sl[3], sh[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      pl[q] = sl[q] = lo[q];
+      ph[q] = sh[q] = hi[q];
+    }
+    for (int o = 1; o < B; o <<= 1) {
+      const int tc = __shfl_up(pc, o);
+      const int uc = __shfl_down(sc, o);
+      float tl[3], th[3], ul[3], uh[3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        tl[q] = __shfl_up(pl[q], o);
+        th[q] = __shfl_up(ph[q], o);
+        ul[q] = __shfl_down(sl[q], o);
+        uh[q] = __shfl_down(sh[q], o);
+      }
+      if (b >= o) {
+        pc += tc;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          pl[q] = fminf(pl[q], tl[q]);
+          ph[q] = fmaxf(ph[q], th[q]);
+        }
+      }
+      if (b + o < B) {
+        sc += uc;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          sl[q] = fminf(sl[q], ul[q]);
+          sh[q] = fmaxf(sh[q], uh[q]);
+        }
+      }
+    }
+    // boundary after bin b: bins [0, b] on the left, the suffix from bin b + 1 on the right
+    const int rc = __shfl_down(sc, 1);
+    float rl[3], rh[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      rl[q] = __shfl_down(sl[q], 1);
+      rh[q] = __shfl_down(sh[q], 1);
+    }
+    const bool aok = a == 0 ? u.axis_ok[0] : (a == 1 ? u.axis_ok[1] : u.axis_ok[2]);
+    if (valid && b <= B - 2 && aok && pc > 0 && rc > 0) {
+      const double alo[3] = {pl[0], pl[1], pl[2]}, ahi[3] = {ph[0], ph[1], ph[2]};
+      const double blo[3] = {rl[0], rl[1], rl[2]}, bhi[3] = {rh[0], rh[1], rh[2]};
+      const double cost = eq2_cost(C, u.alpha, alo, ahi, pc, blo, bhi, rc, clo, chi, k);
+      if (cost < bc) {  // passes visit increasing indices
+        bc = cost;
+        bi = a * (B - 1) + b;
+      }
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const double oc = __shfl_xor(bc, o);
+    const int oi = __shfl_xor(bi, o);
+    if (oc < bc || (oc == bc && oi < bi)) {
+      bc = oc;
+      bi = oi;
+    }
+  }
+  const bool ok = bc < INFINITY;
+  axis_out = ok ? bi / (B - 1) : -1;
+  plane_out = ok ? bi % (B - 1) + 1 : -1;
+  best_out = bc;
+}
+
+// Cross-lane moves inside 16-lane rows (DPP).  A lane whose source lies
+// outside its row keeps `identity`.
+constexpr int kRowShl = 0x100, kRowShr = 0x110;
+template <int CTRL>
+__device__ inline int dpp_i(int identity, int v) {
+  return __builtin_amdgcn_update_dpp(identity, v, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
+__device__ inline float dpp_f(float identity, float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(identity), __float_as_int(v), CTRL,
+                                                    0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ inline double dpp_d(double identity, double v) {
+  const long long iv = __double_as_longlong(v), ii = __double_as_longlong(identity);
+  const int lo = __builtin_amdgcn_update_dpp((int)ii, (int)iv, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(ii >> 32), (int)(iv >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// one step of the inclusive row scans: prefix from lower lanes, suffix from higher
+template <int K>
+__device__ inline void scan_step(int& pc, float pl[3], float ph[3], int& sc, float sl[3], float sh[3]) {
+  pc += dpp_i<kRowShr | K>(0, pc);
+  sc += dpp_i<kRowShl | K>(0, sc);
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    pl[q] = fminf(pl[q], dpp_f<kRowShr | K>(INFINITY, pl[q]));
+    ph[q] = fmaxf(ph[q], dpp_f<kRowShr | K>(-INFINITY, ph[q]));
+    sl[q] = fminf(sl[q], dpp_f<kRowShl | K>(INFINITY, sl[q]));
+    sh[q] = fmaxf(sh[q], dpp_f<kRowShl | K>(-INFINITY, sh[q]));
+  }
+}
+template <int K>
+__device__ inline void argmin_step(double& bc, int& bi) {
+  const double oc = dpp_d<kRowShr | K>(INFINITY, bc);
+  const int oi = dpp_i<kRowShr | K>(1 << 30, bi);
+  if (oc < bc || (oc == bc && oi < bi)) {
+    bc = oc;
+    bi = oi;
+  }
+}
+
+// Eq. (2) on every bin boundary with 16 bins: lane 16 a + b holds bin b of
+// axis a (count c and box lo/hi; lanes 48..63 empty).  Row scans give each
+// boundary's two sides; the first strict minimum in (axis, boundary) order
+// wins, axis -1 when no boundary leaves facets on both sides.
+__device__ void eval16(int c, const float lo[3], const float hi[3], const BuildConst& C,
+                       const NodeSetup& u, const double clo[3], const double chi[3], int k,
+                       int& axis_out, int& plane_out, double& best_out) {
+  const int lane = lane_id();
+  const int a = lane >> 4, b = lane & 15;
+  int pc = c, sc = c;
+  float pl[3], ph[3], sl[3], sh[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    pl[q] = sl[q] = lo[q];
+    ph[q] = sh[q] = hi[q];
+  }
+  scan_step<1>(pc, pl, ph, sc, sl, sh);
+  scan_step<2>(pc, pl, ph, sc, sl, sh);
+  scan_step<4>(pc, pl, ph, sc, sl, sh);
+  scan_step<8>(pc, pl, ph, sc, sl, sh);
+  // boundary after bin b: prefix [0, b] on the left, suffix from b + 1 on the right
+  const int rc = dpp_i<kRowShl | 1>(0, sc);
+  float rl[3], rh[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    rl[q] = dpp_f<kRowShl | 1>(INFINITY, sl[q]);
+    rh[q] = dpp_f<kRowShl | 1>(-INFINITY, sh[q]);
+  }
+  double bc = INFINITY;
+  int bi = 1 << 30;
+  const bool aok = a == 0 ? u.axis_ok[0] : (a == 1 ? u.axis_ok[1] : (a == 2 && u.axis_ok[2]));
+  if (aok && b <= 14 && pc > 0 && rc > 0) {
+    const double alo[3] = {pl[0], pl[1], pl[2]}, ahi[3] = {ph[0], ph[1], ph[2]};
+    const double blo[3] = {rl[0], rl[1], rl[2]}, bhi[3] = {rh[0], rh[1], rh[2]};
+    bc = eq2_cost(C, u.alpha, alo, ahi, pc, blo, bhi, rc, clo, chi, k);
+    bi = a * 15 + b;
+  }
+  argmin_step<1>(bc, bi);
+  argmin_step<2>(bc, bi);
+  argmin_step<4>(bc, bi);
+  argmin_step<8>(bc, bi);
+  // the last lane of each row holds the row's minimum
+  double best = INFINITY;
+  int bidx = 1 << 30;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const long long bits = __double_as_longlong(bc);
+    const int lo32 = __builtin_amdgcn_readlane((int)bits, 16 * r + 15);
+    const int hi32 = __builtin_amdgcn_readlane((int)(bits >> 32), 16 * r + 15);
+    const double rcst = __longlong_as_double(((long long)hi32 << 32) | (unsigned)lo32);
+    const int ridx = __builtin_amdgcn_readlane(bi, 16 * r + 15);
+    if (rcst < best || (rcst == best && ridx < bidx)) {
+      best = rcst;
+      bidx = ridx;
+    }
+  }
+  const bool ok = best < INFINITY;
+  axis_out = ok ? bidx / 15 : -1;
+  plane_out = ok ? bidx % 15 + 1 : -1;
+  best_out = best;
+}
+
+// Eq. (2) on every bin boundary of one node's bins (LDS); all 64 lanes of the
+// wave call it and get the same answer.
+__device__ void wave_eval(const int* cnt, const int* box, const BuildConst& C, const NodeSetup& u,
+                          const double clo[3], const double chi[3], int k, int& axis_out,
+                          int& plane_out, double& best_out) {
+  if (C.nbins != 16) {
+    wave_eval_any(cnt, box, C, u, clo, chi, k, axis_out, plane_out, best_out);
+    return;
+  }
+  const int lane = lane_id();
+  int c = 0;
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  if (lane < 48) {
+    c = cnt[lane];
+    if (c > 0) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        lo[q] = o2f(box[6 * lane + q]);
+        hi[q] = o2f(box[6 * lane + 3 + q]);
+      }
+    }
+  }
+  eval16(c, lo, hi, C, u, clo, chi, k, axis_out, plane_out, best_out);
+}
+
+// Union of the bins [b0, b1) of one axis: child volume and centroid bounds.
+__device__ inline void bins_union(const Bins& S, int B, int axis, int b0, int b1, float lo[3],
+                                  float hi[3], double clo[3], double chi[3]) {
+  int bl[6] = {f2o(INFINITY), f2o(INFINITY), f2o(INFINITY), f2o(-INFINITY), f2o(-INFINITY), f2o(-INFINITY)};
+  long long cl[6] = {d2o(INFINITY), d2o(INFINITY), d2o(INFINITY), d2o(-INFINITY), d2o(-INFINITY), d2o(-INFINITY)};
+  for (int b = b0; b < b1; ++b) {
+    const int slot = axis * B + b;
+    if (S.cnt[slot] == 0) continue;
+    for (int q = 0; q < 3; ++q) {
+      bl[q] = min(bl[q], S.box[6 * slot + q]);
+      bl[3 + q] = max(bl[3 + q], S.box[6 * slot + 3 + q]);
+      cl[q] = min(cl[q], S.cb[6 * slot + q]);
+      cl[3 + q] = max(cl[3 + q], S.cb[6 * slot + 3 + q]);
+    }
+  }
+  for (int q = 0; q < 3; ++q) {
+    lo[q] = o2f(bl[q]);
+    hi[q] = o2f(bl[3 + q]);
+    clo[q] = o2d(cl[q]);
+    chi[q] = o2d(cl[3 + q]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Where a new internal node goes next.
+enum { TO_A = 0, TO_M = 1, TO_S = 2 };
+__device__ inline int classify(const BuildConst& C, int k, int depth, const double cblo[3],
+                               const double cbhi[3], bool a_ok, bool m_ok) {
+  const bool forced = depth + halvings(k, C.max_leaf) >= C.depth_limit;
+  const bool ext = cbhi[0] > cblo[0] || cbhi[1] > cblo[1] || cbhi[2] > cblo[2];
+  if (a_ok && k > kBigNode && !forced && ext) return TO_A;
+  if (m_ok && k > kRegNode) return TO_M;
+  return TO_S;
+}
+
+struct Ctx {
+  BNode* nodes;
+  FacetRec* recs[2];  // by node depth parity
+  int32_t* perm;
+  BuildState* st;
+  int32_t* mlist[2];
+  int32_t* slist;
+  AItem* items[2];
+  int32_t* ccnt[2];
+  char* abins[2];
+  size_t abin_stride;
+  int n, node_cap, item_cap, anode_cap;
+  int la, lm;  // queued big-node levels and medium-node passes
+  BuildConst C;
+};
+
+__device__ inline void set_err(BuildState* st, int bit) { atomicOr(&st->error, bit); }
+
+// Adds a big node to level `lvl`: its bin slot and its chunks.  Returns the
+// slot (the caller clears the bins), -1 on overflow.
+__device__ int push_big(const Ctx& X, int lvl, int id, int k) {
+  const int slot = atomicAdd(&X.st->a_nodes[lvl], 1);
+  const int nit = (k + kChunk - 1) / kChunk;
+  const int base = atomicAdd(&X.st->a_items[lvl], nit);
+  if (slot >= X.anode_cap || base + nit > X.item_cap) {
+    set_err(X.st, 1);
+    return -1;
+  }
+  AItem* it = X.items[lvl & 1];
+  for (int j = 0; j < nit; ++j) {
+    AItem a;
+    a.node = id;
+    a.slot = slot;
+    a.begin = j * kChunk;
+    a.end = min(k, (j + 1) * kChunk);
+    a.first_item = base;
+    a.pad[0] = a.pad[1] = a.pad[2] = 0;
+    it[base + j] = a;
+  }
+  return slot;
+}
+__device__ inline void push_m(const Ctx& X, int pass, int id) {
+  const int pos = atomicAdd(&X.st->m_count[pass], 1);
+  if (pos >= X.n) {
+    set_err(X.st, 2);
+    return;
+  }
+  X.mlist[pass & 1][pos] = id;
+}
+__device__ inline void push_s(const Ctx& X, int id) {
+  const int pos = atomicAdd(&X.st->s_count, 1);
+  if (pos >= X.n) {
+    set_err(X.st, 4);
+    return;
+  }
+  X.slist[pos] = id;
+}
+
+// Writes the two children c0, c0 + 1 of `id` (ids reserved by the caller) and
+// the parent's split.  Returns c0, -1 on overflow.
+__device__ int make_children(const Ctx& X, int c0, int id, const BNode& nd, int axis, int plane,
+                             int flags, double cost, int nleft, const float lo[2][3],
+                             const float hi[2][3], const double clo[2][3], const double chi[2][3]) {
+  if (c0 + 2 > X.node_cap) {
+    set_err(X.st, 8);
+    return -1;
+  }
+  for (int side = 0; side < 2; ++side) {
+    BNode ch;
+    for (int q = 0; q < 3; ++q) {
+      ch.lo[q] = lo[side][q];
+      ch.hi[q] = hi[side][q];
+      ch.cblo[q] = clo[side][q];
+      ch.cbhi[q] = chi[side][q];
+    }
+    ch.left = -1;
+    ch.first = side == 0 ? nd.first : nd.first + nleft;
+    ch.count = side == 0 ? nleft : nd.count - nleft;
+    ch.depth = nd.depth + 1;
+    ch.axis = ch.plane = -1;
+    ch.flags = 0;
+    ch.tidx = -1;
+    ch.cost = 0.0;
+    X.nodes[c0 + side] = ch;
+  }
+  BNode* p = &X.nodes[id];
+  p->left = c0;
+  p->axis = axis;
+  p->plane = plane;
+  p->flags = flags;
+  p->cost = cost;
+  atomicMax(&X.st->depth, nd.depth + 1);
+  return c0;
+}
+
+// ---------------------------------------------------------------------------
+__global__ void k_init(int32_t* words, long long* root, int n) {
+  for (int i = threadIdx.x; i < kStateWords; i += blockDim.x) words[i] = 0;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    reinterpret_cast<BuildState*>(words)->total = 1;
+    reinterpret_cast<BuildState*>(words)->n = n;
+  }
+  if (threadIdx.x < 3) {
+    const int t = threadIdx.x;
+    root[t] = f2o(INFINITY);
+    root[3 + t] = f2o(-INFINITY);
+    root[6 + t] = d2o(INFINITY);
+    root[9 + t] = d2o(-INFINITY);
+  }
+}
 
 __global__ __launch_bounds__(256) void k_prep(const float* __restrict__ tris, int n,
                                               FacetRec* __restrict__ recs, int32_t* __restrict__ perm,
-                                              int32_t* __restrict__ counters,
+                                              BuildState* __restrict__ st,
                                               long long* __restrict__ root) {
   __shared__ int s_box[6];
   __shared__ long long s_cb[6];
@@ -211,7 +595,7 @@ __global__ __launch_bounds__(256) void k_prep(const float* __restrict__ tris, in
     for (int k = 0; k < 9; ++k) x[k] = v[k];
     bool finite = true;
     for (int k = 0; k < 9; ++k) finite = finite && isfinite(x[k]);
-    if (!finite) atomicOr(&counters[C_NONFINITE], 1);
+    if (!finite) atomicOr(&st->nonfinite, 1);
     for (int a = 0; a < 3; ++a) {
       lo[a] = fminf(fminf(x[a], x[3 + a]), x[6 + a]);
       hi[a] = fmaxf(fmaxf(x[a], x[3 + a]), x[6 + a]);
@@ -242,133 +626,266 @@ __global__ __launch_bounds__(256) void k_prep(const float* __restrict__ tris, in
   }
 }
 
-// nodes above kBigNode facets: one work-group of kBigThreads threads each
-constexpr int kBigNode = 256;
-
-// LDS of one node group, carved from dynamic shared memory; sized by nbins.
-struct NodeLds {
-  int ncopy;         // private bin copies (one per wave, or shared round-robin)
-  int* cnt;          // [ncopy][3][B]
-  int* box;          // [ncopy][3][B][6] ordered ints: lo xyz, hi xyz
-  long long* cb;     // [ncopy][3][B][6] ordered int64: centroid lo xyz, hi xyz
-  double* cost;      // [3 (B - 1)]
-  int* wtot;         // [16] per-wave totals of a group scan
-  int* wtot2;        // [kPartE][16] per-slice per-wave totals of the partition
-  int* pick;         // [2]
-  double* best;      // [1]
-  int* cbox;         // [2][6]   child boxes (position splits)
-  long long* ccb;    // [2][6]
-};
-
-__host__ __device__ inline size_t align8(size_t x) { return (x + 7) & ~size_t(7); }
-__host__ __device__ inline size_t bin_copy_bytes(int B) {
-  return align8(sizeof(int) * 3 * B) + align8(sizeof(int) * 3 * B * 6) +
-         align8(sizeof(long long) * 3 * B * 6);
-}
-// Bin copies for a group of `waves` waves: one per wave while they fit in
-// about 44 KB (fewer lanes contend for one bin), at least one.
-__host__ __device__ inline int bin_copies(int B, int waves) {
-  const int fit = (int)((44 * 1024) / bin_copy_bytes(B));
-  return fit < 1 ? 1 : (fit < waves ? fit : waves);
-}
-__host__ __device__ inline size_t node_lds_bytes(int B, int ncopy) {
-  size_t o = 0;
-  o = align8(o + sizeof(int) * 3 * B * ncopy);
-  o = align8(o + sizeof(int) * 3 * B * 6 * ncopy);
-  o = align8(o + sizeof(long long) * 3 * B * 6 * ncopy);
-  o = align8(o + sizeof(double) * 3 * (B - 1));
-  o = align8(o + sizeof(int) * 16);
-  o = align8(o + sizeof(int) * 16 * 8);
-  o = align8(o + sizeof(int) * 2);
-  o = align8(o + sizeof(double));
-  o = align8(o + sizeof(int) * 12);
-  o = align8(o + sizeof(long long) * 12);
-  return o;
-}
-__device__ inline NodeLds node_lds(char* base, int B, int ncopy) {
-  NodeLds L;
-  size_t o = 0;
-  L.ncopy = ncopy;
-  L.cnt = (int*)(base + o);        o = align8(o + sizeof(int) * 3 * B * ncopy);
-  L.box = (int*)(base + o);        o = align8(o + sizeof(int) * 3 * B * 6 * ncopy);
-  L.cb = (long long*)(base + o);   o = align8(o + sizeof(long long) * 3 * B * 6 * ncopy);
-  L.cost = (double*)(base + o);    o = align8(o + sizeof(double) * 3 * (B - 1));
-  L.wtot = (int*)(base + o);       o = align8(o + sizeof(int) * 16);
-  L.wtot2 = (int*)(base + o);      o = align8(o + sizeof(int) * 16 * 8);
-  L.pick = (int*)(base + o);       o = align8(o + sizeof(int) * 2);
-  L.best = (double*)(base + o);    o = align8(o + sizeof(double));
-  L.cbox = (int*)(base + o);       o = align8(o + sizeof(int) * 12);
-  L.ccb = (long long*)(base + o);
-  return L;
-}
-
-struct LevelArgs {
-  BNode* nodes;
-  const FacetRec* in;   // facet records of the level, in reference order
-  FacetRec* out;        // the same records partitioned for the next level
-  int32_t* perm;
-  const int32_t* act;   // node ids of the level, in order
-  const int32_t* sel;   // positions in act handled by this kernel
-  int32_t* cand;        // per child slot: its facet count if it stays internal, else 0
-  const double* inv_l2;
-  const LevelState* st;
-  int32_t n;
-  BuildConst C;
-};
-
-constexpr int kPartE = 8;  // consecutive records per thread and partition round
-
-__device__ inline unsigned long long lanes_below() {
-  const int lane = lane_id();
-  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
-}
-
-// Exclusive wave prefix of a small count v in 0..15 and the wave total, from
-// four ballots (no cross-lane data movement).
-__device__ inline int wave_excl_small(int v, int& total) {
-  const unsigned long long below = lanes_below();
-  int pre = 0, tot = 0;
-#pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    const unsigned long long m = __ballot((v >> b) & 1);
-    pre += __popcll(m & below) << b;
-    tot += __popcll(m) << b;
+// Root node from the reduced bounds; queues it for the first schedule that
+// takes it (nothing when it is a leaf or a facet is not finite).
+__global__ __launch_bounds__(256) void k_root(Ctx X, const long long* root) {
+  __shared__ int s_slot;
+  BNode r;
+  for (int a = 0; a < 3; ++a) {
+    r.lo[a] = o2f((int32_t)root[a]);
+    r.hi[a] = o2f((int32_t)root[3 + a]);
+    r.cblo[a] = o2d(root[6 + a]);
+    r.cbhi[a] = o2d(root[9 + a]);
   }
-  total = tot;
-  return pre;
+  r.left = -1;
+  r.first = 0;
+  r.count = X.n;
+  r.depth = 0;
+  r.axis = r.plane = -1;
+  r.flags = 0;
+  r.tidx = -1;
+  r.cost = 0.0;
+  if (threadIdx.x == 0) {
+    X.nodes[0] = r;
+    double ex = (double)r.hi[0] - (double)r.lo[0];
+    double ey = (double)r.hi[1] - (double)r.lo[1];
+    double ez = (double)r.hi[2] - (double)r.lo[2];
+    double l2 = (ex * ex + ey * ey) + ez * ez;
+    X.st->inv_l2 = l2 > 0.0 ? 1.0 / l2 : 0.0;
+    s_slot = -1;
+    if (X.st->nonfinite == 0 && X.n > X.C.max_leaf) {
+      const int to = classify(X.C, X.n, 0, r.cblo, r.cbhi, X.la > 0, X.lm > 0);
+      if (to == TO_A) s_slot = push_big(X, 0, 0, X.n);
+      else if (to == TO_M) push_m(X, 0, 0);
+      else push_s(X, 0);
+    }
+  }
+  __syncthreads();
+  if (s_slot >= 0)
+    bins_clear(bins_at(X.abins[0] + s_slot * X.abin_stride, X.C.nbins, true), X.C.nbins,
+               threadIdx.x, blockDim.x);
 }
 
-// Group exclusive prefixes of the left and right counts (each 0..15) of G
-// threads, with the group totals.
-template <int G>
-__device__ inline void group_scan2(int nl, int nr, int& pl, int& pr, int& tl, int& tr,
-                                   const NodeLds& S, int gtid) {
-  int wl, wr;
-  pl = wave_excl_small(nl, wl);
-  pr = wave_excl_small(nr, wr);
-  if constexpr (G == 64) {
-    tl = wl;
-    tr = wr;
-  } else {
-    const int wave = gtid >> 6;
-    if (lane_id() == 0) S.wtot[wave] = wl | (wr << 16);
+// ---------------------------------------------------------------------------
+// Big nodes, pass 1: one work-group bins one chunk into LDS (one bin copy per
+// wave while they fit), keeps the chunk's counts and adds its bins to the
+// node's bins with exact atomics.
+constexpr int kAThreads = 256;
+__host__ __device__ inline int a_copies(int B) {
+  const int fit = (int)((40 * 1024) / bins_bytes(B, true));
+  return fit < 1 ? 1 : (fit < kAThreads / 64 ? fit : kAThreads / 64);
+}
+
+__global__ __launch_bounds__(kAThreads) void k_a_bin(Ctx X, int lvl) {
+  extern __shared__ __align__(16) char lds[];
+  if ((int)blockIdx.x >= min(X.st->a_items[lvl], X.item_cap)) return;
+  const int par = lvl & 1;
+  const AItem it = X.items[par][blockIdx.x];
+  const BNode nd = X.nodes[it.node];
+  const int B = X.C.nbins;
+  const int ncopy = a_copies(B);
+  const size_t cs = bins_bytes(B, true);
+  const int tid = threadIdx.x;
+  for (int cp = 0; cp < ncopy; ++cp) bins_clear(bins_at(lds + cp * cs, B, true), B, tid, kAThreads);
+  __syncthreads();
+  const NodeSetup u = node_setup(X.C, nd.depth, nd.count, nd.cblo, nd.cbhi);
+  const Bins S = bins_at(lds + ((tid >> 6) % ncopy) * cs, B, true);
+  const FacetRec* in = X.recs[nd.depth & 1] + nd.first;
+  for (int i = it.begin + tid; i < it.end; i += kAThreads) {
+    const FacetRec r = in[i];
+    const float l[3] = {r.lo.x, r.lo.y, r.lo.z}, h[3] = {r.hi.x, r.hi.y, r.hi.z};
+    double c[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) c[q] = centroid(l[q], h[q]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (!u.axis_ok[a]) continue;
+      const int slot = a * B + bin_of(c[a], nd.cblo[a], u.scale[a], B);
+      atomicAdd(&S.cnt[slot], 1);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        atomicMin(&S.box[6 * slot + q], f2o(l[q]));
+        atomicMax(&S.box[6 * slot + 3 + q], f2o(h[q]));
+        atomicMin(&S.cb[6 * slot + q], d2o(c[q]));
+        atomicMax(&S.cb[6 * slot + 3 + q], d2o(c[q]));
+      }
+    }
+  }
+  __syncthreads();
+  const Bins G = bins_at(X.abins[par] + it.slot * X.abin_stride, B, true);
+  int32_t* cc = X.ccnt[par] + (size_t)blockIdx.x * 3 * RT_MAX_BINS;
+  for (int c = tid; c < 3 * B; c += kAThreads) {
+    int cnt = 0;
+    int bx[6] = {f2o(INFINITY), f2o(INFINITY), f2o(INFINITY), f2o(-INFINITY), f2o(-INFINITY), f2o(-INFINITY)};
+    long long cb[6] = {d2o(INFINITY), d2o(INFINITY), d2o(INFINITY), d2o(-INFINITY), d2o(-INFINITY), d2o(-INFINITY)};
+    for (int cp = 0; cp < ncopy; ++cp) {
+      const Bins P = bins_at(lds + cp * cs, B, true);
+      cnt += P.cnt[c];
+      for (int q = 0; q < 3; ++q) {
+        bx[q] = min(bx[q], P.box[6 * c + q]);
+        bx[3 + q] = max(bx[3 + q], P.box[6 * c + 3 + q]);
+        cb[q] = min(cb[q], P.cb[6 * c + q]);
+        cb[3 + q] = max(cb[3 + q], P.cb[6 * c + 3 + q]);
+      }
+    }
+    cc[c] = cnt;
+    if (cnt > 0) {
+      atomicAdd(&G.cnt[c], cnt);
+      for (int q = 0; q < 3; ++q) {
+        atomicMin(&G.box[6 * c + q], bx[q]);
+        atomicMax(&G.box[6 * c + 3 + q], bx[3 + q]);
+        atomicMin(&G.cb[6 * c + q], cb[q]);
+        atomicMax(&G.cb[6 * c + 3 + q], cb[3 + q]);
+      }
+    }
+  }
+}
+
+// Big nodes, pass 2: every work-group of a node evaluates Eq. (2) on the
+// node's bins (the same answer in each), places its chunk stably after the
+// left-going facets of the chunks before it, and the node's first chunk
+// creates the children and queues them.
+__global__ __launch_bounds__(kAThreads) void k_a_split(Ctx X, int lvl) {
+  extern __shared__ __align__(16) char lds[];
+  __shared__ int s_pick[2];
+  __shared__ double s_best;
+  __shared__ int s_red[kAThreads / 64];
+  __shared__ int s_w[2][kAThreads / 64];
+  __shared__ int s_slot[2];
+  if ((int)blockIdx.x >= min(X.st->a_items[lvl], X.item_cap)) return;
+  const int par = lvl & 1;
+  const AItem it = X.items[par][blockIdx.x];
+  const BNode nd = X.nodes[it.node];
+  const int B = X.C.nbins;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  BuildConst C = X.C;
+  C.inv_l2 = X.st->inv_l2;
+  const Bins S = bins_at(lds, B, true);
+  {
+    const Bins G = bins_at(X.abins[par] + it.slot * X.abin_stride, B, true);
+    for (int c = tid; c < 3 * B; c += kAThreads) {
+      S.cnt[c] = G.cnt[c];
+      for (int q = 0; q < 6; ++q) {
+        S.box[6 * c + q] = G.box[6 * c + q];
+        S.cb[6 * c + q] = G.cb[6 * c + q];
+      }
+    }
+  }
+  __syncthreads();
+  const NodeSetup u = node_setup(C, nd.depth, nd.count, nd.cblo, nd.cbhi);
+  if (wave == 0) {
+    const double clo[3] = {nd.lo[0], nd.lo[1], nd.lo[2]}, chi[3] = {nd.hi[0], nd.hi[1], nd.hi[2]};
+    int axis, plane;
+    double best;
+    wave_eval(S.cnt, S.box, C, u, clo, chi, nd.count, axis, plane, best);
+    if (lane == 0) {
+      s_pick[0] = axis;
+      s_pick[1] = plane;
+      s_best = best;
+    }
+  }
+  __syncthreads();
+  const int axis = s_pick[0], plane = s_pick[1];
+  if (axis < 0) {  // cannot happen for nodes queued here (nonzero extent)
+    if (tid == 0) set_err(X.st, 16);
+    return;
+  }
+  int nleft = 0;
+  for (int b = 0; b < plane; ++b) nleft += S.cnt[axis * B + b];
+  // left-going facets in the chunks before this one
+  int loff = 0;
+  {
+    const int nprev = blockIdx.x - it.first_item;
+    const int terms = nprev * plane;
+    for (int t = tid; t < terms; t += kAThreads) {
+      const int j = it.first_item + t / plane, b = t % plane;
+      loff += X.ccnt[par][(size_t)j * 3 * RT_MAX_BINS + axis * B + b];
+    }
+    loff = wsum(loff);
+    if (lane == 0) s_red[wave] = loff;
     __syncthreads();
-    int pre = 0, tot = 0;
-    for (int w = 0; w < G / 64; ++w) {
-      const int x = S.wtot[w];
-      if (w < wave) pre += x;
-      tot += x;
+    loff = 0;
+    for (int w = 0; w < kAThreads / 64; ++w) loff += s_red[w];
+  }
+  const int roff = it.begin - loff;
+  const int k = nd.count;
+  const bool leaf0 = nleft <= C.max_leaf, leaf1 = k - nleft <= C.max_leaf;
+  const double ax_lo = axis == 0 ? nd.cblo[0] : (axis == 1 ? nd.cblo[1] : nd.cblo[2]);
+  const double ax_scale = axis == 0 ? u.scale[0] : (axis == 1 ? u.scale[1] : u.scale[2]);
+  const FacetRec* in = X.recs[nd.depth & 1] + nd.first;
+  FacetRec* out = X.recs[(nd.depth + 1) & 1] + nd.first;
+  int32_t* perm = X.perm + nd.first;
+  const unsigned long long below = lanes_below();
+  int lb = 0, rb = 0;
+  for (int s0 = it.begin; s0 < it.end; s0 += kAThreads) {
+    const int i = s0 + tid;
+    const bool valid = i < it.end;
+    const FacetRec r = in[valid ? i : it.begin];
+    bool g = false;
+    if (valid) {
+      const float l = axis == 0 ? r.lo.x : (axis == 1 ? r.lo.y : r.lo.z);
+      const float h = axis == 0 ? r.hi.x : (axis == 1 ? r.hi.y : r.hi.z);
+      g = bin_of(centroid(l, h), ax_lo, ax_scale, B) < plane;
+    }
+    const unsigned long long ml = __ballot(valid && g), mr = __ballot(valid && !g);
+    if (lane == 0) {
+      s_w[0][wave] = __popcll(ml);
+      s_w[1][wave] = __popcll(mr);
     }
     __syncthreads();
-    pl += pre & 0xffff;
-    pr += pre >> 16;
-    tl = tot & 0xffff;
-    tr = tot >> 16;
+    int pl = 0, pr = 0, tl = 0, tr = 0;
+    for (int w = 0; w < kAThreads / 64; ++w) {
+      if (w < wave) {
+        pl += s_w[0][w];
+        pr += s_w[1][w];
+      }
+      tl += s_w[0][w];
+      tr += s_w[1][w];
+    }
+    __syncthreads();
+    if (valid) {
+      const int dst = g ? loff + lb + pl + __popcll(ml & below)
+                        : nleft + roff + rb + pr + __popcll(mr & below);
+      if (dst >= 0 && dst < k) {
+        out[dst] = r;
+        if (g ? leaf0 : leaf1) perm[dst] = __float_as_int(r.lo.w);
+      } else {
+        set_err(X.st, 128);
+      }
+    }
+    lb += tl;
+    rb += tr;
   }
+  if (it.begin != 0) return;  // the node's first chunk makes the children
+  if (tid == 0) {
+    float lo[2][3], hi[2][3];
+    double clo[2][3], chi[2][3];
+    bins_union(S, B, axis, 0, plane, lo[0], hi[0], clo[0], chi[0]);
+    bins_union(S, B, axis, plane, B, lo[1], hi[1], clo[1], chi[1]);
+    const int c0 = make_children(X, atomicAdd(&X.st->total, 2), it.node, nd, axis, plane, u.flags,
+                                 s_best, nleft, lo, hi, clo, chi);
+    s_slot[0] = s_slot[1] = -1;
+    if (c0 >= 0) {
+      for (int side = 0; side < 2; ++side) {
+        const int kc = side == 0 ? nleft : k - nleft;
+        if (kc <= C.max_leaf) continue;
+        const int to = classify(C, kc, nd.depth + 1, clo[side], chi[side], lvl + 1 < X.la, X.lm > 0);
+        if (to == TO_A) s_slot[side] = push_big(X, lvl + 1, c0 + side, kc);
+        else if (to == TO_M) push_m(X, 0, c0 + side);
+        else push_s(X, c0 + side);
+      }
+    }
+  }
+  __syncthreads();
+  for (int side = 0; side < 2; ++side)
+    if (s_slot[side] >= 0)
+      bins_clear(bins_at(X.abins[(lvl + 1) & 1] + s_slot[side] * X.abin_stride, B, true), B, tid,
+                 kAThreads);
 }
 
-// Run of consecutive facets that fall in one bin of one axis, kept in
-// registers and merged into the bin when the bin changes.
+// ---------------------------------------------------------------------------
+// One node split by one wave, facet records in global memory.  Returns the
+// left child id (wave-uniform), -1 on overflow.
 struct Run {
   int bin, count;
   float lo[3], hi[3];
@@ -384,205 +901,81 @@ __device__ inline void run_reset(Run& r, int bin) {
     r.chi[q] = -INFINITY;
   }
 }
-__device__ inline void run_flush(const Run& r, const NodeLds& S, int copy, int a, int B) {
+__device__ inline void run_flush(const Run& r, const Bins& S, int a, int B) {
   if (r.count == 0) return;
-  const int slot = (copy * 3 + a) * B + r.bin;
+  const int slot = a * B + r.bin;
   atomicAdd(&S.cnt[slot], r.count);
-  int* bx = S.box + 6 * slot;
-  long long* cb = S.cb + 6 * slot;
   for (int q = 0; q < 3; ++q) {
-    atomicMin(&bx[q], f2o(r.lo[q]));
-    atomicMax(&bx[3 + q], f2o(r.hi[q]));
-    atomicMin(&cb[q], d2o(r.clo[q]));
-    atomicMax(&cb[3 + q], d2o(r.chi[q]));
+    atomicMin(&S.box[6 * slot + q], f2o(r.lo[q]));
+    atomicMax(&S.box[6 * slot + 3 + q], f2o(r.hi[q]));
+    atomicMin(&S.cb[6 * slot + q], d2o(r.clo[q]));
+    atomicMax(&S.cb[6 * slot + 3 + q], d2o(r.chi[q]));
   }
 }
 
-// One node of the level: bin, evaluate Eq. (2), partition, emit children.
-// G threads (one wave or one work-group) handle the node.
-template <int G>
-__device__ void process_node(const LevelArgs& A, int j, const NodeLds& S, int gtid) {
-  const int lane = lane_id();
-  const int id = A.act[j];
-  const BNode nd = A.nodes[id];
-  const int k = nd.count, s = nd.first;
-  const int B = A.C.nbins;
-  BuildConst C = A.C;
-  C.inv_l2 = *A.inv_l2;
-  const int child_base = A.st->child_base;
+constexpr int kPartE = 8;  // consecutive records per lane and partition round
 
-  double alpha = C.alpha;
-  int flags = 0;
-  const bool forced = nd.depth + halvings(k, C.max_leaf) >= C.depth_limit;
-  if (forced) {
-    flags = 1;
-  } else if (nd.depth >= C.max_depth) {
-    alpha = 1.0;
-    flags |= 4;
-  }
-  double ext[3], scale[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    ext[a] = nd.cbhi[a] - nd.cblo[a];
-    scale[a] = ext[a] > 0.0 ? (double)B / ext[a] : 0.0;
-  }
-  if (gtid < 12) {
-    const int side = gtid / 6, c = gtid % 6;
-    S.cbox[6 * side + c] = c < 3 ? f2o(INFINITY) : f2o(-INFINITY);
-    S.ccb[6 * side + c] = c < 3 ? d2o(INFINITY) : d2o(-INFINITY);
-  }
-  int axis = -1, plane = -1;
+__device__ int wave_split_global(const Ctx& X, int id, const Bins& S, int& kc0, int& kc1,
+                                 double ccb[2][6]) {
+  const int lane = lane_id();
+  // the child ids are reserved first: the atomic's round trip overlaps the binning
+  int c0 = 0;
+  if (lane == 0) c0 = atomicAdd(&X.st->total, 2);
+  const BNode nd = X.nodes[id];
+  const int k = nd.count, B = X.C.nbins;
+  BuildConst C = X.C;
+  C.inv_l2 = X.st->inv_l2;
+  const NodeSetup u = node_setup(C, nd.depth, k, nd.cblo, nd.cbhi);
+  const FacetRec* in = X.recs[nd.depth & 1] + nd.first;
+  FacetRec* out = X.recs[(nd.depth + 1) & 1] + nd.first;
+  int32_t* perm = X.perm + nd.first;
+  int axis = -1, plane = -1, flags = u.flags;
   double best = INFINITY;
-  if (!forced) {
-    const int my_copy = (gtid >> 6) % S.ncopy;
-    for (int c = gtid; c < 3 * B * S.ncopy; c += G) {
-      S.cnt[c] = 0;
-      for (int q = 0; q < 3; ++q) {
-        S.box[6 * c + q] = f2o(INFINITY);
-        S.box[6 * c + 3 + q] = f2o(-INFINITY);
-        S.cb[6 * c + q] = d2o(INFINITY);
-        S.cb[6 * c + 3 + q] = d2o(-INFINITY);
-      }
-    }
-    group_sync<G>();
-    // binning: each thread walks a contiguous run of the node's facets
-    const int per = (k + G - 1) / G;
-    const int i0 = min(k, gtid * per), i1 = min(k, i0 + per);
+  if (!u.forced) {
+    bins_clear(S, B, lane, 64);
+    wave_sync();
+    // each lane walks a contiguous run of the node's facets
+    const int per = (k + 63) / 64;
+    const int i0 = min(k, lane * per), i1 = min(k, i0 + per);
     Run run[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) run_reset(run[a], -1);
-    // loads of kBinU facets are issued together before they are merged
     constexpr int kBinU = 4;
     for (int i = i0; i < i1; i += kBinU) {
       float4 lo[kBinU], hi[kBinU];
-      double cu[kBinU][3];
 #pragma unroll
-      for (int u = 0; u < kBinU; ++u) {
-        const int q = min(i + u, i1 - 1);
-        lo[u] = A.in[s + q].lo;
-        hi[u] = A.in[s + q].hi;
+      for (int v = 0; v < kBinU; ++v) {
+        const int q = min(i + v, i1 - 1);
+        lo[v] = in[q].lo;
+        hi[v] = in[q].hi;
       }
 #pragma unroll
-      for (int u = 0; u < kBinU; ++u) {
-        cu[u][0] = centroid(lo[u].x, hi[u].x);
-        cu[u][1] = centroid(lo[u].y, hi[u].y);
-        cu[u][2] = centroid(lo[u].z, hi[u].z);
-      }
-#pragma unroll
-      for (int u = 0; u < kBinU; ++u) {
-        if (i + u >= i1) break;
+      for (int v = 0; v < kBinU; ++v) {
+        if (i + v >= i1) break;
+        const double cu[3] = {centroid(lo[v].x, hi[v].x), centroid(lo[v].y, hi[v].y),
+                              centroid(lo[v].z, hi[v].z)};
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-          if (!(ext[a] > 0.0)) continue;
-          const int b = bin_of(cu[u][a], nd.cblo[a], scale[a], B);
+          if (!u.axis_ok[a]) continue;
+          const int b = bin_of(cu[a], nd.cblo[a], u.scale[a], B);
           if (b != run[a].bin) {
-            run_flush(run[a], S, my_copy, a, B);
+            run_flush(run[a], S, a, B);
             run_reset(run[a], b);
           }
           Run& r = run[a];
           r.count += 1;
-          r.lo[0] = fminf(r.lo[0], lo[u].x); r.lo[1] = fminf(r.lo[1], lo[u].y); r.lo[2] = fminf(r.lo[2], lo[u].z);
-          r.hi[0] = fmaxf(r.hi[0], hi[u].x); r.hi[1] = fmaxf(r.hi[1], hi[u].y); r.hi[2] = fmaxf(r.hi[2], hi[u].z);
-          r.clo[0] = fmin(r.clo[0], cu[u][0]); r.clo[1] = fmin(r.clo[1], cu[u][1]); r.clo[2] = fmin(r.clo[2], cu[u][2]);
-          r.chi[0] = fmax(r.chi[0], cu[u][0]); r.chi[1] = fmax(r.chi[1], cu[u][1]); r.chi[2] = fmax(r.chi[2], cu[u][2]);
+          r.lo[0] = fminf(r.lo[0], lo[v].x); r.lo[1] = fminf(r.lo[1], lo[v].y); r.lo[2] = fminf(r.lo[2], lo[v].z);
+          r.hi[0] = fmaxf(r.hi[0], hi[v].x); r.hi[1] = fmaxf(r.hi[1], hi[v].y); r.hi[2] = fmaxf(r.hi[2], hi[v].z);
+          r.clo[0] = fmin(r.clo[0], cu[0]); r.clo[1] = fmin(r.clo[1], cu[1]); r.clo[2] = fmin(r.clo[2], cu[2]);
+          r.chi[0] = fmax(r.chi[0], cu[0]); r.chi[1] = fmax(r.chi[1], cu[1]); r.chi[2] = fmax(r.chi[2], cu[2]);
         }
       }
     }
 #pragma unroll
-    for (int a = 0; a < 3; ++a) run_flush(run[a], S, my_copy, a, B);
-    group_sync<G>();
-    if (S.ncopy > 1) {  // fold the private copies into copy 0
-      for (int c = gtid; c < 3 * B; c += G) {
-        int cnt = S.cnt[c];
-        int bx[6];
-        long long cb[6];
-        for (int q = 0; q < 6; ++q) {
-          bx[q] = S.box[6 * c + q];
-          cb[q] = S.cb[6 * c + q];
-        }
-        for (int cp = 1; cp < S.ncopy; ++cp) {
-          const int o = cp * 3 * B + c;
-          cnt += S.cnt[o];
-          for (int q = 0; q < 3; ++q) {
-            bx[q] = min(bx[q], S.box[6 * o + q]);
-            bx[3 + q] = max(bx[3 + q], S.box[6 * o + 3 + q]);
-            cb[q] = min(cb[q], S.cb[6 * o + q]);
-            cb[3 + q] = max(cb[3 + q], S.cb[6 * o + 3 + q]);
-          }
-        }
-        S.cnt[c] = cnt;
-        for (int q = 0; q < 6; ++q) {
-          S.box[6 * c + q] = bx[q];
-          S.cb[6 * c + q] = cb[q];
-        }
-      }
-      group_sync<G>();
-    }
-    const int ncand = 3 * (B - 1);
-    double clo[3], chi[3];
-    for (int q = 0; q < 3; ++q) {
-      clo[q] = nd.lo[q];
-      chi[q] = nd.hi[q];
-    }
-    for (int c = gtid; c < ncand; c += G) {
-      const int a = c / (B - 1), pl = c % (B - 1) + 1;
-      double cost = INFINITY;
-      if (ext[a] > 0.0) {
-        double alo[3] = {INFINITY, INFINITY, INFINITY}, ahi[3] = {-INFINITY, -INFINITY, -INFINITY};
-        double blo[3] = {INFINITY, INFINITY, INFINITY}, bhi[3] = {-INFINITY, -INFINITY, -INFINITY};
-        int ka = 0, kb = 0;
-        for (int b = 0; b < B; ++b) {
-          const int slot = a * B + b;
-          const int cnt = S.cnt[slot];
-          if (cnt == 0) continue;
-          const int* bx = S.box + 6 * slot;
-          const double l0 = o2f(bx[0]), l1 = o2f(bx[1]), l2 = o2f(bx[2]);
-          const double h0 = o2f(bx[3]), h1 = o2f(bx[4]), h2 = o2f(bx[5]);
-          if (b < pl) {
-            ka += cnt;
-            alo[0] = fmin(alo[0], l0); alo[1] = fmin(alo[1], l1); alo[2] = fmin(alo[2], l2);
-            ahi[0] = fmax(ahi[0], h0); ahi[1] = fmax(ahi[1], h1); ahi[2] = fmax(ahi[2], h2);
-          } else {
-            kb += cnt;
-            blo[0] = fmin(blo[0], l0); blo[1] = fmin(blo[1], l1); blo[2] = fmin(blo[2], l2);
-            bhi[0] = fmax(bhi[0], h0); bhi[1] = fmax(bhi[1], h1); bhi[2] = fmax(bhi[2], h2);
-          }
-        }
-        if (ka > 0 && kb > 0) cost = eq2_cost(C, alpha, alo, ahi, ka, blo, bhi, kb, clo, chi, k);
-      }
-      S.cost[c] = cost;
-    }
-    group_sync<G>();
-    if (gtid < 64) {
-      // first strict minimum in (axis, plane) order: lexicographic (cost, index)
-      double bc = INFINITY;
-      int bi = 1 << 30;
-      for (int c = gtid; c < ncand; c += 64) {
-        const double x = S.cost[c];
-        if (x < bc) {
-          bc = x;
-          bi = c;
-        }
-      }
-      for (int o = 32; o > 0; o >>= 1) {
-        const double oc = __shfl_xor(bc, o);
-        const int oi = __shfl_xor(bi, o);
-        if (oc < bc || (oc == bc && oi < bi)) {
-          bc = oc;
-          bi = oi;
-        }
-      }
-      if (gtid == 0) {
-        const bool ok = bc < INFINITY;
-        S.pick[0] = ok ? bi / (B - 1) : -1;
-        S.pick[1] = ok ? bi % (B - 1) + 1 : -1;
-        *S.best = bc;
-      }
-    }
-    group_sync<G>();
-    axis = S.pick[0];
-    plane = S.pick[1];
-    best = *S.best;
+    for (int a = 0; a < 3; ++a) run_flush(run[a], S, a, B);
+    wave_sync();
+    const double clo[3] = {nd.lo[0], nd.lo[1], nd.lo[2]}, chi[3] = {nd.hi[0], nd.hi[1], nd.hi[2]};
+    wave_eval(S.cnt, S.box, C, u, clo, chi, k, axis, plane, best);
     if (axis < 0) flags |= 2;
   }
   const bool by_position = axis < 0;
@@ -593,15 +986,10 @@ __device__ void process_node(const LevelArgs& A, int j, const NodeLds& S, int gt
     nleft = 0;
     for (int b = 0; b < plane; ++b) nleft += S.cnt[axis * B + b];
   }
-  const int cnt0 = nleft, cnt1 = k - nleft;
-  const int fst0 = s, fst1 = s + nleft;
-  const bool leaf0 = cnt0 <= C.max_leaf, leaf1 = cnt1 <= C.max_leaf;
-  // split axis constants as scalars (no dynamic indexing of small arrays)
+  const bool leaf0 = nleft <= C.max_leaf, leaf1 = k - nleft <= C.max_leaf;
   const int ax = by_position ? 0 : axis;
   const double ax_lo = ax == 0 ? nd.cblo[0] : (ax == 1 ? nd.cblo[1] : nd.cblo[2]);
-  const double ax_scale = ax == 0 ? scale[0] : (ax == 1 ? scale[1] : scale[2]);
-
-  // stable partition, kPartE consecutive records per thread and round
+  const double ax_scale = ax == 0 ? u.scale[0] : (ax == 1 ? u.scale[1] : u.scale[2]);
   float blo[2][3], bhi[2][3];
   double cbl[2][3], cbh[2][3];
   for (int side = 0; side < 2; ++side)
@@ -611,26 +999,21 @@ __device__ void process_node(const LevelArgs& A, int j, const NodeLds& S, int gt
       cbl[side][q] = INFINITY;
       cbh[side][q] = -INFINITY;
     }
-  // Round of G * kPartE records, slice e = records base + e G + [0, G):
-  // loads and stores are coalesced; one exchange of per-wave slice totals
-  // gives every record its stable rank.
-  constexpr int NW = G / 64;
-  int lbase = 0, rbase = 0;
-  const int wave = gtid >> 6;
   const unsigned long long below = lanes_below();
-  for (int base = 0; base < k; base += G * kPartE) {
+  int lbase = 0, rbase = 0;
+  for (int base = 0; base < k; base += 64 * kPartE) {
     FacetRec r[kPartE];
     bool gl[kPartE], valid[kPartE];
     unsigned long long ml[kPartE], mr[kPartE];
 #pragma unroll
     for (int e = 0; e < kPartE; ++e) {
-      const int i = base + e * G + gtid;
+      const int i = base + e * 64 + lane;
       valid[e] = i < k;
-      r[e] = A.in[s + min(i, k - 1)];
+      r[e] = in[min(i, k - 1)];
     }
 #pragma unroll
     for (int e = 0; e < kPartE; ++e) {
-      const int i = base + e * G + gtid;
+      const int i = base + e * 64 + lane;
       bool g = false;
       if (valid[e]) {
         if (by_position) {
@@ -642,253 +1025,397 @@ __device__ void process_node(const LevelArgs& A, int j, const NodeLds& S, int gt
         }
       }
       gl[e] = g;
-      ml[e] = __ballot(g);
+      ml[e] = __ballot(valid[e] && g);
       mr[e] = __ballot(valid[e] && !g);
     }
-    // per-slice offsets of this wave: earlier slices (all waves) + earlier waves of this slice
-    int offl[kPartE], offr[kPartE];
-    int tl = 0, tr = 0;
-    if constexpr (NW == 1) {
-#pragma unroll
-      for (int e = 0; e < kPartE; ++e) {
-        offl[e] = tl;
-        offr[e] = tr;
-        tl += __popcll(ml[e]);
-        tr += __popcll(mr[e]);
-      }
-    } else {
-      if (lane_id() < kPartE) {
-        int cl = 0, cr = 0;
-#pragma unroll
-        for (int e = 0; e < kPartE; ++e)
-          if (e == lane_id()) {
-            cl = __popcll(ml[e]);
-            cr = __popcll(mr[e]);
-          }
-        S.wtot2[lane_id() * NW + wave] = cl | (cr << 16);
-      }
-      __syncthreads();
-#pragma unroll
-      for (int e = 0; e < kPartE; ++e) {
-        int pre = 0, tot = 0;
-        for (int w = 0; w < NW; ++w) {
-          const int x = S.wtot2[e * NW + w];
-          if (w < wave) pre += x;
-          tot += x;
-        }
-        offl[e] = tl + (pre & 0xffff);
-        offr[e] = tr + (pre >> 16);
-        tl += tot & 0xffff;
-        tr += tot >> 16;
-      }
-      __syncthreads();
-    }
+    int offl = 0, offr = 0;
 #pragma unroll
     for (int e = 0; e < kPartE; ++e) {
-      if (!valid[e]) continue;
-      const int dst = gl[e] ? fst0 + lbase + offl[e] + __popcll(ml[e] & below)
-                            : fst1 + rbase + offr[e] + __popcll(mr[e] & below);
-      A.out[dst] = r[e];
-      if (gl[e] ? leaf0 : leaf1) A.perm[dst] = __float_as_int(r[e].lo.w);
-      if (by_position) {  // no bins: child bounds from the facets themselves
-        const float4 lo = r[e].lo, hi = r[e].hi;
-        const double cx = centroid(lo.x, hi.x), cy = centroid(lo.y, hi.y), cz = centroid(lo.z, hi.z);
-        if (gl[e]) {
-          blo[0][0] = fminf(blo[0][0], lo.x); blo[0][1] = fminf(blo[0][1], lo.y); blo[0][2] = fminf(blo[0][2], lo.z);
-          bhi[0][0] = fmaxf(bhi[0][0], hi.x); bhi[0][1] = fmaxf(bhi[0][1], hi.y); bhi[0][2] = fmaxf(bhi[0][2], hi.z);
-          cbl[0][0] = fmin(cbl[0][0], cx); cbl[0][1] = fmin(cbl[0][1], cy); cbl[0][2] = fmin(cbl[0][2], cz);
-          cbh[0][0] = fmax(cbh[0][0], cx); cbh[0][1] = fmax(cbh[0][1], cy); cbh[0][2] = fmax(cbh[0][2], cz);
+      if (valid[e]) {
+        const int dst = gl[e] ? lbase + offl + __popcll(ml[e] & below)
+                              : nleft + rbase + offr + __popcll(mr[e] & below);
+        if (dst >= 0 && dst < k) {
+          out[dst] = r[e];
+          if (gl[e] ? leaf0 : leaf1) perm[dst] = __float_as_int(r[e].lo.w);
         } else {
-          blo[1][0] = fminf(blo[1][0], lo.x); blo[1][1] = fminf(blo[1][1], lo.y); blo[1][2] = fminf(blo[1][2], lo.z);
-          bhi[1][0] = fmaxf(bhi[1][0], hi.x); bhi[1][1] = fmaxf(bhi[1][1], hi.y); bhi[1][2] = fmaxf(bhi[1][2], hi.z);
-          cbl[1][0] = fmin(cbl[1][0], cx); cbl[1][1] = fmin(cbl[1][1], cy); cbl[1][2] = fmin(cbl[1][2], cz);
-          cbh[1][0] = fmax(cbh[1][0], cx); cbh[1][1] = fmax(cbh[1][1], cy); cbh[1][2] = fmax(cbh[1][2], cz);
+          set_err(X.st, 128);
+        }
+        if (by_position) {  // no bins: child bounds from the facets themselves
+          const float4 lo = r[e].lo, hi = r[e].hi;
+          const double cx = centroid(lo.x, hi.x), cy = centroid(lo.y, hi.y), cz = centroid(lo.z, hi.z);
+          const int sd = gl[e] ? 0 : 1;
+          blo[sd][0] = fminf(blo[sd][0], lo.x); blo[sd][1] = fminf(blo[sd][1], lo.y); blo[sd][2] = fminf(blo[sd][2], lo.z);
+          bhi[sd][0] = fmaxf(bhi[sd][0], hi.x); bhi[sd][1] = fmaxf(bhi[sd][1], hi.y); bhi[sd][2] = fmaxf(bhi[sd][2], hi.z);
+          cbl[sd][0] = fmin(cbl[sd][0], cx); cbl[sd][1] = fmin(cbl[sd][1], cy); cbl[sd][2] = fmin(cbl[sd][2], cz);
+          cbh[sd][0] = fmax(cbh[sd][0], cx); cbh[sd][1] = fmax(cbh[sd][1], cy); cbh[sd][2] = fmax(cbh[sd][2], cz);
         }
       }
+      offl += __popcll(ml[e]);
+      offr += __popcll(mr[e]);
     }
-    lbase += tl;
-    rbase += tr;
+    lbase += offl;
+    rbase += offr;
   }
+  float lo[2][3], hi[2][3];
+  double clo[2][3], chi[2][3];
   if (by_position) {
     for (int side = 0; side < 2; ++side)
       for (int q = 0; q < 3; ++q) {
-        const float l = wmin(blo[side][q]), h = wmax(bhi[side][q]);
-        const double cl = wmin(cbl[side][q]), ch = wmax(cbh[side][q]);
-        if (lane == 0) {
-          atomicMin(&S.cbox[6 * side + q], f2o(l));
-          atomicMax(&S.cbox[6 * side + 3 + q], f2o(h));
-          atomicMin(&S.ccb[6 * side + q], d2o(cl));
-          atomicMax(&S.ccb[6 * side + 3 + q], d2o(ch));
-        }
+        lo[side][q] = wmin(blo[side][q]);
+        hi[side][q] = wmax(bhi[side][q]);
+        clo[side][q] = wmin(cbl[side][q]);
+        chi[side][q] = wmax(cbh[side][q]);
       }
+  } else {
+    bins_union(S, B, axis, 0, plane, lo[0], hi[0], clo[0], chi[0]);
+    bins_union(S, B, axis, plane, B, lo[1], hi[1], clo[1], chi[1]);
   }
-  group_sync<G>();
-  const int c0 = child_base + 2 * j;
-  if (gtid < 2) {
-    BNode ch;
-    if (by_position) {
+  if (lane == 0)
+    c0 = make_children(X, c0, id, nd, axis, plane, flags, by_position ? 0.0 : best, nleft, lo, hi,
+                       clo, chi);
+  c0 = bcast(c0);
+  kc0 = nleft;
+  kc1 = k - nleft;
+  for (int side = 0; side < 2; ++side)
+    for (int q = 0; q < 3; ++q) {
+      ccb[side][q] = clo[side][q];
+      ccb[side][3 + q] = chi[side][q];
+    }
+  return c0;
+}
+
+// Medium nodes: persistent waves take nodes of pass `pass` from its list.
+constexpr int kWaveThreads = 256;  // four independent waves per work-group
+__global__ __launch_bounds__(kWaveThreads) void k_m(Ctx X, int pass) {
+  extern __shared__ __align__(16) char lds[];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int B = X.C.nbins;
+  const Bins S = bins_at(lds + w * bins_bytes(B, true), B, true);
+  const int count = min(X.st->m_count[pass], X.n);
+  const int nw = gridDim.x * (blockDim.x >> 6);
+  for (int i = blockIdx.x * (blockDim.x >> 6) + w; i < count; i += nw) {
+    const int id = X.mlist[pass & 1][i];
+    const int depth = X.nodes[id].depth;
+    int kc[2];
+    double ccb[2][6];
+    const int c0 = wave_split_global(X, id, S, kc[0], kc[1], ccb);
+    if (c0 < 0) break;
+    if (lane < 2 && kc[lane] > X.C.max_leaf) {  // one lane per child: the pushes overlap
+      const double* cb = lane == 0 ? ccb[0] : ccb[1];
+      const int to = classify(X.C, kc[lane], depth + 1, cb, cb + 3, false, pass + 1 < X.lm);
+      if (to == TO_M) push_m(X, pass + 1, c0 + lane);
+      else push_s(X, c0 + lane);
+    }
+    wave_sync();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Subtrees.  A wave takes a subtree root and splits depth-first until every
+// node is a leaf.  Nodes above kRegNode facets are split from global memory;
+// a node at or below it is finished with its records in registers (lane i
+// holds the node's i-th facet), the partition being a permutation of lanes.
+
+// Register subtrees keep their new nodes in LDS (local index 1, 2, ... in
+// sibling pairs) and move them to global ids with one reservation at the end.
+constexpr int kLocal = 2 * kRegNode;  // local node slots (slot 0: copy of the subtree root)
+struct RFrame {                       // stack entry: a local node and its lanes
+  int32_t li, r0, cnt, pad;
+};
+constexpr int kRStack = 64;           // a subtree of <= 64 facets is at most 63 splits deep
+constexpr int kGStack = 72;           // nodes above kRegNode waiting on the global path
+
+__host__ __device__ inline size_t s_wave_bytes(int B) {
+  return bins_bytes(B, true) + align8(sizeof(BNode) * kLocal) + align8(sizeof(RFrame) * kRStack) +
+         align8(sizeof(int) * kGStack);
+}
+
+// Bins of the node on lanes [r0, r0 + cnt) with 16 bins: lane 16 a + b walks
+// the node's facets and keeps those in bin b of axis a.
+__device__ inline void bins16_from_lanes(int r0, int cnt, int packed_bins, const float lo[3],
+                                         const float hi[3], int& c, float bl[3], float bh[3]) {
+  const int lane = lane_id();
+  const int shift = 8 * min(lane >> 4, 2);
+  const int mine = lane & 15;
+  c = 0;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    bl[q] = INFINITY;
+    bh[q] = -INFINITY;
+  }
+  for (int j = r0; j < r0 + cnt; ++j) {
+    const int pj = __builtin_amdgcn_readlane(packed_bins, j);
+    float l[3], h[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      l[q] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lo[q]), j));
+      h[q] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hi[q]), j));
+    }
+    if (((pj >> shift) & 255) == mine) {
+      c += 1;
+#pragma unroll
       for (int q = 0; q < 3; ++q) {
-        ch.lo[q] = o2f(S.cbox[6 * gtid + q]);
-        ch.hi[q] = o2f(S.cbox[6 * gtid + 3 + q]);
-        ch.cblo[q] = o2d(S.ccb[6 * gtid + q]);
-        ch.cbhi[q] = o2d(S.ccb[6 * gtid + 3 + q]);
-      }
-    } else {
-      // union of the bins on this child's side of the plane
-      int bl[6] = {f2o(INFINITY), f2o(INFINITY), f2o(INFINITY), f2o(-INFINITY), f2o(-INFINITY), f2o(-INFINITY)};
-      long long cl[6] = {d2o(INFINITY), d2o(INFINITY), d2o(INFINITY), d2o(-INFINITY), d2o(-INFINITY), d2o(-INFINITY)};
-      const int b0 = gtid == 0 ? 0 : plane, b1 = gtid == 0 ? plane : B;
-      for (int b = b0; b < b1; ++b) {
-        const int slot = axis * B + b;
-        if (S.cnt[slot] == 0) continue;
-        for (int q = 0; q < 3; ++q) {
-          bl[q] = min(bl[q], S.box[6 * slot + q]);
-          bl[3 + q] = max(bl[3 + q], S.box[6 * slot + 3 + q]);
-          cl[q] = min(cl[q], S.cb[6 * slot + q]);
-          cl[3 + q] = max(cl[3 + q], S.cb[6 * slot + 3 + q]);
-        }
-      }
-      for (int q = 0; q < 3; ++q) {
-        ch.lo[q] = o2f(bl[q]);
-        ch.hi[q] = o2f(bl[3 + q]);
-        ch.cblo[q] = o2d(cl[q]);
-        ch.cbhi[q] = o2d(cl[3 + q]);
+        bl[q] = fminf(bl[q], l[q]);
+        bh[q] = fmaxf(bh[q], h[q]);
       }
     }
-    ch.left = -1;
-    ch.first = gtid == 0 ? fst0 : fst1;
-    ch.count = gtid == 0 ? cnt0 : cnt1;
-    ch.depth = nd.depth + 1;
-    ch.axis = ch.plane = -1;
-    ch.flags = 0;
-    ch.tidx = -1;
-    ch.cost = 0.0;
-    A.nodes[c0 + gtid] = ch;
-    A.cand[2 * j + gtid] = (gtid == 0 ? leaf0 : leaf1) ? 0 : ch.count;
   }
-  if (gtid == 2) {
-    BNode* p = &A.nodes[id];
-    p->left = c0;
-    p->axis = axis;
-    p->plane = plane;
-    p->flags = flags;
-    p->cost = by_position ? 0.0 : best;
+  if (lane >= 48) c = 0;
+}
+
+__device__ void wave_subtree_regs(const Ctx& X, int id, const Bins& S, BNode* loc, RFrame* stk) {
+  const int lane = lane_id();
+  const int B = X.C.nbins;
+  BuildConst C = X.C;
+  C.inv_l2 = X.st->inv_l2;
+  const BNode nd = X.nodes[id];
+  const int base = nd.first;
+  const FacetRec* in = X.recs[nd.depth & 1] + base;
+  // lane i holds facet i of the subtree
+  float lo[3] = {0.f, 0.f, 0.f}, hi[3] = {0.f, 0.f, 0.f};
+  int fid = -1;
+  if (lane < nd.count) {
+    const FacetRec r = in[lane];
+    lo[0] = r.lo.x; lo[1] = r.lo.y; lo[2] = r.lo.z;
+    hi[0] = r.hi.x; hi[1] = r.hi.y; hi[2] = r.hi.z;
+    fid = __float_as_int(r.lo.w);
   }
-}
-
-constexpr int kBigThreads = 512;
-
-__global__ __launch_bounds__(kBigThreads) void k_level_big(LevelArgs A) {
-  extern __shared__ __align__(16) char lds[];
-  if ((int)blockIdx.x >= A.st->n_big) return;
-  process_node<kBigThreads>(A, A.sel[blockIdx.x],
-                            node_lds(lds, A.C.nbins, bin_copies(A.C.nbins, kBigThreads / 64)),
-                            threadIdx.x);
-}
-
-// smaller nodes: one wave each, several per work-group (no work-group barrier)
-__global__ __launch_bounds__(256) void k_level_small(LevelArgs A) {
-  extern __shared__ __align__(16) char lds[];
-  const int w = threadIdx.x >> 6;
-  const int q = blockIdx.x * (blockDim.x >> 6) + w;
-  if (q >= A.st->n_small) return;
-  process_node<64>(A, A.sel[q], node_lds(lds + w * node_lds_bytes(A.C.nbins, 1), A.C.nbins, 1),
-                   threadIdx.x & 63);
-}
-
-// Lists the children that stay internal; they become the next level,
-// numbered after every internal node so far, and are sorted into the big
-// and small lists (positions into the level list).  Updates the level state
-// and, for the host, a record {seq, next level size, nodes, internal nodes,
-// levels}.
-__global__ __launch_bounds__(kCompactThreads) void k_compact(
-    const int32_t* __restrict__ cand, int32_t* __restrict__ act_next, int32_t* __restrict__ big,
-    int32_t* __restrict__ small, BNode* __restrict__ nodes, LevelState* __restrict__ st,
-    int32_t* __restrict__ host_out, int seq) {
-  __shared__ int s_w[3][kCompactThreads / 64];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int active = st->active, child_base = st->child_base;
-  const int n_internal = st->n_internal, levels = st->levels;
-  const int tidx_base = n_internal + active;
-  const int m = 2 * active;
-  __syncthreads();  // every thread has read the state before thread 0 rewrites it
-  int base_out = 0, base_big = 0, base_small = 0;
-  for (int base = 0; base < m; base += kCompactThreads) {
-    const int i = base + tid;
-    const int c = i < m ? cand[i] : 0;
-    const bool flag = c > 0;
-    const bool isbig = c > kBigNode;
-    const unsigned long long mk = __ballot(flag), mb = __ballot(isbig), ms = __ballot(flag && !isbig);
-    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  if (lane == 0) {
+    loc[0] = nd;
+    RFrame f;
+    f.li = 0;
+    f.r0 = 0;
+    f.cnt = nd.count;
+    f.pad = 0;
+    stk[0] = f;
+  }
+  int sp = 1, nloc = 1, max_depth = nd.depth;
+  const unsigned long long below = lanes_below();
+  while (sp > 0) {
+    wave_sync();
+    const RFrame f = stk[--sp];
+    const BNode t = loc[f.li];
+    const bool inr = lane >= f.r0 && lane < f.r0 + f.cnt;
+    const NodeSetup u = node_setup(C, t.depth, f.cnt, t.cblo, t.cbhi);
+    int axis = -1, plane = -1, flags = u.flags;
+    double best = INFINITY;
+    int mybins = 0;  // this lane's facet: bin on each axis, 8 bits each
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int b = u.axis_ok[a] ? bin_of(centroid(lo[a], hi[a]), t.cblo[a], u.scale[a], B) : 0;
+      mybins |= b << (8 * a);
+    }
+    if (!u.forced) {
+      const double clo[3] = {t.lo[0], t.lo[1], t.lo[2]}, chi[3] = {t.hi[0], t.hi[1], t.hi[2]};
+      if (B == 16) {
+        int c;
+        float bl[3], bh[3];
+        bins16_from_lanes(f.r0, f.cnt, mybins, lo, hi, c, bl, bh);
+        eval16(c, bl, bh, C, u, clo, chi, f.cnt, axis, plane, best);
+      } else {
+        bins_clear(S, B, lane, 64);
+        wave_sync();
+        if (inr) {
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            if (!u.axis_ok[a]) continue;
+            const int slot = a * B + ((mybins >> (8 * a)) & 255);
+            atomicAdd(&S.cnt[slot], 1);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+              atomicMin(&S.box[6 * slot + q], f2o(lo[q]));
+              atomicMax(&S.box[6 * slot + 3 + q], f2o(hi[q]));
+            }
+          }
+        }
+        wave_sync();
+        wave_eval_any(S.cnt, S.box, C, u, clo, chi, f.cnt, axis, plane, best);
+      }
+      if (axis < 0) flags |= 2;
+    }
+    const bool by_position = axis < 0;
+    const bool g = by_position ? lane - f.r0 < f.cnt / 2
+                               : ((mybins >> (8 * max(axis, 0))) & 255) < plane;
+    const unsigned long long ml = __ballot(inr && g), mr = __ballot(inr && !g);
+    const int nleft = __popcll(ml);
+    const int dst = !inr ? lane
+                    : g ? f.r0 + __popcll(ml & below)
+                        : f.r0 + nleft + __popcll(mr & below);
+    // stable partition of the node's lanes: every lane sends its record to dst
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      lo[q] = __int_as_float(__builtin_amdgcn_ds_permute(dst * 4, __float_as_int(lo[q])));
+      hi[q] = __int_as_float(__builtin_amdgcn_ds_permute(dst * 4, __float_as_int(hi[q])));
+    }
+    fid = __builtin_amdgcn_ds_permute(dst * 4, fid);
+    // child volumes and centroid bounds
+    const int side = !inr ? -1 : (lane < f.r0 + nleft ? 0 : 1);
+    const int kc[2] = {nleft, f.cnt - nleft};
+    const int c0 = nloc;  // local pair (c0, c0 + 1)
+    nloc += 2;
+    if (nloc > kLocal) {  // cannot happen: a subtree of <= 64 facets has < 128 nodes
+      if (lane == 0) set_err(X.st, 32);
+      return;
+    }
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd) {
+      BNode ch;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const bool m = side == sd;
+        const double c = centroid(lo[q], hi[q]);
+        ch.lo[q] = wmin(m ? lo[q] : INFINITY);
+        ch.hi[q] = wmax(m ? hi[q] : -INFINITY);
+        ch.cblo[q] = wmin(m ? c : (double)INFINITY);
+        ch.cbhi[q] = wmax(m ? c : -(double)INFINITY);
+      }
+      ch.left = -1;
+      ch.first = base + (sd == 0 ? f.r0 : f.r0 + nleft);
+      ch.count = kc[sd];
+      ch.depth = t.depth + 1;
+      ch.axis = ch.plane = -1;
+      ch.flags = 0;
+      ch.tidx = -1;
+      ch.cost = 0.0;
+      if (lane == 0) loc[c0 + sd] = ch;
+    }
     if (lane == 0) {
-      s_w[0][wave] = __popcll(mk);
-      s_w[1][wave] = __popcll(mb);
-      s_w[2][wave] = __popcll(ms);
+      BNode* pn = &loc[f.li];
+      pn->left = c0;
+      pn->axis = axis;
+      pn->plane = plane;
+      pn->flags = flags;
+      pn->cost = by_position ? 0.0 : best;
     }
-    __syncthreads();
-    int pre[3] = {0, 0, 0}, tot[3] = {0, 0, 0};
-    for (int w = 0; w < kCompactThreads / 64; ++w)
-      for (int q = 0; q < 3; ++q) {
-        if (w < wave) pre[q] += s_w[q][w];
-        tot[q] += s_w[q][w];
+    max_depth = max(max_depth, t.depth + 1);
+    // leaves: their facets are final; other children go on the stack (right first)
+    for (int sd = 1; sd >= 0; --sd) {
+      if (kc[sd] <= C.max_leaf) {
+        if (side == sd) X.perm[base + lane] = fid;
+        continue;
       }
-    if (flag) {
-      const int pos = base_out + pre[0] + __popcll(mk & below);
-      act_next[pos] = child_base + i;
-      nodes[child_base + i].tidx = tidx_base + pos;
-      if (isbig) big[base_big + pre[1] + __popcll(mb & below)] = pos;
-      else small[base_small + pre[2] + __popcll(ms & below)] = pos;
+      if (sp >= kRStack) {  // cannot happen: a subtree of <= 64 facets is shallower
+        if (lane == 0) set_err(X.st, 32);
+        return;
+      }
+      if (lane == 0) {
+        RFrame ch;
+        ch.li = c0 + sd;
+        ch.r0 = sd == 0 ? f.r0 : f.r0 + nleft;
+        ch.cnt = kc[sd];
+        ch.pad = 0;
+        stk[sp] = ch;
+      }
+      ++sp;
     }
-    base_out += tot[0];
-    base_big += tot[1];
-    base_small += tot[2];
-    __syncthreads();
   }
-  if (tid == 0) {
-    LevelState n;
-    n.active = base_out;
-    n.n_big = base_big;
-    n.n_small = base_small;
-    n.child_base = child_base + m;
-    n.n_internal = n_internal + active;
-    n.levels = levels + (active > 0 ? 1 : 0);
-    n.pad[0] = n.pad[1] = 0;
-    *st = n;
-    host_out[1] = n.active;
-    host_out[2] = n.child_base;  // nodes so far
-    host_out[3] = n.n_internal;
-    host_out[4] = n.levels;
-    __threadfence_system();
-    __atomic_store_n(&host_out[0], seq, __ATOMIC_RELEASE);
+  wave_sync();
+  // local nodes 1 .. nloc - 1 become global ids gbase .. gbase + nloc - 2
+  const int m = nloc - 1;
+  int gbase = 0;
+  if (lane == 0) {
+    gbase = atomicAdd(&X.st->total, m);
+    atomicMax(&X.st->depth, max_depth);
+  }
+  gbase = bcast(gbase);
+  if (gbase + m > X.node_cap) {
+    if (lane == 0) set_err(X.st, 8);
+    return;
+  }
+  // copy out as dwords; `left` (dword 6) is translated to global ids
+  constexpr int kWords = sizeof(BNode) / 4;
+  const int32_t* src = reinterpret_cast<const int32_t*>(loc + 1);
+  int32_t* dstn = reinterpret_cast<int32_t*>(X.nodes + gbase);
+  for (int w = lane; w < m * kWords; w += 64) {
+    int32_t v = src[w];
+    if (w % kWords == 6 && v > 0) v = gbase + v - 1;
+    dstn[w] = v;
+  }
+  if (lane == 0) {
+    BNode* p = &X.nodes[id];
+    p->left = gbase + loc[0].left - 1;
+    p->axis = loc[0].axis;
+    p->plane = loc[0].plane;
+    p->flags = loc[0].flags;
+    p->cost = loc[0].cost;
   }
 }
 
-// First level: the root (node 0) is the only node unless it is already a leaf.
-__global__ void k_level0(LevelState* st, int32_t* act, int32_t* big, int32_t* small, int n,
-                         int max_leaf) {
-  const bool split = n > max_leaf;
-  LevelState z;
-  z.active = split ? 1 : 0;
-  z.n_big = split && n > kBigNode ? 1 : 0;
-  z.n_small = split && n <= kBigNode ? 1 : 0;
-  z.child_base = 1;
-  z.n_internal = 0;
-  z.levels = 0;
-  z.pad[0] = z.pad[1] = 0;
-  *st = z;
-  act[0] = 0;
-  big[0] = 0;
-  small[0] = 0;
+__global__ __launch_bounds__(kWaveThreads) void k_s(Ctx X) {
+  extern __shared__ __align__(16) char lds[];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int B = X.C.nbins;
+  char* mine = lds + w * s_wave_bytes(B);
+  const Bins S = bins_at(mine, B, true);
+  BNode* loc = (BNode*)(mine + bins_bytes(B, true));
+  RFrame* rstk = (RFrame*)(mine + bins_bytes(B, true) + align8(sizeof(BNode) * kLocal));
+  int* gstk = (int*)(mine + bins_bytes(B, true) + align8(sizeof(BNode) * kLocal) +
+                     align8(sizeof(RFrame) * kRStack));
+  const int count = min(X.st->s_count, X.n);
+  const int nw = gridDim.x * (blockDim.x >> 6);
+  for (int i = blockIdx.x * (blockDim.x >> 6) + w; i < count; i += nw) {
+    if (lane == 0) gstk[0] = X.slist[i];
+    int sp = 1;
+    bool failed = false;
+    while (sp > 0 && !failed) {
+      wave_sync();
+      const int id = gstk[--sp];
+      const int k = X.nodes[id].count;
+      if (k <= kRegNode) {
+        Bins Sr = S;  // counts and boxes only
+        Sr.cb = nullptr;
+        wave_subtree_regs(X, id, Sr, loc, rstk);
+        continue;
+      }
+      int kc[2];
+      double ccb[2][6];
+      const int c0 = wave_split_global(X, id, S, kc[0], kc[1], ccb);
+      if (c0 < 0) {
+        failed = true;
+        break;
+      }
+      // the children's records and nodes were written by this wave
+      wave_global_sync();
+      for (int sd = 1; sd >= 0; --sd) {
+        if (kc[sd] <= X.C.max_leaf) continue;
+        if (sp >= kGStack) {
+          if (lane == 0) set_err(X.st, 64);
+          failed = true;
+          break;
+        }
+        if (lane == 0) gstk[sp] = c0 + sd;
+        ++sp;
+      }
+    }
+  }
+}
+
+// Host record at the end of the build: {sequence, nodes, depth, non-finite,
+// error, root lo xyz, root hi xyz}.
+__global__ void k_finish(const BuildState* st, const BNode* nodes, int32_t* host_out, int seq) {
+  if (threadIdx.x != 0) return;
+  host_out[1] = st->total;
+  host_out[2] = st->depth;
+  host_out[3] = st->nonfinite;
+  host_out[4] = st->error;
+  for (int q = 0; q < 3; ++q) {
+    host_out[5 + q] = __float_as_int(nodes[0].lo[q]);
+    host_out[8 + q] = __float_as_int(nodes[0].hi[q]);
+  }
+  __threadfence_system();
+  __atomic_store_n(&host_out[0], seq, __ATOMIC_RELEASE);
 }
 
 __device__ inline float4 f4(float x, float y, float z, float w) { return make_float4(x, y, z, w); }
+// traversal index of an internal node: its child pair
+__device__ inline int pair_index(const BNode& nd) { return (nd.left - 1) >> 1; }
 
 // Traversal nodes (one per internal node) and leaf-ordered facets.
-__global__ void k_emit(const BNode* __restrict__ nodes, int total, const int32_t* __restrict__ perm,
-                       const float* __restrict__ tris, TNode* __restrict__ tn,
-                       TFacet* __restrict__ tf) {
+__global__ void k_emit(const BNode* __restrict__ nodes, const BuildState* __restrict__ st,
+                       const int32_t* __restrict__ perm, const float* __restrict__ tris,
+                       TNode* __restrict__ tn, TFacet* __restrict__ tf) {
   int id = blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= total) return;
+  if (st->error || id >= min(st->total, 2 * st->n - 1)) return;
   const BNode nd = nodes[id];
   if (nd.left < 0) {
     for (int k = nd.first; k < nd.first + nd.count; ++k) {
@@ -917,14 +1444,14 @@ __global__ void k_emit(const BNode* __restrict__ nodes, int total, const int32_t
   t.a = f4(l.lo[0], l.hi[0], l.lo[1], l.hi[1]);
   t.b = f4(r.lo[0], r.hi[0], r.lo[1], r.hi[1]);
   t.c = f4(l.lo[2], l.hi[2], r.lo[2], r.hi[2]);
-  t.d = make_int4(l.left < 0 ? ~l.first : l.tidx, r.left < 0 ? ~r.first : r.tidx, 0, 0);
-  tn[nd.tidx] = t;
+  t.d = make_int4(l.left < 0 ? ~l.first : pair_index(l), r.left < 0 ? ~r.first : pair_index(r), 0, 0);
+  tn[pair_index(nd)] = t;
 }
 
 // ---------------------------------------------------------------------------
 // 4-wide traversal nodes: every even-depth internal node becomes one wide
 // node whose children are its grandchildren, or its children where those are
-// leaves.  Stored at the node's breadth-first internal index.
+// leaves.  Stored at the node's traversal index (its child pair).
 
 __device__ inline float pow2f(int e) { return __int_as_float((e + 127) << 23); }  // e in [-126, 127]
 
@@ -960,9 +1487,10 @@ __device__ inline unsigned quant_hi(float v, float lo, float sc) {
 }
 
 template <int FMT>
-__global__ void k_collapse(const BNode* __restrict__ nodes, int total, FNode4* __restrict__ wn) {
+__global__ void k_collapse(const BNode* __restrict__ nodes, const BuildState* __restrict__ st,
+                           FNode4* __restrict__ wn) {
   const int id = blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= total) return;
+  if (st->error || id >= min(st->total, 2 * st->n - 1)) return;
   const BNode nd = nodes[id];
   const bool root_leaf = id == 0 && nd.left < 0;
   if (!root_leaf && (nd.left < 0 || (nd.depth & 1))) return;
@@ -983,9 +1511,9 @@ __global__ void k_collapse(const BNode* __restrict__ nodes, int total, FNode4* _
     }
   }
   int ref[4] = {0, 0, 0, 0};
-  for (int c = 0; c < nc; ++c) ref[c] = ch[c].left < 0 ? ~ch[c].first : ch[c].tidx;
+  for (int c = 0; c < nc; ++c) ref[c] = ch[c].left < 0 ? ~ch[c].first : pair_index(ch[c]);
   const unsigned mask = (1u << nc) - 1u;
-  const int slot = root_leaf ? 0 : nd.tidx;
+  const int slot = root_leaf ? 0 : pair_index(nd);
   if (FMT == RT_NODE_F4) {
     FNode4 o;
     float v[6][4];
@@ -1038,8 +1566,7 @@ __global__ void k_collapse(const BNode* __restrict__ nodes, int total, FNode4* _
 
 namespace {
 
-// Pinned, device-mapped record the compaction kernel fills at the end of each
-// level: {sequence, next level size, big nodes, small nodes}.
+// Pinned, device-mapped record that k_finish fills at the end of the build.
 struct HostRecord {
   int32_t* host = nullptr;
   int32_t* dev = nullptr;
@@ -1062,15 +1589,22 @@ int host_record(HostRecord& r) {
 // stream synchronisation (which reports device errors) after a while.
 int wait_record(const HostRecord& r, int seq, hipStream_t s) {
   volatile int32_t* h = r.host;
-  for (long spin = 0; spin < 2000000; ++spin) {
+  for (long spin = 0; spin < 20000000; ++spin) {
     if (__atomic_load_n(&h[0], __ATOMIC_ACQUIRE) == seq) return RT_OK;
     if (spin > 1000) __builtin_ia32_pause();
   }
   int rc = check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
   if (rc != RT_OK) return rc;
   if (__atomic_load_n(&h[0], __ATOMIC_ACQUIRE) != seq)
-    return set_error(RT_EHIP, "rt_build: level record not written");
+    return set_error(RT_EHIP, "rt_build: build record not written");
   return RT_OK;
+}
+
+// Persistent work-groups for the wave schedules: enough to cover `items`
+// waves, at most a few per compute unit.
+int wave_groups(int64_t items, int waves_per_group) {
+  const int64_t g = (items + waves_per_group - 1) / waves_per_group;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, 2048));
 }
 
 }  // namespace
@@ -1084,103 +1618,109 @@ int build_tree(Buffers& B, const float* tris, int64_t n64, const rt_split_params
     if (rc != RT_OK) return rc;
   }
   static thread_local int seq = 0;
-  // counters: [0] non-finite flag, bytes 32..39 1/L^2, bytes 64..95 level state
-  double* inv_l2 = reinterpret_cast<double*>(B.counters + 8);
-  LevelState* st = reinterpret_cast<LevelState*>(B.counters + 16);
+  ++seq;
+  BuildState* st = reinterpret_cast<BuildState*>(B.counters);
 
-  HIPCHECK(hipMemsetAsync(B.counters, 0, 32 * sizeof(int32_t), s));
-  hipLaunchKernelGGL(k_root_init, dim3(1), dim3(64), 0, s, B.root_box);
-  const int pb = 256;
-  hipLaunchKernelGGL(k_prep, dim3((n + pb - 1) / pb), dim3(pb), 0, s, tris, n, B.recs_a, B.perm,
-                     B.counters, B.root_box);
-  hipLaunchKernelGGL(k_root, dim3(1), dim3(1), 0, s, B.root_box, n, B.nodes, inv_l2);
-  hipLaunchKernelGGL(k_level0, dim3(1), dim3(1), 0, s, st, B.act_a, B.big, B.small, n, p.max_leaf);
-  HIPCHECK(hipGetLastError());
-
-  BuildConst C;
+  Ctx X;
+  X.nodes = B.nodes;
+  X.recs[0] = B.recs_a;
+  X.recs[1] = B.recs_b;
+  X.perm = B.perm;
+  X.st = st;
+  X.mlist[0] = B.mlist;
+  X.mlist[1] = B.mlist + n;
+  X.slist = B.slist;
+  X.items[0] = B.aitems;
+  X.items[1] = B.aitems + B.item_cap;
+  X.ccnt[0] = B.accnt;
+  X.ccnt[1] = B.accnt + (size_t)B.item_cap * 3 * RT_MAX_BINS;
+  X.abin_stride = bins_bytes(RT_MAX_BINS, true);
+  X.abins[0] = B.abins;
+  X.abins[1] = B.abins + (size_t)B.anode_cap * X.abin_stride;
+  X.n = n;
+  X.node_cap = 2 * n;
+  X.item_cap = (int)B.item_cap;
+  X.anode_cap = (int)B.anode_cap;
+  // big-node levels: enough for balanced halvings down to kBigNode, plus two
+  int la = 0;
+  if (n > kBigNode) {
+    while ((int64_t(kBigNode) << la) < n) ++la;
+    la = std::min(la + 2, kMaxPhaseLevels - 1);
+  }
+  // medium-node passes: balanced halvings from kBigNode down to kRegNode, plus three
+  int lm = 0;
+  if (n > kRegNode) {
+    while ((kRegNode << lm) < std::min(n, kBigNode)) ++lm;
+    lm = std::min(lm + 3, kMaxPhaseLevels - 1);
+  }
+  X.la = la;
+  X.lm = lm;
+  BuildConst& C = X.C;
   C.alpha = (double)p.alpha;
   C.t_isect = (double)p.t_isect;
   C.t_trav = (double)p.t_trav;
   for (int a = 0; a < 3; ++a) C.src[a] = (double)p.src[a];
-  C.inv_l2 = 0.0;
+  C.inv_l2 = 0.0;  // read from the device state by the kernels
   C.max_leaf = p.max_leaf;
   C.nbins = p.nbins;
   C.d_mode = p.d_mode;
   C.d_norm = p.d_norm;
   C.max_depth = p.max_depth;
   C.depth_limit = p.depth_limit;
+  const int Bn = p.nbins;
 
-  const size_t lds1 = node_lds_bytes(p.nbins, 1);
-  const size_t lds_big = node_lds_bytes(p.nbins, bin_copies(p.nbins, kBigThreads / 64));
-  const int small_groups = lds1 * 4 <= 48 * 1024 ? 4 : 2;  // node groups per small work-group
-  const int big_cap = n / (kBigNode + 1);                   // nodes above kBigNode facets
-  const int level_cap = n / (p.max_leaf + 1);               // internal nodes of one level
-  constexpr int kBatch = 4;                                 // levels queued per host wait
-
-  FacetRec* recs[2] = {B.recs_a, B.recs_b};
-  int32_t* acts[2] = {B.act_a, B.act_b};
-  int bound = n > p.max_leaf ? 1 : 0;  // upper bound on the size of the next level to run
-  int level = 0;
-  int total = 1, n_internal = 0, levels = 0;
-  while (bound > 0) {
-    for (int q = 0; q < kBatch; ++q, ++level) {
-      if (level > RT_MAX_DEPTH + 1)
-        return set_error(RT_EDEPTH, "rt_build: tree deeper than the depth limit");
-      LevelArgs A;
-      A.nodes = B.nodes;
-      A.in = recs[level & 1];
-      A.out = recs[(level + 1) & 1];
-      A.perm = B.perm;
-      A.act = acts[level & 1];
-      A.cand = B.cand;
-      A.inv_l2 = inv_l2;
-      A.st = st;
-      A.n = n;
-      A.C = C;
-      const int gb = std::min(bound, big_cap);
-      if (gb > 0) {
-        A.sel = B.big;
-        hipLaunchKernelGGL(k_level_big, dim3(gb), dim3(kBigThreads), lds_big, s, A);
-      }
-      const int gs = (bound + small_groups - 1) / small_groups;
-      A.sel = B.small;
-      hipLaunchKernelGGL(k_level_small, dim3(gs), dim3(64 * small_groups), lds1 * small_groups, s, A);
-      ++seq;
-      hipLaunchKernelGGL(k_compact, dim3(1), dim3(kCompactThreads), 0, s, B.cand,
-                         acts[(level + 1) & 1], B.big, B.small, B.nodes, st, rec.dev, seq);
-      bound = std::min(2 * bound, level_cap);
-    }
-    HIPCHECK(hipGetLastError());
-    {
-      int rc = wait_record(rec, seq, s);
-      if (rc != RT_OK) return rc;
-    }
-    bound = rec.host[1];
-    total = rec.host[2];
-    n_internal = rec.host[3];
-    levels = rec.host[4];
+  hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, s, B.counters, B.root_box, n);
+  const int pb = 256;
+  hipLaunchKernelGGL(k_prep, dim3((n + pb - 1) / pb), dim3(pb), 0, s, tris, n, B.recs_a, B.perm, st,
+                     B.root_box);
+  hipLaunchKernelGGL(k_root, dim3(1), dim3(256), 0, s, X, (const long long*)B.root_box);
+  const size_t lds_abin = a_copies(Bn) * bins_bytes(Bn, true);
+  const size_t lds_asplit = bins_bytes(Bn, true);
+  for (int l = 0; l < la; ++l) {
+    hipLaunchKernelGGL(k_a_bin, dim3(X.item_cap), dim3(kAThreads), lds_abin, s, X, l);
+    hipLaunchKernelGGL(k_a_split, dim3(X.item_cap), dim3(kAThreads), lds_asplit, s, X, l);
   }
+  const int m_waves = 4;
+  const int m_groups = wave_groups(n / (kRegNode + 1) + 1, m_waves);
+  for (int m = 0; m < lm; ++m)
+    hipLaunchKernelGGL(k_m, dim3(m_groups), dim3(64 * m_waves), m_waves * bins_bytes(Bn, true), s,
+                       X, m);
+  const int s_waves = (int)std::max<size_t>(1, std::min<size_t>(4, (60 * 1024) / s_wave_bytes(Bn)));
+  const int s_groups = wave_groups(n / (p.max_leaf + 1) + 1, s_waves);
+  hipLaunchKernelGGL(k_s, dim3(s_groups), dim3(64 * s_waves), s_waves * s_wave_bytes(Bn), s, X);
   const int eb = 256;
-  hipLaunchKernelGGL(k_emit, dim3((total + eb - 1) / eb), dim3(eb), 0, s, B.nodes, total, B.perm,
+  const int max_nodes = std::max(1, 2 * n - 1);
+  hipLaunchKernelGGL(k_emit, dim3((max_nodes + eb - 1) / eb), dim3(eb), 0, s, B.nodes, st, B.perm,
                      tris, B.tnodes, B.tfacets);
   if (p.node_format == RT_NODE_F4)
-    hipLaunchKernelGGL(k_collapse<RT_NODE_F4>, dim3((total + eb - 1) / eb), dim3(eb), 0, s,
-                       B.nodes, total, B.wnodes);
+    hipLaunchKernelGGL(k_collapse<RT_NODE_F4>, dim3((max_nodes + eb - 1) / eb), dim3(eb), 0, s,
+                       B.nodes, st, B.wnodes);
   else if (p.node_format == RT_NODE_Q4)
-    hipLaunchKernelGGL(k_collapse<RT_NODE_Q4>, dim3((total + eb - 1) / eb), dim3(eb), 0, s,
-                       B.nodes, total, B.wnodes);
+    hipLaunchKernelGGL(k_collapse<RT_NODE_Q4>, dim3((max_nodes + eb - 1) / eb), dim3(eb), 0, s,
+                       B.nodes, st, B.wnodes);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, st, B.nodes, rec.dev, seq);
   HIPCHECK(hipGetLastError());
-  int32_t nonfinite = 0;
-  HIPCHECK(hipMemcpyAsync(&nonfinite, B.counters + C_NONFINITE, 4, hipMemcpyDeviceToHost, s));
-  HIPCHECK(hipStreamSynchronize(s));
-  if (nonfinite) return set_error(RT_EINVAL, "rt_build: a facet has a non-finite vertex");
-
+  {
+    int rc = wait_record(rec, seq, s);
+    if (rc != RT_OK) return rc;
+  }
+  const int32_t* h = rec.host;
+  if (h[3]) return set_error(RT_EINVAL, "rt_build: a facet has a non-finite vertex");
+  if (h[4]) return set_error(RT_EHIP, "rt_build: internal capacity check failed (code " +
+                                          std::to_string(h[4]) + ")");
+  const int total = h[1];
+  const int n_internal = (total - 1) / 2;
   info->n_tris = n;
   info->n_nodes = total;
   info->n_internal = n_internal;
   info->n_leaves = total - n_internal;
-  info->depth = levels;  // deepest leaf depth (root alone = 0)
-  info->n_levels = levels;
+  info->depth = h[2];  // deepest leaf depth (root alone = 0)
+  info->n_levels = h[2] + 1;
+  for (int q = 0; q < 3; ++q) {
+    int32_t lo = h[5 + q], hi = h[8 + q];
+    std::memcpy(&info->root_lo[q], &lo, 4);
+    std::memcpy(&info->root_hi[q], &hi, 4);
+  }
   const int64_t node_bytes = p.node_format == RT_NODE_F4 ? sizeof(FNode4)
                              : p.node_format == RT_NODE_Q4 ? sizeof(QNode4) : sizeof(TNode);
   info->node_format = p.node_format;

@@ -10,15 +10,17 @@
 
 namespace rt {
 
-// ---- build-time node (one per binary tree node, breadth-first order) ----
-// The two children of a node are stored next to each other.
+// ---- build-time node ----
+// Node 0 is the root; the two children of a node are stored next to each
+// other (left, left + 1), so an internal node is identified by its child pair
+// (left - 1) / 2, which is also its traversal node index.
 struct BNode {
   float lo[3], hi[3];      // volume: union of the facets' boxes
   int32_t left;            // left child id, -1 leaf
   int32_t first, count;    // facet range in the reference order
   int32_t depth;
   int32_t axis, plane, flags;
-  int32_t tidx;            // index in the traversal node array (internal nodes)
+  int32_t tidx;            // unused (kept for the record layout)
   double cost;
   double cblo[3], cbhi[3]; // bounds of the facets' centroids
 };
@@ -65,19 +67,49 @@ struct alignas(16) FacetRec {
   float4 lo, hi;
 };
 
+// One chunk of a big node's facets, binned and partitioned by one work-group.
+struct AItem {
+  int32_t node;        // node id
+  int32_t slot;        // the node's bin slot on its level
+  int32_t begin, end;  // facet range relative to the node's first facet
+  int32_t first_item;  // list index of the node's first chunk
+  int32_t pad[3];
+};
+
+// Build bookkeeping kept on the device: no pass waits for the host.
+constexpr int kMaxPhaseLevels = 64;
+struct BuildState {
+  int32_t nonfinite;   // a facet has a non-finite vertex
+  int32_t total;       // nodes allocated
+  int32_t depth;       // deepest node
+  int32_t error;       // an internal capacity check failed
+  int32_t s_count;     // subtree roots for the subtree phase
+  int32_t s_next;
+  int32_t n;           // facets of the build
+  int32_t pad;
+  double inv_l2;       // 1 / squared root diagonal (0 if the root is a point)
+  int32_t a_items[kMaxPhaseLevels + 1];  // chunk items per big-node level
+  int32_t a_nodes[kMaxPhaseLevels + 1];  // big nodes per level
+  int32_t m_count[kMaxPhaseLevels + 1];  // nodes per medium-node pass
+  int32_t m_next[kMaxPhaseLevels + 1];
+};
+constexpr int kStateWords = 1024;  // int32 words reserved for BuildState
+static_assert(sizeof(BuildState) <= kStateWords * 4, "BuildState too large");
+
 struct Buffers {
   // build scratch
-  FacetRec* recs_a = nullptr;  // [n] facet records, ping-pong between levels
+  FacetRec* recs_a = nullptr;  // [n] facet records, ping-pong by node depth parity
   FacetRec* recs_b = nullptr;
   int32_t* perm = nullptr;  // [n] final leaf order
   BNode* nodes = nullptr;   // [2n - 1]
-  int32_t* act_a = nullptr; // [n] active node ids
-  int32_t* act_b = nullptr;
-  int32_t* cand = nullptr;  // [2n] facet count of a child that stays internal, else 0
-  int32_t* big = nullptr;   // [n] level positions of nodes above the big-node size
-  int32_t* small = nullptr; // [n] level positions of the other nodes
-  int32_t* counters = nullptr;  // small device counters
+  int32_t* mlist = nullptr; // [2][n] medium-node lists (ping-pong by pass)
+  int32_t* slist = nullptr; // [n] subtree roots
+  AItem* aitems = nullptr;  // [2][item_cap] big-node chunks (ping-pong by level)
+  int32_t* accnt = nullptr; // [2][item_cap][3 RT_MAX_BINS] per-chunk bin counts
+  char* abins = nullptr;    // [2][node_cap][bin bytes] per-node bins of big nodes
+  int32_t* counters = nullptr;   // [kStateWords] BuildState
   long long* root_box = nullptr; // ordered-int root bounds (6 float + 6 double)
+  int64_t item_cap = 0, anode_cap = 0;
   // traversal data
   TNode* tnodes = nullptr;  // [max(n_internal, 1)]
   FNode4* wnodes = nullptr; // [max(n_internal, 1)] wide nodes (QNode4 records use the first half)
@@ -86,6 +118,20 @@ struct Buffers {
   int64_t cap_n = 0;        // facets the buffers can hold
   int64_t bytes = 0;
 };
+
+// build sizes shared by the allocator and the build
+constexpr int kChunk = 512;     // facets per big-node chunk
+constexpr int kBigNode = 1024;  // nodes above this many facets are split chunk-wise
+constexpr int kRegNode = 64;    // subtrees at or below this many facets stay in registers
+inline int64_t item_capacity(int64_t n) { return n / kChunk + n / (kBigNode + 1) + 2; }
+inline int64_t anode_capacity(int64_t n) { return n / (kBigNode + 1) + 1; }
+// bytes of one bin set: counts, ordered-int boxes and (optionally) ordered-int64
+// centroid bounds for 3 axes of B bins
+__host__ __device__ inline size_t align8(size_t x) { return (x + 7) & ~size_t(7); }
+__host__ __device__ inline size_t bins_bytes(int B, bool with_cb) {
+  return align8(sizeof(int) * 3 * B) + align8(sizeof(int) * 3 * B * 6) +
+         (with_cb ? align8(sizeof(long long) * 3 * B * 6) : 0);
+}
 
 // Ordered integer images of floats: signed comparison of the images equals
 // the float order (finite values), so atomic integer min/max give exact float

@@ -414,10 +414,10 @@ def test_quantized_bounds_are_conservative(city, tmp_path):
         f = raw.view(np.float32).reshape(-1, 16)
         u = raw.view(np.uint32).reshape(-1, 16)
         refs = raw.view(np.int32).reshape(-1, 16)[:, 12:16]
-        # breadth-first internal index of every internal binary node
+        # traversal index of every internal binary node: its child pair
         internal = np.nonzero(nodes["left"] >= 0)[0]
         tidx = np.full(nodes.shape[0], -1)
-        tidx[internal] = np.arange(internal.size)      # internal nodes are numbered in order
+        tidx[internal] = (nodes["left"][internal] - 1) // 2
         checked = 0
         for b in internal[nodes["depth"][internal] % 2 == 0]:
             w = tidx[b]
