@@ -31,9 +31,9 @@ namespace {
 bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
 void free_buffers(Buffers& B) {
-  void* ptrs[] = {B.recs_a, B.recs_b,   B.perm,     B.nodes,  B.mlist,   B.slist,
-                  B.aitems, B.accnt,    B.abins,    B.counters, B.root_box, B.tnodes,
-                  B.tfacets, B.wnodes,  B.queue};
+  void* ptrs[] = {B.recs_a, B.recs_b, B.perm,   B.nodes,    B.cnodes,   B.used,
+                  B.rank,   B.bsum,   B.mfront, B.sfront,   B.aitems,   B.accnt,   B.abins,
+                  B.counters, B.root_box, B.tnodes, B.tfacets, B.wnodes, B.queue};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   B = Buffers();
@@ -62,11 +62,16 @@ int ensure_buffers(Buffers& B, int64_t n) {
   if (rc == RT_OK) rc = alloc(B.perm, nn, bytes);
   if (rc == RT_OK) rc = alloc(B.nodes, 2 * nn, bytes);
   const int64_t icap = item_capacity(n), acap = anode_capacity(n);
-  if (rc == RT_OK) rc = alloc(B.mlist, 2 * nn, bytes);
-  if (rc == RT_OK) rc = alloc(B.slist, nn, bytes);
+  if (rc == RT_OK) rc = alloc(B.cnodes, 2 * nn, bytes);
+  if (rc == RT_OK) rc = alloc(B.used, nn, bytes);
+  if (rc == RT_OK) rc = alloc(B.rank, nn, bytes);
+  if (rc == RT_OK) rc = alloc(B.bsum, 2 * (nn / kScanBlock + 1), bytes);
+  if (rc == RT_OK) rc = alloc(B.mfront, 2 * nn, bytes);
+  if (rc == RT_OK) rc = alloc(B.sfront, nn, bytes);
   if (rc == RT_OK) rc = alloc(B.aitems, 2 * (size_t)icap, bytes);
   if (rc == RT_OK) rc = alloc(B.accnt, 2 * (size_t)icap * 3 * RT_MAX_BINS, bytes);
-  if (rc == RT_OK) rc = alloc(B.abins, 2 * (size_t)acap * bins_bytes(RT_MAX_BINS, true), bytes);
+  if (rc == RT_OK)
+    rc = alloc(B.abins, 2 * (size_t)acap * kBinReplicas * bins_bytes(RT_MAX_BINS, true), bytes);
   if (rc == RT_OK) rc = alloc(B.counters, kStateWords, bytes);
   if (rc == RT_OK) rc = alloc(B.root_box, 12, bytes);
   if (rc == RT_OK) rc = alloc(B.tnodes, nn, bytes);
@@ -250,7 +255,7 @@ int rt_bvh_download(const rt_bvh* b, rt_node_rec* nodes, int64_t node_cap, int32
   const int64_t nn = b->info.n_nodes;
   BNode* tmp = new (std::nothrow) BNode[nn];
   if (!tmp) return set_error(RT_ENOMEM, "rt_bvh_download: host allocation failed");
-  rc = check_hip(hipMemcpy(tmp, b->buf.nodes, sizeof(BNode) * nn, hipMemcpyDeviceToHost), "hipMemcpy");
+  rc = check_hip(hipMemcpy(tmp, b->buf.cnodes, sizeof(BNode) * nn, hipMemcpyDeviceToHost), "hipMemcpy");
   if (rc == RT_OK)
     rc = check_hip(hipMemcpy(perm, b->buf.perm, sizeof(int32_t) * b->info.n_tris,
                              hipMemcpyDeviceToHost), "hipMemcpy");

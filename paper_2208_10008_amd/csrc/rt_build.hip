@@ -13,8 +13,9 @@
 //                 per lane, and the wave walks the subtree depth-first
 // A fixed number of passes is queued for each schedule; whatever is left over
 // moves on to the next schedule, which handles nodes of any size.  Node ids
-// come from an atomic counter (root 0, siblings adjacent), the lists between
-// passes live on the device, and the host reads a single record at the end.
+// follow from the split positions (no counter), pending nodes are filed by
+// their first facet, a final pass compacts the ids, and the host reads a
+// single record at the end.
 //
 // Every decision (bin index, Eq. (2) cost, argmin) is made in float64 with a
 // fixed operation order and no contraction into fused multiply-adds, so the
@@ -318,6 +319,35 @@ __device__ inline double dpp_d(double identity, double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
+// Wave-wide min / max: DPP inside each 16-lane row, then the four row results.
+constexpr int kQuadXor1 = 0xB1, kQuadXor2 = 0x4E, kRowHalfMirror = 0x141, kRowMirror = 0x140;
+__device__ inline float rmin(float v) {
+  v = fminf(v, dpp_f<kQuadXor1>(v, v));
+  v = fminf(v, dpp_f<kQuadXor2>(v, v));
+  v = fminf(v, dpp_f<kRowHalfMirror>(v, v));
+  v = fminf(v, dpp_f<kRowMirror>(v, v));
+  const float a = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+  const float b = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+  const float c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+  const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+  return fminf(fminf(a, b), fminf(c, d));
+}
+__device__ inline float rmax(float v) { return -rmin(-v); }
+__device__ inline double rlane(double v, int l) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)bits, l);
+  const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ inline double rmin(double v) {
+  v = fmin(v, dpp_d<kQuadXor1>(v, v));
+  v = fmin(v, dpp_d<kQuadXor2>(v, v));
+  v = fmin(v, dpp_d<kRowHalfMirror>(v, v));
+  v = fmin(v, dpp_d<kRowMirror>(v, v));
+  return fmin(fmin(rlane(v, 0), rlane(v, 16)), fmin(rlane(v, 32), rlane(v, 48)));
+}
+__device__ inline double rmax(double v) { return -rmin(-v); }
+
 // one step of the inclusive row scans: prefix from lower lanes, suffix from higher
 template <int K>
 __device__ inline void scan_step(int& pc, float pl[3], float ph[3], int& sc, float sl[3], float sh[3]) {
@@ -468,21 +498,22 @@ struct Ctx {
   FacetRec* recs[2];  // by node depth parity
   int32_t* perm;
   BuildState* st;
-  int32_t* mlist[2];
-  int32_t* slist;
+  int32_t* used;
+  int32_t* mfront[2];
+  int32_t* sfront;
   AItem* items[2];
   int32_t* ccnt[2];
   char* abins[2];
-  size_t abin_stride;
-  int n, node_cap, item_cap, anode_cap;
+  size_t abin_stride;  // bytes of one bin set; a node slot holds kBinReplicas of them
+  int n, item_cap, anode_cap;
   int la, lm;  // queued big-node levels and medium-node passes
   BuildConst C;
 };
 
 __device__ inline void set_err(BuildState* st, int bit) { atomicOr(&st->error, bit); }
 
-// Adds a big node to level `lvl`: its bin slot and its chunks.  Returns the
-// slot (the caller clears the bins), -1 on overflow.
+// Adds a big node to level `lvl`: a bin slot and its chunks.  Returns the
+// slot (the caller clears its bins), -1 on overflow.
 __device__ int push_big(const Ctx& X, int lvl, int id, int k) {
   const int slot = atomicAdd(&X.st->a_nodes[lvl], 1);
   const int nit = (k + kChunk - 1) / kChunk;
@@ -499,36 +530,38 @@ __device__ int push_big(const Ctx& X, int lvl, int id, int k) {
     a.begin = j * kChunk;
     a.end = min(k, (j + 1) * kChunk);
     a.first_item = base;
-    a.pad[0] = a.pad[1] = a.pad[2] = 0;
+    a.n_items = nit;
+    a.pad[0] = a.pad[1] = 0;
     it[base + j] = a;
   }
   return slot;
 }
-__device__ inline void push_m(const Ctx& X, int pass, int id) {
-  const int pos = atomicAdd(&X.st->m_count[pass], 1);
-  if (pos >= X.n) {
-    set_err(X.st, 2);
-    return;
-  }
-  X.mlist[pass & 1][pos] = id;
+__device__ inline char* node_bins(const Ctx& X, int lvl, int slot, int rep) {
+  return X.abins[lvl & 1] + ((size_t)slot * kBinReplicas + rep) * X.abin_stride;
 }
-__device__ inline void push_s(const Ctx& X, int id) {
-  const int pos = atomicAdd(&X.st->s_count, 1);
-  if (pos >= X.n) {
-    set_err(X.st, 4);
-    return;
-  }
-  X.slist[pos] = id;
+__device__ inline void clear_node_bins(const Ctx& X, int lvl, int slot, int t, int nt) {
+  for (int r = 0; r < kBinReplicas; ++r)
+    bins_clear(bins_at(node_bins(X, lvl, slot, r), X.C.nbins, true), X.C.nbins, t, nt);
 }
+// Medium nodes and subtree roots are filed under their first facet: no two
+// pending nodes share one, so no counter is needed.
+__device__ inline void push_m(const Ctx& X, int pass, int id, int first) {
+  X.mfront[pass & 1][first] = id;
+}
+__device__ inline void push_s(const Ctx& X, int id, int first) { X.sfront[first] = id; }
 
-// Writes the two children c0, c0 + 1 of `id` (ids reserved by the caller) and
-// the parent's split.  Returns c0, -1 on overflow.
-__device__ int make_children(const Ctx& X, int c0, int id, const BNode& nd, int axis, int plane,
-                             int flags, double cost, int nleft, const float lo[2][3],
-                             const float hi[2][3], const double clo[2][3], const double chi[2][3]) {
-  if (c0 + 2 > X.node_cap) {
+// Writes the two children of `id` and the parent's split.  The children's ids
+// come from the split boundary b (the left child's last facet): 2b + 1 and
+// 2b + 2.  Distinct internal nodes have distinct boundaries, so ids never
+// collide.  Returns the left child id.
+__device__ int make_children(const Ctx& X, int id, const BNode& nd, int axis, int plane, int flags,
+                             double cost, int nleft, const float lo[2][3], const float hi[2][3],
+                             const double clo[2][3], const double chi[2][3]) {
+  const int b = nd.first + nleft - 1;
+  const int c0 = 2 * b + 1;
+  if (nleft < 1 || nleft >= nd.count || b < 0 || b + 1 >= X.n) {  // both sides are never empty
     set_err(X.st, 8);
-    return -1;
+    return c0;
   }
   for (int side = 0; side < 2; ++side) {
     BNode ch;
@@ -554,7 +587,7 @@ __device__ int make_children(const Ctx& X, int c0, int id, const BNode& nd, int 
   p->plane = plane;
   p->flags = flags;
   p->cost = cost;
-  atomicMax(&X.st->depth, nd.depth + 1);
+  X.used[b] = nd.depth + 1;
   return c0;
 }
 
@@ -562,10 +595,7 @@ __device__ int make_children(const Ctx& X, int c0, int id, const BNode& nd, int 
 __global__ void k_init(int32_t* words, long long* root, int n) {
   for (int i = threadIdx.x; i < kStateWords; i += blockDim.x) words[i] = 0;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    reinterpret_cast<BuildState*>(words)->total = 1;
-    reinterpret_cast<BuildState*>(words)->n = n;
-  }
+  if (threadIdx.x == 0) reinterpret_cast<BuildState*>(words)->n = n;
   if (threadIdx.x < 3) {
     const int t = threadIdx.x;
     root[t] = f2o(INFINITY);
@@ -578,7 +608,9 @@ __global__ void k_init(int32_t* words, long long* root, int n) {
 __global__ __launch_bounds__(256) void k_prep(const float* __restrict__ tris, int n,
                                               FacetRec* __restrict__ recs, int32_t* __restrict__ perm,
                                               BuildState* __restrict__ st,
-                                              long long* __restrict__ root) {
+                                              long long* __restrict__ root, int32_t* __restrict__ used,
+                                              int32_t* __restrict__ mfront,
+                                              int32_t* __restrict__ sfront) {
   __shared__ int s_box[6];
   __shared__ long long s_cb[6];
   if (threadIdx.x < 6) {
@@ -606,6 +638,10 @@ __global__ __launch_bounds__(256) void k_prep(const float* __restrict__ tris, in
     r.hi = make_float4(hi[0], hi[1], hi[2], 0.f);
     recs[i] = r;
     perm[i] = i;  // final unless the facets are split
+    used[i] = 0;
+    mfront[i] = -1;
+    mfront[n + i] = -1;
+    sfront[i] = -1;
   }
   for (int a = 0; a < 3; ++a) {
     const float l = wmin(lo[a]), h = wmax(hi[a]);
@@ -630,6 +666,9 @@ __global__ __launch_bounds__(256) void k_prep(const float* __restrict__ tris, in
 // takes it (nothing when it is a leaf or a facet is not finite).
 __global__ __launch_bounds__(256) void k_root(Ctx X, const long long* root) {
   __shared__ int s_slot;
+  if (threadIdx.x == 0) s_slot = -1;
+  __syncthreads();
+  if (threadIdx.x == 0) {
   BNode r;
   for (int a = 0; a < 3; ++a) {
     r.lo[a] = o2f((int32_t)root[a]);
@@ -645,31 +684,62 @@ __global__ __launch_bounds__(256) void k_root(Ctx X, const long long* root) {
   r.flags = 0;
   r.tidx = -1;
   r.cost = 0.0;
-  if (threadIdx.x == 0) {
-    X.nodes[0] = r;
-    double ex = (double)r.hi[0] - (double)r.lo[0];
-    double ey = (double)r.hi[1] - (double)r.lo[1];
-    double ez = (double)r.hi[2] - (double)r.lo[2];
-    double l2 = (ex * ex + ey * ey) + ez * ez;
-    X.st->inv_l2 = l2 > 0.0 ? 1.0 / l2 : 0.0;
-    s_slot = -1;
-    if (X.st->nonfinite == 0 && X.n > X.C.max_leaf) {
-      const int to = classify(X.C, X.n, 0, r.cblo, r.cbhi, X.la > 0, X.lm > 0);
-      if (to == TO_A) s_slot = push_big(X, 0, 0, X.n);
-      else if (to == TO_M) push_m(X, 0, 0);
-      else push_s(X, 0);
-    }
+  X.nodes[0] = r;
+  double ex = (double)r.hi[0] - (double)r.lo[0];
+  double ey = (double)r.hi[1] - (double)r.lo[1];
+  double ez = (double)r.hi[2] - (double)r.lo[2];
+  double l2 = (ex * ex + ey * ey) + ez * ez;
+  X.st->inv_l2 = l2 > 0.0 ? 1.0 / l2 : 0.0;
+  if (X.st->nonfinite == 0 && X.n > X.C.max_leaf) {
+    const int to = classify(X.C, X.n, 0, r.cblo, r.cbhi, X.la > 0, X.lm > 0);
+    if (to == TO_A) s_slot = push_big(X, 0, 0, X.n);
+    else if (to == TO_M) push_m(X, 0, 0, 0);
+    else push_s(X, 0, 0);
+  }
   }
   __syncthreads();
-  if (s_slot >= 0)
-    bins_clear(bins_at(X.abins[0] + s_slot * X.abin_stride, X.C.nbins, true), X.C.nbins,
-               threadIdx.x, blockDim.x);
+  if (s_slot >= 0) clear_node_bins(X, 0, s_slot, threadIdx.x, blockDim.x);
 }
 
 // ---------------------------------------------------------------------------
+// Run of consecutive facets that fall in one bin of one axis, kept in
+// registers and merged into the bin when the bin changes.
+struct Run {
+  int bin, count;
+  float lo[3], hi[3];
+  double clo[3], chi[3];
+};
+__device__ inline void run_reset(Run& r, int bin) {
+  r.bin = bin;
+  r.count = 0;
+  for (int q = 0; q < 3; ++q) {
+    r.lo[q] = INFINITY;
+    r.hi[q] = -INFINITY;
+    r.clo[q] = INFINITY;
+    r.chi[q] = -INFINITY;
+  }
+}
+__device__ inline void run_add(Run& r, const float4& lo, const float4& hi, const double cu[3]) {
+  r.count += 1;
+  r.lo[0] = fminf(r.lo[0], lo.x); r.lo[1] = fminf(r.lo[1], lo.y); r.lo[2] = fminf(r.lo[2], lo.z);
+  r.hi[0] = fmaxf(r.hi[0], hi.x); r.hi[1] = fmaxf(r.hi[1], hi.y); r.hi[2] = fmaxf(r.hi[2], hi.z);
+  r.clo[0] = fmin(r.clo[0], cu[0]); r.clo[1] = fmin(r.clo[1], cu[1]); r.clo[2] = fmin(r.clo[2], cu[2]);
+  r.chi[0] = fmax(r.chi[0], cu[0]); r.chi[1] = fmax(r.chi[1], cu[1]); r.chi[2] = fmax(r.chi[2], cu[2]);
+}
+__device__ inline void run_flush(const Run& r, const Bins& S, int a, int B) {
+  if (r.count == 0) return;
+  const int slot = a * B + r.bin;
+  atomicAdd(&S.cnt[slot], r.count);
+  for (int q = 0; q < 3; ++q) {
+    atomicMin(&S.box[6 * slot + q], f2o(r.lo[q]));
+    atomicMax(&S.box[6 * slot + 3 + q], f2o(r.hi[q]));
+    atomicMin(&S.cb[6 * slot + q], d2o(r.clo[q]));
+    atomicMax(&S.cb[6 * slot + 3 + q], d2o(r.chi[q]));
+  }
+}
+
 // Big nodes, pass 1: one work-group bins one chunk into LDS (one bin copy per
-// wave while they fit), keeps the chunk's counts and adds its bins to the
-// node's bins with exact atomics.
+// wave while they fit) and stores the chunk's bins.
 constexpr int kAThreads = 256;
 __host__ __device__ inline int a_copies(int B) {
   const int fit = (int)((40 * 1024) / bins_bytes(B, true));
@@ -691,28 +761,37 @@ __global__ __launch_bounds__(kAThreads) void k_a_bin(Ctx X, int lvl) {
   const NodeSetup u = node_setup(X.C, nd.depth, nd.count, nd.cblo, nd.cbhi);
   const Bins S = bins_at(lds + ((tid >> 6) % ncopy) * cs, B, true);
   const FacetRec* in = X.recs[nd.depth & 1] + nd.first;
-  for (int i = it.begin + tid; i < it.end; i += kAThreads) {
-    const FacetRec r = in[i];
-    const float l[3] = {r.lo.x, r.lo.y, r.lo.z}, h[3] = {r.hi.x, r.hi.y, r.hi.z};
-    double c[3];
+  // each thread walks a contiguous run of the chunk; consecutive facets that
+  // share a bin are merged in registers before they reach LDS
+  constexpr int kPer = kChunk / kAThreads;
+  const int i0 = it.begin + tid * kPer;
+  FacetRec rr[kPer];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) c[q] = centroid(l[q], h[q]);
+  for (int v = 0; v < kPer; ++v) rr[v] = in[min(i0 + v, it.end - 1)];
+  Run run[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) run_reset(run[a], -1);
+#pragma unroll
+  for (int v = 0; v < kPer; ++v) {
+    if (i0 + v >= it.end) break;
+    const float4 lo = rr[v].lo, hi = rr[v].hi;
+    const double cu[3] = {centroid(lo.x, hi.x), centroid(lo.y, hi.y), centroid(lo.z, hi.z)};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       if (!u.axis_ok[a]) continue;
-      const int slot = a * B + bin_of(c[a], nd.cblo[a], u.scale[a], B);
-      atomicAdd(&S.cnt[slot], 1);
-#pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        atomicMin(&S.box[6 * slot + q], f2o(l[q]));
-        atomicMax(&S.box[6 * slot + 3 + q], f2o(h[q]));
-        atomicMin(&S.cb[6 * slot + q], d2o(c[q]));
-        atomicMax(&S.cb[6 * slot + 3 + q], d2o(c[q]));
+      const int b = bin_of(cu[a], nd.cblo[a], u.scale[a], B);
+      if (b != run[a].bin) {
+        run_flush(run[a], S, a, B);
+        run_reset(run[a], b);
       }
+      run_add(run[a], lo, hi, cu);
     }
   }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) run_flush(run[a], S, a, B);
   __syncthreads();
-  const Bins G = bins_at(X.abins[par] + it.slot * X.abin_stride, B, true);
+  // this chunk's counts, and its bins added to one replica of the node's bins
+  const Bins G = bins_at(node_bins(X, lvl, it.slot, blockIdx.x % kBinReplicas), B, true);
   int32_t* cc = X.ccnt[par] + (size_t)blockIdx.x * 3 * RT_MAX_BINS;
   for (int c = tid; c < 3 * B; c += kAThreads) {
     int cnt = 0;
@@ -741,17 +820,16 @@ __global__ __launch_bounds__(kAThreads) void k_a_bin(Ctx X, int lvl) {
   }
 }
 
-// Big nodes, pass 2: every work-group of a node evaluates Eq. (2) on the
-// node's bins (the same answer in each), places its chunk stably after the
-// left-going facets of the chunks before it, and the node's first chunk
-// creates the children and queues them.
+// Big nodes, pass 2: every work-group of a node folds the node's chunk bins
+// and evaluates Eq. (2) on them (the same answer in each), places its chunk
+// stably after the left-going facets of the chunks before it, and the node's
+// first chunk writes the children and queues them.
 __global__ __launch_bounds__(kAThreads) void k_a_split(Ctx X, int lvl) {
   extern __shared__ __align__(16) char lds[];
   __shared__ int s_pick[2];
   __shared__ double s_best;
   __shared__ int s_red[kAThreads / 64];
   __shared__ int s_w[2][kAThreads / 64];
-  __shared__ int s_slot[2];
   if ((int)blockIdx.x >= min(X.st->a_items[lvl], X.item_cap)) return;
   const int par = lvl & 1;
   const AItem it = X.items[par][blockIdx.x];
@@ -761,14 +839,30 @@ __global__ __launch_bounds__(kAThreads) void k_a_split(Ctx X, int lvl) {
   BuildConst C = X.C;
   C.inv_l2 = X.st->inv_l2;
   const Bins S = bins_at(lds, B, true);
+  // fold the replicas of the node's bins
   {
-    const Bins G = bins_at(X.abins[par] + it.slot * X.abin_stride, B, true);
+    Bins R[kBinReplicas];
+#pragma unroll
+    for (int r = 0; r < kBinReplicas; ++r) R[r] = bins_at(node_bins(X, lvl, it.slot, r), B, true);
     for (int c = tid; c < 3 * B; c += kAThreads) {
-      S.cnt[c] = G.cnt[c];
-      for (int q = 0; q < 6; ++q) {
-        S.box[6 * c + q] = G.box[6 * c + q];
-        S.cb[6 * c + q] = G.cb[6 * c + q];
+      int cnt = 0;
+#pragma unroll
+      for (int r = 0; r < kBinReplicas; ++r) cnt += R[r].cnt[c];
+      S.cnt[c] = cnt;
+    }
+    for (int e = tid; e < 3 * B * 6; e += kAThreads) {
+      const bool lo = e % 6 < 3;
+      int bx = R[0].box[e];
+      long long cb = R[0].cb[e];
+#pragma unroll
+      for (int r = 1; r < kBinReplicas; ++r) {
+        const int x = R[r].box[e];
+        const long long y = R[r].cb[e];
+        bx = lo ? min(bx, x) : max(bx, x);
+        cb = lo ? min(cb, y) : max(cb, y);
       }
+      S.box[e] = bx;
+      S.cb[e] = cb;
     }
   }
   __syncthreads();
@@ -856,71 +950,37 @@ __global__ __launch_bounds__(kAThreads) void k_a_split(Ctx X, int lvl) {
     lb += tl;
     rb += tr;
   }
-  if (it.begin != 0) return;  // the node's first chunk makes the children
+  if (it.begin != 0) return;  // the node's first chunk writes the children
   if (tid == 0) {
     float lo[2][3], hi[2][3];
     double clo[2][3], chi[2][3];
     bins_union(S, B, axis, 0, plane, lo[0], hi[0], clo[0], chi[0]);
     bins_union(S, B, axis, plane, B, lo[1], hi[1], clo[1], chi[1]);
-    const int c0 = make_children(X, atomicAdd(&X.st->total, 2), it.node, nd, axis, plane, u.flags,
-                                 s_best, nleft, lo, hi, clo, chi);
-    s_slot[0] = s_slot[1] = -1;
-    if (c0 >= 0) {
-      for (int side = 0; side < 2; ++side) {
-        const int kc = side == 0 ? nleft : k - nleft;
-        if (kc <= C.max_leaf) continue;
-        const int to = classify(C, kc, nd.depth + 1, clo[side], chi[side], lvl + 1 < X.la, X.lm > 0);
-        if (to == TO_A) s_slot[side] = push_big(X, lvl + 1, c0 + side, kc);
-        else if (to == TO_M) push_m(X, 0, c0 + side);
-        else push_s(X, c0 + side);
-      }
+    const int c0 = make_children(X, it.node, nd, axis, plane, u.flags, s_best, nleft, lo, hi, clo, chi);
+    for (int side = 0; side < 2; ++side) {
+      s_w[0][side] = -1;
+      const int kc = side == 0 ? nleft : k - nleft;
+      if (kc <= C.max_leaf) continue;
+      const int first = nd.first + (side == 0 ? 0 : nleft);
+      const int to = classify(C, kc, nd.depth + 1, clo[side], chi[side], lvl + 1 < X.la, X.lm > 0);
+      if (to == TO_A) s_w[0][side] = push_big(X, lvl + 1, c0 + side, kc);
+      else if (to == TO_M) push_m(X, 0, c0 + side, first);
+      else push_s(X, c0 + side, first);
     }
   }
   __syncthreads();
   for (int side = 0; side < 2; ++side)
-    if (s_slot[side] >= 0)
-      bins_clear(bins_at(X.abins[(lvl + 1) & 1] + s_slot[side] * X.abin_stride, B, true), B, tid,
-                 kAThreads);
+    if (s_w[0][side] >= 0) clear_node_bins(X, lvl + 1, s_w[0][side], tid, kAThreads);
 }
 
 // ---------------------------------------------------------------------------
 // One node split by one wave, facet records in global memory.  Returns the
-// left child id (wave-uniform), -1 on overflow.
-struct Run {
-  int bin, count;
-  float lo[3], hi[3];
-  double clo[3], chi[3];
-};
-__device__ inline void run_reset(Run& r, int bin) {
-  r.bin = bin;
-  r.count = 0;
-  for (int q = 0; q < 3; ++q) {
-    r.lo[q] = INFINITY;
-    r.hi[q] = -INFINITY;
-    r.clo[q] = INFINITY;
-    r.chi[q] = -INFINITY;
-  }
-}
-__device__ inline void run_flush(const Run& r, const Bins& S, int a, int B) {
-  if (r.count == 0) return;
-  const int slot = a * B + r.bin;
-  atomicAdd(&S.cnt[slot], r.count);
-  for (int q = 0; q < 3; ++q) {
-    atomicMin(&S.box[6 * slot + q], f2o(r.lo[q]));
-    atomicMax(&S.box[6 * slot + 3 + q], f2o(r.hi[q]));
-    atomicMin(&S.cb[6 * slot + q], d2o(r.clo[q]));
-    atomicMax(&S.cb[6 * slot + 3 + q], d2o(r.chi[q]));
-  }
-}
-
+// left child id (wave-uniform) and the children's sizes and centroid bounds.
 constexpr int kPartE = 8;  // consecutive records per lane and partition round
 
 __device__ int wave_split_global(const Ctx& X, int id, const Bins& S, int& kc0, int& kc1,
                                  double ccb[2][6]) {
   const int lane = lane_id();
-  // the child ids are reserved first: the atomic's round trip overlaps the binning
-  int c0 = 0;
-  if (lane == 0) c0 = atomicAdd(&X.st->total, 2);
   const BNode nd = X.nodes[id];
   const int k = nd.count, B = X.C.nbins;
   BuildConst C = X.C;
@@ -1071,9 +1131,8 @@ __device__ int wave_split_global(const Ctx& X, int id, const Bins& S, int& kc0, 
     bins_union(S, B, axis, plane, B, lo[1], hi[1], clo[1], chi[1]);
   }
   if (lane == 0)
-    c0 = make_children(X, c0, id, nd, axis, plane, flags, by_position ? 0.0 : best, nleft, lo, hi,
-                       clo, chi);
-  c0 = bcast(c0);
+    make_children(X, id, nd, axis, plane, flags, by_position ? 0.0 : best, nleft, lo, hi, clo, chi);
+  const int c0 = 2 * (nd.first + nleft - 1) + 1;
   kc0 = nleft;
   kc1 = k - nleft;
   for (int side = 0; side < 2; ++side)
@@ -1084,50 +1143,60 @@ __device__ int wave_split_global(const Ctx& X, int id, const Bins& S, int& kc0, 
   return c0;
 }
 
-// Medium nodes: persistent waves take nodes of pass `pass` from its list.
+// Medium nodes: one wave per window of kMWindow facet positions; a pending
+// node (more than kRegNode facets) is filed under its first facet, so a
+// window holds at most one.
+constexpr int kMWindow = kRegNode + 1;
 constexpr int kWaveThreads = 256;  // four independent waves per work-group
 __global__ __launch_bounds__(kWaveThreads) void k_m(Ctx X, int pass) {
   extern __shared__ __align__(16) char lds[];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int B = X.C.nbins;
   const Bins S = bins_at(lds + w * bins_bytes(B, true), B, true);
-  const int count = min(X.st->m_count[pass], X.n);
-  const int nw = gridDim.x * (blockDim.x >> 6);
-  for (int i = blockIdx.x * (blockDim.x >> 6) + w; i < count; i += nw) {
-    const int id = X.mlist[pass & 1][i];
-    const int depth = X.nodes[id].depth;
+  const int base = (blockIdx.x * (blockDim.x >> 6) + w) * kMWindow;
+  if (base >= X.n) return;
+  int32_t* front = X.mfront[pass & 1];
+  const int slot = base + lane;
+  const int mine = lane < kMWindow && slot < X.n ? front[slot] : -1;
+  if (mine >= 0) front[slot] = -1;  // free for pass + 2
+  unsigned long long todo = __ballot(mine >= 0);
+  while (todo) {
+    const int src = __ffsll((long long)todo) - 1;
+    todo &= todo - 1;
+    const int id = __shfl(mine, src);
+    const int depth = X.nodes[id].depth, first0 = X.nodes[id].first;
     int kc[2];
     double ccb[2][6];
     const int c0 = wave_split_global(X, id, S, kc[0], kc[1], ccb);
-    if (c0 < 0) break;
-    if (lane < 2 && kc[lane] > X.C.max_leaf) {  // one lane per child: the pushes overlap
+    if (lane < 2 && kc[lane] > X.C.max_leaf) {
       const double* cb = lane == 0 ? ccb[0] : ccb[1];
       const int to = classify(X.C, kc[lane], depth + 1, cb, cb + 3, false, pass + 1 < X.lm);
-      if (to == TO_M) push_m(X, pass + 1, c0 + lane);
-      else push_s(X, c0 + lane);
+      const int first = first0 + (lane == 0 ? 0 : kc[0]);
+      if (to == TO_M) push_m(X, pass + 1, c0 + lane, first);
+      else push_s(X, c0 + lane, first);
     }
     wave_sync();
   }
 }
 
 // ---------------------------------------------------------------------------
-// Subtrees.  A wave takes a subtree root and splits depth-first until every
-// node is a leaf.  Nodes above kRegNode facets are split from global memory;
-// a node at or below it is finished with its records in registers (lane i
-// holds the node's i-th facet), the partition being a permutation of lanes.
+// Subtrees.  A wave takes the subtree roots filed in its window of facet
+// positions and splits each depth-first until every node is a leaf.  Nodes
+// above kRegNode facets are split from global memory; a node at or below it
+// is finished with its records in registers (lane i holds the node's i-th
+// facet), the partition being a permutation of lanes.
 
-// Register subtrees keep their new nodes in LDS (local index 1, 2, ... in
-// sibling pairs) and move them to global ids with one reservation at the end.
-constexpr int kLocal = 2 * kRegNode;  // local node slots (slot 0: copy of the subtree root)
-struct RFrame {                       // stack entry: a local node and its lanes
-  int32_t li, r0, cnt, pad;
+// Node of a register subtree, kept on an LDS stack.
+struct RNode {
+  int32_t id, r0, cnt, depth;
+  float lo[3], hi[3];
+  double cblo[3], cbhi[3];
 };
-constexpr int kRStack = 64;           // a subtree of <= 64 facets is at most 63 splits deep
-constexpr int kGStack = 72;           // nodes above kRegNode waiting on the global path
+constexpr int kRStack = 64;   // a register subtree (<= kRegNode facets) is less deep
+constexpr int kGStack = 72;   // nodes above kRegNode waiting on the global path
 
 __host__ __device__ inline size_t s_wave_bytes(int B) {
-  return bins_bytes(B, true) + align8(sizeof(BNode) * kLocal) + align8(sizeof(RFrame) * kRStack) +
-         align8(sizeof(int) * kGStack);
+  return bins_bytes(B, true) + align8(sizeof(RNode) * kRStack) + align8(sizeof(int) * kGStack);
 }
 
 // Bins of the node on lanes [r0, r0 + cnt) with 16 bins: lane 16 a + b walks
@@ -1163,7 +1232,7 @@ __device__ inline void bins16_from_lanes(int r0, int cnt, int packed_bins, const
   if (lane >= 48) c = 0;
 }
 
-__device__ void wave_subtree_regs(const Ctx& X, int id, const Bins& S, BNode* loc, RFrame* stk) {
+__device__ void wave_subtree_regs(const Ctx& X, int id, const Bins& S, RNode* stk) {
   const int lane = lane_id();
   const int B = X.C.nbins;
   BuildConst C = X.C;
@@ -1181,22 +1250,26 @@ __device__ void wave_subtree_regs(const Ctx& X, int id, const Bins& S, BNode* lo
     fid = __float_as_int(r.lo.w);
   }
   if (lane == 0) {
-    loc[0] = nd;
-    RFrame f;
-    f.li = 0;
-    f.r0 = 0;
-    f.cnt = nd.count;
-    f.pad = 0;
-    stk[0] = f;
+    RNode t;
+    t.id = id;
+    t.r0 = 0;
+    t.cnt = nd.count;
+    t.depth = nd.depth;
+    for (int q = 0; q < 3; ++q) {
+      t.lo[q] = nd.lo[q];
+      t.hi[q] = nd.hi[q];
+      t.cblo[q] = nd.cblo[q];
+      t.cbhi[q] = nd.cbhi[q];
+    }
+    stk[0] = t;
   }
-  int sp = 1, nloc = 1, max_depth = nd.depth;
+  int sp = 1;
   const unsigned long long below = lanes_below();
   while (sp > 0) {
     wave_sync();
-    const RFrame f = stk[--sp];
-    const BNode t = loc[f.li];
-    const bool inr = lane >= f.r0 && lane < f.r0 + f.cnt;
-    const NodeSetup u = node_setup(C, t.depth, f.cnt, t.cblo, t.cbhi);
+    const RNode t = stk[--sp];
+    const bool inr = lane >= t.r0 && lane < t.r0 + t.cnt;
+    const NodeSetup u = node_setup(C, t.depth, t.cnt, t.cblo, t.cbhi);
     int axis = -1, plane = -1, flags = u.flags;
     double best = INFINITY;
     int mybins = 0;  // this lane's facet: bin on each axis, 8 bits each
@@ -1210,8 +1283,8 @@ __device__ void wave_subtree_regs(const Ctx& X, int id, const Bins& S, BNode* lo
       if (B == 16) {
         int c;
         float bl[3], bh[3];
-        bins16_from_lanes(f.r0, f.cnt, mybins, lo, hi, c, bl, bh);
-        eval16(c, bl, bh, C, u, clo, chi, f.cnt, axis, plane, best);
+        bins16_from_lanes(t.r0, t.cnt, mybins, lo, hi, c, bl, bh);
+        eval16(c, bl, bh, C, u, clo, chi, t.cnt, axis, plane, best);
       } else {
         bins_clear(S, B, lane, 64);
         wave_sync();
@@ -1229,18 +1302,18 @@ __device__ void wave_subtree_regs(const Ctx& X, int id, const Bins& S, BNode* lo
           }
         }
         wave_sync();
-        wave_eval_any(S.cnt, S.box, C, u, clo, chi, f.cnt, axis, plane, best);
+        wave_eval_any(S.cnt, S.box, C, u, clo, chi, t.cnt, axis, plane, best);
       }
       if (axis < 0) flags |= 2;
     }
     const bool by_position = axis < 0;
-    const bool g = by_position ? lane - f.r0 < f.cnt / 2
+    const bool g = by_position ? lane - t.r0 < t.cnt / 2
                                : ((mybins >> (8 * max(axis, 0))) & 255) < plane;
     const unsigned long long ml = __ballot(inr && g), mr = __ballot(inr && !g);
     const int nleft = __popcll(ml);
     const int dst = !inr ? lane
-                    : g ? f.r0 + __popcll(ml & below)
-                        : f.r0 + nleft + __popcll(mr & below);
+                    : g ? t.r0 + __popcll(ml & below)
+                        : t.r0 + nleft + __popcll(mr & below);
     // stable partition of the node's lanes: every lane sends its record to dst
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
@@ -1249,95 +1322,55 @@ __device__ void wave_subtree_regs(const Ctx& X, int id, const Bins& S, BNode* lo
     }
     fid = __builtin_amdgcn_ds_permute(dst * 4, fid);
     // child volumes and centroid bounds
-    const int side = !inr ? -1 : (lane < f.r0 + nleft ? 0 : 1);
-    const int kc[2] = {nleft, f.cnt - nleft};
-    const int c0 = nloc;  // local pair (c0, c0 + 1)
-    nloc += 2;
-    if (nloc > kLocal) {  // cannot happen: a subtree of <= 64 facets has < 128 nodes
-      if (lane == 0) set_err(X.st, 32);
-      return;
-    }
+    const int side = !inr ? -1 : (lane < t.r0 + nleft ? 0 : 1);
+    float clo_f[2][3], chi_f[2][3];
+    double ccl[2][3], cch[2][3];
 #pragma unroll
-    for (int sd = 0; sd < 2; ++sd) {
-      BNode ch;
+    for (int s = 0; s < 2; ++s)
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
-        const bool m = side == sd;
+        const bool m = side == s;
         const double c = centroid(lo[q], hi[q]);
-        ch.lo[q] = wmin(m ? lo[q] : INFINITY);
-        ch.hi[q] = wmax(m ? hi[q] : -INFINITY);
-        ch.cblo[q] = wmin(m ? c : (double)INFINITY);
-        ch.cbhi[q] = wmax(m ? c : -(double)INFINITY);
+        clo_f[s][q] = rmin(m ? lo[q] : INFINITY);
+        chi_f[s][q] = rmax(m ? hi[q] : -INFINITY);
+        ccl[s][q] = rmin(m ? c : (double)INFINITY);
+        cch[s][q] = rmax(m ? c : -(double)INFINITY);
       }
-      ch.left = -1;
-      ch.first = base + (sd == 0 ? f.r0 : f.r0 + nleft);
-      ch.count = kc[sd];
-      ch.depth = t.depth + 1;
-      ch.axis = ch.plane = -1;
-      ch.flags = 0;
-      ch.tidx = -1;
-      ch.cost = 0.0;
-      if (lane == 0) loc[c0 + sd] = ch;
-    }
-    if (lane == 0) {
-      BNode* pn = &loc[f.li];
-      pn->left = c0;
-      pn->axis = axis;
-      pn->plane = plane;
-      pn->flags = flags;
-      pn->cost = by_position ? 0.0 : best;
-    }
-    max_depth = max(max_depth, t.depth + 1);
+    BNode pn;
+    pn.first = base + t.r0;
+    pn.count = t.cnt;
+    pn.depth = t.depth;
+    if (lane == 0)
+      make_children(X, t.id, pn, axis, plane, flags, by_position ? 0.0 : best, nleft, clo_f, chi_f,
+                    ccl, cch);
+    const int c0 = 2 * (base + t.r0 + nleft - 1) + 1;
+    const int kc[2] = {nleft, t.cnt - nleft};
     // leaves: their facets are final; other children go on the stack (right first)
-    for (int sd = 1; sd >= 0; --sd) {
-      if (kc[sd] <= C.max_leaf) {
-        if (side == sd) X.perm[base + lane] = fid;
+    for (int s = 1; s >= 0; --s) {
+      if (kc[s] <= C.max_leaf) {
+        if (side == s) X.perm[base + lane] = fid;
         continue;
       }
-      if (sp >= kRStack) {  // cannot happen: a subtree of <= 64 facets is shallower
+      if (sp >= kRStack) {  // cannot happen: register subtrees are shallower
         if (lane == 0) set_err(X.st, 32);
         return;
       }
       if (lane == 0) {
-        RFrame ch;
-        ch.li = c0 + sd;
-        ch.r0 = sd == 0 ? f.r0 : f.r0 + nleft;
-        ch.cnt = kc[sd];
-        ch.pad = 0;
+        RNode ch;
+        ch.id = c0 + s;
+        ch.r0 = s == 0 ? t.r0 : t.r0 + nleft;
+        ch.cnt = kc[s];
+        ch.depth = t.depth + 1;
+        for (int q = 0; q < 3; ++q) {
+          ch.lo[q] = clo_f[s][q];
+          ch.hi[q] = chi_f[s][q];
+          ch.cblo[q] = ccl[s][q];
+          ch.cbhi[q] = cch[s][q];
+        }
         stk[sp] = ch;
       }
       ++sp;
     }
-  }
-  wave_sync();
-  // local nodes 1 .. nloc - 1 become global ids gbase .. gbase + nloc - 2
-  const int m = nloc - 1;
-  int gbase = 0;
-  if (lane == 0) {
-    gbase = atomicAdd(&X.st->total, m);
-    atomicMax(&X.st->depth, max_depth);
-  }
-  gbase = bcast(gbase);
-  if (gbase + m > X.node_cap) {
-    if (lane == 0) set_err(X.st, 8);
-    return;
-  }
-  // copy out as dwords; `left` (dword 6) is translated to global ids
-  constexpr int kWords = sizeof(BNode) / 4;
-  const int32_t* src = reinterpret_cast<const int32_t*>(loc + 1);
-  int32_t* dstn = reinterpret_cast<int32_t*>(X.nodes + gbase);
-  for (int w = lane; w < m * kWords; w += 64) {
-    int32_t v = src[w];
-    if (w % kWords == 6 && v > 0) v = gbase + v - 1;
-    dstn[w] = v;
-  }
-  if (lane == 0) {
-    BNode* p = &X.nodes[id];
-    p->left = gbase + loc[0].left - 1;
-    p->axis = loc[0].axis;
-    p->plane = loc[0].plane;
-    p->flags = loc[0].flags;
-    p->cost = loc[0].cost;
   }
 }
 
@@ -1347,14 +1380,21 @@ __global__ __launch_bounds__(kWaveThreads) void k_s(Ctx X) {
   const int B = X.C.nbins;
   char* mine = lds + w * s_wave_bytes(B);
   const Bins S = bins_at(mine, B, true);
-  BNode* loc = (BNode*)(mine + bins_bytes(B, true));
-  RFrame* rstk = (RFrame*)(mine + bins_bytes(B, true) + align8(sizeof(BNode) * kLocal));
-  int* gstk = (int*)(mine + bins_bytes(B, true) + align8(sizeof(BNode) * kLocal) +
-                     align8(sizeof(RFrame) * kRStack));
-  const int count = min(X.st->s_count, X.n);
-  const int nw = gridDim.x * (blockDim.x >> 6);
-  for (int i = blockIdx.x * (blockDim.x >> 6) + w; i < count; i += nw) {
-    if (lane == 0) gstk[0] = X.slist[i];
+  RNode* rstk = (RNode*)(mine + bins_bytes(B, true));
+  int* gstk = (int*)(mine + bins_bytes(B, true) + align8(sizeof(RNode) * kRStack));
+  // subtree roots hold more than max_leaf facets, so a window of
+  // min(64, max_leaf + 1) facet positions holds at most one of them
+  const int win = min(64, X.C.max_leaf + 1);
+  const int wbase = (blockIdx.x * (blockDim.x >> 6) + w) * win;
+  if (wbase >= X.n) return;
+  const int slot = wbase + lane;
+  const int root = lane < win && slot < X.n ? X.sfront[slot] : -1;
+  unsigned long long todo = __ballot(root >= 0);
+  while (todo) {
+    const int src = __ffsll((long long)todo) - 1;
+    todo &= todo - 1;
+    const int rid = __shfl(root, src);
+    if (lane == 0) gstk[0] = rid;
     int sp = 1;
     bool failed = false;
     while (sp > 0 && !failed) {
@@ -1364,16 +1404,12 @@ __global__ __launch_bounds__(kWaveThreads) void k_s(Ctx X) {
       if (k <= kRegNode) {
         Bins Sr = S;  // counts and boxes only
         Sr.cb = nullptr;
-        wave_subtree_regs(X, id, Sr, loc, rstk);
+        wave_subtree_regs(X, id, Sr, rstk);
         continue;
       }
       int kc[2];
       double ccb[2][6];
       const int c0 = wave_split_global(X, id, S, kc[0], kc[1], ccb);
-      if (c0 < 0) {
-        failed = true;
-        break;
-      }
       // the children's records and nodes were written by this wave
       wave_global_sync();
       for (int sd = 1; sd >= 0; --sd) {
@@ -1387,6 +1423,78 @@ __global__ __launch_bounds__(kWaveThreads) void k_s(Ctx X) {
         ++sp;
       }
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Compaction: the used split boundaries, in order, become traversal indices
+// 0, 1, ... (the root's and index 0 then trade places, so that traversal
+// starts at 0); node ids follow (children of index r are 2 r + 1, 2 r + 2).
+__global__ __launch_bounds__(kScanBlock) void k_count(const int32_t* __restrict__ used, int nb,
+                                                      int32_t* __restrict__ bsum,
+                                                      int32_t* __restrict__ bmax) {
+  __shared__ int s_c[kScanBlock / 64], s_m[kScanBlock / 64];
+  const int b = blockIdx.x * kScanBlock + threadIdx.x;
+  const int u = b < nb ? used[b] : 0;
+  int c = __popcll(__ballot(u > 0));
+  int m = u;
+  for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o));
+  const int wave = threadIdx.x >> 6;
+  if (lane_id() == 0) {
+    s_c[wave] = c;
+    s_m[wave] = m;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tc = 0, tm = 0;
+    for (int w = 0; w < kScanBlock / 64; ++w) {
+      tc += s_c[w];
+      tm = max(tm, s_m[w]);
+    }
+    bsum[blockIdx.x] = tc;
+    bmax[blockIdx.x] = tm;
+  }
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_rank(const int32_t* __restrict__ used, int nb,
+                                                     const int32_t* __restrict__ bsum,
+                                                     const int32_t* __restrict__ bmax,
+                                                     int32_t* __restrict__ rank,
+                                                     BuildState* __restrict__ st) {
+  __shared__ int s_w[kScanBlock / 64];
+  __shared__ int s_pre, s_max;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = lane_id();
+  const bool last = blockIdx.x == gridDim.x - 1;
+  // exclusive prefix of the earlier blocks (and, in the last block, the deepest child)
+  int pre = 0, dm = 0;
+  for (int j = tid; j < (int)blockIdx.x; j += kScanBlock) pre += bsum[j];
+  if (last)
+    for (int j = tid; j < (int)gridDim.x; j += kScanBlock) dm = max(dm, bmax[j]);
+  pre = wsum(pre);
+  for (int o = 32; o > 0; o >>= 1) dm = max(dm, __shfl_xor(dm, o));
+  if (lane == 0) s_w[wave] = pre;
+  if (tid == 0) s_max = 0;
+  __syncthreads();
+  if (lane == 0) atomicMax(&s_max, dm);
+  if (tid == 0) {
+    int t = 0;
+    for (int w = 0; w < kScanBlock / 64; ++w) t += s_w[w];
+    s_pre = t;
+  }
+  __syncthreads();
+  const int b = blockIdx.x * kScanBlock + tid;
+  const bool u = b < nb && used[b] > 0;
+  const unsigned long long m = __ballot(u);
+  if (lane == 0) s_w[wave] = __popcll(m);
+  __syncthreads();
+  int off = s_pre;
+  for (int w = 0; w < wave; ++w) off += s_w[w];
+  if (u) rank[b] = off + __popcll(m & lanes_below());
+  if (last && tid == 0) {
+    int t = s_pre;
+    for (int w = 0; w < kScanBlock / 64; ++w) t += s_w[w];
+    st->total = 2 * t + 1;
+    st->depth = s_max;
   }
 }
 
@@ -1410,42 +1518,70 @@ __device__ inline float4 f4(float x, float y, float z, float w) { return make_fl
 // traversal index of an internal node: its child pair
 __device__ inline int pair_index(const BNode& nd) { return (nd.left - 1) >> 1; }
 
-// Traversal nodes (one per internal node) and leaf-ordered facets.
+// One used split boundary b (or, for the extra last index, the root): copies
+// its two children to their compact ids, writes its traversal node and the
+// leaf-ordered facets of its leaf children.
+__device__ inline void emit_leaf(const BNode& nd, const int32_t* __restrict__ perm,
+                                 const float* __restrict__ tris, TFacet* __restrict__ tf) {
+  for (int k = nd.first; k < nd.first + nd.count; ++k) {
+    const int f = perm[k];
+    const float* v = tris + 9 * (int64_t)f;
+    const uint32_t tag = (uint32_t)f | (k == nd.first + nd.count - 1 ? kLastFacet : 0u);
+    TFacet o;
+    o.p0 = f4(v[0], v[1], v[2], __uint_as_float(tag));
+    o.p1 = f4(v[3], v[4], v[5], 0.f);
+    o.p2 = f4(v[6], v[7], v[8], 0.f);
+    tf[k] = o;
+  }
+}
+// Traversal starts at index 0, so the root's pair swaps its rank with rank 0.
+__device__ inline int remap(int r, int rr) { return r == rr ? 0 : (r == 0 ? rr : r); }
+__device__ inline int compact_left(int left, const int32_t* __restrict__ rank, int rr) {
+  return left < 0 ? -1 : 2 * remap(rank[(left - 1) >> 1], rr) + 1;
+}
+
 __global__ void k_emit(const BNode* __restrict__ nodes, const BuildState* __restrict__ st,
+                       const int32_t* __restrict__ used, const int32_t* __restrict__ rank,
                        const int32_t* __restrict__ perm, const float* __restrict__ tris,
-                       TNode* __restrict__ tn, TFacet* __restrict__ tf) {
-  int id = blockIdx.x * blockDim.x + threadIdx.x;
-  if (st->error || id >= min(st->total, 2 * st->n - 1)) return;
-  const BNode nd = nodes[id];
-  if (nd.left < 0) {
-    for (int k = nd.first; k < nd.first + nd.count; ++k) {
-      int f = perm[k];
-      const float* v = tris + 9 * (int64_t)f;
-      uint32_t tag = (uint32_t)f | (k == nd.first + nd.count - 1 ? kLastFacet : 0u);
-      TFacet o;
-      o.p0 = f4(v[0], v[1], v[2], __uint_as_float(tag));
-      o.p1 = f4(v[3], v[4], v[5], 0.f);
-      o.p2 = f4(v[6], v[7], v[8], 0.f);
-      tf[k] = o;
-    }
-    if (id == 0) {  // the whole scene is one leaf: a root with one child
+                       BNode* __restrict__ cn, TNode* __restrict__ tn, TFacet* __restrict__ tf) {
+  const int n = st->n;
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (st->error || b >= n) return;
+  const int root_left = nodes[0].left;
+  const int rr = root_left < 0 ? 0 : rank[(root_left - 1) >> 1];
+  if (b == n - 1) {  // the root (a boundary index that is never used)
+    BNode r = nodes[0];
+    r.left = compact_left(r.left, rank, rr);
+    cn[0] = r;
+    if (r.left < 0) {  // the whole scene is one leaf: a root with one empty child
+      emit_leaf(r, perm, tris, tf);
       TNode t;
-      t.a = f4(nd.lo[0], nd.hi[0], nd.lo[1], nd.hi[1]);
+      t.a = f4(r.lo[0], r.hi[0], r.lo[1], r.hi[1]);
       // an empty volume: lo = hi = +inf gives an empty slab on every axis
       t.b = f4(INFINITY, INFINITY, INFINITY, INFINITY);
-      t.c = f4(nd.lo[2], nd.hi[2], INFINITY, INFINITY);
+      t.c = f4(r.lo[2], r.hi[2], INFINITY, INFINITY);
       t.d = make_int4(~0, ~0, 0, 0);
       tn[0] = t;
     }
     return;
   }
-  const BNode l = nodes[nd.left], r = nodes[nd.left + 1];
+  if (used[b] <= 0) return;
+  const int r = remap(rank[b], rr);
+  BNode ch[2];
+  for (int side = 0; side < 2; ++side) {
+    ch[side] = nodes[2 * b + 1 + side];
+    ch[side].left = compact_left(ch[side].left, rank, rr);
+    cn[2 * r + 1 + side] = ch[side];
+    if (ch[side].left < 0) emit_leaf(ch[side], perm, tris, tf);
+  }
+  const BNode& l = ch[0];
+  const BNode& q = ch[1];
   TNode t;
   t.a = f4(l.lo[0], l.hi[0], l.lo[1], l.hi[1]);
-  t.b = f4(r.lo[0], r.hi[0], r.lo[1], r.hi[1]);
-  t.c = f4(l.lo[2], l.hi[2], r.lo[2], r.hi[2]);
-  t.d = make_int4(l.left < 0 ? ~l.first : pair_index(l), r.left < 0 ? ~r.first : pair_index(r), 0, 0);
-  tn[pair_index(nd)] = t;
+  t.b = f4(q.lo[0], q.hi[0], q.lo[1], q.hi[1]);
+  t.c = f4(l.lo[2], l.hi[2], q.lo[2], q.hi[2]);
+  t.d = make_int4(l.left < 0 ? ~l.first : pair_index(l), q.left < 0 ? ~q.first : pair_index(q), 0, 0);
+  tn[r] = t;
 }
 
 // ---------------------------------------------------------------------------
@@ -1600,13 +1736,6 @@ int wait_record(const HostRecord& r, int seq, hipStream_t s) {
   return RT_OK;
 }
 
-// Persistent work-groups for the wave schedules: enough to cover `items`
-// waves, at most a few per compute unit.
-int wave_groups(int64_t items, int waves_per_group) {
-  const int64_t g = (items + waves_per_group - 1) / waves_per_group;
-  return (int)std::max<int64_t>(1, std::min<int64_t>(g, 2048));
-}
-
 }  // namespace
 
 int build_tree(Buffers& B, const float* tris, int64_t n64, const rt_split_params& p,
@@ -1627,31 +1756,31 @@ int build_tree(Buffers& B, const float* tris, int64_t n64, const rt_split_params
   X.recs[1] = B.recs_b;
   X.perm = B.perm;
   X.st = st;
-  X.mlist[0] = B.mlist;
-  X.mlist[1] = B.mlist + n;
-  X.slist = B.slist;
+  X.used = B.used;
+  X.mfront[0] = B.mfront;
+  X.mfront[1] = B.mfront + n;
+  X.sfront = B.sfront;
   X.items[0] = B.aitems;
   X.items[1] = B.aitems + B.item_cap;
   X.ccnt[0] = B.accnt;
   X.ccnt[1] = B.accnt + (size_t)B.item_cap * 3 * RT_MAX_BINS;
   X.abin_stride = bins_bytes(RT_MAX_BINS, true);
   X.abins[0] = B.abins;
-  X.abins[1] = B.abins + (size_t)B.anode_cap * X.abin_stride;
+  X.abins[1] = B.abins + (size_t)B.anode_cap * kBinReplicas * X.abin_stride;
   X.n = n;
-  X.node_cap = 2 * n;
   X.item_cap = (int)B.item_cap;
   X.anode_cap = (int)B.anode_cap;
-  // big-node levels: enough for balanced halvings down to kBigNode, plus two
+  // big-node levels: enough for balanced halvings down to kBigNode, plus one
   int la = 0;
   if (n > kBigNode) {
     while ((int64_t(kBigNode) << la) < n) ++la;
-    la = std::min(la + 2, kMaxPhaseLevels - 1);
+    la = std::min(la + 1, kMaxPhaseLevels - 1);
   }
-  // medium-node passes: balanced halvings from kBigNode down to kRegNode, plus three
+  // medium-node passes: balanced halvings from kBigNode down to kRegNode, plus two
   int lm = 0;
   if (n > kRegNode) {
     while ((kRegNode << lm) < std::min(n, kBigNode)) ++lm;
-    lm = std::min(lm + 3, kMaxPhaseLevels - 1);
+    lm = std::min(lm + 2, kMaxPhaseLevels - 1);
   }
   X.la = la;
   X.lm = lm;
@@ -1672,7 +1801,7 @@ int build_tree(Buffers& B, const float* tris, int64_t n64, const rt_split_params
   hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, s, B.counters, B.root_box, n);
   const int pb = 256;
   hipLaunchKernelGGL(k_prep, dim3((n + pb - 1) / pb), dim3(pb), 0, s, tris, n, B.recs_a, B.perm, st,
-                     B.root_box);
+                     B.root_box, B.used, B.mfront, B.sfront);
   hipLaunchKernelGGL(k_root, dim3(1), dim3(256), 0, s, X, (const long long*)B.root_box);
   const size_t lds_abin = a_copies(Bn) * bins_bytes(Bn, true);
   const size_t lds_asplit = bins_bytes(Bn, true);
@@ -1680,25 +1809,33 @@ int build_tree(Buffers& B, const float* tris, int64_t n64, const rt_split_params
     hipLaunchKernelGGL(k_a_bin, dim3(X.item_cap), dim3(kAThreads), lds_abin, s, X, l);
     hipLaunchKernelGGL(k_a_split, dim3(X.item_cap), dim3(kAThreads), lds_asplit, s, X, l);
   }
-  const int m_waves = 4;
-  const int m_groups = wave_groups(n / (kRegNode + 1) + 1, m_waves);
+  // one wave per window of facet positions
+  const int m_windows = (n + kMWindow - 1) / kMWindow;
   for (int m = 0; m < lm; ++m)
-    hipLaunchKernelGGL(k_m, dim3(m_groups), dim3(64 * m_waves), m_waves * bins_bytes(Bn, true), s,
-                       X, m);
+    hipLaunchKernelGGL(k_m, dim3((m_windows + 3) / 4), dim3(256), 4 * bins_bytes(Bn, true), s, X, m);
   const int s_waves = (int)std::max<size_t>(1, std::min<size_t>(4, (60 * 1024) / s_wave_bytes(Bn)));
-  const int s_groups = wave_groups(n / (p.max_leaf + 1) + 1, s_waves);
-  hipLaunchKernelGGL(k_s, dim3(s_groups), dim3(64 * s_waves), s_waves * s_wave_bytes(Bn), s, X);
+  const int s_win = std::min(64, p.max_leaf + 1);
+  const int s_windows = (n + s_win - 1) / s_win;
+  hipLaunchKernelGGL(k_s, dim3((s_windows + s_waves - 1) / s_waves), dim3(64 * s_waves),
+                     s_waves * s_wave_bytes(Bn), s, X);
+  // compaction and traversal data
+  const int nb = std::max(n - 1, 0);  // split boundaries
+  const int nblk = std::max(1, (nb + kScanBlock - 1) / kScanBlock);
+  int32_t* bsum = B.bsum;
+  int32_t* bmax = B.bsum + (n / kScanBlock + 1);
+  hipLaunchKernelGGL(k_count, dim3(nblk), dim3(kScanBlock), 0, s, B.used, nb, bsum, bmax);
+  hipLaunchKernelGGL(k_rank, dim3(nblk), dim3(kScanBlock), 0, s, B.used, nb, bsum, bmax, B.rank, st);
   const int eb = 256;
+  hipLaunchKernelGGL(k_emit, dim3((n + eb - 1) / eb), dim3(eb), 0, s, B.nodes, st, B.used, B.rank,
+                     B.perm, tris, B.cnodes, B.tnodes, B.tfacets);
   const int max_nodes = std::max(1, 2 * n - 1);
-  hipLaunchKernelGGL(k_emit, dim3((max_nodes + eb - 1) / eb), dim3(eb), 0, s, B.nodes, st, B.perm,
-                     tris, B.tnodes, B.tfacets);
   if (p.node_format == RT_NODE_F4)
     hipLaunchKernelGGL(k_collapse<RT_NODE_F4>, dim3((max_nodes + eb - 1) / eb), dim3(eb), 0, s,
-                       B.nodes, st, B.wnodes);
+                       B.cnodes, st, B.wnodes);
   else if (p.node_format == RT_NODE_Q4)
     hipLaunchKernelGGL(k_collapse<RT_NODE_Q4>, dim3((max_nodes + eb - 1) / eb), dim3(eb), 0, s,
-                       B.nodes, st, B.wnodes);
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, st, B.nodes, rec.dev, seq);
+                       B.cnodes, st, B.wnodes);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, st, B.cnodes, rec.dev, seq);
   HIPCHECK(hipGetLastError());
   {
     int rc = wait_record(rec, seq, s);

@@ -73,27 +73,24 @@ struct AItem {
   int32_t slot;        // the node's bin slot on its level
   int32_t begin, end;  // facet range relative to the node's first facet
   int32_t first_item;  // list index of the node's first chunk
-  int32_t pad[3];
+  int32_t n_items;     // chunks of the node
+  int32_t pad[2];
 };
 
 // Build bookkeeping kept on the device: no pass waits for the host.
 constexpr int kMaxPhaseLevels = 64;
 struct BuildState {
   int32_t nonfinite;   // a facet has a non-finite vertex
-  int32_t total;       // nodes allocated
+  int32_t total;       // nodes of the finished tree
   int32_t depth;       // deepest node
   int32_t error;       // an internal capacity check failed
-  int32_t s_count;     // subtree roots for the subtree phase
-  int32_t s_next;
   int32_t n;           // facets of the build
-  int32_t pad;
+  int32_t pad[3];
   double inv_l2;       // 1 / squared root diagonal (0 if the root is a point)
   int32_t a_items[kMaxPhaseLevels + 1];  // chunk items per big-node level
   int32_t a_nodes[kMaxPhaseLevels + 1];  // big nodes per level
-  int32_t m_count[kMaxPhaseLevels + 1];  // nodes per medium-node pass
-  int32_t m_next[kMaxPhaseLevels + 1];
 };
-constexpr int kStateWords = 1024;  // int32 words reserved for BuildState
+constexpr int kStateWords = 512;  // int32 words reserved for BuildState
 static_assert(sizeof(BuildState) <= kStateWords * 4, "BuildState too large");
 
 struct Buffers {
@@ -101,12 +98,16 @@ struct Buffers {
   FacetRec* recs_a = nullptr;  // [n] facet records, ping-pong by node depth parity
   FacetRec* recs_b = nullptr;
   int32_t* perm = nullptr;  // [n] final leaf order
-  BNode* nodes = nullptr;   // [2n - 1]
-  int32_t* mlist = nullptr; // [2][n] medium-node lists (ping-pong by pass)
-  int32_t* slist = nullptr; // [n] subtree roots
+  BNode* nodes = nullptr;   // [2n] nodes at build ids: children of split boundary b are 2b+1, 2b+2
+  BNode* cnodes = nullptr;  // [2n] the finished tree, ids compacted (2 n_internal + 1 nodes)
+  int32_t* used = nullptr;  // [n] per split boundary: depth of its children, 0 if unused
+  int32_t* rank = nullptr;  // [n] per used split boundary: its compact pair index
+  int32_t* bsum = nullptr;  // [2][n / kScanBlock + 1] per-block used count and deepest child
+  int32_t* mfront = nullptr; // [2][n] medium nodes by first facet (ping-pong by pass), -1 none
+  int32_t* sfront = nullptr; // [n] subtree roots by first facet, -1 none
   AItem* aitems = nullptr;  // [2][item_cap] big-node chunks (ping-pong by level)
   int32_t* accnt = nullptr; // [2][item_cap][3 RT_MAX_BINS] per-chunk bin counts
-  char* abins = nullptr;    // [2][node_cap][bin bytes] per-node bins of big nodes
+  char* abins = nullptr;    // [2][anode_cap][kBinReplicas][bin bytes] bins of each big node
   int32_t* counters = nullptr;   // [kStateWords] BuildState
   long long* root_box = nullptr; // ordered-int root bounds (6 float + 6 double)
   int64_t item_cap = 0, anode_cap = 0;
@@ -122,7 +123,9 @@ struct Buffers {
 // build sizes shared by the allocator and the build
 constexpr int kChunk = 512;     // facets per big-node chunk
 constexpr int kBigNode = 1024;  // nodes above this many facets are split chunk-wise
-constexpr int kRegNode = 64;    // subtrees at or below this many facets stay in registers
+constexpr int kRegNode = 32;    // subtrees at or below this many facets stay in registers
+constexpr int kScanBlock = 1024;
+constexpr int kBinReplicas = 8; // copies of a big node's bins that chunks add into
 inline int64_t item_capacity(int64_t n) { return n / kChunk + n / (kBigNode + 1) + 2; }
 inline int64_t anode_capacity(int64_t n) { return n / (kBigNode + 1) + 1; }
 // bytes of one bin set: counts, ordered-int boxes and (optionally) ordered-int64
