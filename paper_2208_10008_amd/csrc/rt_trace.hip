@@ -9,6 +9,7 @@
 // facet id.  After a hit the ray may be reflected about the facet plane and
 // traced again; the path length is summed in float64.
 #include <hip/hip_runtime.h>
+#include <climits>
 
 #include <algorithm>
 #include <atomic>
@@ -282,6 +283,46 @@ __device__ Hit closest(const void* __restrict__ nodes, const TFacet* __restrict_
   h.t = r.tmax;
   h.u = h.v = 0.f;
   int best_id = 0x7fffffff;  // h.id, or the largest id while there is no hit
+  if constexpr (FMT == RT_NODE_BIN2) {
+    // speculative traversal: a lane parks the first leaf it reaches and keeps
+    // descending; leaves are tested once every lane has one parked
+    constexpr int kDone = INT_MIN;
+    int leaf = 0;  // parked leaf (< 0), 0 none
+    while (node != kDone) {
+      while (node >= 0) {
+        if (STATS) ++nvis;
+        const TNode nd = static_cast<const TNode*>(nodes)[node];
+        float n0, n1;
+        const bool h0 = slab(r, nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.c.x, nd.c.y, r.tmin, h.t, n0);
+        const bool h1 = slab(r, nd.b.x, nd.b.y, nd.b.z, nd.b.w, nd.c.z, nd.c.w, r.tmin, h.t, n1);
+        if (h0 && h1) {
+          const bool first0 = n0 <= n1;
+          st.push(first0 ? nd.d.y : nd.d.x);
+          node = first0 ? nd.d.x : nd.d.y;
+        } else if (h0) {
+          node = nd.d.x;
+        } else if (h1) {
+          node = nd.d.y;
+        } else if (!st.pop(node)) {
+          node = kDone;
+        }
+        if (node < 0 && node != kDone && leaf == 0) {
+          leaf = node;
+          if (!st.pop(node)) node = kDone;
+        }
+        if (__ballot(leaf == 0 && node != kDone) == 0ull) break;
+      }
+      while (leaf < 0) {
+        leaf_test<STATS>(tf, r, leaf, skip_pos, h, best_id, ntest);
+        leaf = 0;
+        if (node < 0 && node != kDone) {
+          leaf = node;
+          if (!st.pop(node)) node = kDone;
+        }
+      }
+    }
+    return h;
+  }
   for (;;) {
     while (node >= 0) {
       if (STATS) ++nvis;
@@ -517,8 +558,10 @@ void launch_sd(const Buffers& B, const float* rays, int64_t n, int max_b, rt_hit
 }
 
 // Stack entries a ray can need: one per binary level below the root, or up
-// to three per 4-wide level.  A short LDS stack keeps more waves resident.
-constexpr int kShortStack = 32;
+// to three per 4-wide level.  A short LDS stack keeps more waves resident:
+// 20 entries (5 KB per wave) let 8 waves share a compute unit's 160 KB.
+constexpr int kShortStack = 20;
+constexpr int kMidStack = 32;
 template <int FMT>
 constexpr int stack_need(int depth) {
   return FMT == RT_NODE_BIN2 ? depth : 3 * ((depth + 1) / 2);
@@ -531,6 +574,9 @@ void launch(const Buffers& B, int depth, const float* rays, int64_t n, int max_b
   if (stack_need<FMT>(depth) <= kShortStack)
     launch_sd<FMT, kShortStack, BOUNCE, SEG, STATS>(B, rays, n, max_b, out, path_len, n_hits, seg,
                                                     stats, grid, refill, s);
+  else if (stack_need<FMT>(depth) <= kMidStack)
+    launch_sd<FMT, kMidStack, BOUNCE, SEG, STATS>(B, rays, n, max_b, out, path_len, n_hits, seg,
+                                                  stats, grid, refill, s);
   else
     launch_sd<FMT, stack_need<FMT>(RT_MAX_DEPTH), BOUNCE, SEG, STATS>(B, rays, n, max_b, out,
                                                                       path_len, n_hits, seg,
