@@ -123,7 +123,7 @@ struct Buffers {
 // build sizes shared by the allocator and the build
 constexpr int kChunk = 512;     // facets per big-node chunk
 constexpr int kBigNode = 1024;  // nodes above this many facets are split chunk-wise
-constexpr int kRegNode = 32;    // subtrees at or below this many facets stay in registers
+constexpr int kRegNode = 16;    // subtrees at or below this many facets stay in registers
 constexpr int kScanBlock = 1024;
 constexpr int kBinReplicas = 8; // copies of a big node's bins that chunks add into
 inline int64_t item_capacity(int64_t n) { return n / kChunk + n / (kBigNode + 1) + 2; }
