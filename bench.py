@@ -16,7 +16,6 @@ comparison, facet tests and nodes per ray, per-step latency percentiles.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -47,12 +46,16 @@ def parse():
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one plain device copy of this size (counter calibration)")
+    ap.add_argument("--no-probe", action="store_true",
+                    help="skip the streaming-read probes (measured L2 / MALL / HBM ceilings)")
+    ap.add_argument("--no-stats", action="store_true",
+                    help="skip the instrumented launch (node and facet counts)")
     return ap.parse_args()
 
 
 def kernel_source_hash():
-    with open(TRACE_SRC, "rb") as f:
-        return hashlib.sha1(f.read()).hexdigest()[:12]
+    from paper_2208_10008_amd.traffic import source_sha1
+    return source_sha1(TRACE_SRC)
 
 
 def load_traffic(workload_name):
@@ -66,6 +69,33 @@ def load_traffic(workload_name):
     if rec.get("kernel_source_sha1") != kernel_source_hash() or rec.get("workload") != workload_name:
         return None
     return rec.get("hbm_bytes_per_launch")
+
+
+def probe_ceilings(R, torch):
+    """Streaming-read bandwidth (GB/s) from working sets that stay in each
+    XCD's L2 (2 MiB read whole by every work-group), in the Infinity Cache
+    (64 MiB: every work-group cycles over its own 64 KiB slice, 8 MiB per XCD,
+    more than its L2) and in HBM (4 GiB in disjoint slices)."""
+    groups = 1024
+    sink = torch.empty(groups, dtype=torch.int32, device="cuda")
+    big = torch.ones(4 << 28, dtype=torch.int32, device="cuda")  # 4 GiB
+    out = {}
+    for name, mib, span, passes in (("l2", 2, 2 << 20, 4), ("mall", 64, 64 << 10, 128),
+                                    ("hbm", 4096, 4 << 20, 1)):
+        buf = big[: mib << 18]
+        best = None
+        for _ in range(4):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            moved = R.rt_probe_read(buf, span, passes, groups, sink)
+            e1.record()
+            e1.synchronize()
+            ms = e0.elapsed_time(e1)
+            best = ms if best is None else min(best, ms)
+        out[name] = round(moved / (best * 1e-3) / 1e9, 1)
+    del big
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -134,9 +164,12 @@ def main():
     trace_mean_ms = float(np.mean(trace_ms))
 
     # instrumented launch (outside the timed region): nodes and facet tests
-    stats = torch.empty((n, 2), dtype=torch.int32, device="cuda")
-    R.rt_trace_ex(bvh.handle, rays, nb, out, path_len, n_hits, ray_stats=stats)
-    st = stats.cpu().numpy().astype(np.int64)
+    if args.no_stats:
+        st = np.zeros((n, 2), np.int64)
+    else:
+        stats = torch.empty((n, 2), dtype=torch.int32, device="cuda")
+        R.rt_trace_ex(bvh.handle, rays, nb, out, path_len, n_hits, ray_stats=stats)
+        st = stats.cpu().numpy().astype(np.int64)
     nodes_total, tests_total = int(st[:, 0].sum()), int(st[:, 1].sum())
     alg_bytes = segments * (RAY_BYTES + HIT_BYTES) + nodes_total * NODE_BYTES + tests_total * FACET_BYTES
     achieved = alg_bytes / (trace_mean_ms * 1e-3) / 1e9
@@ -144,12 +177,14 @@ def main():
     info = bvh.info()
 
     if args.copy_mib:
-        # a plain elementwise copy kernel: reads and writes copy_mib MiB each
+        # one plain copy kernel (k_probe_copy): reads and writes copy_mib MiB each
         a = torch.ones(args.copy_mib * 2 ** 18, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
         torch.cuda.synchronize()
-        torch.mul(a, 1.0, out=b)
+        R.rt_probe_copy(a, b)
         torch.cuda.synchronize()
+        del a, b
+    ceilings = None if args.no_probe else probe_ceilings(R, torch)
 
     result = {
         "metric": METRIC,
@@ -176,6 +211,8 @@ def main():
             "traffic": traffic,
             "kernel": "k_trace<bounce>", "kernel_ms": round(trace_mean_ms, 4),
             "alg_bytes_per_launch": alg_bytes,
+            "measured_ceilings_gbs": ceilings,
+            "frac_of_measured_l2": (round(achieved / ceilings["l2"], 4) if ceilings else None),
         },
         "segments_per_step": segments,
         "trace_only_mrays_s": round(segments / (trace_mean_ms * 1e-3) / 1e6, 2),
@@ -241,10 +278,24 @@ def cpu_baseline(w, alpha, max_leaf):
             break
     runs.sort()
     tot, build, segs = runs[len(runs) // 2]
+    # brute force (every ray against every facet, the definition of the hit):
+    # the 242-facet scene whole and a seeded subsample of this workload's rays
+    from rtgen import workloads
+    mc = workloads.microcell()
+    t0 = time.perf_counter()
+    oracle.brute(mc.tris, mc.rays, nthreads=threads)
+    t_mc = time.perf_counter() - t0
+    sub = np.random.default_rng(0).choice(w.n_rays, size=min(w.n_rays, 65536), replace=False)
+    t0 = time.perf_counter()
+    oracle.brute(w.tris, w.rays[np.sort(sub)], nthreads=threads)
+    t_sub = time.perf_counter() - t0
     return {"value": round(segs / tot / 1e6, 3), "unit": "Mrays/s", "cores": threads,
             "kind": "oracle", "seconds_per_step": round(tot, 3), "build_s": round(build, 3),
             "sample": f"whole workload: {w.n_rays} rays, <= {w.max_bounces} segments each, "
-                      f"float64 build + traversal, median of {len(runs)} runs"}
+                      f"float64 build + traversal, median of {len(runs)} runs",
+            "brute_force_mrays_s": {
+                mc.name: round(mc.n_rays / t_mc / 1e6, 4),
+                f"{w.name} (65536 primary rays)": round(len(sub) / t_sub / 1e6, 4)}}
 
 
 if __name__ == "__main__":

@@ -68,6 +68,7 @@ assert NODE_DTYPE.itemsize == 64
 EXPORTS = ("rt_split_params_default", "rt_build", "rt_rebuild", "rt_trace",
            "rt_trace_bounces", "rt_trace_ex", "rt_bvh_info_get", "rt_bvh_download",
            "rt_bvh_export_trace_nodes", "rt_bvh_destroy", "rt_last_error")
+PROBE_EXPORTS = ("rt_probe_read", "rt_probe_copy")  # include/rt_probe.h
 
 _lib = None
 
@@ -95,8 +96,11 @@ def load(path: str = LIB_PATH):
     lib.rt_bvh_destroy.restype = None
     lib.rt_last_error.argtypes = []
     lib.rt_last_error.restype = ctypes.c_char_p
+    lib.rt_probe_read.argtypes = [P, i64, i64, i32, i32, P, P]
+    lib.rt_probe_copy.argtypes = [P, P, i64, P]
     for name in ("rt_build", "rt_rebuild", "rt_trace", "rt_trace_bounces", "rt_trace_ex",
-                 "rt_bvh_info_get", "rt_bvh_download", "rt_bvh_export_trace_nodes"):
+                 "rt_bvh_info_get", "rt_bvh_download", "rt_bvh_export_trace_nodes",
+                 "rt_probe_read", "rt_probe_copy"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -219,6 +223,24 @@ def rt_bvh_export_trace_nodes(handle) -> np.ndarray:
     _check(lib.rt_bvh_export_trace_nodes(handle, buf.ctypes.data_as(ctypes.c_void_p),
                                          ctypes.byref(nbytes)))
     return buf
+
+
+def rt_probe_read(buf, span_bytes, passes, groups, sink, stream=None):
+    """Each of `groups` work-groups streams `span_bytes` of `buf` (a device
+    tensor) `passes` times; `sink` is a device int32 tensor of >= groups
+    entries.  Returns the bytes moved."""
+    nbytes = buf.numel() * buf.element_size()
+    _check(load().rt_probe_read(buf.data_ptr(), nbytes, span_bytes, passes, groups,
+                                sink.data_ptr(), _stream(stream)))
+    return span_bytes * passes * groups
+
+
+def rt_probe_copy(src, dst, stream=None):
+    """Plain device copy of src into dst (same byte size)."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() < nbytes:
+        raise RtError(RT_EINVAL, "rt_probe_copy: dst too small")
+    _check(load().rt_probe_copy(src.data_ptr(), dst.data_ptr(), nbytes, _stream(stream)))
 
 
 def rt_bvh_destroy(handle):

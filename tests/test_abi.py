@@ -13,16 +13,18 @@ import paper_2208_10008_amd as R
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "rt_mi355x.h")
+PROBE_HEADER = os.path.join(ROOT, "include", "rt_probe.h")
 
 
-def declared_functions():
-    text = open(HEADER).read()
+def declared_functions(header=HEADER):
+    text = open(header).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(rt_[a-z_]+)\s*\(", text)))
 
 
 def test_header_declares_expected_entry_points():
     assert set(declared_functions()) == set(R.EXPORTS)
+    assert set(declared_functions(PROBE_HEADER)) == set(R.PROBE_EXPORTS)
 
 
 def test_library_exports_every_declared_symbol():
@@ -33,6 +35,9 @@ def test_library_exports_every_declared_symbol():
                          text=True, check=True).stdout
     exported = {l.split()[-1] for l in out.splitlines() if " T " in l}
     assert set(declared_functions()) <= exported
+    assert set(declared_functions(PROBE_HEADER)) <= exported
+    for name in declared_functions(PROBE_HEADER):
+        assert hasattr(lib, name), name
 
 
 def test_library_is_gfx950_code(tmp_path):
@@ -132,3 +137,22 @@ def test_binding_rejects_host_tensors():
     torch = pytest.importorskip("torch")
     with pytest.raises(R.RtError):
         R.rt_build(torch.zeros((4, 9)), R.SplitParams())
+
+
+def test_probe_argument_checks():
+    lib = R.load()
+    buf = np.zeros(64, np.float32)
+    p = ctypes.c_void_p(buf.ctypes.data)
+    odd = ctypes.c_void_p(buf.ctypes.data + 4)
+    assert lib.rt_probe_read(None, 64, 64, 1, 1, p, None) == R.RT_EINVAL
+    assert lib.rt_probe_read(p, 64, 64, 1, 1, None, None) == R.RT_EINVAL
+    assert lib.rt_probe_read(odd, 64, 64, 1, 1, p, None) == R.RT_EINVAL
+    assert lib.rt_probe_read(p, 60, 48, 1, 1, p, None) == R.RT_EINVAL
+    assert lib.rt_probe_read(p, 64, 80, 1, 1, p, None) == R.RT_EINVAL    # span > bytes
+    assert lib.rt_probe_read(p, 64, 64, 0, 1, p, None) == R.RT_EINVAL
+    assert lib.rt_probe_read(p, 64, 64, 1, 0, p, None) == R.RT_EINVAL
+    assert lib.rt_probe_copy(None, p, 64, None) == R.RT_EINVAL
+    assert lib.rt_probe_copy(p, odd, 64, None) == R.RT_EINVAL
+    assert lib.rt_probe_copy(p, p, 64, None) == R.RT_EINVAL          # overlapping ranges
+    assert lib.rt_probe_copy(p, ctypes.c_void_p(buf.ctypes.data + 128), 0, None) == R.RT_EINVAL
+    assert b"rt_probe" in lib.rt_last_error()
