@@ -209,6 +209,65 @@ int rt_bvh_export_trace_nodes(const rt_bvh* b, void* host, int64_t* bytes);
 
 void rt_bvh_destroy(rt_bvh* b); /* NULL is a no-op; waits for the device */
 
+/* ---- batched trace (Sec. III-B for many transmitters and scenes) ---------
+ * Many queries -- each a resident tree, a set of launched rays and a bounce
+ * limit -- traced in one launch per node format.  Every query's results are
+ * exactly those of rt_trace_bounces on the same tree and rays: they do not
+ * depend on the other queries, their order or the launch shape. */
+typedef struct rt_query {
+  const rt_bvh* bvh;    /* resident tree (built, not destroyed while a launch is pending) */
+  const float* rays;    /* device float32 [n][8], 16-byte aligned */
+  int64_t n;            /* rays, >= 0 */
+  int32_t max_bounces;  /* 1..RT_MAX_BOUNCES: segments per chain */
+  int32_t status;       /* written by rt_batch_set: RT_OK, or RT_EINVAL and left out */
+  rt_hit* out;          /* device [max_bounces][n], 16-byte aligned */
+  double* path_len;     /* device [n] (float64 path length per chain) or NULL */
+  int32_t* n_hits;      /* device [n] (facets hit per chain) or NULL */
+} rt_query;
+
+#define RT_BATCH_DIRECT 0 /* one work-group per 64-ray batch of every query */
+#define RT_BATCH_QUEUE 1  /* persistent work-groups take 64-ray batches from an atomic counter */
+#define RT_ORDER_GIVEN 0  /* queries start in the order given */
+#define RT_ORDER_COST 1   /* queries with the most rays x bounces start first */
+
+typedef struct rt_batch_config {
+  int32_t mode;  /* RT_BATCH_* */
+  int32_t grid;  /* RT_BATCH_QUEUE: persistent work-groups, 0 = as many as fit the device */
+  int32_t order; /* RT_ORDER_* */
+  int32_t graph; /* 1: launch through a hipGraph (captured on a stream of the batch's own,
+                    launched on the caller's), captured again when the batch's shape (queries
+                    per format, batches, depths) or the configuration changes */
+} rt_batch_config;
+
+typedef struct rt_batch rt_batch; /* opaque: device query table, pinned staging, graph */
+
+/* New batch holding up to max_queries queries (1..65536); defaults: DIRECT,
+ * ORDER_COST, no graph.  Errors: RT_EINVAL, RT_ENOMEM, RT_EHIP. */
+int rt_batch_create(int32_t max_queries, rt_batch** out);
+
+/* Sets the queries (host array, copied; each query's status is written).
+ * Invalid queries (NULL or unbuilt tree, NULL or misaligned pointers, n < 0,
+ * bounces out of range) get RT_EINVAL and are left out; the others are kept.
+ * Waits until an earlier launch of this batch has read its table.
+ * Errors: RT_EINVAL (NULL batch or array, nq outside 0..max_queries). */
+int rt_batch_set(rt_batch* b, rt_query* queries, int32_t nq);
+
+int rt_batch_configure(rt_batch* b, const rt_batch_config* cfg); /* RT_EINVAL on bad values */
+int rt_batch_get_config(const rt_batch* b, rt_batch_config* cfg);
+
+/* Enqueues the table upload and the trace launches on stream s (no wait).
+ * Errors: RT_EINVAL, RT_EHIP. */
+int rt_batch_launch(rt_batch* b, hipStream_t s);
+
+/* Times every launch shape (DIRECT and QUEUE at 1x and 2x the resident
+ * work-groups, both orders) over `reps` launches each on stream s, keeps the
+ * fastest (the graph flag is left as it is) and returns its average time per
+ * launch in *ms (may be NULL).  Writes the results of the queries several
+ * times over.  Synchronises the stream.  Errors: RT_EINVAL, RT_EHIP. */
+int rt_batch_autotune(rt_batch* b, int32_t reps, hipStream_t s, float* ms);
+
+void rt_batch_destroy(rt_batch* b); /* NULL is a no-op; waits for the device */
+
 const char* rt_last_error(void); /* thread-local, never NULL */
 
 #ifdef __cplusplus

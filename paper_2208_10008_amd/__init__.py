@@ -59,6 +59,21 @@ class rt_trace_opts(ctypes.Structure):
                 ("refill", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class rt_query(ctypes.Structure):
+    _fields_ = [("bvh", ctypes.c_void_p), ("rays", ctypes.c_void_p), ("n", ctypes.c_int64),
+                ("max_bounces", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("out", ctypes.c_void_p), ("path_len", ctypes.c_void_p),
+                ("n_hits", ctypes.c_void_p)]
+
+
+class rt_batch_config(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("grid", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("graph", ctypes.c_int32)]
+
+
+BATCH_MODES = {"direct": 0, "queue": 1}
+BATCH_ORDERS = {"given": 0, "cost": 1}
+
 # numpy view of rt_node_rec (64 bytes)
 NODE_DTYPE = np.dtype([("lo", "<f4", 3), ("hi", "<f4", 3), ("left", "<i4"), ("first", "<i4"),
                        ("count", "<i4"), ("depth", "<i4"), ("axis", "<i4"), ("plane", "<i4"),
@@ -67,7 +82,9 @@ assert NODE_DTYPE.itemsize == 64
 
 EXPORTS = ("rt_split_params_default", "rt_build", "rt_rebuild", "rt_trace",
            "rt_trace_bounces", "rt_trace_ex", "rt_bvh_info_get", "rt_bvh_download",
-           "rt_bvh_export_trace_nodes", "rt_bvh_destroy", "rt_last_error")
+           "rt_bvh_export_trace_nodes", "rt_bvh_destroy", "rt_last_error", "rt_batch_create",
+           "rt_batch_set", "rt_batch_configure", "rt_batch_get_config", "rt_batch_launch",
+           "rt_batch_autotune", "rt_batch_destroy")
 PROBE_EXPORTS = ("rt_probe_read", "rt_probe_copy")  # include/rt_probe.h
 
 _lib = None
@@ -97,10 +114,20 @@ def load(path: str = LIB_PATH):
     lib.rt_last_error.argtypes = []
     lib.rt_last_error.restype = ctypes.c_char_p
     lib.rt_probe_read.argtypes = [P, i64, i64, i32, i32, P, P]
+    lib.rt_batch_create.argtypes = [i32, ctypes.POINTER(P)]
+    lib.rt_batch_set.argtypes = [P, ctypes.POINTER(rt_query), i32]
+    lib.rt_batch_configure.argtypes = [P, ctypes.POINTER(rt_batch_config)]
+    lib.rt_batch_get_config.argtypes = [P, ctypes.POINTER(rt_batch_config)]
+    lib.rt_batch_launch.argtypes = [P, P]
+    lib.rt_batch_autotune.argtypes = [P, i32, P, ctypes.POINTER(ctypes.c_float)]
+    lib.rt_batch_destroy.argtypes = [P]
+    lib.rt_batch_destroy.restype = None
     lib.rt_probe_copy.argtypes = [P, P, i64, P]
     for name in ("rt_build", "rt_rebuild", "rt_trace", "rt_trace_bounces", "rt_trace_ex",
                  "rt_bvh_info_get", "rt_bvh_download", "rt_bvh_export_trace_nodes",
-                 "rt_probe_read", "rt_probe_copy"):
+                 "rt_probe_read", "rt_probe_copy", "rt_batch_create", "rt_batch_set",
+                 "rt_batch_configure", "rt_batch_get_config", "rt_batch_launch",
+                 "rt_batch_autotune"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -302,6 +329,71 @@ class BVH:
     def close(self):
         if getattr(self, "handle", None):
             rt_bvh_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many trace queries in one launch (rt_batch).  A query is a dict with
+    keys bvh (BVH), rays (float32 [n, 8] CUDA tensor), max_bounces, and
+    optionally out, path_len, n_hits (allocated when missing)."""
+
+    def __init__(self, max_queries: int):
+        h = ctypes.c_void_p()
+        _check(load().rt_batch_create(max_queries, ctypes.byref(h)))
+        self.handle = h
+        self.queries = []
+
+    def set(self, queries):
+        import torch
+        arr = (rt_query * max(len(queries), 1))()
+        for k, q in enumerate(queries):
+            rays = _dev(q["rays"], torch.float32, 8, "rays")
+            n, nb = rays.shape[0], int(q["max_bounces"])
+            if q.get("out") is None:
+                q["out"] = torch.empty((nb, n, 4), dtype=torch.int32, device=rays.device)
+            if q.get("path_len") is None:
+                q["path_len"] = torch.empty(n, dtype=torch.float64, device=rays.device)
+            if q.get("n_hits") is None:
+                q["n_hits"] = torch.empty(n, dtype=torch.int32, device=rays.device)
+            arr[k].bvh = q["bvh"].handle
+            arr[k].rays = rays.data_ptr()
+            arr[k].n = n
+            arr[k].max_bounces = nb
+            arr[k].out = q["out"].data_ptr()
+            arr[k].path_len = q["path_len"].data_ptr()
+            arr[k].n_hits = q["n_hits"].data_ptr()
+        _check(load().rt_batch_set(self.handle, arr, len(queries)))
+        self.queries = queries
+        return [arr[k].status for k in range(len(queries))]
+
+    def configure(self, mode="direct", grid=0, order="cost", graph=False):
+        c = rt_batch_config(BATCH_MODES[mode], grid, BATCH_ORDERS[order], int(bool(graph)))
+        _check(load().rt_batch_configure(self.handle, ctypes.byref(c)))
+
+    def config(self) -> dict:
+        c = rt_batch_config()
+        _check(load().rt_batch_get_config(self.handle, ctypes.byref(c)))
+        inv_m = {v: k for k, v in BATCH_MODES.items()}
+        inv_o = {v: k for k, v in BATCH_ORDERS.items()}
+        return {"mode": inv_m[c.mode], "grid": c.grid, "order": inv_o[c.order], "graph": bool(c.graph)}
+
+    def launch(self, stream=None):
+        _check(load().rt_batch_launch(self.handle, _stream(stream)))
+
+    def autotune(self, reps=2, stream=None) -> float:
+        ms = ctypes.c_float()
+        _check(load().rt_batch_autotune(self.handle, reps, _stream(stream), ctypes.byref(ms)))
+        return ms.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().rt_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -162,6 +162,20 @@ __device__ __host__ inline double o2d(long long i) {
   return d;
 }
 
+// One query of a batched trace launch (device table entry, 64 bytes + pad).
+struct alignas(16) BatchQuery {
+  const void* nodes;     // traversal nodes of the query's tree
+  const TFacet* facets;  // its leaf-ordered facets
+  const float4* rays;    // [n][2] float4
+  rt_hit* out;           // [max_b][n]
+  double* path_len;      // [n] or null
+  int32_t* n_hits;       // [n] or null
+  int64_t n;
+  int64_t first_batch;   // first work-group number of the query in the launch
+  int32_t max_b;
+  int32_t pad[3];
+};
+
 // error reporting (thread-local message), defined in rt_api.hip
 int set_error(int code, const std::string& msg);
 int check_hip(hipError_t e, const char* what);
@@ -173,6 +187,13 @@ int build_tree(Buffers& B, const float* tris, int64_t n, const rt_split_params& 
 int launch_trace(const Buffers& B, int node_format, int depth, const float* rays, int64_t n,
                  int32_t max_bounces, rt_hit* out, double* path_len, int32_t* n_hits,
                  const rt_trace_opts* opts, hipStream_t s);
+// Batched launch over table[0 .. nq) (device), all of one node format;
+// total_batches work-groups, or `grid` persistent work-groups taking batches
+// from `queue` when grid > 0.  depth: deepest tree of the queries.
+int launch_trace_batch(const BatchQuery* table, int nq, int64_t total_batches, int node_format,
+                       int depth, int grid, unsigned long long* queue, hipStream_t s);
+// Work-groups of the trace kernel that fit the device at once for this format and depth.
+int trace_resident_groups(int node_format, int depth);
 
 }  // namespace rt
 

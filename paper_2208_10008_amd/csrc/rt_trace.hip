@@ -420,26 +420,22 @@ __device__ inline void store_hit(rt_hit* out, int64_t k, const Hit& h) {
 
 constexpr int kBlock = 64;  // one wave per work-group: the LDS stack is per wave
 
-// Persistent wavefronts: each wave keeps one reflection chain per lane and
-// takes rays from a global queue with one atomic per wave (ballot + popcount
-// give each free lane its ray).  By default a wave takes a new batch of 64
-// consecutive rays once all its chains have ended, so a wave traces adjacent
-// launch directions together; with `refill` it tops up free lanes at every
-// segment.  A wave exits once the queue is drained and its lanes are idle; no
-// wave ever waits for another.
-template <int FMT, int SD, bool BOUNCE, bool SEG, bool STATS>
-__global__ __launch_bounds__(kBlock) void k_trace(const void* __restrict__ tn,
-                                                  const TFacet* __restrict__ tf,
-                                                  const float4* __restrict__ rays, int64_t n,
-                                                  int max_b, rt_hit* __restrict__ out,
-                                                  double* __restrict__ path_len,
-                                                  int32_t* __restrict__ n_hits,
-                                                  float4* __restrict__ seg,
-                                                  uint32_t* __restrict__ stats,
-                                                  unsigned long long* __restrict__ queue,
-                                                  int refill) {
-  __shared__ int s_stack[SD * kBlock];
-  const int lane = threadIdx.x;
+// One wave traces reflection chains, one per lane (Sec. III-B re-launch).
+// Rays come either as the batch [base, base + 64) of this work-group (a work-
+// group of the default launch; `drained` afterwards) or, with a queue, from a
+// global counter with one atomic per wave (ballot + popcount give each free
+// lane its ray): by default a new batch of 64 consecutive rays once all the
+// wave's chains have ended, so a wave traces adjacent launch directions
+// together; with `refill` it tops up free lanes at every segment.  A wave
+// exits once its rays are done; no wave ever waits for another.
+template <int FMT, bool BOUNCE, bool SEG, bool STATS>
+__device__ void trace_chains(const void* __restrict__ tn, const TFacet* __restrict__ tf,
+                             const float4* __restrict__ rays, int64_t n, int max_b,
+                             rt_hit* __restrict__ out, double* __restrict__ path_len,
+                             int32_t* __restrict__ n_hits, float4* __restrict__ seg,
+                             uint32_t* __restrict__ stats, unsigned long long* __restrict__ queue,
+                             int refill, int64_t batch_base, int* stack) {
+  const int lane = threadIdx.x & 63;
   const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   int64_t i = -1;  // ray of this lane, -1 when free
   float ox = 0.f, oy = 0.f, oz = 0.f, dx = 0.f, dy = 0.f, dz = 0.f, tmin = 0.f, tmax = 0.f;
@@ -453,8 +449,7 @@ __global__ __launch_bounds__(kBlock) void k_trace(const void* __restrict__ tn,
       const int leader = __ffsll((long long)free_lanes) - 1;
       unsigned long long base = 0;
       if (queue == nullptr) {
-        // one batch per work-group: rays [64 b, 64 b + 64) of work-group b
-        base = (unsigned long long)blockIdx.x * kBlock;
+        base = (unsigned long long)batch_base;
         drained = true;
       } else {
         if (lane == leader) base = atomicAdd(queue, (unsigned long long)__popcll(free_lanes));
@@ -484,7 +479,7 @@ __global__ __launch_bounds__(kBlock) void k_trace(const void* __restrict__ tn,
       seg[2 * ((int64_t)b * n + i) + 1] = make_float4(dx, dy, dz, tmax);
     }
     const RayPre r = prepare(ox, oy, oz, dx, dy, dz, tmin, tmax);
-    Hit h = closest<FMT, STATS>(tn, tf, r, skip, s_stack + lane, nvis, ntest);
+    Hit h = closest<FMT, STATS>(tn, tf, r, skip, stack, nvis, ntest);
     N2 nrm;
     if (h.id >= 0) {
       // the facet is decided; its distance is recomputed accurately
@@ -523,6 +518,73 @@ __global__ __launch_bounds__(kBlock) void k_trace(const void* __restrict__ tn,
       }
       i = -1;
     }
+  }
+}
+
+template <int FMT, int SD, bool BOUNCE, bool SEG, bool STATS>
+__global__ __launch_bounds__(kBlock) void k_trace(const void* __restrict__ tn,
+                                                  const TFacet* __restrict__ tf,
+                                                  const float4* __restrict__ rays, int64_t n,
+                                                  int max_b, rt_hit* __restrict__ out,
+                                                  double* __restrict__ path_len,
+                                                  int32_t* __restrict__ n_hits,
+                                                  float4* __restrict__ seg,
+                                                  uint32_t* __restrict__ stats,
+                                                  unsigned long long* __restrict__ queue,
+                                                  int refill) {
+  __shared__ int s_stack[SD * kBlock];
+  trace_chains<FMT, BOUNCE, SEG, STATS>(tn, tf, rays, n, max_b, out, path_len, n_hits, seg, stats,
+                                        queue, refill, (int64_t)blockIdx.x * kBlock,
+                                        s_stack + threadIdx.x);
+}
+
+// Many queries (trees, ray sets, bounce limits) in one launch: work-group g
+// finds its query by binary search over the queries' first batch numbers and
+// traces that query's batch g - first.  Queries of one launch share the node
+// format; each brings its own tree.
+template <int FMT, int SD>
+__global__ __launch_bounds__(kBlock) void k_trace_batch(const BatchQuery* __restrict__ q, int nq) {
+  __shared__ int s_stack[SD * kBlock];
+  const int64_t g = blockIdx.x;
+  int lo = 0, hi = nq - 1;  // last query whose first batch <= g
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (q[mid].first_batch <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  const BatchQuery Q = q[lo];
+  const int64_t local = g - Q.first_batch;
+  if (local * kBlock >= Q.n) return;
+  trace_chains<FMT, true, false, false>(Q.nodes, Q.facets, Q.rays, Q.n, Q.max_b, Q.out, Q.path_len,
+                                        Q.n_hits, nullptr, nullptr, nullptr, 0, local * kBlock,
+                                        s_stack + threadIdx.x);
+}
+
+// Persistent form of the batched launch: each wave takes batch numbers from
+// a global counter (one atomic per 64 rays) until all are done.
+template <int FMT, int SD>
+__global__ __launch_bounds__(kBlock) void k_trace_batch_q(const BatchQuery* __restrict__ q, int nq,
+                                                          int64_t total,
+                                                          unsigned long long* __restrict__ queue) {
+  __shared__ int s_stack[SD * kBlock];
+  const int lane = threadIdx.x & 63;
+  for (;;) {
+    unsigned long long g = 0;
+    if (lane == 0) g = atomicAdd(queue, 1ull);
+    g = __shfl(g, 0);
+    if (g >= (unsigned long long)total) break;
+    int lo = 0, hi = nq - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (q[mid].first_batch <= (int64_t)g) lo = mid;
+      else hi = mid - 1;
+    }
+    const BatchQuery Q = q[lo];
+    const int64_t local = (int64_t)g - Q.first_batch;
+    if (local * kBlock >= Q.n) continue;
+    trace_chains<FMT, true, false, false>(Q.nodes, Q.facets, Q.rays, Q.n, Q.max_b, Q.out,
+                                          Q.path_len, Q.n_hits, nullptr, nullptr, nullptr, 0,
+                                          local * kBlock, s_stack + threadIdx.x);
   }
 }
 
@@ -601,7 +663,65 @@ void launch_fmt(const Buffers& B, int depth, const float* rays, int64_t n, int m
   }
 }
 
+template <int FMT, int SD>
+void launch_batch_sd(const BatchQuery* table, int nq, int64_t total, int grid,
+                     unsigned long long* queue, hipStream_t s) {
+  if (grid > 0) {
+    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(1), 0, s, queue);
+    hipLaunchKernelGGL((k_trace_batch_q<FMT, SD>), dim3((unsigned)std::min<int64_t>(grid, total)),
+                       dim3(kBlock), 0, s, table, nq, total, queue);
+  } else {
+    hipLaunchKernelGGL((k_trace_batch<FMT, SD>), dim3((unsigned)total), dim3(kBlock), 0, s, table,
+                       nq);
+  }
+}
+
+template <int FMT>
+void launch_batch_fmt(const BatchQuery* table, int nq, int64_t total, int depth, int grid,
+                      unsigned long long* queue, hipStream_t s) {
+  if (stack_need<FMT>(depth) <= kShortStack)
+    launch_batch_sd<FMT, kShortStack>(table, nq, total, grid, queue, s);
+  else if (stack_need<FMT>(depth) <= kMidStack)
+    launch_batch_sd<FMT, kMidStack>(table, nq, total, grid, queue, s);
+  else
+    launch_batch_sd<FMT, stack_need<FMT>(RT_MAX_DEPTH)>(table, nq, total, grid, queue, s);
+}
+
+template <int FMT, int SD>
+int resident_sd() {
+  int dev = 0, cus = 0, per_cu = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_trace_batch_q<FMT, SD>, kBlock, 0);
+  return std::max(1, cus * std::max(1, per_cu));
+}
+template <int FMT>
+int resident_fmt(int depth) {
+  if (stack_need<FMT>(depth) <= kShortStack) return resident_sd<FMT, kShortStack>();
+  if (stack_need<FMT>(depth) <= kMidStack) return resident_sd<FMT, kMidStack>();
+  return resident_sd<FMT, stack_need<FMT>(RT_MAX_DEPTH)>();
+}
+
 }  // namespace
+
+int launch_trace_batch(const BatchQuery* table, int nq, int64_t total, int node_format, int depth,
+                       int grid, unsigned long long* queue, hipStream_t s) {
+  if (nq <= 0 || total <= 0) return RT_OK;
+  switch (node_format) {
+    case RT_NODE_F4: launch_batch_fmt<RT_NODE_F4>(table, nq, total, depth, grid, queue, s); break;
+    case RT_NODE_Q4: launch_batch_fmt<RT_NODE_Q4>(table, nq, total, depth, grid, queue, s); break;
+    default: launch_batch_fmt<RT_NODE_BIN2>(table, nq, total, depth, grid, queue, s); break;
+  }
+  return check_hip(hipGetLastError(), "batch trace launch");
+}
+
+int trace_resident_groups(int node_format, int depth) {
+  switch (node_format) {
+    case RT_NODE_F4: return resident_fmt<RT_NODE_F4>(depth);
+    case RT_NODE_Q4: return resident_fmt<RT_NODE_Q4>(depth);
+    default: return resident_fmt<RT_NODE_BIN2>(depth);
+  }
+}
 
 int launch_trace(const Buffers& B, int node_format, int depth, const float* rays, int64_t n,
                  int32_t max_b, rt_hit* out, double* path_len, int32_t* n_hits,

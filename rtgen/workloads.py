@@ -108,3 +108,14 @@ def multiscene_queries(seed: int = 0, per_scene: int = 8, levels=(6, 9), bounces
             nb = int(rng.integers(bounces[0], bounces[1] + 1))
             out.append((s, tx, lv, nb))
     return out
+
+
+# Trees of the multi-scene set are built once per scene with the ray source
+# point at the scene centre, 25 m up; queries bring their own transmitters.
+MULTI_SRC = (0.0, 0.0, 25.0)
+
+
+def multiscene_rays(tx, level: int) -> np.ndarray:
+    """Rays of one multi-scene query: the level's icosphere from tx,
+    tmin 1e-4 m, tmax 2 km."""
+    return icosphere.make_rays(tx, icosphere.directions(level), 1e-4, 2000.0)

@@ -61,12 +61,16 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu %zu\\n", offsetof(rt_node_rec, cost), offsetof(rt_bvh_info, root_lo),
          offsetof(rt_split_params, max_leaf), offsetof(rt_trace_opts, block),
          offsetof(rt_split_params, node_format), offsetof(rt_bvh_info, n_trace_nodes));
+  printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(rt_query), offsetof(rt_query, max_bounces),
+         offsetof(rt_query, status), offsetof(rt_query, out), offsetof(rt_query, n_hits),
+         sizeof(rt_batch_config));
   return 0;
 }""")
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-D__HIP_PLATFORM_AMD__", "-I" + os.path.join(ROOT, "include"),
                     "-I/opt/rocm/include", str(src), "-o", str(exe)], check=True)
-    a, b = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")[:2]
+    a, b, c = subprocess.run([str(exe)], capture_output=True, text=True,
+                             check=True).stdout.split("\n")[:3]
     sizes = [int(x) for x in a.split()]
     offs = [int(x) for x in b.split()]
     assert sizes == [ctypes.sizeof(R.rt_split_params), 16, ctypes.sizeof(R.rt_bvh_info),
@@ -74,6 +78,9 @@ int main(void) {
     assert offs == [R.NODE_DTYPE.fields["cost"][1], R.rt_bvh_info.root_lo.offset,
                     R.rt_split_params.max_leaf.offset, R.rt_trace_opts.block.offset,
                     R.rt_split_params.node_format.offset, R.rt_bvh_info.n_trace_nodes.offset]
+    assert [int(x) for x in c.split()] == [ctypes.sizeof(R.rt_query), R.rt_query.max_bounces.offset,
+                                           R.rt_query.status.offset, R.rt_query.out.offset,
+                                           R.rt_query.n_hits.offset, ctypes.sizeof(R.rt_batch_config)]
 
 
 def test_defaults():
@@ -156,3 +163,21 @@ def test_probe_argument_checks():
     assert lib.rt_probe_copy(p, p, 64, None) == R.RT_EINVAL          # overlapping ranges
     assert lib.rt_probe_copy(p, ctypes.c_void_p(buf.ctypes.data + 128), 0, None) == R.RT_EINVAL
     assert b"rt_probe" in lib.rt_last_error()
+
+
+def test_batch_argument_checks():
+    """Checks that fail before any device call."""
+    lib = R.load()
+    h = ctypes.c_void_p()
+    assert lib.rt_batch_create(0, ctypes.byref(h)) == R.RT_EINVAL and not h.value
+    assert lib.rt_batch_create(65537, ctypes.byref(h)) == R.RT_EINVAL
+    assert lib.rt_batch_create(4, None) == R.RT_EINVAL
+    q = (R.rt_query * 1)()
+    assert lib.rt_batch_set(None, q, 1) == R.RT_EINVAL
+    c = R.rt_batch_config(0, 0, 1, 0)
+    assert lib.rt_batch_configure(None, ctypes.byref(c)) == R.RT_EINVAL
+    assert lib.rt_batch_get_config(None, ctypes.byref(c)) == R.RT_EINVAL
+    assert lib.rt_batch_launch(None, None) == R.RT_EINVAL
+    assert lib.rt_batch_autotune(None, 1, None, None) == R.RT_EINVAL
+    lib.rt_batch_destroy(None)
+    assert b"rt_batch" in lib.rt_last_error()
