@@ -183,6 +183,16 @@ int rt_trace_ex(const rt_bvh* b, const float* rays, int64_t n, int32_t max_bounc
                 rt_hit* out, double* path_len, int32_t* n_hits, const rt_trace_opts* opts,
                 hipStream_t s);
 
+/* ---- launched rays (Sec. III-A) -----------------------------------------
+ * Writes n rays from the source point (ox, oy, oz) along the first n launch
+ * directions of a resident direction table: rays[i] = (o, tmin, dirs[i],
+ * tmax), float32 [n][8].  dirs: device float32 [>= n][3] (the directions of a
+ * subdivided icosahedron in first-appearance order, so any prefix is a valid
+ * launch set).  rays 16-byte aligned.  Enqueued on s.
+ * Errors: RT_EINVAL (NULL, misaligned, n < 0, tmin > tmax or not finite), RT_EHIP. */
+int rt_rays_from_directions(const float* dirs, int64_t n, float ox, float oy, float oz, float tmin,
+                            float tmax, float* rays, hipStream_t s);
+
 /* ---- inspection and lifetime ------------------------------------------ */
 int rt_bvh_info_get(const rt_bvh* b, rt_bvh_info* info); /* host struct */
 

@@ -84,7 +84,7 @@ EXPORTS = ("rt_split_params_default", "rt_build", "rt_rebuild", "rt_trace",
            "rt_trace_bounces", "rt_trace_ex", "rt_bvh_info_get", "rt_bvh_download",
            "rt_bvh_export_trace_nodes", "rt_bvh_destroy", "rt_last_error", "rt_batch_create",
            "rt_batch_set", "rt_batch_configure", "rt_batch_get_config", "rt_batch_launch",
-           "rt_batch_autotune", "rt_batch_destroy")
+           "rt_batch_autotune", "rt_batch_destroy", "rt_rays_from_directions")
 PROBE_EXPORTS = ("rt_probe_read", "rt_probe_copy")  # include/rt_probe.h
 
 _lib = None
@@ -120,6 +120,8 @@ def load(path: str = LIB_PATH):
     lib.rt_batch_get_config.argtypes = [P, ctypes.POINTER(rt_batch_config)]
     lib.rt_batch_launch.argtypes = [P, P]
     lib.rt_batch_autotune.argtypes = [P, i32, P, ctypes.POINTER(ctypes.c_float)]
+    f32 = ctypes.c_float
+    lib.rt_rays_from_directions.argtypes = [P, i64, f32, f32, f32, f32, f32, P, P]
     lib.rt_batch_destroy.argtypes = [P]
     lib.rt_batch_destroy.restype = None
     lib.rt_probe_copy.argtypes = [P, P, i64, P]
@@ -127,7 +129,7 @@ def load(path: str = LIB_PATH):
                  "rt_bvh_info_get", "rt_bvh_download", "rt_bvh_export_trace_nodes",
                  "rt_probe_read", "rt_probe_copy", "rt_batch_create", "rt_batch_set",
                  "rt_batch_configure", "rt_batch_get_config", "rt_batch_launch",
-                 "rt_batch_autotune"):
+                 "rt_batch_autotune", "rt_rays_from_directions"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -336,6 +338,21 @@ class BVH:
             self.close()
         except Exception:
             pass
+
+
+def rt_rays_from_directions(dirs, n, src, tmin, tmax, rays=None, stream=None):
+    """Rays [n, 8] from src along the first n rows of dirs (float32 [m, 3]
+    CUDA tensor, m >= n)."""
+    import torch
+    if not isinstance(dirs, torch.Tensor) or not dirs.is_cuda or dirs.dtype != torch.float32 \
+            or dirs.dim() != 2 or dirs.shape[1] != 3 or not dirs.is_contiguous() or dirs.shape[0] < n:
+        raise RtError(RT_EINVAL, "dirs must be a contiguous float32 CUDA tensor [>= n, 3]")
+    if rays is None:
+        rays = torch.empty((n, 8), dtype=torch.float32, device=dirs.device)
+    _check(load().rt_rays_from_directions(dirs.data_ptr(), n, float(src[0]), float(src[1]),
+                                          float(src[2]), float(tmin), float(tmax),
+                                          rays.data_ptr(), _stream(stream)))
+    return rays
 
 
 class Batch:

@@ -1,7 +1,10 @@
 // Memory-system probes (declared in include/rt_probe.h): streaming reads over
 // a chosen working set and a plain copy, for the traversal kernel's roofline
-// and for calibrating the hardware byte counters.
+// and for calibrating the hardware byte counters; and rays from a resident
+// table of launch directions (rt_rays_from_directions, rt_mi355x.h).
 #include <hip/hip_runtime.h>
+
+#include <cmath>
 
 #include "rt_internal.h"
 #include "rt_probe.h"
@@ -63,6 +66,16 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_copy(const uint4* __res
 
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
+// rays[i] = (o, tmin, dirs[i], tmax)
+__global__ __launch_bounds__(256) void k_rays(const float* __restrict__ dirs, int64_t n, float ox,
+                                              float oy, float oz, float tmin, float tmax,
+                                              float4* __restrict__ rays) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  rays[2 * i] = make_float4(ox, oy, oz, tmin);
+  rays[2 * i + 1] = make_float4(dirs[3 * i], dirs[3 * i + 1], dirs[3 * i + 2], tmax);
+}
+
 }  // namespace
 }  // namespace rt
 
@@ -83,6 +96,21 @@ int rt_probe_read(const void* buf, int64_t bytes, int64_t span, int32_t passes, 
   hipLaunchKernelGGL(k_probe_read, dim3(groups), dim3(kProbeThreads), 0, s,
                      static_cast<const uint4*>(buf), bytes / 16, span / 16, passes, sink);
   return check_hip(hipGetLastError(), "rt_probe_read");
+}
+
+int rt_rays_from_directions(const float* dirs, int64_t n, float ox, float oy, float oz, float tmin,
+                            float tmax, float* rays, hipStream_t s) {
+  if (n < 0) return set_error(RT_EINVAL, "rt_rays_from_directions: n must be >= 0");
+  if (n == 0) return RT_OK;
+  if (!dirs || !rays) return set_error(RT_EINVAL, "rt_rays_from_directions: NULL pointer");
+  if (!aligned16(rays) || (reinterpret_cast<uintptr_t>(dirs) & 3u))
+    return set_error(RT_EINVAL, "rt_rays_from_directions: rays must be 16-byte aligned");
+  if (!(tmin <= tmax) || !std::isfinite(ox) || !std::isfinite(oy) || !std::isfinite(oz) ||
+      !std::isfinite(tmin))
+    return set_error(RT_EINVAL, "rt_rays_from_directions: source and range must be finite, tmin <= tmax");
+  hipLaunchKernelGGL(k_rays, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dirs, n, ox, oy, oz,
+                     tmin, tmax, reinterpret_cast<float4*>(rays));
+  return check_hip(hipGetLastError(), "rt_rays_from_directions");
 }
 
 int rt_probe_copy(const void* src, void* dst, int64_t bytes, hipStream_t s) {

@@ -1,0 +1,406 @@
+"""Continuous-batching trace server over resident scenes.
+
+Scenes and their trees stay resident in HBM, and so does a table of launch
+directions (a level-9 icosphere, first-appearance order).  A query is
+(scene, transmitter, ray count, bounce depth) -- its rays are the first
+`count` table directions from the transmitter, made on the device -- or
+(scene, host rays, bounce depth); it is checked when it is
+submitted (a malformed query gets an error status and never enters the
+queue), waits in arrival order, and is admitted when an execution slot is
+free and its device memory (rays, hits, path lengths, hit counts) fits the
+HBM budget.  Each slot owns a stream and a batch (rt_batch): the admitted
+queries are uploaded, traced in one batched launch and copied back on that
+stream, so a batch admitted while others are still on the device overlaps
+with them.  Latency is measured from a query's arrival to its results being
+in host memory.
+
+    python -m paper_2208_10008_amd.serve --duration 60 --rate 200
+
+runs the Poisson workload over the 8 scenes of the multi-scene set and
+prints one JSON line (p50 / p99 latency, aggregate segments per second,
+queue depth, admission waits).
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import dataclasses
+import itertools
+import json
+import math
+import threading
+import time
+from typing import Callable, Optional
+
+import numpy as np
+
+from . import rt_rays_from_directions as _rays_from_directions
+
+# request states
+PENDING, RUNNING, DONE, FAILED, CANCELLED = "pending", "running", "done", "failed", "cancelled"
+MAX_RAYS = 1 << 26
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    scene: int
+    max_bounces: int
+    arrival: float            # time.perf_counter() at submission
+    tx: Optional[tuple] = None            # transmitter of generated rays
+    n_rays: int = 0                       # ... and their count
+    rays: Optional[np.ndarray] = None     # or float32 [n, 8] host rays
+    status: str = PENDING
+    error: str = ""
+    admitted: float = math.nan
+    done: float = math.nan
+    out: Optional[np.ndarray] = None       # int32 [max_bounces, n, 4] (rt_hit records)
+    path_len: Optional[np.ndarray] = None  # float64 [n]
+    n_hits: Optional[np.ndarray] = None    # int32 [n]
+
+    @property
+    def n(self) -> int:
+        return self.rays.shape[0] if self.rays is not None else self.n_rays
+
+    def device_bytes(self) -> int:
+        """Device memory the query holds while it runs."""
+        return self.n * (32 + 16 * self.max_bounces + 8 + 4)
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+def check_request(req: Request, scenes, max_generated: int = MAX_RAYS) -> str:
+    """Why a query cannot run ('' when it can)."""
+    if req.scene not in scenes:
+        return f"scene {req.scene} is not resident"
+    if req.rays is None:
+        if req.tx is None or len(req.tx) != 3 or not np.isfinite(np.asarray(req.tx, float)).all():
+            return "transmitter must be three finite coordinates"
+        if not 1 <= req.n_rays <= max_generated:
+            return f"ray count must lie in 1..{max_generated}"
+    else:
+        r = req.rays
+        if not isinstance(r, np.ndarray) or r.dtype != np.float32 or r.ndim != 2 or r.shape[1] != 8:
+            return "rays must be float32 [n, 8]"
+        if not 1 <= r.shape[0] <= MAX_RAYS:
+            return f"ray count must lie in 1..{MAX_RAYS}"
+        if not np.isfinite(r).all():
+            return "rays must be finite"
+    if not 1 <= req.max_bounces <= 64:
+        return "bounce depth must lie in 1..64"
+    return ""
+
+
+class Scheduler:
+    """Admission policy, independent of the device: arrival order, a free
+    slot and room in the memory budget; the head of the queue is never
+    overtaken (no starvation)."""
+
+    def __init__(self, budget_bytes: int, slots: int, max_batch: int):
+        self.budget = budget_bytes
+        self.used = 0
+        self.free_slots = list(range(slots))
+        self.max_batch = max_batch
+        self.pending: collections.deque = collections.deque()
+        self.rejected = []         # queries that can never fit the budget
+        self.admission_waits = 0   # passes where the head waited for memory or a slot
+
+    def enqueue(self, req: Request):
+        self.pending.append(req)
+
+    def cancel(self, req: Request) -> bool:
+        if req.status == PENDING and req in self.pending:
+            self.pending.remove(req)
+            req.status = CANCELLED
+            return True
+        return False
+
+    def admit(self):
+        """Returns (slot, requests) for the next batch, or None."""
+        if not self.pending:
+            return None
+        if not self.free_slots:
+            self.admission_waits += 1
+            return None
+        batch, need = [], 0
+        while self.pending and len(batch) < self.max_batch:
+            req = self.pending[0]
+            b = req.device_bytes()
+            if b > self.budget:  # can never fit
+                self.pending.popleft()
+                req.status, req.error = FAILED, "query exceeds the memory budget"
+                self.rejected.append(req)
+                continue
+            if self.used + need + b > self.budget:
+                break
+            batch.append(self.pending.popleft())
+            need += b
+        if not batch:
+            self.admission_waits += 1
+            return None
+        self.used += need
+        return self.free_slots.pop(0), batch
+
+    def release(self, slot: int, batch):
+        self.used -= sum(r.device_bytes() for r in batch)
+        self.free_slots.append(slot)
+
+
+class GpuExecutor:
+    """Resident scenes and launch directions, one stream and one rt_batch per
+    slot.  Generated rays run from tmin to tmax along each direction."""
+
+    def __init__(self, scenes, slots: int, max_batch: int, level: int = 9, tmin: float = 1e-4,
+                 tmax: float = 2000.0):
+        import torch
+        from rtgen import icosphere
+        from . import Batch
+        self.torch = torch
+        self.scenes = scenes
+        self.dirs = torch.from_numpy(icosphere.directions(level).astype(np.float32)).cuda()
+        self.max_generated = self.dirs.shape[0]
+        self.tmin, self.tmax = tmin, tmax
+        self.streams = [torch.cuda.Stream() for _ in range(slots)]
+        self.batches = [Batch(max_batch) for _ in range(slots)]
+        self.events = [None] * slots
+        self.work = [None] * slots
+
+    def launch(self, slot: int, reqs):
+        torch = self.torch
+        s = self.streams[slot]
+        qs, host = [], []
+        with torch.cuda.stream(s):
+            for r in reqs:
+                if r.rays is None:
+                    rays = _rays_from_directions(self.dirs, r.n_rays, r.tx, self.tmin, self.tmax,
+                                                 stream=s)
+                else:
+                    rays = torch.from_numpy(r.rays).pin_memory().to("cuda", non_blocking=True)
+                qs.append({"bvh": self.scenes[r.scene], "rays": rays, "max_bounces": r.max_bounces})
+            self.batches[slot].set(qs)
+            self.batches[slot].launch(stream=s)
+            for q in qs:
+                out = torch.empty(q["out"].shape, dtype=torch.int32, pin_memory=True)
+                pl = torch.empty(q["path_len"].shape, dtype=torch.float64, pin_memory=True)
+                nh = torch.empty(q["n_hits"].shape, dtype=torch.int32, pin_memory=True)
+                out.copy_(q["out"], non_blocking=True)
+                pl.copy_(q["path_len"], non_blocking=True)
+                nh.copy_(q["n_hits"], non_blocking=True)
+                host.append((out, pl, nh))
+            ev = torch.cuda.Event()
+            ev.record(s)
+        self.events[slot] = ev
+        self.work[slot] = (reqs, qs, host)
+
+    def poll(self, slot: int) -> bool:
+        return self.events[slot] is not None and self.events[slot].query()
+
+    def collect(self, slot: int):
+        reqs, qs, host = self.work[slot]
+        for r, (out, pl, nh) in zip(reqs, host):
+            r.out, r.path_len, r.n_hits = out.numpy(), pl.numpy(), nh.numpy()
+        self.events[slot] = None
+        self.work[slot] = None
+        return reqs
+
+
+class Server:
+    """Continuous batching: one thread admits, launches and completes.
+
+    executor: GpuExecutor (or any object with launch / poll / collect and a
+    `scenes` mapping, e.g. a host stand-in in tests)."""
+
+    def __init__(self, executor, budget_bytes: int, slots: int = 4, max_batch: int = 64,
+                 clock: Callable[[], float] = time.perf_counter):
+        self.ex = executor
+        self.sched = Scheduler(budget_bytes, slots, max_batch)
+        self.clock = clock
+        self.lock = threading.Lock()
+        self.inbox: collections.deque = collections.deque()
+        self.running = {}
+        self.finished = []
+        self.depth_samples = []
+        self.max_running = 0       # most batches on the device at once
+        self.ids = itertools.count()
+        self.thread = None
+        self.stop_flag = False
+
+    def submit(self, scene: int, max_bounces: int, rays: Optional[np.ndarray] = None,
+               tx=None, n_rays: int = 0) -> Request:
+        """A query: host rays, or a transmitter and a ray count."""
+        req = Request(next(self.ids), scene, int(max_bounces), self.clock(), tx=tx,
+                      n_rays=int(n_rays), rays=rays)
+        err = check_request(req, self.ex.scenes, getattr(self.ex, "max_generated", MAX_RAYS))
+        if err:  # never enters the queue
+            req.status, req.error = FAILED, err
+            with self.lock:
+                self.finished.append(req)
+            return req
+        self.inbox.append(req)
+        return req
+
+    def cancel(self, req: Request) -> bool:
+        with self.lock:
+            return self.sched.cancel(req)
+
+    def step(self) -> bool:
+        """One scheduling pass; returns True when anything happened."""
+        busy = False
+        with self.lock:
+            while self.inbox:
+                self.sched.enqueue(self.inbox.popleft())
+            self.depth_samples.append(len(self.sched.pending))
+            # completions
+            for slot in list(self.running):
+                if self.ex.poll(slot):
+                    reqs = self.ex.collect(slot)
+                    now = self.clock()
+                    for r in reqs:
+                        r.done, r.status = now, DONE
+                    self.sched.release(slot, reqs)
+                    self.finished.extend(reqs)
+                    del self.running[slot]
+                    busy = True
+            # admissions
+            while True:
+                got = self.sched.admit()
+                if self.sched.rejected:
+                    self.finished.extend(self.sched.rejected)
+                    self.sched.rejected.clear()
+                if got is None:
+                    break
+                slot, reqs = got
+                now = self.clock()
+                for r in reqs:
+                    r.admitted, r.status = now, RUNNING
+                self.ex.launch(slot, reqs)
+                self.running[slot] = reqs
+                self.max_running = max(self.max_running, len(self.running))
+                busy = True
+        return busy
+
+    def idle(self) -> bool:
+        with self.lock:
+            return not self.inbox and not self.sched.pending and not self.running
+
+    def run_until_idle(self, timeout: float = 600.0):
+        t0 = time.perf_counter()
+        while not self.idle():
+            if not self.step():
+                time.sleep(2e-5)
+            if time.perf_counter() - t0 > timeout:
+                raise TimeoutError("server did not drain")
+
+    def start(self):
+        def loop():
+            while not self.stop_flag:
+                if not self.step():
+                    time.sleep(2e-5)
+        self.stop_flag = False
+        self.thread = threading.Thread(target=loop, daemon=True)
+        self.thread.start()
+
+    def stop(self):
+        self.stop_flag = True
+        if self.thread:
+            self.thread.join()
+            self.thread = None
+
+    def metrics(self) -> dict:
+        done = [r for r in self.finished if r.status == DONE]
+        lat = np.array([r.latency for r in done]) if done else np.zeros(1)
+        segs = sum(int(np.minimum(r.n_hits + 1, r.max_bounces).sum()) for r in done)
+        span = (max(r.done for r in done) - min(r.arrival for r in done)) if done else 0.0
+        return {"queries": len(done), "failed": sum(r.status == FAILED for r in self.finished),
+                "latency_ms_p50": round(1e3 * float(np.percentile(lat, 50)), 3),
+                "latency_ms_p99": round(1e3 * float(np.percentile(lat, 99)), 3),
+                "latency_ms_max": round(1e3 * float(lat.max()), 3),
+                "segments": segs, "rays": sum(r.n for r in done),
+                "mrays_s": round(segs / span / 1e6, 2) if span > 0 else 0.0,
+                "queue_depth_mean": round(float(np.mean(self.depth_samples or [0])), 2),
+                "queue_depth_max": int(max(self.depth_samples or [0])),
+                "admission_waits": self.sched.admission_waits,
+                "max_batches_in_flight": self.max_running}
+
+
+def poisson_queries(duration: float, rate: float, seed: int = 0, scenes=range(8)):
+    """Config-5 query stream: Poisson arrivals; per query a scene (uniform), a
+    transmitter uniform over the scene outside buildings at 5-40 m, a ray
+    count log-uniform in 10k-1M (icosphere prefix) and a bounce depth uniform
+    in 1-6.  Returns [(arrival_s, scene, tx, n_rays, max_bounces)]."""
+    from rtgen import scenes as sc, workloads
+    rng = np.random.default_rng(seed)
+    geo = {s: workloads.multiscene_scene(s) for s in scenes}
+    out, t = [], 0.0
+    scene_ids = list(scenes)
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t > duration:
+            break
+        s = scene_ids[int(rng.integers(len(scene_ids)))]
+        tris, half = geo[s]
+        tx = sc.free_point(rng, half, tris, float(rng.uniform(5.0, 40.0)))
+        n = int(round(10 ** rng.uniform(4.0, 6.0)))
+        nb = int(rng.integers(1, 7))
+        out.append((t, s, tuple(float(x) for x in tx), n, nb))
+    return out
+
+
+def resident_scenes(ids=range(8)):
+    """Trees of the multi-scene set built once (source point: scene centre,
+    25 m up)."""
+    import torch
+    from . import BVH, SplitParams
+    from rtgen import workloads
+    out = {}
+    for s in ids:
+        tris, _ = workloads.multiscene_scene(s)
+        out[s] = BVH(torch.from_numpy(tris).cuda(),
+                     SplitParams(alpha=0.4, src=workloads.MULTI_SRC))
+    return out
+
+
+def run_stream(server: Server, stream, clock=time.perf_counter):
+    """Feeds the query stream at its arrival times (relative to now) while
+    the server thread runs; returns when every query has finished."""
+    server.start()
+    t0 = clock()
+    for at, s, tx, n, nb in stream:
+        while clock() - t0 < at:
+            time.sleep(max(0.0, min(1e-3, at - (clock() - t0))))
+        server.submit(s, nb, tx=tx, n_rays=n)
+    while not server.idle():
+        time.sleep(1e-3)
+    server.stop()
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--duration", type=float, default=60.0)
+    ap.add_argument("--rate", type=float, default=200.0)
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--max-batch", type=int, default=64)
+    ap.add_argument("--budget-gib", type=float, default=16.0)
+    ap.add_argument("--seed", type=int, default=0)
+    a = ap.parse_args()
+    import torch
+    t0 = time.perf_counter()
+    stream = poisson_queries(a.duration, a.rate, a.seed)
+    scenes = resident_scenes()
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    srv = Server(GpuExecutor(scenes, a.slots, a.max_batch), int(a.budget_gib * 2 ** 30),
+                 a.slots, a.max_batch)
+    run_stream(srv, stream)
+    m = srv.metrics()
+    m.update({"workload": f"poisson {a.rate:g}/s for {a.duration:g} s over 8 scenes "
+                          f"(1k-200k facets), 10k-1M rays, 1-6 bounces",
+              "slots": a.slots, "max_batch": a.max_batch, "budget_gib": a.budget_gib,
+              "setup_s": round(setup, 1)})
+    print(json.dumps(m), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -181,3 +181,17 @@ def test_batch_argument_checks():
     assert lib.rt_batch_autotune(None, 1, None, None) == R.RT_EINVAL
     lib.rt_batch_destroy(None)
     assert b"rt_batch" in lib.rt_last_error()
+
+
+def test_rays_from_directions_argument_checks():
+    lib = R.load()
+    buf = np.zeros(64, np.float32)
+    p = ctypes.c_void_p(buf.ctypes.data)
+    assert lib.rt_rays_from_directions(p, 0, 0, 0, 0, 0, 1, p, None) == R.RT_OK   # nothing to do
+    assert lib.rt_rays_from_directions(None, 2, 0, 0, 0, 0, 1, p, None) == R.RT_EINVAL
+    assert lib.rt_rays_from_directions(p, 2, 0, 0, 0, 0, 1, None, None) == R.RT_EINVAL
+    assert lib.rt_rays_from_directions(p, -1, 0, 0, 0, 0, 1, p, None) == R.RT_EINVAL
+    assert lib.rt_rays_from_directions(p, 2, 0, 0, 0, 2, 1, p, None) == R.RT_EINVAL
+    assert lib.rt_rays_from_directions(p, 2, float("nan"), 0, 0, 0, 1, p, None) == R.RT_EINVAL
+    assert lib.rt_rays_from_directions(p, 2, 0, 0, 0, 0, 1, ctypes.c_void_p(buf.ctypes.data + 4),
+                                       None) == R.RT_EINVAL

@@ -1,0 +1,77 @@
+"""Serving on the GPU: a query's results through the continuous-batching
+server are the same, bit for bit, as the same query traced alone, while
+other batches share the device; a short Poisson stream reports latency."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import paper_2208_10008_amd as R
+from paper_2208_10008_amd import serve
+from rtgen import icosphere, workloads
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def scenes():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return serve.resident_scenes(range(3))
+
+
+def test_device_rays_equal_host_rays(scenes):
+    dirs = torch.from_numpy(icosphere.directions(9).astype(np.float32)).cuda()
+    for tx, n in (((1.5, -20.25, 7.0), 1), ((300.1, 12.7, 33.3), 40_961), ((0.0, 0.0, 25.0), 999_999)):
+        dev_rays = R.rt_rays_from_directions(dirs, n, tx, 1e-4, 2000.0).cpu().numpy()
+        host = icosphere.make_rays(tx, icosphere.directions_n(n), 1e-4, 2000.0)
+        assert np.array_equal(dev_rays.view(np.uint32), host.view(np.uint32))
+
+
+def test_results_equal_alone_in_the_mix(scenes):
+    rng = np.random.default_rng(11)
+    ex = serve.GpuExecutor(scenes, slots=3, max_batch=4)
+    srv = serve.Server(ex, budget_bytes=1 << 30, slots=3, max_batch=4)
+    srv.start()
+    reqs = []
+    for k in range(14):
+        s = int(rng.integers(0, 3))
+        tris, half = workloads.multiscene_scene(s)
+        tx = tuple(float(x) for x in (rng.uniform(-0.4, 0.4) * half, rng.uniform(-0.4, 0.4) * half,
+                                      rng.uniform(5, 40)))
+        n = int(round(10 ** rng.uniform(3.0, 5.3)))
+        nb = int(rng.integers(1, 7))
+        reqs.append(srv.submit(s, nb, tx=tx, n_rays=n))
+        time.sleep(float(rng.uniform(0.0, 0.004)))
+    while not srv.idle():
+        time.sleep(1e-3)
+    srv.stop()
+    m = srv.metrics()
+    log("mix:", m)
+    assert m["queries"] == 14 and m["failed"] == 0
+    assert m["max_batches_in_flight"] >= 2, "no two batches were on the device together"
+    for r in reqs:
+        assert r.status == serve.DONE
+        rays = torch.from_numpy(icosphere.make_rays(r.tx, icosphere.directions_n(r.n_rays),
+                                                    1e-4, 2000.0)).cuda()
+        out, pl, nh = scenes[r.scene].trace_bounces(rays, r.max_bounces)
+        assert np.array_equal(out.cpu().numpy(), r.out), f"query {r.rid}: hits differ"
+        assert np.array_equal(pl.cpu().numpy(), r.path_len), f"query {r.rid}: path lengths differ"
+        assert np.array_equal(nh.cpu().numpy(), r.n_hits), f"query {r.rid}: hit counts differ"
+
+
+def test_short_poisson_stream(scenes):
+    stream = serve.poisson_queries(duration=1.5, rate=150.0, seed=4, scenes=range(3))
+    srv = serve.Server(serve.GpuExecutor(scenes, slots=4, max_batch=16), budget_bytes=4 << 30,
+                       slots=4, max_batch=16)
+    serve.run_stream(srv, stream)
+    m = srv.metrics()
+    log("poisson:", m)
+    assert m["queries"] == len(stream) and m["failed"] == 0
+    assert 0 < m["latency_ms_p50"] <= m["latency_ms_p99"] < 5000
+    assert m["mrays_s"] > 0
