@@ -36,6 +36,10 @@ import numpy as np
 
 from . import rt_rays_from_directions as _rays_from_directions
 
+def _align(x: int, a: int = 256) -> int:
+    return (x + a - 1) // a * a
+
+
 # request states
 PENDING, RUNNING, DONE, FAILED, CANCELLED = "pending", "running", "done", "failed", "cancelled"
 MAX_RAYS = 1 << 26
@@ -65,6 +69,10 @@ class Request:
     def device_bytes(self) -> int:
         """Device memory the query holds while it runs."""
         return self.n * (32 + 16 * self.max_bounces + 8 + 4)
+
+    def result_bytes(self) -> int:
+        """Host staging its results take: hits, path lengths, hit counts."""
+        return _align(self.n * 16 * self.max_bounces) + _align(self.n * 8) + _align(self.n * 4)
 
     @property
     def latency(self) -> float:
@@ -98,8 +106,10 @@ class Scheduler:
     slot and room in the memory budget; the head of the queue is never
     overtaken (no starvation)."""
 
-    def __init__(self, budget_bytes: int, slots: int, max_batch: int):
+    def __init__(self, budget_bytes: int, slots: int, max_batch: int,
+                 max_batch_bytes: int = 1 << 62):
         self.budget = budget_bytes
+        self.max_batch_bytes = max_batch_bytes  # results one batch may stage
         self.used = 0
         self.free_slots = list(range(slots))
         self.max_batch = max_batch
@@ -124,19 +134,20 @@ class Scheduler:
         if not self.free_slots:
             self.admission_waits += 1
             return None
-        batch, need = [], 0
+        batch, need, staged = [], 0, 0
         while self.pending and len(batch) < self.max_batch:
             req = self.pending[0]
-            b = req.device_bytes()
-            if b > self.budget:  # can never fit
+            b, rb = req.device_bytes(), req.result_bytes()
+            if b > self.budget or rb > self.max_batch_bytes:  # can never fit
                 self.pending.popleft()
                 req.status, req.error = FAILED, "query exceeds the memory budget"
                 self.rejected.append(req)
                 continue
-            if self.used + need + b > self.budget:
+            if self.used + need + b > self.budget or staged + rb > self.max_batch_bytes:
                 break
             batch.append(self.pending.popleft())
             need += b
+            staged += rb
         if not batch:
             self.admission_waits += 1
             return None
@@ -153,7 +164,7 @@ class GpuExecutor:
     slot.  Generated rays run from tmin to tmax along each direction."""
 
     def __init__(self, scenes, slots: int, max_batch: int, level: int = 9, tmin: float = 1e-4,
-                 tmax: float = 2000.0):
+                 tmax: float = 2000.0, stage_bytes: int = 1 << 30):
         import torch
         from rtgen import icosphere
         from . import Batch
@@ -164,6 +175,10 @@ class GpuExecutor:
         self.tmin, self.tmax = tmin, tmax
         self.streams = [torch.cuda.Stream() for _ in range(slots)]
         self.batches = [Batch(max_batch) for _ in range(slots)]
+        # pinned result staging, one buffer per slot, allocated once
+        self.stage_bytes = stage_bytes
+        self.stages = [torch.empty(stage_bytes, dtype=torch.uint8, pin_memory=True)
+                       for _ in range(slots)]
         self.events = [None] * slots
         self.work = [None] * slots
 
@@ -181,14 +196,18 @@ class GpuExecutor:
                 qs.append({"bvh": self.scenes[r.scene], "rays": rays, "max_bounces": r.max_bounces})
             self.batches[slot].set(qs)
             self.batches[slot].launch(stream=s)
+            stage, off = self.stages[slot], 0
+
+            def view(t):
+                nonlocal off
+                nb = t.numel() * t.element_size()
+                v = stage[off:off + nb].view(t.dtype).view(t.shape)
+                off += _align(nb)
+                v.copy_(t, non_blocking=True)
+                return v
             for q in qs:
-                out = torch.empty(q["out"].shape, dtype=torch.int32, pin_memory=True)
-                pl = torch.empty(q["path_len"].shape, dtype=torch.float64, pin_memory=True)
-                nh = torch.empty(q["n_hits"].shape, dtype=torch.int32, pin_memory=True)
-                out.copy_(q["out"], non_blocking=True)
-                pl.copy_(q["path_len"], non_blocking=True)
-                nh.copy_(q["n_hits"], non_blocking=True)
-                host.append((out, pl, nh))
+                host.append((view(q["out"]), view(q["path_len"]), view(q["n_hits"])))
+            assert off <= self.stage_bytes
             ev = torch.cuda.Event()
             ev.record(s)
         self.events[slot] = ev
@@ -199,8 +218,8 @@ class GpuExecutor:
 
     def collect(self, slot: int):
         reqs, qs, host = self.work[slot]
-        for r, (out, pl, nh) in zip(reqs, host):
-            r.out, r.path_len, r.n_hits = out.numpy(), pl.numpy(), nh.numpy()
+        for r, (out, pl, nh) in zip(reqs, host):  # out of the slot's staging
+            r.out, r.path_len, r.n_hits = out.numpy().copy(), pl.numpy().copy(), nh.numpy().copy()
         self.events[slot] = None
         self.work[slot] = None
         return reqs
@@ -215,7 +234,8 @@ class Server:
     def __init__(self, executor, budget_bytes: int, slots: int = 4, max_batch: int = 64,
                  clock: Callable[[], float] = time.perf_counter):
         self.ex = executor
-        self.sched = Scheduler(budget_bytes, slots, max_batch)
+        self.sched = Scheduler(budget_bytes, slots, max_batch,
+                               getattr(executor, "stage_bytes", 1 << 62))
         self.clock = clock
         self.lock = threading.Lock()
         self.inbox: collections.deque = collections.deque()
@@ -362,17 +382,29 @@ def resident_scenes(ids=range(8)):
     return out
 
 
-def run_stream(server: Server, stream, clock=time.perf_counter):
+def run_stream(server: Server, stream, clock=time.perf_counter, progress=None):
     """Feeds the query stream at its arrival times (relative to now) while
-    the server thread runs; returns when every query has finished."""
+    the server thread runs; returns when every query has finished.
+    progress: seconds between status lines on stderr (None: quiet)."""
+    import sys
     server.start()
-    t0 = clock()
+    t0 = last = clock()
+
+    def report():
+        nonlocal last
+        if progress and clock() - last >= progress:
+            last = clock()
+            print(f"[serve] t={last - t0:.1f}s finished={len(server.finished)} "
+                  f"pending={len(server.sched.pending)} running={len(server.running)}",
+                  file=sys.stderr, flush=True)
     for at, s, tx, n, nb in stream:
         while clock() - t0 < at:
             time.sleep(max(0.0, min(1e-3, at - (clock() - t0))))
         server.submit(s, nb, tx=tx, n_rays=n)
+        report()
     while not server.idle():
         time.sleep(1e-3)
+        report()
     server.stop()
 
 
@@ -385,15 +417,18 @@ def main():
     ap.add_argument("--budget-gib", type=float, default=16.0)
     ap.add_argument("--seed", type=int, default=0)
     a = ap.parse_args()
+    import sys
     import torch
     t0 = time.perf_counter()
     stream = poisson_queries(a.duration, a.rate, a.seed)
+    print(f"[serve] {len(stream)} queries drawn", file=sys.stderr, flush=True)
     scenes = resident_scenes()
     torch.cuda.synchronize()
-    setup = time.perf_counter() - t0
+    print("[serve] scenes resident", file=sys.stderr, flush=True)
     srv = Server(GpuExecutor(scenes, a.slots, a.max_batch), int(a.budget_gib * 2 ** 30),
                  a.slots, a.max_batch)
-    run_stream(srv, stream)
+    setup = time.perf_counter() - t0
+    run_stream(srv, stream, progress=5.0)
     m = srv.metrics()
     m.update({"workload": f"poisson {a.rate:g}/s for {a.duration:g} s over 8 scenes "
                           f"(1k-200k facets), 10k-1M rays, 1-6 bounces",

@@ -212,16 +212,32 @@ def dense_city(seed: int = 0, min_tris: int = 200_000, half: float = 1500.0,
     return _pack(tris)
 
 
-def free_point(tris_seed_rng, half, tris: np.ndarray, z) -> tuple:
-    """Uniform (x, y) in the area whose vertical line meets no roof facet,
-    i.e. not inside a building (walls and roofs have z > 0 vertices)."""
-    rng = tris_seed_rng
+_ROOF_BOXES: dict = {}
+
+
+def _roof_boxes(tris: np.ndarray):
+    """Footprint boxes (grown by 1 m) of the flat roof facets, cached per array."""
+    key = (tris.__array_interface__["data"][0], tris.shape)
+    hit = _ROOF_BOXES.get(key)
+    if hit is not None and hit[0] is tris:
+        return hit[1], hit[2]
     roofs = tris.reshape(-1, 3, 3)
     flat = (roofs[:, 0, 2] == roofs[:, 1, 2]) & (roofs[:, 1, 2] == roofs[:, 2, 2]) \
         & (roofs[:, 0, 2] > 0)
     r = roofs[flat].astype(np.float64)
     lo = r[:, :, :2].min(1) - 1.0
     hi = r[:, :, :2].max(1) + 1.0
+    if len(_ROOF_BOXES) > 16:
+        _ROOF_BOXES.clear()
+    _ROOF_BOXES[key] = (tris, lo, hi)
+    return lo, hi
+
+
+def free_point(tris_seed_rng, half, tris: np.ndarray, z) -> tuple:
+    """Uniform (x, y) in the area whose vertical line meets no roof facet,
+    i.e. not inside a building (walls and roofs have z > 0 vertices)."""
+    rng = tris_seed_rng
+    lo, hi = _roof_boxes(tris)
     while True:
         x = rng.uniform(-half * 0.95, half * 0.95)
         y = rng.uniform(-half * 0.95, half * 0.95)
