@@ -271,7 +271,7 @@ __device__ inline void leaf_test(const TFacet* __restrict__ tf, const RayPre& r,
 }
 
 template <int FMT, bool STATS>
-__device__ Hit closest(const void* __restrict__ nodes, const TFacet* __restrict__ tf,
+__device__ __forceinline__ Hit closest(const void* __restrict__ nodes, const TFacet* __restrict__ tf,
                        const RayPre& r, int skip_pos, int* stack_col, uint32_t& nvis,
                        uint32_t& ntest) {
   Stack st;
@@ -323,89 +323,87 @@ __device__ Hit closest(const void* __restrict__ nodes, const TFacet* __restrict_
     }
     return h;
   }
-  for (;;) {
+  // 4-wide nodes, the same speculative order: children sorted near first,
+  // the first leaf a lane reaches is parked while it keeps descending
+  constexpr int kDone = INT_MIN;
+  int leaf = 0;
+  while (node != kDone) {
     while (node >= 0) {
       if (STATS) ++nvis;
-      if constexpr (FMT == RT_NODE_BIN2) {
-        const TNode nd = static_cast<const TNode*>(nodes)[node];
-        float n0, n1;
-        const bool h0 = slab(r, nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.c.x, nd.c.y, r.tmin, h.t, n0);
-        const bool h1 = slab(r, nd.b.x, nd.b.y, nd.b.z, nd.b.w, nd.c.z, nd.c.w, r.tmin, h.t, n1);
-        if (h0 && h1) {
-          const bool first0 = n0 <= n1;
-          st.push(first0 ? nd.d.y : nd.d.x);
-          node = first0 ? nd.d.x : nd.d.y;
-        } else if (h0) {
-          node = nd.d.x;
-        } else if (h1) {
-          node = nd.d.y;
-        } else if (!st.pop(node)) {
-          return h;
+      float key[4];
+      int ref[4];
+      unsigned mask;
+      if constexpr (FMT == RT_NODE_F4) {
+        const FNode4 nd = static_cast<const FNode4*>(nodes)[node];
+        mask = nd.meta.x;
+        const float lx[4] = {nd.lox.x, nd.lox.y, nd.lox.z, nd.lox.w};
+        const float hx[4] = {nd.hix.x, nd.hix.y, nd.hix.z, nd.hix.w};
+        const float ly[4] = {nd.loy.x, nd.loy.y, nd.loy.z, nd.loy.w};
+        const float hy[4] = {nd.hiy.x, nd.hiy.y, nd.hiy.z, nd.hiy.w};
+        const float lz[4] = {nd.loz.x, nd.loz.y, nd.loz.z, nd.loz.w};
+        const float hz[4] = {nd.hiz.x, nd.hiz.y, nd.hiz.z, nd.hiz.w};
+        const int rr[4] = {nd.ref.x, nd.ref.y, nd.ref.z, nd.ref.w};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          float tn;
+          const bool hit = ((mask >> c) & 1u) &&
+                           slab(r, lx[c], hx[c], ly[c], hy[c], lz[c], hz[c], r.tmin, h.t, tn);
+          key[c] = hit ? tn : INFINITY;
+          ref[c] = rr[c];
         }
       } else {
-        float key[4];
-        int ref[4];
-        unsigned mask;
-        if constexpr (FMT == RT_NODE_F4) {
-          const FNode4 nd = static_cast<const FNode4*>(nodes)[node];
-          mask = nd.meta.x;
-          const float lx[4] = {nd.lox.x, nd.lox.y, nd.lox.z, nd.lox.w};
-          const float hx[4] = {nd.hix.x, nd.hix.y, nd.hix.z, nd.hix.w};
-          const float ly[4] = {nd.loy.x, nd.loy.y, nd.loy.z, nd.loy.w};
-          const float hy[4] = {nd.hiy.x, nd.hiy.y, nd.hiy.z, nd.hiy.w};
-          const float lz[4] = {nd.loz.x, nd.loz.y, nd.loz.z, nd.loz.w};
-          const float hz[4] = {nd.hiz.x, nd.hiz.y, nd.hiz.z, nd.hiz.w};
-          const int rr[4] = {nd.ref.x, nd.ref.y, nd.ref.z, nd.ref.w};
+        const QNode4 nd = static_cast<const QNode4*>(nodes)[node];
+        const unsigned meta = __float_as_uint(nd.h.w);
+        mask = meta >> 24;
+        const float sx = pow2f((int)(meta & 255u) - 127);
+        const float sy = pow2f((int)((meta >> 8) & 255u) - 127);
+        const float sz = pow2f((int)((meta >> 16) & 255u) - 127);
+        const int rr[4] = {nd.ref.x, nd.ref.y, nd.ref.z, nd.ref.w};
 #pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            float tn;
-            const bool hit = ((mask >> c) & 1u) &&
-                             slab(r, lx[c], hx[c], ly[c], hy[c], lz[c], hz[c], r.tmin, h.t, tn);
-            key[c] = hit ? tn : INFINITY;
-            ref[c] = rr[c];
-          }
-        } else {
-          const QNode4 nd = static_cast<const QNode4*>(nodes)[node];
-          const unsigned meta = __float_as_uint(nd.h.w);
-          mask = meta >> 24;
-          const float sx = pow2f((int)(meta & 255u) - 127);
-          const float sy = pow2f((int)((meta >> 8) & 255u) - 127);
-          const float sz = pow2f((int)((meta >> 16) & 255u) - 127);
-          const int rr[4] = {nd.ref.x, nd.ref.y, nd.ref.z, nd.ref.w};
-#pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            // decode exactly as the builder verified: fmaf(q, 2^e, origin)
-            const float lx = fmaf(qbyte(nd.qa.x, c), sx, nd.h.x);
-            const float ly = fmaf(qbyte(nd.qa.y, c), sy, nd.h.y);
-            const float lz = fmaf(qbyte(nd.qa.z, c), sz, nd.h.z);
-            const float hx = fmaf(qbyte(nd.qa.w, c), sx, nd.h.x);
-            const float hy = fmaf(qbyte(nd.qb.x, c), sy, nd.h.y);
-            const float hz = fmaf(qbyte(nd.qb.y, c), sz, nd.h.z);
-            float tn;
-            const bool hit = ((mask >> c) & 1u) && slab(r, lx, hx, ly, hy, lz, hz, r.tmin, h.t, tn);
-            key[c] = hit ? tn : INFINITY;
-            ref[c] = rr[c];
-          }
-        }
-        // nearest first
-        cswap(key[0], ref[0], key[1], ref[1]);
-        cswap(key[2], ref[2], key[3], ref[3]);
-        cswap(key[0], ref[0], key[2], ref[2]);
-        cswap(key[1], ref[1], key[3], ref[3]);
-        cswap(key[1], ref[1], key[2], ref[2]);
-        if (key[0] == INFINITY) {
-          if (!st.pop(node)) return h;
-        } else {
-          if (key[3] != INFINITY) st.push(ref[3]);
-          if (key[2] != INFINITY) st.push(ref[2]);
-          if (key[1] != INFINITY) st.push(ref[1]);
-          node = ref[0];
+        for (int c = 0; c < 4; ++c) {
+          // decode exactly as the builder verified: fmaf(q, 2^e, origin)
+          const float lx = fmaf(qbyte(nd.qa.x, c), sx, nd.h.x);
+          const float ly = fmaf(qbyte(nd.qa.y, c), sy, nd.h.y);
+          const float lz = fmaf(qbyte(nd.qa.z, c), sz, nd.h.z);
+          const float hx = fmaf(qbyte(nd.qa.w, c), sx, nd.h.x);
+          const float hy = fmaf(qbyte(nd.qb.x, c), sy, nd.h.y);
+          const float hz = fmaf(qbyte(nd.qb.y, c), sz, nd.h.z);
+          float tn;
+          const bool hit = ((mask >> c) & 1u) && slab(r, lx, hx, ly, hy, lz, hz, r.tmin, h.t, tn);
+          key[c] = hit ? tn : INFINITY;
+          ref[c] = rr[c];
         }
       }
+      // nearest first
+      cswap(key[0], ref[0], key[1], ref[1]);
+      cswap(key[2], ref[2], key[3], ref[3]);
+      cswap(key[0], ref[0], key[2], ref[2]);
+      cswap(key[1], ref[1], key[3], ref[3]);
+      cswap(key[1], ref[1], key[2], ref[2]);
+      if (key[0] == INFINITY) {
+        if (!st.pop(node)) node = kDone;
+      } else {
+        if (key[3] != INFINITY) st.push(ref[3]);
+        if (key[2] != INFINITY) st.push(ref[2]);
+        if (key[1] != INFINITY) st.push(ref[1]);
+        node = ref[0];
+      }
+      if (node < 0 && node != kDone && leaf == 0) {
+        leaf = node;
+        if (!st.pop(node)) node = kDone;
+      }
+      if (__ballot(leaf == 0 && node != kDone) == 0ull) break;
     }
-    leaf_test<STATS>(tf, r, node, skip_pos, h, best_id, ntest);
-    if (!st.pop(node)) return h;
+    while (leaf < 0) {
+      leaf_test<STATS>(tf, r, leaf, skip_pos, h, best_id, ntest);
+      leaf = 0;
+      if (node < 0 && node != kDone) {
+        leaf = node;
+        if (!st.pop(node)) node = kDone;
+      }
+    }
   }
+  return h;
 }
 
 __device__ inline void store_hit(rt_hit* out, int64_t k, const Hit& h) {
@@ -429,7 +427,7 @@ constexpr int kBlock = 64;  // one wave per work-group: the LDS stack is per wav
 // together; with `refill` it tops up free lanes at every segment.  A wave
 // exits once its rays are done; no wave ever waits for another.
 template <int FMT, bool BOUNCE, bool SEG, bool STATS>
-__device__ void trace_chains(const void* __restrict__ tn, const TFacet* __restrict__ tf,
+__device__ __forceinline__ void trace_chains(const void* __restrict__ tn, const TFacet* __restrict__ tf,
                              const float4* __restrict__ rays, int64_t n, int max_b,
                              rt_hit* __restrict__ out, double* __restrict__ path_len,
                              int32_t* __restrict__ n_hits, float4* __restrict__ seg,
