@@ -519,7 +519,9 @@ __device__ __forceinline__ void trace_chains(const void* __restrict__ tn, const 
   }
 }
 
-template <int FMT, int SD, bool BOUNCE, bool SEG, bool STATS>
+// The LDS stack (dynamic shared memory) holds exactly the entries the tree
+// can need: stack_need(depth) per lane, in lane-column layout.
+template <int FMT, bool BOUNCE, bool SEG, bool STATS>
 __global__ __launch_bounds__(kBlock) void k_trace(const void* __restrict__ tn,
                                                   const TFacet* __restrict__ tf,
                                                   const float4* __restrict__ rays, int64_t n,
@@ -530,7 +532,7 @@ __global__ __launch_bounds__(kBlock) void k_trace(const void* __restrict__ tn,
                                                   uint32_t* __restrict__ stats,
                                                   unsigned long long* __restrict__ queue,
                                                   int refill) {
-  __shared__ int s_stack[SD * kBlock];
+  extern __shared__ int s_stack[];
   trace_chains<FMT, BOUNCE, SEG, STATS>(tn, tf, rays, n, max_b, out, path_len, n_hits, seg, stats,
                                         queue, refill, (int64_t)blockIdx.x * kBlock,
                                         s_stack + threadIdx.x);
@@ -540,9 +542,9 @@ __global__ __launch_bounds__(kBlock) void k_trace(const void* __restrict__ tn,
 // finds its query by binary search over the queries' first batch numbers and
 // traces that query's batch g - first.  Queries of one launch share the node
 // format; each brings its own tree.
-template <int FMT, int SD>
+template <int FMT>
 __global__ __launch_bounds__(kBlock) void k_trace_batch(const BatchQuery* __restrict__ q, int nq) {
-  __shared__ int s_stack[SD * kBlock];
+  extern __shared__ int s_stack[];
   const int64_t g = blockIdx.x;
   int lo = 0, hi = nq - 1;  // last query whose first batch <= g
   while (lo < hi) {
@@ -560,11 +562,11 @@ __global__ __launch_bounds__(kBlock) void k_trace_batch(const BatchQuery* __rest
 
 // Persistent form of the batched launch: each wave takes batch numbers from
 // a global counter (one atomic per 64 rays) until all are done.
-template <int FMT, int SD>
+template <int FMT>
 __global__ __launch_bounds__(kBlock) void k_trace_batch_q(const BatchQuery* __restrict__ q, int nq,
                                                           int64_t total,
                                                           unsigned long long* __restrict__ queue) {
-  __shared__ int s_stack[SD * kBlock];
+  extern __shared__ int s_stack[];
   const int lane = threadIdx.x & 63;
   for (;;) {
     unsigned long long g = 0;
@@ -588,19 +590,23 @@ __global__ __launch_bounds__(kBlock) void k_trace_batch_q(const BatchQuery* __re
 
 __global__ void k_queue_reset(unsigned long long* q) { *q = 0ull; }
 
-template <int FMT, int SD, bool BOUNCE, bool SEG, bool STATS>
-void launch_sd(const Buffers& B, const float* rays, int64_t n, int max_b, rt_hit* out,
-               double* path_len, int32_t* n_hits, float* seg, uint32_t* stats, int grid,
-               int refill, hipStream_t s) {
-  auto kern = k_trace<FMT, SD, BOUNCE, SEG, STATS>;
-  static int resident = 0;  // persistent work-groups that fit the device at once
-  if (resident == 0) {
-    int dev = 0, cus = 0, per_cu = 0;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, 0);
-    resident = std::max(1, cus * std::max(1, per_cu));
-  }
+// Stack entries a ray can need: one per binary level below the root, or up
+// to three per 4-wide level.  Sizing the LDS stack to the tree keeps the
+// most waves resident (20 entries = 5 KB per wave lets 8 waves share a
+// compute unit's 160 KB).
+template <int FMT>
+constexpr int stack_need(int depth) {
+  return FMT == RT_NODE_BIN2 ? depth : 3 * ((depth + 1) / 2);
+}
+template <int FMT>
+size_t stack_bytes(int depth) {
+  return sizeof(int) * kBlock * std::max(1, stack_need<FMT>(depth));
+}
+
+template <int FMT, bool BOUNCE, bool SEG, bool STATS>
+void launch(const Buffers& B, int depth, const float* rays, int64_t n, int max_b, rt_hit* out,
+            double* path_len, int32_t* n_hits, float* seg, uint32_t* stats, int grid,
+            int refill, hipStream_t s) {
   const int64_t batches = (n + kBlock - 1) / kBlock;
   const void* nodes = FMT == RT_NODE_BIN2 ? (const void*)B.tnodes : (const void*)B.wnodes;
   unsigned long long* q = nullptr;
@@ -611,36 +617,10 @@ void launch_sd(const Buffers& B, const float* rays, int64_t n, int max_b, rt_hit
     blocks = std::min<int64_t>(grid, batches);
     hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(1), 0, s, q);
   }
-  (void)resident;
-  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kBlock), 0, s, nodes, B.tfacets,
+  hipLaunchKernelGGL((k_trace<FMT, BOUNCE, SEG, STATS>), dim3((unsigned)blocks), dim3(kBlock),
+                     stack_bytes<FMT>(depth), s, nodes, B.tfacets,
                      reinterpret_cast<const float4*>(rays), n, max_b, out, path_len, n_hits,
                      reinterpret_cast<float4*>(seg), stats, q, refill);
-}
-
-// Stack entries a ray can need: one per binary level below the root, or up
-// to three per 4-wide level.  A short LDS stack keeps more waves resident:
-// 20 entries (5 KB per wave) let 8 waves share a compute unit's 160 KB.
-constexpr int kShortStack = 20;
-constexpr int kMidStack = 32;
-template <int FMT>
-constexpr int stack_need(int depth) {
-  return FMT == RT_NODE_BIN2 ? depth : 3 * ((depth + 1) / 2);
-}
-
-template <int FMT, bool BOUNCE, bool SEG, bool STATS>
-void launch(const Buffers& B, int depth, const float* rays, int64_t n, int max_b, rt_hit* out,
-            double* path_len, int32_t* n_hits, float* seg, uint32_t* stats, int grid,
-            int refill, hipStream_t s) {
-  if (stack_need<FMT>(depth) <= kShortStack)
-    launch_sd<FMT, kShortStack, BOUNCE, SEG, STATS>(B, rays, n, max_b, out, path_len, n_hits, seg,
-                                                    stats, grid, refill, s);
-  else if (stack_need<FMT>(depth) <= kMidStack)
-    launch_sd<FMT, kMidStack, BOUNCE, SEG, STATS>(B, rays, n, max_b, out, path_len, n_hits, seg,
-                                                  stats, grid, refill, s);
-  else
-    launch_sd<FMT, stack_need<FMT>(RT_MAX_DEPTH), BOUNCE, SEG, STATS>(B, rays, n, max_b, out,
-                                                                      path_len, n_hits, seg,
-                                                                      stats, grid, refill, s);
 }
 
 template <int FMT>
@@ -661,43 +641,27 @@ void launch_fmt(const Buffers& B, int depth, const float* rays, int64_t n, int m
   }
 }
 
-template <int FMT, int SD>
-void launch_batch_sd(const BatchQuery* table, int nq, int64_t total, int grid,
-                     unsigned long long* queue, hipStream_t s) {
+template <int FMT>
+void launch_batch_fmt(const BatchQuery* table, int nq, int64_t total, int depth, int grid,
+                      unsigned long long* queue, hipStream_t s) {
+  const size_t lds = stack_bytes<FMT>(depth);
   if (grid > 0) {
     hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(1), 0, s, queue);
-    hipLaunchKernelGGL((k_trace_batch_q<FMT, SD>), dim3((unsigned)std::min<int64_t>(grid, total)),
-                       dim3(kBlock), 0, s, table, nq, total, queue);
+    hipLaunchKernelGGL((k_trace_batch_q<FMT>), dim3((unsigned)std::min<int64_t>(grid, total)),
+                       dim3(kBlock), lds, s, table, nq, total, queue);
   } else {
-    hipLaunchKernelGGL((k_trace_batch<FMT, SD>), dim3((unsigned)total), dim3(kBlock), 0, s, table,
-                       nq);
+    hipLaunchKernelGGL((k_trace_batch<FMT>), dim3((unsigned)total), dim3(kBlock), lds, s, table, nq);
   }
 }
 
 template <int FMT>
-void launch_batch_fmt(const BatchQuery* table, int nq, int64_t total, int depth, int grid,
-                      unsigned long long* queue, hipStream_t s) {
-  if (stack_need<FMT>(depth) <= kShortStack)
-    launch_batch_sd<FMT, kShortStack>(table, nq, total, grid, queue, s);
-  else if (stack_need<FMT>(depth) <= kMidStack)
-    launch_batch_sd<FMT, kMidStack>(table, nq, total, grid, queue, s);
-  else
-    launch_batch_sd<FMT, stack_need<FMT>(RT_MAX_DEPTH)>(table, nq, total, grid, queue, s);
-}
-
-template <int FMT, int SD>
-int resident_sd() {
+int resident_fmt(int depth) {
   int dev = 0, cus = 0, per_cu = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_trace_batch_q<FMT, SD>, kBlock, 0);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_trace_batch_q<FMT>, kBlock,
+                                                     stack_bytes<FMT>(depth));
   return std::max(1, cus * std::max(1, per_cu));
-}
-template <int FMT>
-int resident_fmt(int depth) {
-  if (stack_need<FMT>(depth) <= kShortStack) return resident_sd<FMT, kShortStack>();
-  if (stack_need<FMT>(depth) <= kMidStack) return resident_sd<FMT, kMidStack>();
-  return resident_sd<FMT, stack_need<FMT>(RT_MAX_DEPTH)>();
 }
 
 }  // namespace
