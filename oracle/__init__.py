@@ -17,6 +17,10 @@ Functions and what pins them:
   :func:`brute` on every ray.
 * :func:`bounces` -- specular reflection chains; pinned by image-source
   closed forms.
+* :mod:`oracle.reception` -- receiving spheres of Sec. III-C, Eq. (4), in
+  numpy float64.  Pinned by a hand-worked example, the exact mean number of
+  receptions in free space, hole-free coverage of an icosphere launch, and
+  image-source path lengths over a ground and a wall.
 """
 from __future__ import annotations
 

@@ -148,3 +148,16 @@ def angular_spacing(level: int) -> float:
     the icosahedron edge angle halved once per subdivision."""
     edge = np.arccos(1.0 / np.sqrt(5.0))   # 63.43 degrees
     return float(edge / 2 ** level)
+
+
+@functools.lru_cache(maxsize=None)
+def edge_angles(level: int) -> np.ndarray:
+    """Angles (rad, float64) between the launch directions joined by an edge
+    of the subdivided icosahedron at a level, one per edge.  Their mean and
+    maximum are the usual choices for the angle between adjacent rays."""
+    v = directions(level)
+    f = faces(level)
+    e = np.concatenate([f[:, [0, 1]], f[:, [1, 2]], f[:, [2, 0]]])
+    e = np.unique(np.sort(e, axis=1), axis=0)
+    c = np.clip((v[e[:, 0]] * v[e[:, 1]]).sum(1), -1.0, 1.0)
+    return np.arccos(c)

@@ -68,3 +68,13 @@ def test_spacing_and_rays():
     assert np.all(r[:, 0:3] == np.float32([1, 2, 3])) and np.all(r[:, 3] == np.float32(1e-4))
     first = ico.directions_n(100)
     assert first.shape == (100, 3) and np.array_equal(first, ico.directions(3)[:100])
+
+
+@pytest.mark.parametrize("level", [0, 2, 4])
+def test_edge_angles(level):
+    a = ico.edge_angles(level)
+    assert a.size == 30 * 4 ** level                        # E = 3F / 2
+    # level 0: every edge subtends arccos(1/sqrt(5)); later levels split each
+    # edge in two, so angles shrink by about half per level
+    assert abs(a.min() - ico.angular_spacing(level)) < 1e-12
+    assert a.max() < 1.25 * ico.angular_spacing(level)
