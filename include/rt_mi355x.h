@@ -193,6 +193,76 @@ int rt_trace_ex(const rt_bvh* b, const float* rays, int64_t n, int32_t max_bounc
 int rt_rays_from_directions(const float* dirs, int64_t n, float ox, float oy, float oz, float tmin,
                             float tmax, float* rays, hipStream_t s);
 
+/* ---- ray reception (Sec. III-C, Eq. (4)) ---------------------------------
+ * A field point R receives segment b of a ray (b = 0: the launched ray, b = k:
+ * after k reflections; origin o, direction d, range [tmin, t_end] with t_end
+ * the hit's t, or tmax when the segment missed) when the foot of the
+ * perpendicular from R lies in that range and R lies in the receiving sphere
+ * of radius l * delta / sqrt(3):
+ *     w = R - o,  s = (w.d) / (d.d),  dist^2 = |w - s d|^2,
+ *     l = L_b + |w|  (L_b = sum over the earlier hits of t |d|, the path
+ *                     length up to o; l is the path source -> R),
+ *     received  <=>  tmin <= s <= t_end  and  3 dist^2 <= (l delta)^2.
+ * Evaluated in float64 from the float32 segment, in exactly this order,
+ * without fused multiply-add, so equal inputs give equal decisions on any
+ * IEEE float64 implementation.  Field points with a NaN coordinate are never
+ * received. */
+typedef struct rt_reception {
+  int32_t rx;    /* index of the field point */
+  int32_t ray;   /* index of the ray */
+  int32_t order; /* segment index b (number of reflections before it) */
+  int32_t keep;  /* 0 as found; rt_receive_dedup sets 1 on one reception per path */
+  double l;      /* path length from the source to the field point along the ray */
+  double dist;   /* distance of the field point from the segment's line */
+} rt_reception; /* 32 bytes */
+
+typedef struct rt_receivers {
+  const double* pos;  /* device float64 [n][3] field points, 8-byte aligned */
+  int32_t n;          /* number of field points, >= 0 */
+  int32_t reserved;   /* must be 0 */
+  double delta;       /* angle between adjacent launched rays, radians, finite, >= 0 */
+  rt_reception* rec;  /* device [cap] output, 16-byte aligned (nullable when cap == 0) */
+  int64_t cap;        /* records rec can hold, 0 .. 2^31 - 1 */
+  int64_t* count;     /* device int64: set to the number of receptions found, which
+                         may exceed cap; only min(count, cap) records are written, in
+                         no particular order (a truncated set is an arbitrary subset) */
+} rt_receivers;
+
+/* rt_trace_bounces that also tests every traced segment against the field
+ * points as it is traced (the segment is never stored).  rx is a host struct.
+ * Cost: one float64 test per segment and field point, so meant for up to a few
+ * hundred field points.  Errors: as rt_trace_bounces; RT_EINVAL for a bad rx
+ * (NULL count, n >= 2^31 rays, misaligned or NULL pos / rec, delta not
+ * finite or negative, cap out of range). */
+int rt_trace_receive(const rt_bvh* b, const float* rays, int64_t n, int32_t max_bounces,
+                     rt_hit* out, double* path_len, int32_t* n_hits, const rt_receivers* rx,
+                     hipStream_t s);
+
+/* The same reception test over stored chains: seg_rays [max_bounces][n][8]
+ * (as written by rt_trace_ex's seg_rays) and hits [max_bounces][n] (as
+ * written by rt_trace_bounces).  Segment b of ray i exists when b == 0 or
+ * hits[b - 1][i] is a hit (and so on down to 0); only existing segments are
+ * read.  Results equal rt_trace_receive's on the chains that produced them.
+ * Errors: RT_EINVAL (NULL / misaligned arrays, n outside 0..2^31 - 1,
+ * max_bounces outside 1..RT_MAX_BOUNCES, bad rx), RT_EHIP. */
+int rt_receive_segments(const float* seg_rays, const rt_hit* hits, int64_t n,
+                        int32_t max_bounces, const rt_receivers* rx, hipStream_t s);
+
+/* Bytes of device workspace rt_receive_dedup needs for cap records and
+ * n_rx field points (256-byte multiple); -1 if the sizes are out of range. */
+int64_t rt_receive_dedup_workspace(int64_t cap, int32_t n_rx);
+
+/* Groups the first min(*rx->count, rx->cap) records by (field point, order,
+ * facets hit before the segment, read from hits [max_bounces][n]) and sets
+ * keep = 1 on one record per group -- the smallest dist, ties to the smaller
+ * ray index -- and keep = 0 on the others.  Neighbouring rays whose receiving
+ * spheres overlap give one group per propagation path.  work: device, at
+ * least rt_receive_dedup_workspace(rx->cap, rx->n) bytes, 256-byte aligned.
+ * Records whose rx, ray or order are out of range are left with keep = 0.
+ * Errors: RT_EINVAL (NULL / misaligned, workspace too small), RT_EHIP. */
+int rt_receive_dedup(const rt_hit* hits, int64_t n, int32_t max_bounces, const rt_receivers* rx,
+                     void* work, int64_t work_bytes, hipStream_t s);
+
 /* ---- inspection and lifetime ------------------------------------------ */
 int rt_bvh_info_get(const rt_bvh* b, rt_bvh_info* info); /* host struct */
 

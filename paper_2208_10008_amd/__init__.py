@@ -71,6 +71,17 @@ class rt_batch_config(ctypes.Structure):
                 ("graph", ctypes.c_int32)]
 
 
+class rt_receivers(ctypes.Structure):
+    _fields_ = [("pos", ctypes.c_void_p), ("n", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("delta", ctypes.c_double), ("rec", ctypes.c_void_p), ("cap", ctypes.c_int64),
+                ("count", ctypes.c_void_p)]
+
+
+# numpy view of rt_reception (32 bytes)
+RECEPTION_DTYPE = np.dtype([("rx", "<i4"), ("ray", "<i4"), ("order", "<i4"), ("keep", "<i4"),
+                            ("l", "<f8"), ("dist", "<f8")])
+assert RECEPTION_DTYPE.itemsize == 32
+
 BATCH_MODES = {"direct": 0, "queue": 1}
 BATCH_ORDERS = {"given": 0, "cost": 1}
 
@@ -84,7 +95,9 @@ EXPORTS = ("rt_split_params_default", "rt_build", "rt_rebuild", "rt_trace",
            "rt_trace_bounces", "rt_trace_ex", "rt_bvh_info_get", "rt_bvh_download",
            "rt_bvh_export_trace_nodes", "rt_bvh_destroy", "rt_last_error", "rt_batch_create",
            "rt_batch_set", "rt_batch_configure", "rt_batch_get_config", "rt_batch_launch",
-           "rt_batch_autotune", "rt_batch_destroy", "rt_rays_from_directions")
+           "rt_batch_autotune", "rt_batch_destroy", "rt_rays_from_directions",
+           "rt_trace_receive", "rt_receive_segments", "rt_receive_dedup_workspace",
+           "rt_receive_dedup")
 PROBE_EXPORTS = ("rt_probe_read", "rt_probe_copy")  # include/rt_probe.h
 
 _lib = None
@@ -125,11 +138,18 @@ def load(path: str = LIB_PATH):
     lib.rt_batch_destroy.argtypes = [P]
     lib.rt_batch_destroy.restype = None
     lib.rt_probe_copy.argtypes = [P, P, i64, P]
+    RX = ctypes.POINTER(rt_receivers)
+    lib.rt_trace_receive.argtypes = [P, P, i64, i32, P, P, P, RX, P]
+    lib.rt_receive_segments.argtypes = [P, P, i64, i32, RX, P]
+    lib.rt_receive_dedup_workspace.argtypes = [i64, i32]
+    lib.rt_receive_dedup_workspace.restype = i64
+    lib.rt_receive_dedup.argtypes = [P, i64, i32, RX, P, i64, P]
     for name in ("rt_build", "rt_rebuild", "rt_trace", "rt_trace_bounces", "rt_trace_ex",
                  "rt_bvh_info_get", "rt_bvh_download", "rt_bvh_export_trace_nodes",
                  "rt_probe_read", "rt_probe_copy", "rt_batch_create", "rt_batch_set",
                  "rt_batch_configure", "rt_batch_get_config", "rt_batch_launch",
-                 "rt_batch_autotune", "rt_rays_from_directions"):
+                 "rt_batch_autotune", "rt_rays_from_directions", "rt_trace_receive",
+                 "rt_receive_segments", "rt_receive_dedup"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -226,6 +246,77 @@ def rt_trace_ex(handle, rays, max_bounces, out, path_len=None, n_hits=None, seg_
     o.block, o.grid, o.refill = block, grid, refill
     _check(lib.rt_trace_ex(handle, _ptr(rays), rays.shape[0], max_bounces, _ptr(out),
                            _ptr(path_len), _ptr(n_hits), ctypes.byref(o), _stream(stream)))
+
+
+def rt_trace_receive(handle, rays, max_bounces, out, path_len, n_hits, receivers: "Receivers",
+                     stream=None):
+    lib = load()
+    c = receivers.c()
+    _check(lib.rt_trace_receive(handle, _ptr(rays), rays.shape[0], max_bounces, _ptr(out),
+                                _ptr(path_len), _ptr(n_hits), ctypes.byref(c), _stream(stream)))
+
+
+def rt_receive_segments(seg_rays, hits, max_bounces, receivers: "Receivers", stream=None):
+    """seg_rays [max_bounces, n, 8] float32, hits [max_bounces, n, 4] int32 view of rt_hit."""
+    lib = load()
+    c = receivers.c()
+    _check(lib.rt_receive_segments(_ptr(seg_rays), _ptr(hits), hits.shape[1], max_bounces,
+                                   ctypes.byref(c), _stream(stream)))
+
+
+def rt_receive_dedup_workspace(cap, n_rx) -> int:
+    return int(load().rt_receive_dedup_workspace(cap, n_rx))
+
+
+def rt_receive_dedup(hits, max_bounces, receivers: "Receivers", work, stream=None):
+    lib = load()
+    c = receivers.c()
+    _check(lib.rt_receive_dedup(_ptr(hits), hits.shape[1], max_bounces, ctypes.byref(c),
+                                _ptr(work), work.numel() * work.element_size(), _stream(stream)))
+
+
+class Receivers:
+    """Field points (float64 [n, 3] CUDA tensor), the launch's ray spacing
+    delta (radians) and a device buffer of `cap` reception records
+    (rt_reception) with its counter."""
+
+    def __init__(self, pos, delta: float, cap: int):
+        import torch
+        _dev(pos, torch.float64, 3, "pos")
+        self.pos = pos
+        self.delta = float(delta)
+        self.cap = int(cap)
+        self.rec = torch.zeros((max(self.cap, 1), 8), dtype=torch.int32, device=pos.device)
+        self.count_buf = torch.zeros(1, dtype=torch.int64, device=pos.device)
+        self._work = None
+
+    def c(self) -> rt_receivers:
+        c = rt_receivers()
+        c.pos = self.pos.data_ptr() if self.pos.shape[0] else None
+        c.n = self.pos.shape[0]
+        c.reserved = 0
+        c.delta = self.delta
+        c.rec = self.rec.data_ptr()
+        c.cap = self.cap
+        c.count = self.count_buf.data_ptr()
+        return c
+
+    def count(self) -> int:
+        """Receptions found by the last call (may exceed cap); synchronises."""
+        return int(self.count_buf.item())
+
+    def records(self) -> np.ndarray:
+        """The stored records as a numpy RECEPTION_DTYPE array (synchronises)."""
+        k = min(self.count(), self.cap)
+        return self.rec[:k].cpu().numpy().view(RECEPTION_DTYPE).reshape(-1)
+
+    def dedup(self, hits, max_bounces, stream=None):
+        """Marks one record per (field point, order, facet sequence) as kept."""
+        import torch
+        need = rt_receive_dedup_workspace(self.cap, self.pos.shape[0])
+        if self._work is None or self._work.numel() < need:
+            self._work = torch.empty(max(need, 256), dtype=torch.uint8, device=self.pos.device)
+        rt_receive_dedup(hits, max_bounces, self, self._work, stream)
 
 
 def rt_bvh_info_get(handle) -> rt_bvh_info:
@@ -326,6 +417,22 @@ class BVH:
         else:
             rt_trace_ex(self.handle, rays, max_bounces, out, path_len, n_hits, seg_rays,
                         ray_stats, block, grid, refill, stream)
+        return out, path_len, n_hits
+
+    def trace_receive(self, rays, max_bounces, receivers: Receivers, out=None, path_len=None,
+                      n_hits=None, stream=None):
+        """Reflection chains with every segment tested against the field
+        points (Sec. III-C); the receptions land in ``receivers``."""
+        import torch
+        _dev(rays, torch.float32, 8, "rays")
+        n = rays.shape[0]
+        if out is None:
+            out = self.hits_buffer(n, max_bounces)
+        if path_len is None:
+            path_len = torch.empty(n, dtype=torch.float64, device=rays.device)
+        if n_hits is None:
+            n_hits = torch.empty(n, dtype=torch.int32, device=rays.device)
+        rt_trace_receive(self.handle, rays, max_bounces, out, path_len, n_hits, receivers, stream)
         return out, path_len, n_hits
 
     def close(self):

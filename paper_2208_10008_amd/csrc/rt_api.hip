@@ -144,6 +144,9 @@ int do_build(rt_bvh* b, const float* tris, int64_t n, const rt_split_params* p, 
   return RT_OK;
 }
 
+
+}  // namespace
+
 int check_trace_args(const rt_bvh* b, const float* rays, int64_t n, int32_t max_b, const rt_hit* out,
                      const double* path_len, const int32_t* n_hits, const rt_trace_opts* opts) {
   if (!b || b->info.n_tris <= 0) return set_error(RT_EINVAL, "trace: invalid tree handle");
@@ -168,8 +171,6 @@ int check_trace_args(const rt_bvh* b, const float* rays, int64_t n, int32_t max_
   }
   return RT_OK;
 }
-
-}  // namespace
 }  // namespace rt
 
 using namespace rt;

@@ -176,9 +176,74 @@ struct alignas(16) BatchQuery {
   int32_t pad[3];
 };
 
+// ---- ray reception (Sec. III-C, Eq. (4)) ----
+struct RecvArgs {
+  const double* pos;            // [n_rx][3]
+  rt_reception* rec;            // [cap]
+  unsigned long long* count;    // receptions found
+  int64_t cap;
+  double delta;
+  int32_t n_rx;
+  int32_t pad;
+};
+
+// Path length t |d| of a segment in float64, without contraction, so that
+// the tracer and the reception kernels accumulate the same bits.
+__device__ __forceinline__ double seg_path(float t, float dx, float dy, float dz) {
+#pragma clang fp contract(off)
+  const double x = dx, y = dy, z = dz;
+  return (double)t * sqrt(x * x + y * y + z * z);
+}
+
+// Tests one segment (origin o, direction d, range [t0, t1], path length L
+// before it) of ray `ray` against every field point and appends the
+// receptions.  Called by every active lane of a wave with the same field
+// point list; one atomic per wave and field point with receptions.
+__device__ __forceinline__ void receive_segment(const RecvArgs& a, int64_t ray, int order,
+                                                float ox, float oy, float oz, float dx, float dy,
+                                                float dz, float t0, float t1, double L) {
+#pragma clang fp contract(off)
+  const int lane = threadIdx.x & 63;
+  const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  const double Ox = ox, Oy = oy, Oz = oz, Dx = dx, Dy = dy, Dz = dz, T0 = t0, T1 = t1;
+  const double dd = Dx * Dx + Dy * Dy + Dz * Dz;
+  for (int r = 0; r < a.n_rx; ++r) {
+    const double wx = a.pos[3 * r] - Ox, wy = a.pos[3 * r + 1] - Oy, wz = a.pos[3 * r + 2] - Oz;
+    const double s = (wx * Dx + wy * Dy + wz * Dz) / dd;
+    const double px = wx - s * Dx, py = wy - s * Dy, pz = wz - s * Dz;
+    const double dist2 = px * px + py * py + pz * pz;
+    const double l = L + sqrt(wx * wx + wy * wy + wz * wz);
+    const double rr = l * a.delta;
+    const bool ok = (s >= T0) && (s <= T1) && (3.0 * dist2 <= rr * rr);
+    const unsigned long long m = __ballot(ok);
+    if (m == 0ull) continue;
+    const int leader = __ffsll((long long)m) - 1;
+    unsigned long long base = 0;
+    if (lane == leader) base = atomicAdd(a.count, (unsigned long long)__popcll(m));
+    base = __shfl(base, leader);
+    if (ok) {
+      const unsigned long long k = base + __popcll(m & below);
+      if (k < (unsigned long long)a.cap) {
+        rt_reception e;
+        e.rx = r;
+        e.ray = (int32_t)ray;
+        e.order = order;
+        e.keep = 0;
+        e.l = l;
+        e.dist = sqrt(dist2);
+        a.rec[k] = e;
+      }
+    }
+  }
+}
+
 // error reporting (thread-local message), defined in rt_api.hip
 int set_error(int code, const std::string& msg);
 int check_hip(hipError_t e, const char* what);
+
+// Argument checks of the trace calls (api.hip).
+int check_trace_args(const rt_bvh* b, const float* rays, int64_t n, int32_t max_b, const rt_hit* out,
+                     const double* path_len, const int32_t* n_hits, const rt_trace_opts* opts);
 
 // build.hip
 int build_tree(Buffers& B, const float* tris, int64_t n, const rt_split_params& p,
@@ -194,6 +259,10 @@ int launch_trace_batch(const BatchQuery* table, int nq, int64_t total_batches, i
                        int depth, int grid, unsigned long long* queue, hipStream_t s);
 // Work-groups of the trace kernel that fit the device at once for this format and depth.
 int trace_resident_groups(int node_format, int depth);
+// Chains with the reception test of every segment (receive.hip zeroes the count first).
+int launch_trace_receive(const Buffers& B, int node_format, int depth, const float* rays,
+                         int64_t n, int32_t max_bounces, rt_hit* out, double* path_len,
+                         int32_t* n_hits, const RecvArgs& recv, hipStream_t s);
 
 }  // namespace rt
 

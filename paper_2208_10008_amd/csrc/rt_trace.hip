@@ -426,13 +426,14 @@ constexpr int kBlock = 64;  // one wave per work-group: the LDS stack is per wav
 // wave's chains have ended, so a wave traces adjacent launch directions
 // together; with `refill` it tops up free lanes at every segment.  A wave
 // exits once its rays are done; no wave ever waits for another.
-template <int FMT, bool BOUNCE, bool SEG, bool STATS>
+template <int FMT, bool BOUNCE, bool SEG, bool STATS, bool RECV>
 __device__ __forceinline__ void trace_chains(const void* __restrict__ tn, const TFacet* __restrict__ tf,
                              const float4* __restrict__ rays, int64_t n, int max_b,
                              rt_hit* __restrict__ out, double* __restrict__ path_len,
                              int32_t* __restrict__ n_hits, float4* __restrict__ seg,
                              uint32_t* __restrict__ stats, unsigned long long* __restrict__ queue,
-                             int refill, int64_t batch_base, int* stack) {
+                             int refill, int64_t batch_base, int* stack,
+                             const RecvArgs& recv) {
   const int lane = threadIdx.x & 63;
   const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   int64_t i = -1;  // ray of this lane, -1 when free
@@ -487,10 +488,12 @@ __device__ __forceinline__ void trace_chains(const void* __restrict__ tn, const 
       if (isfinite(tp)) h.t = fminf(fmaxf(tp, tmin), tmax);
     }
     store_hit(out, (int64_t)b * n + i, h);
+    if (RECV)  // receiving spheres (Sec. III-C): path holds the length before this segment
+      receive_segment(recv, i, b, ox, oy, oz, dx, dy, dz, tmin, h.id >= 0 ? h.t : tmax, path);
     bool more = false;
     if (BOUNCE && h.id >= 0) {
       ++hits;
-      path += (double)h.t * sqrt((double)dx * dx + (double)dy * dy + (double)dz * dz);
+      path += seg_path(h.t, dx, dy, dz);
       if (b + 1 < max_b) {
         // specular reflection about the facet plane, launched from the hit point
         ox = fmaf(h.t, dx, ox);
@@ -533,9 +536,24 @@ __global__ __launch_bounds__(kBlock) void k_trace(const void* __restrict__ tn,
                                                   unsigned long long* __restrict__ queue,
                                                   int refill) {
   extern __shared__ int s_stack[];
-  trace_chains<FMT, BOUNCE, SEG, STATS>(tn, tf, rays, n, max_b, out, path_len, n_hits, seg, stats,
-                                        queue, refill, (int64_t)blockIdx.x * kBlock,
-                                        s_stack + threadIdx.x);
+  trace_chains<FMT, BOUNCE, SEG, STATS, false>(tn, tf, rays, n, max_b, out, path_len, n_hits, seg,
+                                               stats, queue, refill, (int64_t)blockIdx.x * kBlock,
+                                               s_stack + threadIdx.x, RecvArgs{});
+}
+
+// Reflection chains whose segments are tested against field points as they
+// are traced (Sec. III-C): nothing per segment is stored.
+template <int FMT>
+__global__ __launch_bounds__(kBlock) void k_trace_recv(const void* __restrict__ tn,
+                                                       const TFacet* __restrict__ tf,
+                                                       const float4* __restrict__ rays, int64_t n,
+                                                       int max_b, rt_hit* __restrict__ out,
+                                                       double* __restrict__ path_len,
+                                                       int32_t* __restrict__ n_hits, RecvArgs recv) {
+  extern __shared__ int s_stack[];
+  trace_chains<FMT, true, false, false, true>(tn, tf, rays, n, max_b, out, path_len, n_hits, nullptr,
+                                              nullptr, nullptr, 0, (int64_t)blockIdx.x * kBlock,
+                                              s_stack + threadIdx.x, recv);
 }
 
 // Many queries (trees, ray sets, bounce limits) in one launch: work-group g
@@ -555,9 +573,9 @@ __global__ __launch_bounds__(kBlock) void k_trace_batch(const BatchQuery* __rest
   const BatchQuery Q = q[lo];
   const int64_t local = g - Q.first_batch;
   if (local * kBlock >= Q.n) return;
-  trace_chains<FMT, true, false, false>(Q.nodes, Q.facets, Q.rays, Q.n, Q.max_b, Q.out, Q.path_len,
-                                        Q.n_hits, nullptr, nullptr, nullptr, 0, local * kBlock,
-                                        s_stack + threadIdx.x);
+  trace_chains<FMT, true, false, false, false>(Q.nodes, Q.facets, Q.rays, Q.n, Q.max_b, Q.out,
+                                               Q.path_len, Q.n_hits, nullptr, nullptr, nullptr, 0,
+                                               local * kBlock, s_stack + threadIdx.x, RecvArgs{});
 }
 
 // Persistent form of the batched launch: each wave takes batch numbers from
@@ -582,9 +600,9 @@ __global__ __launch_bounds__(kBlock) void k_trace_batch_q(const BatchQuery* __re
     const BatchQuery Q = q[lo];
     const int64_t local = (int64_t)g - Q.first_batch;
     if (local * kBlock >= Q.n) continue;
-    trace_chains<FMT, true, false, false>(Q.nodes, Q.facets, Q.rays, Q.n, Q.max_b, Q.out,
-                                          Q.path_len, Q.n_hits, nullptr, nullptr, nullptr, 0,
-                                          local * kBlock, s_stack + threadIdx.x);
+    trace_chains<FMT, true, false, false, false>(Q.nodes, Q.facets, Q.rays, Q.n, Q.max_b, Q.out,
+                                                 Q.path_len, Q.n_hits, nullptr, nullptr, nullptr, 0,
+                                                 local * kBlock, s_stack + threadIdx.x, RecvArgs{});
   }
 }
 
@@ -683,6 +701,32 @@ int trace_resident_groups(int node_format, int depth) {
     case RT_NODE_Q4: return resident_fmt<RT_NODE_Q4>(depth);
     default: return resident_fmt<RT_NODE_BIN2>(depth);
   }
+}
+
+int launch_trace_receive(const Buffers& B, int node_format, int depth, const float* rays,
+                         int64_t n, int32_t max_b, rt_hit* out, double* path_len,
+                         int32_t* n_hits, const RecvArgs& recv, hipStream_t s) {
+  if (n == 0) return RT_OK;
+  const unsigned blocks = (unsigned)((n + kBlock - 1) / kBlock);
+  const float4* r4 = reinterpret_cast<const float4*>(rays);
+  switch (node_format) {
+    case RT_NODE_F4:
+      hipLaunchKernelGGL(k_trace_recv<RT_NODE_F4>, dim3(blocks), dim3(kBlock),
+                         stack_bytes<RT_NODE_F4>(depth), s, (const void*)B.wnodes, B.tfacets, r4,
+                         n, max_b, out, path_len, n_hits, recv);
+      break;
+    case RT_NODE_Q4:
+      hipLaunchKernelGGL(k_trace_recv<RT_NODE_Q4>, dim3(blocks), dim3(kBlock),
+                         stack_bytes<RT_NODE_Q4>(depth), s, (const void*)B.wnodes, B.tfacets, r4,
+                         n, max_b, out, path_len, n_hits, recv);
+      break;
+    default:
+      hipLaunchKernelGGL(k_trace_recv<RT_NODE_BIN2>, dim3(blocks), dim3(kBlock),
+                         stack_bytes<RT_NODE_BIN2>(depth), s, (const void*)B.tnodes, B.tfacets, r4,
+                         n, max_b, out, path_len, n_hits, recv);
+      break;
+  }
+  return check_hip(hipGetLastError(), "trace+receive launch");
 }
 
 int launch_trace(const Buffers& B, int node_format, int depth, const float* rays, int64_t n,

@@ -119,3 +119,67 @@ def multiscene_rays(tx, level: int) -> np.ndarray:
     """Rays of one multi-scene query: the level's icosphere from tx,
     tmin 1e-4 m, tmax 2 km."""
     return icosphere.make_rays(tx, icosphere.directions(level), 1e-4, 2000.0)
+
+
+def reception_chains(seed: int = 0, groups: int = 600, per_group: int = 8, max_b: int = 4,
+                     n_rx: int = 256, n_ids: int = 3):
+    """Synthetic stored chains and field points for the receiving-sphere test.
+
+    Rays come in groups of ``per_group`` nearly identical chains (the base
+    chain's float64 origins and directions moved by up to 1e-3 relative, the
+    same facet ids, hit parameters moved by up to 1e-3), so that several rays
+    of a group pass near the same field point, as neighbouring launched rays
+    do.  Per segment of a base chain, in draw order: origin ~ U(-50, 50)^3,
+    direction ~ N(0, 1)^3 scaled to a length ~ U(0.5, 2), tmin ~ U(0, 0.01),
+    tmax ~ U(50, 200), hit with probability 0.7 at t ~ U(tmin + 1, tmax) on
+    facet ~ U{0 .. n_ids - 1}.  A chain ends at its first miss; rows of
+    segments never traced are NaN with id -1 and t = +inf.
+
+    Field points: each picks a random existing segment of a random base
+    chain, a parameter s ~ U(t0 - 5 %, t1 + 5 %) of its range and an offset
+    perpendicular to it of length ~ U(0, 4) m.
+
+    Returns (seg float32 [max_b, m, 8], hit_id int32 [max_b, m],
+    hit_t float32 [max_b, m], receivers float64 [n_rx, 3]), m = groups *
+    per_group.
+    """
+    rng = np.random.default_rng(seed)
+    m = groups * per_group
+    seg = np.full((max_b, m, 8), np.nan, np.float32)
+    hid = np.full((max_b, m), -1, np.int32)
+    ht = np.full((max_b, m), np.inf, np.float32)
+    base = []
+    for g in range(groups):
+        chain = []
+        for b in range(max_b):
+            o = rng.uniform(-50, 50, 3)
+            d = rng.normal(size=3)
+            d *= rng.uniform(0.5, 2.0) / np.linalg.norm(d)
+            t0, t1 = rng.uniform(0, 0.01), rng.uniform(50, 200)
+            hit = rng.uniform() < 0.7
+            t = rng.uniform(t0 + 1, t1)
+            fid = int(rng.integers(0, n_ids))
+            chain.append((o, d, t0, t1, hit, t, fid))
+            if not hit:
+                break
+        base.append(chain)
+        for k in range(per_group):
+            i = g * per_group + k
+            for b, (o, d, t0, t1, hit, t, fid) in enumerate(chain):
+                jo = o * (1 + rng.uniform(-1e-3, 1e-3, 3)) if k else o
+                jd = d * (1 + rng.uniform(-1e-3, 1e-3, 3)) if k else d
+                seg[b, i] = [*jo, t0, *jd, t1]
+                if hit:
+                    hid[b, i] = fid
+                    ht[b, i] = t * (1 + rng.uniform(-1e-3, 1e-3)) if k else t
+    rx = np.empty((n_rx, 3))
+    for r in range(n_rx):
+        chain = base[int(rng.integers(0, groups))]
+        o, d, t0, t1, hit, t, _ = chain[int(rng.integers(0, len(chain)))]
+        end = t if hit else t1
+        s = rng.uniform(t0 - 0.05 * (end - t0), end + 0.05 * (end - t0))
+        p = rng.normal(size=3)
+        p -= d * (p @ d) / (d @ d)
+        p *= rng.uniform(0, 4.0) / np.linalg.norm(p)
+        rx[r] = o + s * d + p
+    return seg, hid, ht, rx

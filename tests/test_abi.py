@@ -64,13 +64,16 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(rt_query), offsetof(rt_query, max_bounces),
          offsetof(rt_query, status), offsetof(rt_query, out), offsetof(rt_query, n_hits),
          sizeof(rt_batch_config));
+  printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(rt_reception), offsetof(rt_reception, l),
+         offsetof(rt_reception, dist), sizeof(rt_receivers), offsetof(rt_receivers, delta),
+         offsetof(rt_receivers, cap), offsetof(rt_receivers, count));
   return 0;
 }""")
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-D__HIP_PLATFORM_AMD__", "-I" + os.path.join(ROOT, "include"),
                     "-I/opt/rocm/include", str(src), "-o", str(exe)], check=True)
-    a, b, c = subprocess.run([str(exe)], capture_output=True, text=True,
-                             check=True).stdout.split("\n")[:3]
+    a, b, c, d = subprocess.run([str(exe)], capture_output=True, text=True,
+                                check=True).stdout.split("\n")[:4]
     sizes = [int(x) for x in a.split()]
     offs = [int(x) for x in b.split()]
     assert sizes == [ctypes.sizeof(R.rt_split_params), 16, ctypes.sizeof(R.rt_bvh_info),
@@ -81,6 +84,10 @@ int main(void) {
     assert [int(x) for x in c.split()] == [ctypes.sizeof(R.rt_query), R.rt_query.max_bounces.offset,
                                            R.rt_query.status.offset, R.rt_query.out.offset,
                                            R.rt_query.n_hits.offset, ctypes.sizeof(R.rt_batch_config)]
+    assert [int(x) for x in d.split()] == [R.RECEPTION_DTYPE.itemsize, R.RECEPTION_DTYPE.fields["l"][1],
+                                           R.RECEPTION_DTYPE.fields["dist"][1],
+                                           ctypes.sizeof(R.rt_receivers), R.rt_receivers.delta.offset,
+                                           R.rt_receivers.cap.offset, R.rt_receivers.count.offset]
 
 
 def test_defaults():
@@ -195,3 +202,47 @@ def test_rays_from_directions_argument_checks():
     assert lib.rt_rays_from_directions(p, 2, float("nan"), 0, 0, 0, 1, p, None) == R.RT_EINVAL
     assert lib.rt_rays_from_directions(p, 2, 0, 0, 0, 0, 1, ctypes.c_void_p(buf.ctypes.data + 4),
                                        None) == R.RT_EINVAL
+
+
+def test_reception_argument_checks():
+    """Checks that fail before any device call."""
+    lib = R.load()
+    buf = np.zeros(256, np.float64)
+    base = buf.ctypes.data
+    base += (-base) % 256
+    p = ctypes.c_void_p(base)
+
+    def rx(**kw):
+        r = R.rt_receivers(pos=base, n=2, reserved=0, delta=0.01, rec=base, cap=4, count=base)
+        for k, v in kw.items():
+            setattr(r, k, v)
+        return ctypes.byref(r)
+
+    seg = lib.rt_receive_segments
+    assert seg(p, p, 4, 2, None, None) == R.RT_EINVAL
+    assert seg(p, p, 4, 2, rx(n=-1), None) == R.RT_EINVAL
+    assert seg(p, p, 4, 2, rx(reserved=1), None) == R.RT_EINVAL
+    assert seg(p, p, 4, 2, rx(pos=None), None) == R.RT_EINVAL
+    assert seg(p, p, 4, 2, rx(pos=base + 4), None) == R.RT_EINVAL
+    assert seg(p, p, 4, 2, rx(delta=float("nan")), None) == R.RT_EINVAL
+    assert seg(p, p, 4, 2, rx(delta=-1.0), None) == R.RT_EINVAL
+    assert seg(p, p, 4, 2, rx(cap=-1), None) == R.RT_EINVAL
+    assert seg(p, p, 4, 2, rx(cap=1 << 31), None) == R.RT_EINVAL
+    assert seg(p, p, 4, 2, rx(rec=None), None) == R.RT_EINVAL
+    assert seg(p, p, 4, 2, rx(rec=base + 8), None) == R.RT_EINVAL
+    assert seg(p, p, 4, 2, rx(count=None), None) == R.RT_EINVAL
+    assert seg(p, p, 4, 0, rx(), None) == R.RT_EINVAL                 # max_bounces
+    assert seg(p, p, 4, 65, rx(), None) == R.RT_EINVAL
+    assert seg(p, p, -1, 2, rx(), None) == R.RT_EINVAL
+    assert seg(p, p, 1 << 31, 2, rx(), None) == R.RT_EINVAL
+    assert seg(None, p, 4, 2, rx(), None) == R.RT_EINVAL
+    assert seg(ctypes.c_void_p(base + 4), p, 4, 2, rx(), None) == R.RT_EINVAL
+    assert lib.rt_trace_receive(None, p, 4, 2, p, None, None, rx(), None) == R.RT_EINVAL
+    ws = lib.rt_receive_dedup_workspace
+    assert ws(10, 3) == 256 and ws(100, 0) == 512 and ws(-1, 0) == -1 and ws(1 << 31, 0) == -1
+    assert ws(0, -1) == -1
+    assert lib.rt_receive_dedup(p, 4, 2, rx(), None, 1 << 20, None) == R.RT_EINVAL
+    assert lib.rt_receive_dedup(p, 4, 2, rx(), ctypes.c_void_p(base + 8), 1 << 20, None) == R.RT_EINVAL
+    assert lib.rt_receive_dedup(p, 4, 2, rx(), p, 8, None) == R.RT_EINVAL   # too small
+    assert lib.rt_receive_dedup(p, 4, 0, rx(), p, 1 << 20, None) == R.RT_EINVAL
+    assert lib.rt_receive_dedup(p, 4, 2, rx(cap=0), None, 0, None) == R.RT_OK   # nothing stored
