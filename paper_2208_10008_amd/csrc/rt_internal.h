@@ -199,30 +199,55 @@ __device__ __forceinline__ double seg_path(float t, float dx, float dy, float dz
 // before it) of ray `ray` against every field point and appends the
 // receptions.  Called by every active lane of a wave with the same field
 // point list; one atomic per wave and field point with receptions.
+//
+// The decision is the float64 expression below.  Before it, a float32 test
+// rejects pairs that cannot pass: with w = R - o and c = |w x d|^2 =
+// dist^2 |d|^2, a received pair has dist <= (L + |w|) delta / sqrt(3); the
+// float32 values of w, c, |w| and |d|^2 are within a few 1e-7 of
+// |o|_1 + |w| + L of the exact ones, and the test allows 1e-4 of that sum
+// plus 0.1 % of the radius, so every pair the float64 test would receive
+// passes it (a NaN or overflow in float32 also passes).  Most pairs are far
+// from the line and stop here; the float64 test runs when a lane needs it.
 __device__ __forceinline__ void receive_segment(const RecvArgs& a, int64_t ray, int order,
                                                 float ox, float oy, float oz, float dx, float dy,
                                                 float dz, float t0, float t1, double L) {
-#pragma clang fp contract(off)
   const int lane = threadIdx.x & 63;
   const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  const double Ox = ox, Oy = oy, Oz = oz, Dx = dx, Dy = dy, Dz = dz, T0 = t0, T1 = t1;
-  const double dd = Dx * Dx + Dy * Dy + Dz * Dz;
+  const float ddf = dx * dx + dy * dy + dz * dz;
+  const float Lf = (float)L;
+  const float base = fabsf(ox) + fabsf(oy) + fabsf(oz) + Lf;
+  const float kd = (float)(a.delta * 0.57735026918962576) * 1.001f;  // delta / sqrt(3)
   for (int r = 0; r < a.n_rx; ++r) {
-    const double wx = a.pos[3 * r] - Ox, wy = a.pos[3 * r + 1] - Oy, wz = a.pos[3 * r + 2] - Oz;
-    const double s = (wx * Dx + wy * Dy + wz * Dz) / dd;
-    const double px = wx - s * Dx, py = wy - s * Dy, pz = wz - s * Dz;
-    const double dist2 = px * px + py * py + pz * pz;
-    const double l = L + sqrt(wx * wx + wy * wy + wz * wz);
-    const double rr = l * a.delta;
-    const bool ok = (s >= T0) && (s <= T1) && (3.0 * dist2 <= rr * rr);
+    const double Rx = a.pos[3 * r], Ry = a.pos[3 * r + 1], Rz = a.pos[3 * r + 2];
+    const float wx = (float)Rx - ox, wy = (float)Ry - oy, wz = (float)Rz - oz;
+    const float cx = wy * dz - wz * dy, cy = wz * dx - wx * dz, cz = wx * dy - wy * dx;
+    const float c = cx * cx + cy * cy + cz * cz;
+    const float wl = sqrtf(wx * wx + wy * wy + wz * wz);
+    const float rad = (Lf + wl) * kd + 1e-4f * (base + wl);
+    const bool maybe = !(c > ddf * rad * rad * 1.001f);
+    if (__ballot(maybe) == 0ull) continue;
+    bool ok = false;
+    double l = 0.0, dist2 = 0.0;
+    if (maybe) {
+#pragma clang fp contract(off)
+      const double Ox = ox, Oy = oy, Oz = oz, Dx = dx, Dy = dy, Dz = dz;
+      const double dd = Dx * Dx + Dy * Dy + Dz * Dz;
+      const double ex = Rx - Ox, ey = Ry - Oy, ez = Rz - Oz;
+      const double s = (ex * Dx + ey * Dy + ez * Dz) / dd;
+      const double px = ex - s * Dx, py = ey - s * Dy, pz = ez - s * Dz;
+      dist2 = px * px + py * py + pz * pz;
+      l = L + sqrt(ex * ex + ey * ey + ez * ez);
+      const double rr = l * a.delta;
+      ok = (s >= (double)t0) && (s <= (double)t1) && (3.0 * dist2 <= rr * rr);
+    }
     const unsigned long long m = __ballot(ok);
     if (m == 0ull) continue;
     const int leader = __ffsll((long long)m) - 1;
-    unsigned long long base = 0;
-    if (lane == leader) base = atomicAdd(a.count, (unsigned long long)__popcll(m));
-    base = __shfl(base, leader);
+    unsigned long long base_k = 0;
+    if (lane == leader) base_k = atomicAdd(a.count, (unsigned long long)__popcll(m));
+    base_k = __shfl(base_k, leader);
     if (ok) {
-      const unsigned long long k = base + __popcll(m & below);
+      const unsigned long long k = base_k + __popcll(m & below);
       if (k < (unsigned long long)a.cap) {
         rt_reception e;
         e.rx = r;

@@ -183,3 +183,12 @@ def reception_chains(seed: int = 0, groups: int = 600, per_group: int = 8, max_b
         p *= rng.uniform(0, 4.0) / np.linalg.norm(p)
         rx[r] = o + s * d + p
     return seg, hid, ht, rx
+
+
+def field_points(tris: np.ndarray, half: float, n: int, seed: int) -> np.ndarray:
+    """n receiver positions (float64 [n, 3]) outside the buildings: (x, y)
+    uniform in the square of half-side 0.95 * half that no roof covers,
+    height ~ U(1.5, 30) m drawn before each position."""
+    rng = np.random.default_rng(seed)
+    pts = [scenes.free_point(rng, half, tris, float(rng.uniform(1.5, 30.0))) for _ in range(n)]
+    return np.array(pts, np.float64).reshape(-1, 3)

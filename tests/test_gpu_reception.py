@@ -121,12 +121,6 @@ def test_stored_chains_edge_cases():
     assert not np.any(recv.records()["rx"] == 0)
 
 
-def city_receivers(tris, half, n, seed):
-    rng = np.random.default_rng(seed)
-    pts = [scenes.free_point(rng, half, tris, float(rng.uniform(1.5, 30.0))) for _ in range(n)]
-    return np.array(pts, np.float64)
-
-
 @pytest.fixture(scope="module")
 def micro_city():
     """Multi-scene scene 1 (about 4k facets on an 816 m square) and a Tx at
@@ -141,7 +135,7 @@ def test_fused_equals_stored_chain_kernel(micro_city, fmt):
     tris, half, src = micro_city
     level, nb = 6, 4
     rays = workloads.multiscene_rays(src, level)
-    rx = city_receivers(tris, half * 0.5, 32, 5)
+    rx = workloads.field_points(tris, half * 0.5, 32, 5)
     delta = float(icosphere.edge_angles(level).mean())
     bvh = R.BVH(dev(tris), R.SplitParams(alpha=0.4, src=src, node_format=fmt))
     d_rays = dev(rays)
@@ -221,7 +215,7 @@ def test_traced_receptions_against_float64_chains(micro_city):
     tris, half, src = micro_city
     level, nb = 6, 4
     rays = workloads.multiscene_rays(src, level)
-    rx = city_receivers(tris, half * 0.5, 24, 6)
+    rx = workloads.field_points(tris, half * 0.5, 24, 6)
     delta = float(icosphere.edge_angles(level).mean())
     p = R.SplitParams(alpha=0.4, src=src)
     bvh = R.BVH(dev(tris), p)
@@ -243,7 +237,7 @@ def test_city24k_full_size_receptions():
     receptions agree with those on the checker's chains."""
     w = workloads.city24k()
     nb = w.max_bounces
-    rx = city_receivers(w.tris, 1000.0 * 0.4, 64, 9)
+    rx = workloads.field_points(w.tris, 1000.0 * 0.4, 64, 9)
     delta = float(icosphere.edge_angles(w.level).mean())
     p = R.SplitParams(alpha=0.4, src=w.tx)
     bvh = R.BVH(dev(w.tris), p)
