@@ -243,3 +243,199 @@ def free_point(tris_seed_rng, half, tris: np.ndarray, z) -> tuple:
         y = rng.uniform(-half * 0.95, half * 0.95)
         if not np.any((lo[:, 0] <= x) & (x <= hi[:, 0]) & (lo[:, 1] <= y) & (y <= hi[:, 1])):
             return (float(x), float(y), float(z))
+
+
+# ---------------------------------------------------------------------------
+# Paper-size stand-ins: an 8 x 6 x 3.5 m study room of exactly 2,778 facets
+# and a campus of exactly 7,608 facets (the paper's facet counts, Sec. IV-A).
+
+
+def _box(x0, y0, z0, x1, y1, z1) -> list:
+    """Closed axis-aligned box, 12 triangles."""
+    c = [(x0, y0), (x1, y0), (x1, y1), (x0, y1)]
+    tris = []
+    for k in range(4):
+        (ax, ay), (bx, by) = c[k], c[(k + 1) % 4]
+        tris += _quad((ax, ay, z0), (bx, by, z0), (bx, by, z1), (ax, ay, z1))
+    tris += _quad(*[(x, y, z1) for (x, y) in c])
+    tris += _quad(*[(x, y, z0) for (x, y) in reversed(c)])
+    return tris
+
+
+def _disc(cx, cy, z, r, m) -> list:
+    """Flat disc of radius r at height z as a fan of m >= 3 triangles."""
+    pts = [(cx + r * math.cos(2 * math.pi * k / m), cy + r * math.sin(2 * math.pi * k / m), z)
+           for k in range(m)]
+    return [((cx, cy, z), pts[k], pts[(k + 1) % m]) for k in range(m)]
+
+
+def study_room(seed: int = 0, target: int = 2778) -> np.ndarray:
+    """Study room 8 x 6 x 3.5 m ([0, 8] x [0, 6] x [0, 3.5]) furnished like
+    the paper's indoor scene: shell (floor, ceiling, 4 walls: 12 facets), 12
+    desks (top + 4 legs: 60 each) with 12 chairs (seat, back, 4 legs: 72
+    each) in a 4 x 3 grid at x >= 2.8, 6 windows (pane 0.03 m inside the
+    wall, 4 frame bars, 6 guard-rail bars: 122 each) on the walls y = 6 and
+    x = 8, a door (slab + handle) on the wall y = 0, 3 cabinets and an open
+    bookshelf (2 sides, back, 5 shelves), a podium, a whiteboard, 6 ceiling
+    lamps, and a round table whose top is a fan of as many triangles as are
+    needed to reach ``target`` facets.  The paper's Tx (1.46, 2.42, 2.1) and
+    Rx (1.2, 1.2, 1.5) stay in free space.
+
+    Draw order: per desk (row-major) dx, dy ~ U(-0.1, 0.1), width scale
+    ~ U(0.95, 1.05); per lamp dx ~ U(-0.2, 0.2)."""
+    rng = np.random.default_rng(seed)
+    X, Y, H = 8.0, 6.0, 3.5
+    t = []
+    t += _quad((0, 0, 0), (X, 0, 0), (X, Y, 0), (0, Y, 0))
+    t += _quad((0, 0, H), (0, Y, H), (X, Y, H), (X, 0, H))
+    t += _quad((0, 0, 0), (0, Y, 0), (0, Y, H), (0, 0, H))
+    t += _quad((X, 0, 0), (X, 0, H), (X, Y, H), (X, Y, 0))
+    t += _quad((0, 0, 0), (0, 0, H), (X, 0, H), (X, 0, 0))
+    t += _quad((0, Y, 0), (X, Y, 0), (X, Y, H), (0, Y, H))
+    for row in range(3):
+        for col in range(4):
+            dx, dy = rng.uniform(-0.1, 0.1, 2)
+            sw = rng.uniform(0.95, 1.05)
+            x0, y0 = 2.9 + 1.25 * col + dx, 0.9 + 1.6 * row + dy
+            w, d = 1.0 * sw, 0.6
+            t += _box(x0, y0, 0.72, x0 + w, y0 + d, 0.75)
+            for lx, ly in ((x0 + 0.03, y0 + 0.03), (x0 + w - 0.08, y0 + 0.03),
+                           (x0 + 0.03, y0 + d - 0.08), (x0 + w - 0.08, y0 + d - 0.08)):
+                t += _box(lx, ly, 0.0, lx + 0.05, ly + 0.05, 0.72)
+            cx0, cy0 = x0 + 0.3, y0 + d + 0.15
+            t += _box(cx0, cy0, 0.42, cx0 + 0.42, cy0 + 0.42, 0.46)
+            t += _box(cx0, cy0 + 0.38, 0.46, cx0 + 0.42, cy0 + 0.42, 0.9)
+            for lx, ly in ((cx0, cy0), (cx0 + 0.38, cy0), (cx0, cy0 + 0.38), (cx0 + 0.38, cy0 + 0.38)):
+                t += _box(lx, ly, 0.0, lx + 0.04, ly + 0.04, 0.42)
+
+    def window(u0, u1, wall):  # wall "y" (y = 6) or "x" (x = 8); u along the wall
+        z0, z1, inset = 0.9, 2.3, 0.03
+        w = []
+        if wall == "y":
+            p = lambda u, v, z: (u, Y - v, z)
+        else:
+            p = lambda u, v, z: (X - v, u, z)
+
+        def slab(ua, ub, va, vb, za, zb):
+            a, b = p(ua, va, za), p(ub, vb, zb)
+            return _box(min(a[0], b[0]), min(a[1], b[1]), za, max(a[0], b[0]), max(a[1], b[1]), zb)
+
+        w += _quad(p(u0, inset, z0), p(u1, inset, z0), p(u1, inset, z1), p(u0, inset, z1))
+        w += slab(u0 - 0.05, u1 + 0.05, 0.0, 0.06, z0 - 0.05, z0)
+        w += slab(u0 - 0.05, u1 + 0.05, 0.0, 0.06, z1, z1 + 0.05)
+        w += slab(u0 - 0.05, u0, 0.0, 0.06, z0, z1)
+        w += slab(u1, u1 + 0.05, 0.0, 0.06, z0, z1)
+        for k in range(6):
+            u = u0 + (k + 0.5) * (u1 - u0) / 6
+            w += slab(u - 0.01, u + 0.01, 0.12, 0.14, z0, z1)
+        return w
+
+    for uc in (4.0, 5.5, 7.0):
+        t += window(uc - 0.6, uc + 0.6, "y")
+    for uc in (1.5, 3.0, 4.5):
+        t += window(uc - 0.6, uc + 0.6, "x")
+    t += _box(6.5, 0.02, 0.0, 7.4, 0.06, 2.1)
+    t += _box(6.6, 0.06, 1.0, 6.75, 0.1, 1.05)
+    for cx in (0.3, 1.25, 2.2):
+        t += _box(cx, 5.5, 0.0, cx + 0.9, 5.95, 2.0)
+    t += _box(0.05, 3.8, 0.0, 0.4, 3.82, 2.2)
+    t += _box(0.05, 5.28, 0.0, 0.4, 5.3, 2.2)
+    t += _box(0.02, 3.8, 0.0, 0.05, 5.3, 2.2)
+    for z in (0.02, 0.5, 1.0, 1.5, 2.0):
+        t += _box(0.05, 3.82, z, 0.4, 5.28, z + 0.02)
+    t += _box(0.6, 3.0, 0.0, 1.2, 3.5, 1.1)
+    t += _box(0.02, 0.6, 0.9, 0.04, 2.9, 2.1)
+    for k in range(6):
+        lx = 2.4 + 1.8 * (k % 3) + rng.uniform(-0.2, 0.2)
+        ly = 1.5 if k < 3 else 4.2
+        t += _box(lx, ly, 3.34, lx + 1.2, ly + 0.3, 3.4)
+    rest = target - len(t) - 4 * 12
+    if rest < 3:
+        raise ValueError("study_room: target below the furniture's facet count")
+    t += _disc(1.9, 4.4, 0.75, 0.55, rest)
+    for lx, ly in ((1.85, 4.35), (1.85, 4.4), (1.9, 4.35), (1.9, 4.4)):
+        t += _box(lx, ly, 0.0, lx + 0.03, ly + 0.03, 0.75)
+    assert len(t) == target
+    return _pack(t)
+
+
+def _tessellated_building(rng, poly, h, cell) -> list:
+    """Walls of an extruded convex polygon as grids of about cell x cell m
+    quads, and a fan roof over the top edge points.  Draw order: nothing
+    (deterministic)."""
+    n = len(poly)
+    nv = max(1, int(round(h / cell)))
+    zs = [h * j / nv for j in range(nv + 1)]
+    tris, top = [], []
+    for k in range(n):
+        (ax, ay), (bx, by) = poly[k], poly[(k + 1) % n]
+        nu = max(1, int(round(math.hypot(bx - ax, by - ay) / cell)))
+        g = [[(ax + (bx - ax) * i / nu, ay + (by - ay) * i / nu, z) for z in zs] for i in range(nu + 1)]
+        for i in range(nu):
+            for j in range(nv):
+                tris += _quad(g[i][j], g[i + 1][j], g[i + 1][j + 1], g[i][j + 1])
+        top += [g[i][nv] for i in range(nu)]
+    cx = sum(p[0] for p in poly) / n
+    cy = sum(p[1] for p in poly) / n
+    c = (cx, cy, h)
+    tris += [(c, top[k], top[(k + 1) % len(top)]) for k in range(len(top))]
+    return tris
+
+
+def campus(seed: int = 0, target: int = 7608, size: float = 1000.0,
+           keep_free=((450.0, 450.0), (450.0, 550.0))) -> np.ndarray:
+    """Campus of exactly ``target`` facets on [0, size]^2: ground (2 facets),
+    non-overlapping buildings with tessellated facades, and a playground whose
+    flat oval track (a fan 0.05 m above the ground) takes the facets left over.
+
+    Per building, draws in order: kind ~ U(0, 1) (< 0.7 rectangular), height
+    ~ lognormal(ln 18, 0.5) clipped to [6, 60] m, facade cell ~ U(6, 15) m;
+    rectangle: sides ~ U(20, 90) and U(15, 40) m, rotation 0 or 90 degrees
+    ~ U{0, 1}; prism: n ~ U{5..8} corners on a circle of radius ~ U(12, 35)
+    m; then the centre uniform with the footprint inside the area.  A
+    building whose box (grown by 10 m) meets another's, or covers a point of
+    ``keep_free`` (the paper's Tx and Rx), is drawn again; buildings are
+    added while the facet count stays 300 below the target (at most 4,000
+    draws)."""
+    rng = np.random.default_rng(seed)
+    t = _quad((0, 0, 0), (size, 0, 0), (size, size, 0), (0, size, 0))
+    boxes = []
+    play = (180.0, 780.0, 90.0, 55.0)   # playground centre and half-axes, kept free
+    boxes.append((play[0] - play[2], play[1] - play[3], play[0] + play[2], play[1] + play[3]))
+    draws = 0
+    while draws < 4000 and len(t) < target - 300:
+        draws += 1
+        kind = rng.uniform()
+        h = float(np.clip(rng.lognormal(math.log(18.0), 0.5), 6.0, 60.0))
+        cell = rng.uniform(6.0, 15.0)
+        if kind < 0.7:
+            a, b = rng.uniform(20, 90), rng.uniform(15, 40)
+            if rng.integers(0, 2):
+                a, b = b, a
+            cx, cy = rng.uniform(a / 2, size - a / 2), rng.uniform(b / 2, size - b / 2)
+            poly = [(cx - a / 2, cy - b / 2), (cx + a / 2, cy - b / 2),
+                    (cx + a / 2, cy + b / 2), (cx - a / 2, cy + b / 2)]
+        else:
+            n = int(rng.integers(5, 9))
+            rad = rng.uniform(12, 35)
+            cx, cy = rng.uniform(rad, size - rad), rng.uniform(rad, size - rad)
+            poly = [(cx + rad * math.cos(2 * math.pi * k / n), cy + rad * math.sin(2 * math.pi * k / n))
+                    for k in range(n)]
+        xs, ys = [p[0] for p in poly], [p[1] for p in poly]
+        bb = (min(xs) - 10, min(ys) - 10, max(xs) + 10, max(ys) + 10)
+        if any(bb[0] <= fx <= bb[2] and bb[1] <= fy <= bb[3] for fx, fy in keep_free):
+            continue
+        if any(bb[0] < o[2] and o[0] < bb[2] and bb[1] < o[3] and o[1] < bb[3] for o in boxes):
+            continue
+        bt = _tessellated_building(rng, poly, h, cell)
+        if len(t) + len(bt) > target - 64:
+            continue
+        boxes.append(bb)
+        t += bt
+    rest = target - len(t)
+    cx, cy, ax, ay = play
+    pts = [(cx + ax * math.cos(2 * math.pi * k / rest), cy + ay * math.sin(2 * math.pi * k / rest), 0.05)
+           for k in range(rest)]
+    t += [((cx, cy, 0.05), pts[k], pts[(k + 1) % rest]) for k in range(rest)]
+    assert len(t) == target
+    return _pack(t)

@@ -192,3 +192,42 @@ def field_points(tris: np.ndarray, half: float, n: int, seed: int) -> np.ndarray
     rng = np.random.default_rng(seed)
     pts = [scenes.free_point(rng, half, tris, float(rng.uniform(1.5, 30.0))) for _ in range(n)]
     return np.array(pts, np.float64).reshape(-1, 3)
+
+
+@dataclasses.dataclass
+class PaperScene:
+    """A stand-in for one of the paper's two simulation scenes, with the
+    paper's Tx, Rx, leaf threshold, Eq. (2) weight alpha and reflection
+    order (Sec. IV-A)."""
+    name: str
+    tris: np.ndarray
+    tx: tuple
+    rx: tuple
+    max_leaf: int
+    alpha: float
+    max_order: int       # highest reflection order received
+    tmax: float
+
+    @property
+    def max_bounces(self) -> int:
+        """Segments per chain: a path with k reflections is received on segment k."""
+        return self.max_order + 1
+
+    def rays(self, level: int) -> np.ndarray:
+        return icosphere.make_rays(self.tx, icosphere.directions(level), 1e-4, self.tmax)
+
+
+def paper_indoor(seed: int = 0) -> PaperScene:
+    """Study room 8 x 6 x 3.5 m, 2,778 facets; Tx (1.46, 2.42, 2.1), Rx (1.2,
+    1.2, 1.5); 250 facets per leaf, alpha 0.7; reflection orders 1 and 2;
+    tmax 20 m per segment."""
+    return PaperScene("indoor-2778", scenes.study_room(seed), (1.46, 2.42, 2.1), (1.2, 1.2, 1.5),
+                      250, 0.7, 2, 20.0)
+
+
+def paper_outdoor(seed: int = 0) -> PaperScene:
+    """Campus 1 x 1 km, 7,608 facets; Tx (450, 450, 10), Rx (450, 550, 25);
+    820 facets per leaf, alpha 0.4; reflection order 3; tmax 2 km per
+    segment."""
+    return PaperScene("outdoor-7608", scenes.campus(seed), (450.0, 450.0, 10.0),
+                      (450.0, 550.0, 25.0), 820, 0.4, 3, 2000.0)

@@ -10,9 +10,11 @@ the winner's t (relative 1e-4), or a miss when the winner itself lies within
 import numpy as np
 
 import oracle
+from oracle import reception as rc
 
 CLEAN = 1e-4
 T_REL = 1e-5
+BAND = 5e-3   # reception: relative distance from the Eq. (4) threshold treated as borderline
 
 
 def _rel(a, s):
@@ -83,3 +85,68 @@ def canonical_compare(gpu_nodes, gpu_perm, tree: "oracle.Tree"):
             assert gn["left"] >= 0
             stack.append((gn["left"], tree.left[o]))
             stack.append((gn["left"] + 1, tree.right[o]))
+
+
+def keyed(rec):
+    rec = np.sort(rec, order=("rx", "ray", "order"))
+    return rec, [tuple(int(x) for x in r) for r in zip(rec["rx"], rec["ray"], rec["order"])]
+
+
+def oracle_quantities(ch, L, rx, keys, delta):
+    """q = sqrt(3) dist / (l delta) and the foot's distance from the nearer end
+    (fraction of the segment) for (rx, ray, order) keys on the checker's chains."""
+    out = []
+    for r, i, b in keys:
+        s_row = ch.seg[b, i]
+        o, d = s_row[0:3], s_row[4:7]
+        t0 = s_row[3]
+        t1 = ch.t[b, i] if ch.id[b, i] >= 0 else s_row[7]
+        w = rx[r] - o
+        s = (w @ d) / (d @ d)
+        dist = np.linalg.norm(w - s * d)
+        l = L[b, i] + np.linalg.norm(w)
+        q = np.sqrt(3) * dist / (l * delta) if l * delta > 0 else np.inf
+        edge = min(abs(s - t0), abs(s - t1)) / max(t1 - t0, 1e-9)
+        out.append((q, edge))
+    return out
+
+
+def agree_with_checker(tris, rays, rx, delta, nb, params, got, ids_g, t_g, nthreads=16):
+    """Receptions (Sec. III-C) on the checker's float64 chains against the
+    GPU's.  On rays whose chains agree with the checker's (same facets, hit
+    distances within 1e-5, margins above 1e-4) the receptions must agree,
+    except where the checker's own test lies within BAND of its threshold
+    (sqrt(3) dist / (l delta) = 1) or of a segment end; l and dist within
+    2e-5 of l.  got: GPU records, ids_g / t_g: GPU hits [nb, m]."""
+    tree = oracle.build_tree(tris, params)
+    ch = oracle.bounces(tris, rays, nb, tree=tree, nthreads=nthreads)
+    ref = rc.receive(ch.seg, ch.id, ch.t, rx, delta)
+    L = rc.path_prefix(ch.seg, ch.id, ch.t)
+    # rays whose chains agree up to segment b
+    agree = np.zeros((nb, rays.shape[0]), bool)
+    ok = np.ones(rays.shape[0], bool)
+    for b in range(nb):
+        same = (ids_g[b] == ch.id[b]) & (ch.margin[b] > 1e-4)
+        hit = ch.id[b] >= 0
+        with np.errstate(invalid="ignore"):
+            tclose = ~hit | (np.abs(t_g[b] - ch.t[b]) <= 1e-5 * np.maximum(ch.t[b], 1e-3))
+        ok = ok & same & tclose
+        agree[b] = ok
+        ok = ok & hit
+    g, gk = keyed(got)
+    r, rk = keyed(ref)
+    gset, rset = set(gk), set(rk)
+    only = [k for k in (gset ^ rset) if agree[k[2], k[1]]]
+    bad = [(k, q, e) for k, (q, e) in zip(only, oracle_quantities(ch, L, rx, only, delta))
+           if abs(q - 1) > BAND and e > BAND]
+    assert not bad, f"{len(bad)} receptions differ away from the boundary, e.g. {bad[:3]}"
+    both = sorted(k for k in gset & rset if agree[k[2], k[1]])
+    gi = {k: n for n, k in enumerate(gk)}
+    ri = {k: n for n, k in enumerate(rk)}
+    lg = np.array([g["l"][gi[k]] for k in both])
+    lr = np.array([r["l"][ri[k]] for k in both])
+    dg = np.array([g["dist"][gi[k]] for k in both])
+    dr = np.array([r["dist"][ri[k]] for k in both])
+    assert np.all(np.abs(lg - lr) <= 2e-5 * lr), "path lengths"
+    assert np.all(np.abs(dg - dr) <= 2e-5 * lr), "distances"
+    return {"gpu": len(gk), "checker": len(rk), "compared": len(both), "borderline": len(only)}
