@@ -16,7 +16,9 @@ Functions and what pins them:
 * :func:`trace_bvh` -- Sec. III-B traversal of that tree; must equal
   :func:`brute` on every ray.
 * :func:`bounces` -- specular reflection chains; pinned by image-source
-  closed forms.
+  closed forms.  :func:`bounces_energy` -- the same chains stopped by the
+  energy rule of Sec. III-B; pinned by closed-form stop points in a corridor
+  and over a ground and a wall.
 * :mod:`oracle.reception` -- receiving spheres of Sec. III-C, Eq. (4), in
   numpy float64.  Pinned by a hand-worked example, the exact mean number of
   receptions in free space, hole-free coverage of an icosphere launch, and
@@ -84,6 +86,9 @@ def _load():
         lib.or_tree_export.argtypes = [P] * 13
         lib.or_trace_bvh.argtypes = [P, i64, P, P, i64, P, i32, P, P, P, P, P, P, P, P]
         lib.or_bounces.argtypes = [P, i64, P, P, i64, i32, i32, P, P, P, P, P, P, P, P]
+        lib.or_bounces_energy.argtypes = [P, i64, P, P, i64, i32, i32, P, P, i32,
+                                          ctypes.c_double, ctypes.c_double,
+                                          P, P, P, P, P, P, P, P, P]
         _lib = lib
     return _lib
 
@@ -261,3 +266,33 @@ def bounces(tris, rays, max_b: int, tree: Tree | None = None, nthreads=0,
     if rc != 0:
         raise RuntimeError("or_bounces failed")
     return Chains(i, t, u, v, mg, seg, pl, nh)
+
+
+def bounces_energy(tris, rays, max_b: int, material, refl, k0: float, min_power: float,
+                   tree: Tree | None = None, nthreads=0, segments=True):
+    """Chains stopped by energy (Sec. III-B): after the reflection at hit j
+    the power ratio is P_j = prod(refl[material[f_i]], i <= j) * k0 / l_j^2
+    (l_j the path length to the hit, k0 = (lambda / 4 pi)^2); the next segment
+    is launched only while P_j >= min_power.  Returns (Chains, power [m]) with
+    power = P of the last hit (0 without hits)."""
+    tris, rays = _f32(tris, 9), _f32(rays, 8)
+    material = np.ascontiguousarray(material, dtype=np.int32)
+    refl = np.ascontiguousarray(refl, dtype=np.float64)
+    if material.shape != (tris.shape[0],):
+        raise ValueError("material must hold one index per facet")
+    m = rays.shape[0]
+    shape = (max_b, m)
+    i = np.empty(shape, np.int32)
+    t, u, v, mg = (np.empty(shape) for _ in range(4))
+    seg = np.empty((max_b, m, 8)) if segments else None
+    pl = np.empty(m)
+    nh = np.empty(m, np.int32)
+    pw = np.empty(m)
+    rc = _load().or_bounces_energy(_ptr(tris), tris.shape[0],
+                                   None if tree is None else tree.handle, _ptr(rays), m, max_b,
+                                   nthreads, _ptr(material), _ptr(refl), refl.shape[0],
+                                   float(k0), float(min_power), _ptr(i), _ptr(t), _ptr(u),
+                                   _ptr(v), _ptr(mg), _ptr(seg), _ptr(pl), _ptr(nh), _ptr(pw))
+    if rc != 0:
+        raise RuntimeError("or_bounces_energy failed")
+    return Chains(i, t, u, v, mg, seg, pl, nh), pw

@@ -573,16 +573,31 @@ int or_trace_bvh(const float* tris, int64_t n, const or_tree* tree, const float*
   return 0;
 }
 
-int or_bounces(const float* tris, int64_t n, const or_tree* tree, const float* rays,
-               int64_t m, int32_t max_b, int32_t nthreads, int32_t* id, double* t,
-               double* u, double* v, double* margin, double* seg, double* path_len,
-               int32_t* n_hits) {
-  if (!tris || !rays || !id || !t || !u || !v || !path_len || !n_hits || max_b < 1) return -1;
-  if (tree && (int64_t)tree->perm.size() != n) return -1;
+}  // extern "C"
+
+namespace {
+
+// Stop rule of Sec. III-B by energy: after the reflection at hit j (facet
+// f_j, path length l_j from the source to the hit point) the chain carries
+// the power ratio P_j = (prod_{i <= j} g(f_i)) * k0 / l_j^2, where g is the
+// power reflection coefficient of the facet's material and k0 = (lambda /
+// (4 pi))^2 the free-space constant; the next segment is launched only while
+// P_j >= min_power.  A material index outside [0, n_mat) reflects nothing.
+struct EnergyRule {
+  const int32_t* material;
+  const double* refl;
+  int32_t n_mat;
+  double k0, min_power;
+};
+
+void chains(const float* tris, int64_t n, const or_tree* tree, const float* rays, int64_t m,
+            int32_t max_b, int32_t nthreads, int32_t* id, double* t, double* u, double* v,
+            double* margin, double* seg, double* path_len, int32_t* n_hits,
+            const EnergyRule* en, double* power) {
   parallel_for(m, nthreads, [&](int64_t i) {
     Ray r = load_ray(rays, i);
     int32_t skip = -1, hits = 0;
-    double path = 0.0;
+    double path = 0.0, gain = 1.0, last_power = 0.0;
     int32_t b = 0;
     for (; b < max_b; ++b) {
       const int64_t k = (int64_t)b * m + i;
@@ -597,6 +612,12 @@ int or_bounces(const float* tris, int64_t n, const or_tree* tree, const float* r
       if (res.id < 0) break;
       ++hits;
       path += res.t * std::sqrt(dot(r.d, r.d));
+      if (en) {
+        const int32_t mat = en->material[res.id];
+        gain *= (mat >= 0 && mat < en->n_mat) ? en->refl[mat] : 0.0;
+        last_power = gain * en->k0 / (path * path);
+        if (!(last_power >= en->min_power)) break;
+      }
       r = reflect(tris, r, res);
       skip = res.id;
     }
@@ -610,7 +631,37 @@ int or_bounces(const float* tris, int64_t n, const or_tree* tree, const float* r
     }
     path_len[i] = path;
     n_hits[i] = hits;
+    if (power) power[i] = last_power;
   });
+}
+
+}  // namespace
+
+extern "C" {
+
+int or_bounces(const float* tris, int64_t n, const or_tree* tree, const float* rays,
+               int64_t m, int32_t max_b, int32_t nthreads, int32_t* id, double* t,
+               double* u, double* v, double* margin, double* seg, double* path_len,
+               int32_t* n_hits) {
+  if (!tris || !rays || !id || !t || !u || !v || !path_len || !n_hits || max_b < 1) return -1;
+  if (tree && (int64_t)tree->perm.size() != n) return -1;
+  chains(tris, n, tree, rays, m, max_b, nthreads, id, t, u, v, margin, seg, path_len, n_hits,
+         nullptr, nullptr);
+  return 0;
+}
+
+int or_bounces_energy(const float* tris, int64_t n, const or_tree* tree, const float* rays,
+                      int64_t m, int32_t max_b, int32_t nthreads, const int32_t* material,
+                      const double* refl, int32_t n_mat, double k0, double min_power,
+                      int32_t* id, double* t, double* u, double* v, double* margin, double* seg,
+                      double* path_len, int32_t* n_hits, double* power) {
+  if (!tris || !rays || !id || !t || !u || !v || !path_len || !n_hits || !power || max_b < 1 ||
+      !material || n_mat < 0 || (n_mat > 0 && !refl))
+    return -1;
+  if (tree && (int64_t)tree->perm.size() != n) return -1;
+  const EnergyRule en{material, refl, n_mat, k0, min_power};
+  chains(tris, n, tree, rays, m, max_b, nthreads, id, t, u, v, margin, seg, path_len, n_hits, &en,
+         power);
   return 0;
 }
 

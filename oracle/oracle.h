@@ -88,6 +88,18 @@ int or_bounces(const float* tris, int64_t n, const or_tree* tree,
                int32_t* id, double* t, double* u, double* v, double* margin,
                double* seg, double* path_len, int32_t* n_hits);
 
+/* or_bounces with the energy stop rule of Sec. III-B: after the reflection at
+ * hit j the chain carries P_j = (prod of refl[material[f_i]] over its hits)
+ * * k0 / l_j^2 (l_j: path length to the hit, k0 = (lambda / 4 pi)^2); the next
+ * segment is launched only while P_j >= min_power.  material [n] per facet id
+ * (index outside [0, n_mat): reflects nothing); power [m] = P of the last hit,
+ * 0 without hits. */
+int or_bounces_energy(const float* tris, int64_t n, const or_tree* tree, const float* rays,
+                      int64_t m, int32_t max_b, int32_t nthreads, const int32_t* material,
+                      const double* refl, int32_t n_mat, double k0, double min_power,
+                      int32_t* id, double* t, double* u, double* v, double* margin, double* seg,
+                      double* path_len, int32_t* n_hits, double* power);
+
 #ifdef __cplusplus
 }
 #endif
