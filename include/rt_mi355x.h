@@ -263,6 +263,37 @@ int64_t rt_receive_dedup_workspace(int64_t cap, int32_t n_rx);
 int rt_receive_dedup(const rt_hit* hits, int64_t n, int32_t max_bounces, const rt_receivers* rx,
                      void* work, int64_t work_bytes, hipStream_t s);
 
+/* ---- energy stop rule (Sec. III-B) ---------------------------------------
+ * Besides the reflection order, a chain ends when its energy has decayed
+ * below a threshold.  After the reflection at hit j (facet f_j, path length
+ * l_j from the source to the hit point, accumulated in float64 as path_len)
+ * the chain carries the power ratio
+ *     P_j = (refl[material[f_1]] * ... * refl[material[f_j]]) * k0 / l_j^2,
+ * refl being the power reflection coefficient of a material and k0 the
+ * free-space constant (lambda / (4 pi))^2 of isotropic antennas, evaluated in
+ * float64 in this order; the next segment is launched only while
+ * P_j >= min_power.  A material index outside [0, n_materials) reflects
+ * nothing (P = 0).  min_power = 0 never stops a chain. */
+typedef struct rt_energy {
+  const int32_t* material; /* device [n_tris]: material index of each facet (caller's ids) */
+  const double* refl;      /* device [n_materials]: power reflection coefficients */
+  int32_t n_materials;     /* >= 0 (refl may be NULL when 0) */
+  int32_t reserved;        /* must be 0 */
+  double k0;               /* free-space constant, finite, > 0 */
+  double min_power;        /* threshold, finite, >= 0 */
+  double* power;           /* device [n], nullable: P of each chain's last hit, 0 without hits */
+} rt_energy;
+
+/* rt_trace_bounces with the energy stop rule (e: host struct), and, when rx
+ * is not NULL, the receiving-sphere test of every traced segment as in
+ * rt_trace_receive.  Errors: as rt_trace_bounces / rt_trace_receive; RT_EINVAL
+ * for a NULL e or material, n_materials < 0, NULL refl with n_materials > 0,
+ * misaligned arrays, k0 not finite and positive, min_power not finite and
+ * >= 0, reserved != 0. */
+int rt_trace_energy(const rt_bvh* b, const float* rays, int64_t n, int32_t max_bounces,
+                    const rt_energy* e, rt_hit* out, double* path_len, int32_t* n_hits,
+                    const rt_receivers* rx, hipStream_t s);
+
 /* ---- inspection and lifetime ------------------------------------------ */
 int rt_bvh_info_get(const rt_bvh* b, rt_bvh_info* info); /* host struct */
 

@@ -77,6 +77,13 @@ class rt_receivers(ctypes.Structure):
                 ("count", ctypes.c_void_p)]
 
 
+class rt_energy(ctypes.Structure):
+    _fields_ = [("material", ctypes.c_void_p), ("refl", ctypes.c_void_p),
+                ("n_materials", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("k0", ctypes.c_double), ("min_power", ctypes.c_double),
+                ("power", ctypes.c_void_p)]
+
+
 # numpy view of rt_reception (32 bytes)
 RECEPTION_DTYPE = np.dtype([("rx", "<i4"), ("ray", "<i4"), ("order", "<i4"), ("keep", "<i4"),
                             ("l", "<f8"), ("dist", "<f8")])
@@ -97,7 +104,7 @@ EXPORTS = ("rt_split_params_default", "rt_build", "rt_rebuild", "rt_trace",
            "rt_batch_set", "rt_batch_configure", "rt_batch_get_config", "rt_batch_launch",
            "rt_batch_autotune", "rt_batch_destroy", "rt_rays_from_directions",
            "rt_trace_receive", "rt_receive_segments", "rt_receive_dedup_workspace",
-           "rt_receive_dedup")
+           "rt_receive_dedup", "rt_trace_energy")
 PROBE_EXPORTS = ("rt_probe_read", "rt_probe_copy")  # include/rt_probe.h
 
 _lib = None
@@ -144,12 +151,13 @@ def load(path: str = LIB_PATH):
     lib.rt_receive_dedup_workspace.argtypes = [i64, i32]
     lib.rt_receive_dedup_workspace.restype = i64
     lib.rt_receive_dedup.argtypes = [P, i64, i32, RX, P, i64, P]
+    lib.rt_trace_energy.argtypes = [P, P, i64, i32, ctypes.POINTER(rt_energy), P, P, P, RX, P]
     for name in ("rt_build", "rt_rebuild", "rt_trace", "rt_trace_bounces", "rt_trace_ex",
                  "rt_bvh_info_get", "rt_bvh_download", "rt_bvh_export_trace_nodes",
                  "rt_probe_read", "rt_probe_copy", "rt_batch_create", "rt_batch_set",
                  "rt_batch_configure", "rt_batch_get_config", "rt_batch_launch",
                  "rt_batch_autotune", "rt_rays_from_directions", "rt_trace_receive",
-                 "rt_receive_segments", "rt_receive_dedup"):
+                 "rt_receive_segments", "rt_receive_dedup", "rt_trace_energy"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -319,6 +327,48 @@ class Receivers:
         rt_receive_dedup(hits, max_bounces, self, self._work, stream)
 
 
+class Energy:
+    """The energy stop rule (Sec. III-B): material index per facet (int32
+    [n_tris] CUDA tensor, caller's facet order), power reflection coefficient
+    per material (float64 [n_materials] CUDA tensor), the free-space constant
+    k0 = (lambda / 4 pi)^2 and the threshold min_power; ``power`` (float64 [n])
+    receives each chain's power ratio after its last hit when given."""
+
+    def __init__(self, material, refl, k0: float, min_power: float, power=None):
+        import torch
+        if material.dtype != torch.int32 or material.dim() != 1 or not material.is_cuda:
+            raise RtError(RT_EINVAL, "material must be an int32 CUDA tensor [n_tris]")
+        if refl.dtype != torch.float64 or refl.dim() != 1 or not refl.is_cuda:
+            raise RtError(RT_EINVAL, "refl must be a float64 CUDA tensor [n_materials]")
+        self.material, self.refl = material.contiguous(), refl.contiguous()
+        self.k0, self.min_power, self.power = float(k0), float(min_power), power
+
+    @staticmethod
+    def k0_for(frequency_hz: float) -> float:
+        """(lambda / (4 pi))^2 for a frequency in Hz (isotropic antennas)."""
+        lam = 299_792_458.0 / frequency_hz
+        return (lam / (4.0 * np.pi)) ** 2
+
+    def c(self) -> rt_energy:
+        e = rt_energy()
+        e.material = self.material.data_ptr()
+        e.refl = self.refl.data_ptr() if self.refl.numel() else None
+        e.n_materials = self.refl.numel()
+        e.reserved = 0
+        e.k0, e.min_power = self.k0, self.min_power
+        e.power = None if self.power is None else self.power.data_ptr()
+        return e
+
+
+def rt_trace_energy(handle, rays, max_bounces, energy: Energy, out, path_len, n_hits,
+                    receivers: "Receivers | None" = None, stream=None):
+    lib = load()
+    e = energy.c()
+    rx = None if receivers is None else ctypes.byref(receivers.c())
+    _check(lib.rt_trace_energy(handle, _ptr(rays), rays.shape[0], max_bounces, ctypes.byref(e),
+                               _ptr(out), _ptr(path_len), _ptr(n_hits), rx, _stream(stream)))
+
+
 def rt_bvh_info_get(handle) -> rt_bvh_info:
     info = rt_bvh_info()
     _check(load().rt_bvh_info_get(handle, ctypes.byref(info)))
@@ -433,6 +483,23 @@ class BVH:
         if n_hits is None:
             n_hits = torch.empty(n, dtype=torch.int32, device=rays.device)
         rt_trace_receive(self.handle, rays, max_bounces, out, path_len, n_hits, receivers, stream)
+        return out, path_len, n_hits
+
+    def trace_energy(self, rays, max_bounces, energy: Energy, receivers: Receivers | None = None,
+                     out=None, path_len=None, n_hits=None, stream=None):
+        """Reflection chains that also stop by energy (Sec. III-B); with
+        ``receivers``, every traced segment is tested as in trace_receive."""
+        import torch
+        _dev(rays, torch.float32, 8, "rays")
+        n = rays.shape[0]
+        if out is None:
+            out = self.hits_buffer(n, max_bounces)
+        if path_len is None:
+            path_len = torch.empty(n, dtype=torch.float64, device=rays.device)
+        if n_hits is None:
+            n_hits = torch.empty(n, dtype=torch.int32, device=rays.device)
+        rt_trace_energy(self.handle, rays, max_bounces, energy, out, path_len, n_hits, receivers,
+                        stream)
         return out, path_len, n_hits
 
     def close(self):

@@ -262,6 +262,22 @@ __device__ __forceinline__ void receive_segment(const RecvArgs& a, int64_t ray, 
   }
 }
 
+// ---- energy stop rule (Sec. III-B) ----
+struct EnergyArgs {
+  const int32_t* material;  // [n_tris] by caller facet id
+  const double* refl;       // [n_mat]
+  double* power;            // [n] or null
+  double k0, min_power;
+  int32_t n_mat;
+  int32_t pad;
+};
+
+// Power ratio after a reflection: gain * k0 / l^2, float64 without contraction.
+__device__ __forceinline__ double chain_power(double gain, double k0, double l) {
+#pragma clang fp contract(off)
+  return gain * k0 / (l * l);
+}
+
 // error reporting (thread-local message), defined in rt_api.hip
 int set_error(int code, const std::string& msg);
 int check_hip(hipError_t e, const char* what);
@@ -288,6 +304,11 @@ int trace_resident_groups(int node_format, int depth);
 int launch_trace_receive(const Buffers& B, int node_format, int depth, const float* rays,
                          int64_t n, int32_t max_bounces, rt_hit* out, double* path_len,
                          int32_t* n_hits, const RecvArgs& recv, hipStream_t s);
+// Chains stopped by energy, with the reception test when recv is not null.
+int launch_trace_energy(const Buffers& B, int node_format, int depth, const float* rays,
+                        int64_t n, int32_t max_bounces, rt_hit* out, double* path_len,
+                        int32_t* n_hits, const RecvArgs* recv, const EnergyArgs& en,
+                        hipStream_t s);
 
 }  // namespace rt
 

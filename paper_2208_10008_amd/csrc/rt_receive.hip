@@ -1,6 +1,8 @@
 // Ray reception by receiving spheres (Sec. III-C, Eq. (4)) on gfx950:
 //   rt_trace_receive     -- chains traced with every segment tested as it ends
 //                           (the test sits in the trace loop, see rt_trace.hip)
+//   rt_trace_energy      -- chains that also stop by energy (Sec. III-B),
+//                           optionally with the same reception test
 //   rt_receive_segments  -- the same test over stored chains, one ray per lane
 //   rt_receive_dedup     -- one reception per (field point, order, facet sequence)
 // The test itself (receive_segment, rt_internal.h) is float64 without
@@ -151,6 +153,23 @@ int check_rx(const rt_receivers* rx, const char* who) {
   return RT_OK;
 }
 
+int check_energy(const rt_energy* e) {
+  if (!e) return set_error(RT_EINVAL, "rt_trace_energy: energy struct is NULL");
+  if (!e->material || !aligned_to(e->material, 4))
+    return set_error(RT_EINVAL, "rt_trace_energy: material must be non-NULL and 4-byte aligned");
+  if (e->n_materials < 0 || e->reserved != 0)
+    return set_error(RT_EINVAL, "rt_trace_energy: n_materials must be >= 0, reserved 0");
+  if (e->n_materials > 0 && (!e->refl || !aligned_to(e->refl, 8)))
+    return set_error(RT_EINVAL, "rt_trace_energy: refl must be non-NULL and 8-byte aligned");
+  if (!std::isfinite(e->k0) || !(e->k0 > 0.0))
+    return set_error(RT_EINVAL, "rt_trace_energy: k0 must be finite and > 0");
+  if (!std::isfinite(e->min_power) || e->min_power < 0.0)
+    return set_error(RT_EINVAL, "rt_trace_energy: min_power must be finite and >= 0");
+  if (e->power && !aligned_to(e->power, 8))
+    return set_error(RT_EINVAL, "rt_trace_energy: power must be 8-byte aligned");
+  return RT_OK;
+}
+
 RecvArgs args_of(const rt_receivers* rx) {
   RecvArgs a;
   a.pos = rx->pos;
@@ -184,6 +203,36 @@ int rt_trace_receive(const rt_bvh* b, const float* rays, int64_t n, int32_t max_
   if (rc != RT_OK || n == 0) return rc;
   return launch_trace_receive(b->buf, b->info.node_format, b->info.depth, rays, n, max_bounces,
                               out, path_len, n_hits, a, s);
+}
+
+int rt_trace_energy(const rt_bvh* b, const float* rays, int64_t n, int32_t max_bounces,
+                    const rt_energy* e, rt_hit* out, double* path_len, int32_t* n_hits,
+                    const rt_receivers* rx, hipStream_t s) {
+  int rc = check_energy(e);
+  if (rc != RT_OK) return rc;
+  rc = check_trace_args(b, rays, n, max_bounces, out, path_len, n_hits, nullptr);
+  if (rc != RT_OK) return rc;
+  RecvArgs a{};
+  if (rx) {
+    rc = check_rx(rx, "rt_trace_energy");
+    if (rc != RT_OK) return rc;
+    if (n > INT32_MAX) return set_error(RT_EINVAL, "rt_trace_energy: n must be < 2^31 with receivers");
+    a = args_of(rx);
+    hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, s, a.count);
+    rc = check_hip(hipGetLastError(), "reception count reset");
+    if (rc != RT_OK) return rc;
+  }
+  if (n == 0) return RT_OK;
+  EnergyArgs en;
+  en.material = e->material;
+  en.refl = e->refl;
+  en.power = e->power;
+  en.k0 = e->k0;
+  en.min_power = e->min_power;
+  en.n_mat = e->n_materials;
+  en.pad = 0;
+  return launch_trace_energy(b->buf, b->info.node_format, b->info.depth, rays, n, max_bounces, out,
+                             path_len, n_hits, rx ? &a : nullptr, en, s);
 }
 
 int rt_receive_segments(const float* seg_rays, const rt_hit* hits, int64_t n, int32_t max_bounces,

@@ -426,20 +426,20 @@ constexpr int kBlock = 64;  // one wave per work-group: the LDS stack is per wav
 // wave's chains have ended, so a wave traces adjacent launch directions
 // together; with `refill` it tops up free lanes at every segment.  A wave
 // exits once its rays are done; no wave ever waits for another.
-template <int FMT, bool BOUNCE, bool SEG, bool STATS, bool RECV>
+template <int FMT, bool BOUNCE, bool SEG, bool STATS, bool RECV, bool ENERGY = false>
 __device__ __forceinline__ void trace_chains(const void* __restrict__ tn, const TFacet* __restrict__ tf,
                              const float4* __restrict__ rays, int64_t n, int max_b,
                              rt_hit* __restrict__ out, double* __restrict__ path_len,
                              int32_t* __restrict__ n_hits, float4* __restrict__ seg,
                              uint32_t* __restrict__ stats, unsigned long long* __restrict__ queue,
                              int refill, int64_t batch_base, int* stack,
-                             const RecvArgs& recv) {
+                             const RecvArgs& recv, const EnergyArgs& en = EnergyArgs{}) {
   const int lane = threadIdx.x & 63;
   const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   int64_t i = -1;  // ray of this lane, -1 when free
   float ox = 0.f, oy = 0.f, oz = 0.f, dx = 0.f, dy = 0.f, dz = 0.f, tmin = 0.f, tmax = 0.f;
   int skip = -1, b = 0, hits = 0;
-  double path = 0.0;
+  double path = 0.0, gain = 1.0, last_power = 0.0;
   uint32_t nvis = 0, ntest = 0;
   bool drained = false;
   for (;;) {
@@ -466,6 +466,8 @@ __device__ __forceinline__ void trace_chains(const void* __restrict__ tn, const 
           b = 0;
           hits = 0;
           path = 0.0;
+          gain = 1.0;
+          last_power = 0.0;
           nvis = ntest = 0;
         }
       }
@@ -494,7 +496,14 @@ __device__ __forceinline__ void trace_chains(const void* __restrict__ tn, const 
     if (BOUNCE && h.id >= 0) {
       ++hits;
       path += seg_path(h.t, dx, dy, dz);
-      if (b + 1 < max_b) {
+      bool alive = true;
+      if (ENERGY) {  // stop by energy (Sec. III-B)
+        const int mat = en.material[h.id];
+        gain *= (mat >= 0 && mat < en.n_mat) ? en.refl[mat] : 0.0;
+        last_power = chain_power(gain, en.k0, path);
+        alive = last_power >= en.min_power;
+      }
+      if (alive && b + 1 < max_b) {
         // specular reflection about the facet plane, launched from the hit point
         ox = fmaf(h.t, dx, ox);
         oy = fmaf(h.t, dy, oy);
@@ -512,6 +521,7 @@ __device__ __forceinline__ void trace_chains(const void* __restrict__ tn, const 
         for (int q = b + 1; q < max_b; ++q) store_hit(out, (int64_t)q * n + i, none);
         if (path_len) path_len[i] = path;
         if (n_hits) n_hits[i] = hits;
+        if (ENERGY && en.power) en.power[i] = last_power;
       }
       if (STATS) {
         stats[2 * i] = nvis;
@@ -554,6 +564,23 @@ __global__ __launch_bounds__(kBlock) void k_trace_recv(const void* __restrict__ 
   trace_chains<FMT, true, false, false, true>(tn, tf, rays, n, max_b, out, path_len, n_hits, nullptr,
                                               nullptr, nullptr, 0, (int64_t)blockIdx.x * kBlock,
                                               s_stack + threadIdx.x, recv);
+}
+
+// Reflection chains that also stop by energy (Sec. III-B), with or without
+// the reception test of every segment.
+template <int FMT, bool RECV>
+__global__ __launch_bounds__(kBlock) void k_trace_energy(const void* __restrict__ tn,
+                                                         const TFacet* __restrict__ tf,
+                                                         const float4* __restrict__ rays, int64_t n,
+                                                         int max_b, rt_hit* __restrict__ out,
+                                                         double* __restrict__ path_len,
+                                                         int32_t* __restrict__ n_hits,
+                                                         RecvArgs recv, EnergyArgs en) {
+  extern __shared__ int s_stack[];
+  trace_chains<FMT, true, false, false, RECV, true>(tn, tf, rays, n, max_b, out, path_len, n_hits,
+                                                    nullptr, nullptr, nullptr, 0,
+                                                    (int64_t)blockIdx.x * kBlock,
+                                                    s_stack + threadIdx.x, recv, en);
 }
 
 // Many queries (trees, ray sets, bounce limits) in one launch: work-group g
@@ -727,6 +754,43 @@ int launch_trace_receive(const Buffers& B, int node_format, int depth, const flo
       break;
   }
   return check_hip(hipGetLastError(), "trace+receive launch");
+}
+
+namespace {
+template <int FMT>
+void launch_energy_fmt(const Buffers& B, int depth, const float4* rays, int64_t n, int max_b,
+                       rt_hit* out, double* path_len, int32_t* n_hits, const RecvArgs* recv,
+                       const EnergyArgs& en, hipStream_t s) {
+  const unsigned blocks = (unsigned)((n + kBlock - 1) / kBlock);
+  const void* nodes = FMT == RT_NODE_BIN2 ? (const void*)B.tnodes : (const void*)B.wnodes;
+  if (recv)
+    hipLaunchKernelGGL((k_trace_energy<FMT, true>), dim3(blocks), dim3(kBlock),
+                       stack_bytes<FMT>(depth), s, nodes, B.tfacets, rays, n, max_b, out, path_len,
+                       n_hits, *recv, en);
+  else
+    hipLaunchKernelGGL((k_trace_energy<FMT, false>), dim3(blocks), dim3(kBlock),
+                       stack_bytes<FMT>(depth), s, nodes, B.tfacets, rays, n, max_b, out, path_len,
+                       n_hits, RecvArgs{}, en);
+}
+}  // namespace
+
+int launch_trace_energy(const Buffers& B, int node_format, int depth, const float* rays, int64_t n,
+                        int32_t max_b, rt_hit* out, double* path_len, int32_t* n_hits,
+                        const RecvArgs* recv, const EnergyArgs& en, hipStream_t s) {
+  if (n == 0) return RT_OK;
+  const float4* r4 = reinterpret_cast<const float4*>(rays);
+  switch (node_format) {
+    case RT_NODE_F4:
+      launch_energy_fmt<RT_NODE_F4>(B, depth, r4, n, max_b, out, path_len, n_hits, recv, en, s);
+      break;
+    case RT_NODE_Q4:
+      launch_energy_fmt<RT_NODE_Q4>(B, depth, r4, n, max_b, out, path_len, n_hits, recv, en, s);
+      break;
+    default:
+      launch_energy_fmt<RT_NODE_BIN2>(B, depth, r4, n, max_b, out, path_len, n_hits, recv, en, s);
+      break;
+  }
+  return check_hip(hipGetLastError(), "trace+energy launch");
 }
 
 int launch_trace(const Buffers& B, int node_format, int depth, const float* rays, int64_t n,

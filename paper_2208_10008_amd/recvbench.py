@@ -34,10 +34,11 @@ def main():
     ap.add_argument("--receivers", default="1,16,64,256")
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--dedup-receivers", type=int, default=64)
+    ap.add_argument("--thresholds", default="1e-9,1e-10,1e-11,0")
     a = ap.parse_args()
     import torch
 
-    from . import BVH, Receivers, SplitParams, rt_receive_segments
+    from . import BVH, Energy, Receivers, SplitParams, rt_receive_segments
     from rtgen import icosphere, workloads
 
     def say(*m):
@@ -104,6 +105,24 @@ def main():
     res["dedup"] = {"field_points": k, "ms": round(t, 4), "receptions": int(rec.size),
                     "kept": int(rec["keep"].sum())}
     say(f"dedup, {k} field points: {t:.3f} ms, {rec.size} -> {int(rec['keep'].sum())}")
+    del seg
+    mat = torch.from_numpy(workloads.city_materials(w.n_tris, 0)).cuda()
+    refl = torch.from_numpy(workloads.REFLECTION).cuda()
+    res["energy"] = {"k0": workloads.free_space_k0(), "reflection": workloads.REFLECTION.tolist(),
+                     "thresholds": {}}
+    for thr in (float(x) for x in a.thresholds.split(",")):
+        en = Energy(mat, refl, workloads.free_space_k0(), thr,
+                    power=torch.empty(n, dtype=torch.float64, device="cuda"))
+        t = timed(lambda: bvh.trace_energy(rays, nb, en, out=out, path_len=pl, n_hits=nh))
+        hits = nh.long()
+        stopped = (en.power < thr) & (hits > 0)
+        segs_e = int(torch.where(stopped, hits, torch.clamp(hits + 1, max=nb)).sum().item())
+        res["energy"]["thresholds"][repr(thr)] = {
+            "ms": round(t, 4), "segments": segs_e, "vs_fixed_order": round(t / t_trace, 4),
+            "stopped_by_energy": round(float(stopped.double().mean().item()), 4),
+            "mrays_s": round(segs_e / (t * 1e-3) / 1e6, 1)}
+        say(f"energy stop at {thr:g}: {t:.3f} ms, {segs_e} segments, "
+            f"{float(stopped.double().mean().item()):.3f} stopped by energy")
     print(json.dumps(res), flush=True)
 
 

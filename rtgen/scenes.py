@@ -246,6 +246,12 @@ def free_point(tris_seed_rng, half, tris: np.ndarray, z) -> tuple:
 
 
 # ---------------------------------------------------------------------------
+# Materials the paper names for its scenes (Sec. IV-A), as indices.
+MATERIALS = ("concrete", "wood", "metal", "glass")
+CONCRETE, WOOD, METAL, GLASS = range(4)
+
+
+# ---------------------------------------------------------------------------
 # Paper-size stand-ins: an 8 x 6 x 3.5 m study room of exactly 2,778 facets
 # and a campus of exactly 7,608 facets (the paper's facet counts, Sec. IV-A).
 
@@ -269,7 +275,7 @@ def _disc(cx, cy, z, r, m) -> list:
     return [((cx, cy, z), pts[k], pts[(k + 1) % m]) for k in range(m)]
 
 
-def study_room(seed: int = 0, target: int = 2778) -> np.ndarray:
+def study_room(seed: int = 0, target: int = 2778, materials: bool = False):
     """Study room 8 x 6 x 3.5 m ([0, 8] x [0, 6] x [0, 3.5]) furnished like
     the paper's indoor scene: shell (floor, ceiling, 4 walls: 12 facets), 12
     desks (top + 4 legs: 60 each) with 12 chairs (seat, back, 4 legs: 72
@@ -282,16 +288,27 @@ def study_room(seed: int = 0, target: int = 2778) -> np.ndarray:
     Rx (1.2, 1.2, 1.5) stay in free space.
 
     Draw order: per desk (row-major) dx, dy ~ U(-0.1, 0.1), width scale
-    ~ U(0.95, 1.05); per lamp dx ~ U(-0.2, 0.2)."""
+    ~ U(0.95, 1.05); per lamp dx ~ U(-0.2, 0.2).
+
+    With ``materials``, also returns the material index (``MATERIALS``) of
+    every facet, as the paper describes the room: walls, floor and ceiling
+    concrete; desks, chairs, door, cabinets, shelves, podium, whiteboard and
+    table wood; window frames, guard rails, door handle and lamps metal;
+    window panes glass."""
     rng = np.random.default_rng(seed)
     X, Y, H = 8.0, 6.0, 3.5
     t = []
+    mat = []
+
+    def tag(code):  # facets added since the last tag get this material
+        mat.extend([code] * (len(t) - len(mat)))
     t += _quad((0, 0, 0), (X, 0, 0), (X, Y, 0), (0, Y, 0))
     t += _quad((0, 0, H), (0, Y, H), (X, Y, H), (X, 0, H))
     t += _quad((0, 0, 0), (0, Y, 0), (0, Y, H), (0, 0, H))
     t += _quad((X, 0, 0), (X, 0, H), (X, Y, H), (X, Y, 0))
     t += _quad((0, 0, 0), (0, 0, H), (X, 0, H), (X, 0, 0))
     t += _quad((0, Y, 0), (X, Y, 0), (X, Y, H), (0, Y, H))
+    tag(CONCRETE)
     for row in range(3):
         for col in range(4):
             dx, dy = rng.uniform(-0.1, 0.1, 2)
@@ -307,8 +324,10 @@ def study_room(seed: int = 0, target: int = 2778) -> np.ndarray:
             t += _box(cx0, cy0 + 0.38, 0.46, cx0 + 0.42, cy0 + 0.42, 0.9)
             for lx, ly in ((cx0, cy0), (cx0 + 0.38, cy0), (cx0, cy0 + 0.38), (cx0 + 0.38, cy0 + 0.38)):
                 t += _box(lx, ly, 0.0, lx + 0.04, ly + 0.04, 0.42)
+    tag(WOOD)
 
     def window(u0, u1, wall):  # wall "y" (y = 6) or "x" (x = 8); u along the wall
+        # returns (pane facets, frame and guard-rail facets)
         z0, z1, inset = 0.9, 2.3, 0.03
         w = []
         if wall == "y":
@@ -320,7 +339,7 @@ def study_room(seed: int = 0, target: int = 2778) -> np.ndarray:
             a, b = p(ua, va, za), p(ub, vb, zb)
             return _box(min(a[0], b[0]), min(a[1], b[1]), za, max(a[0], b[0]), max(a[1], b[1]), zb)
 
-        w += _quad(p(u0, inset, z0), p(u1, inset, z0), p(u1, inset, z1), p(u0, inset, z1))
+        pane = _quad(p(u0, inset, z0), p(u1, inset, z0), p(u1, inset, z1), p(u0, inset, z1))
         w += slab(u0 - 0.05, u1 + 0.05, 0.0, 0.06, z0 - 0.05, z0)
         w += slab(u0 - 0.05, u1 + 0.05, 0.0, 0.06, z1, z1 + 0.05)
         w += slab(u0 - 0.05, u0, 0.0, 0.06, z0, z1)
@@ -328,14 +347,19 @@ def study_room(seed: int = 0, target: int = 2778) -> np.ndarray:
         for k in range(6):
             u = u0 + (k + 0.5) * (u1 - u0) / 6
             w += slab(u - 0.01, u + 0.01, 0.12, 0.14, z0, z1)
-        return w
+        return pane, w
 
-    for uc in (4.0, 5.5, 7.0):
-        t += window(uc - 0.6, uc + 0.6, "y")
-    for uc in (1.5, 3.0, 4.5):
-        t += window(uc - 0.6, uc + 0.6, "x")
+    for wall, centres in (("y", (4.0, 5.5, 7.0)), ("x", (1.5, 3.0, 4.5))):
+        for uc in centres:
+            pane, metal = window(uc - 0.6, uc + 0.6, wall)
+            t += pane
+            tag(GLASS)
+            t += metal
+            tag(METAL)
     t += _box(6.5, 0.02, 0.0, 7.4, 0.06, 2.1)
+    tag(WOOD)
     t += _box(6.6, 0.06, 1.0, 6.75, 0.1, 1.05)
+    tag(METAL)
     for cx in (0.3, 1.25, 2.2):
         t += _box(cx, 5.5, 0.0, cx + 0.9, 5.95, 2.0)
     t += _box(0.05, 3.8, 0.0, 0.4, 3.82, 2.2)
@@ -345,18 +369,21 @@ def study_room(seed: int = 0, target: int = 2778) -> np.ndarray:
         t += _box(0.05, 3.82, z, 0.4, 5.28, z + 0.02)
     t += _box(0.6, 3.0, 0.0, 1.2, 3.5, 1.1)
     t += _box(0.02, 0.6, 0.9, 0.04, 2.9, 2.1)
+    tag(WOOD)
     for k in range(6):
         lx = 2.4 + 1.8 * (k % 3) + rng.uniform(-0.2, 0.2)
         ly = 1.5 if k < 3 else 4.2
         t += _box(lx, ly, 3.34, lx + 1.2, ly + 0.3, 3.4)
+    tag(METAL)
     rest = target - len(t) - 4 * 12
     if rest < 3:
         raise ValueError("study_room: target below the furniture's facet count")
     t += _disc(1.9, 4.4, 0.75, 0.55, rest)
     for lx, ly in ((1.85, 4.35), (1.85, 4.4), (1.9, 4.35), (1.9, 4.4)):
         t += _box(lx, ly, 0.0, lx + 0.03, ly + 0.03, 0.75)
-    assert len(t) == target
-    return _pack(t)
+    tag(WOOD)
+    assert len(t) == target and len(mat) == target
+    return (_pack(t), np.array(mat, np.int32)) if materials else _pack(t)
 
 
 def _tessellated_building(rng, poly, h, cell) -> list:
@@ -383,7 +410,7 @@ def _tessellated_building(rng, poly, h, cell) -> list:
 
 
 def campus(seed: int = 0, target: int = 7608, size: float = 1000.0,
-           keep_free=((450.0, 450.0), (450.0, 550.0))) -> np.ndarray:
+           keep_free=((450.0, 450.0), (450.0, 550.0)), materials: bool = False):
     """Campus of exactly ``target`` facets on [0, size]^2: ground (2 facets),
     non-overlapping buildings with tessellated facades, and a playground whose
     flat oval track (a fan 0.05 m above the ground) takes the facets left over.
@@ -396,9 +423,14 @@ def campus(seed: int = 0, target: int = 7608, size: float = 1000.0,
     building whose box (grown by 10 m) meets another's, or covers a point of
     ``keep_free`` (the paper's Tx and Rx), is drawn again; buildings are
     added while the facet count stays 300 below the target (at most 4,000
-    draws)."""
+    draws).  With ``materials``, also returns a material index per facet:
+    ground and playground concrete, each building concrete or (with
+    probability 0.3, drawn from a second generator seeded seed + 1 in
+    building order) glass."""
     rng = np.random.default_rng(seed)
+    mrng = np.random.default_rng(seed + 1)
     t = _quad((0, 0, 0), (size, 0, 0), (size, size, 0), (0, size, 0))
+    mat = [CONCRETE, CONCRETE]
     boxes = []
     play = (180.0, 780.0, 90.0, 55.0)   # playground centre and half-axes, kept free
     boxes.append((play[0] - play[2], play[1] - play[3], play[0] + play[2], play[1] + play[3]))
@@ -432,10 +464,12 @@ def campus(seed: int = 0, target: int = 7608, size: float = 1000.0,
             continue
         boxes.append(bb)
         t += bt
+        mat += [GLASS if mrng.uniform() < 0.3 else CONCRETE] * len(bt)
     rest = target - len(t)
     cx, cy, ax, ay = play
     pts = [(cx + ax * math.cos(2 * math.pi * k / rest), cy + ay * math.sin(2 * math.pi * k / rest), 0.05)
            for k in range(rest)]
     t += [((cx, cy, 0.05), pts[k], pts[(k + 1) % rest]) for k in range(rest)]
-    assert len(t) == target
-    return _pack(t)
+    mat += [CONCRETE] * rest
+    assert len(t) == target and len(mat) == target
+    return (_pack(t), np.array(mat, np.int32)) if materials else _pack(t)

@@ -194,6 +194,39 @@ def field_points(tris: np.ndarray, half: float, n: int, seed: int) -> np.ndarray
     return np.array(pts, np.float64).reshape(-1, 3)
 
 
+def normal_incidence_reflection(eps_r: float) -> float:
+    """Power reflection coefficient |(1 - sqrt(eps)) / (1 + sqrt(eps))|^2 of a
+    lossless dielectric half-space at normal incidence."""
+    r = (1.0 - math.sqrt(eps_r)) / (1.0 + math.sqrt(eps_r))
+    return r * r
+
+
+# Power reflection coefficient per material index (scenes.MATERIALS order):
+# the paper names the materials but gives no values, so these are illustrative
+# inputs -- normal-incidence values for relative permittivities 5.3 (concrete),
+# 2.0 (wood) and 6.3 (glass), and 1 for metal (a perfect conductor).
+REFLECTION = np.array([normal_incidence_reflection(5.3), normal_incidence_reflection(2.0), 1.0,
+                       normal_incidence_reflection(6.3)])
+FREQUENCY_HZ = 2.4e9      # the paper's simulation frequency (Sec. IV-A)
+
+
+def free_space_k0(frequency_hz: float = FREQUENCY_HZ) -> float:
+    """(lambda / (4 pi))^2: power ratio between isotropic antennas 1 m apart."""
+    lam = 299_792_458.0 / frequency_hz
+    return (lam / (4.0 * math.pi)) ** 2
+
+
+def city_materials(n_tris: int, seed: int = 0) -> np.ndarray:
+    """Material index per facet of a city scene: the two ground facets
+    concrete, every other facet concrete / glass / metal with probabilities
+    0.8 / 0.15 / 0.05 (one draw per facet)."""
+    rng = np.random.default_rng(seed)
+    u = rng.uniform(size=n_tris)
+    m = np.where(u < 0.8, scenes.CONCRETE, np.where(u < 0.95, scenes.GLASS, scenes.METAL))
+    m[:2] = scenes.CONCRETE
+    return m.astype(np.int32)
+
+
 @dataclasses.dataclass
 class PaperScene:
     """A stand-in for one of the paper's two simulation scenes, with the
@@ -207,6 +240,7 @@ class PaperScene:
     alpha: float
     max_order: int       # highest reflection order received
     tmax: float
+    material: np.ndarray = None   # int32 [n] material index per facet (scenes.MATERIALS)
 
     @property
     def max_bounces(self) -> int:
@@ -221,13 +255,15 @@ def paper_indoor(seed: int = 0) -> PaperScene:
     """Study room 8 x 6 x 3.5 m, 2,778 facets; Tx (1.46, 2.42, 2.1), Rx (1.2,
     1.2, 1.5); 250 facets per leaf, alpha 0.7; reflection orders 1 and 2;
     tmax 20 m per segment."""
-    return PaperScene("indoor-2778", scenes.study_room(seed), (1.46, 2.42, 2.1), (1.2, 1.2, 1.5),
-                      250, 0.7, 2, 20.0)
+    tris, mat = scenes.study_room(seed, materials=True)
+    return PaperScene("indoor-2778", tris, (1.46, 2.42, 2.1), (1.2, 1.2, 1.5), 250, 0.7, 2, 20.0,
+                      mat)
 
 
 def paper_outdoor(seed: int = 0) -> PaperScene:
     """Campus 1 x 1 km, 7,608 facets; Tx (450, 450, 10), Rx (450, 550, 25);
     820 facets per leaf, alpha 0.4; reflection order 3; tmax 2 km per
     segment."""
-    return PaperScene("outdoor-7608", scenes.campus(seed), (450.0, 450.0, 10.0),
-                      (450.0, 550.0, 25.0), 820, 0.4, 3, 2000.0)
+    tris, mat = scenes.campus(seed, materials=True)
+    return PaperScene("outdoor-7608", tris, (450.0, 450.0, 10.0), (450.0, 550.0, 25.0), 820, 0.4,
+                      3, 2000.0, mat)

@@ -67,13 +67,15 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(rt_reception), offsetof(rt_reception, l),
          offsetof(rt_reception, dist), sizeof(rt_receivers), offsetof(rt_receivers, delta),
          offsetof(rt_receivers, cap), offsetof(rt_receivers, count));
+  printf("%zu %zu %zu %zu\\n", sizeof(rt_energy), offsetof(rt_energy, k0),
+         offsetof(rt_energy, min_power), offsetof(rt_energy, power));
   return 0;
 }""")
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-D__HIP_PLATFORM_AMD__", "-I" + os.path.join(ROOT, "include"),
                     "-I/opt/rocm/include", str(src), "-o", str(exe)], check=True)
-    a, b, c, d = subprocess.run([str(exe)], capture_output=True, text=True,
-                                check=True).stdout.split("\n")[:4]
+    a, b, c, d, e = subprocess.run([str(exe)], capture_output=True, text=True,
+                                   check=True).stdout.split("\n")[:5]
     sizes = [int(x) for x in a.split()]
     offs = [int(x) for x in b.split()]
     assert sizes == [ctypes.sizeof(R.rt_split_params), 16, ctypes.sizeof(R.rt_bvh_info),
@@ -88,6 +90,8 @@ int main(void) {
                                            R.RECEPTION_DTYPE.fields["dist"][1],
                                            ctypes.sizeof(R.rt_receivers), R.rt_receivers.delta.offset,
                                            R.rt_receivers.cap.offset, R.rt_receivers.count.offset]
+    assert [int(x) for x in e.split()] == [ctypes.sizeof(R.rt_energy), R.rt_energy.k0.offset,
+                                           R.rt_energy.min_power.offset, R.rt_energy.power.offset]
 
 
 def test_defaults():
@@ -246,3 +250,33 @@ def test_reception_argument_checks():
     assert lib.rt_receive_dedup(p, 4, 2, rx(), p, 8, None) == R.RT_EINVAL   # too small
     assert lib.rt_receive_dedup(p, 4, 0, rx(), p, 1 << 20, None) == R.RT_EINVAL
     assert lib.rt_receive_dedup(p, 4, 2, rx(cap=0), None, 0, None) == R.RT_OK   # nothing stored
+
+
+def test_energy_argument_checks():
+    """Checks that fail before any device call: the energy struct is checked
+    first, then the tree handle."""
+    lib = R.load()
+    buf = np.zeros(64, np.float64)
+    base = buf.ctypes.data + (-buf.ctypes.data) % 64
+    p = ctypes.c_void_p(base)
+
+    def en(**kw):
+        e = R.rt_energy(material=base, refl=base, n_materials=2, reserved=0, k0=1e-4,
+                        min_power=1e-9, power=None)
+        for k, v in kw.items():
+            setattr(e, k, v)
+        return ctypes.byref(e)
+
+    f = lib.rt_trace_energy
+    for kw, word in ((dict(material=None), b"material"), (dict(material=base + 2), b"material"),
+                     (dict(n_materials=-1), b"n_materials"), (dict(reserved=3), b"reserved"),
+                     (dict(refl=None), b"refl"), (dict(refl=base + 4), b"refl"),
+                     (dict(k0=0.0), b"k0"), (dict(k0=float("inf")), b"k0"),
+                     (dict(min_power=-1.0), b"min_power"), (dict(min_power=float("nan")), b"min_power"),
+                     (dict(power=base + 4), b"power")):
+        assert f(None, p, 4, 2, en(**kw), p, None, None, None, None) == R.RT_EINVAL, kw
+        assert word in lib.rt_last_error(), (kw, lib.rt_last_error())
+    assert f(None, p, 4, 2, None, p, None, None, None, None) == R.RT_EINVAL
+    # a valid struct (refl may be NULL without materials) reaches the tree check
+    assert f(None, p, 4, 2, en(refl=None, n_materials=0), p, None, None, None, None) == R.RT_EINVAL
+    assert b"tree" in lib.rt_last_error()
