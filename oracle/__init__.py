@@ -19,6 +19,10 @@ Functions and what pins them:
   closed forms.  :func:`bounces_energy` -- the same chains stopped by the
   energy rule of Sec. III-B; pinned by closed-form stop points in a corridor
   and over a ground and a wall.
+* :mod:`oracle.diffraction` -- wedge edges and Keller-cone diffracted rays
+  (Sec. III-B), numpy float64.  Pinned by edge counts of closed solids, the
+  coplanarity threshold, the Keller law, a right wedge's exterior angle, the
+  tube radius and the distance to an edge segment.
 * :mod:`oracle.reception` -- receiving spheres of Sec. III-C, Eq. (4), in
   numpy float64.  Pinned by a hand-worked example, the exact mean number of
   receptions in free space, hole-free coverage of an icosphere launch, and
