@@ -294,6 +294,59 @@ int rt_trace_energy(const rt_bvh* b, const float* rays, int64_t n, int32_t max_b
                     const rt_energy* e, rt_hit* out, double* path_len, int32_t* n_hits,
                     const rt_receivers* rx, hipStream_t s);
 
+/* ---- edge diffraction (Sec. III-B: rays meeting facets give reflected and
+ * diffracted rays) ---------------------------------------------------------
+ * Wedges.  Edge k of facet f runs from its vertex k to vertex (k + 1) % 3.
+ * Two half-edges are one edge when their end points are equal float32 points
+ * (in either order).  An edge of exactly one facet is free (neighbour -1); an
+ * edge of exactly two facets is a wedge when their normals
+ * n = (v1 - v0) x (v2 - v0) (float64) satisfy (n_a.n_b)^2 < cos^2(1 deg)
+ * |n_a|^2 |n_b|^2 (neighbour = the other facet's index); any other edge does
+ * not diffract (-2).
+ *
+ * Diffraction of a stored chain's hit: segment b of a ray hits facet f at
+ * p = o + t d after a path l = L_b + t |d|.  The nearest wedge or free edge of
+ * f whose segment lies within the ray-tube radius rho = l delta / sqrt(3)
+ * (Eq. (4)) of p (ties to the lower edge index) diffracts at q, the point of
+ * the edge nearest p.  With unit edge direction e and unit incident direction
+ * i, c = i.e, r = i - c e, sin(beta) = |r| (no diffraction when 0), u = r / |r|,
+ * w = e x u, the Keller-cone directions are c e + sin(beta) (cos_k u + sin_k w)
+ * for the caller's (cos_k, sin_k) table; at a wedge, directions whose part
+ * across the edge lies strictly between the two facets (towards their third
+ * vertices) point into the solid and are dropped.  All of it in float64 in
+ * this order without fused multiply-add; q and the directions are rounded to
+ * float32 once.  Diffracted rays are ordinary rays: trace them with
+ * rt_trace_bounces. */
+typedef struct rt_diffracted {
+  int32_t ray;    /* parent ray */
+  int32_t order;  /* parent segment (reflections before the diffracting hit) */
+  int32_t facet;  /* facet hit */
+  int32_t edge;   /* 0..2: the facet's edge that diffracts */
+  int32_t cone;   /* index in the cone table */
+  int32_t pad;
+  double path;    /* path length from the source to the diffraction point q */
+  float ray8[8];  /* the diffracted ray as in rays[]: q, parent tmin, direction, parent tmax */
+} rt_diffracted;  /* 64 bytes */
+
+/* Neighbour of every half-edge: nbr device int32 [n][3].  tris: device
+ * float32 [n][9].  Synchronises the stream (sorts with temporary device
+ * memory).  Errors: RT_EINVAL (NULL / misaligned, n < 1 or >= 2^29,
+ * non-finite vertex), RT_ENOMEM, RT_EHIP. */
+int rt_wedges(const float* tris, int64_t n, int32_t* nbr, hipStream_t s);
+
+/* Diffracted rays of stored chains (seg_rays and hits as for
+ * rt_receive_segments) over the facets tris [n_tris][9] with their
+ * neighbours nbr [n_tris][3] from rt_wedges.  cone: device float64
+ * [n_cone][2] (cos, sin); out: device [cap] records, *count (device int64)
+ * set to the number found (only min(count, cap) written, in no particular
+ * order).  Hits on facet indices outside [0, n_tris) do not diffract.
+ * Errors: RT_EINVAL (NULL / misaligned, sizes out of range, delta not finite
+ * or negative, n_cone outside 0..1024), RT_EHIP. */
+int rt_diffract_segments(const float* tris, int64_t n_tris, const int32_t* nbr,
+                         const float* seg_rays, const rt_hit* hits, int64_t n,
+                         int32_t max_bounces, double delta, const double* cone, int32_t n_cone,
+                         rt_diffracted* out, int64_t cap, int64_t* count, hipStream_t s);
+
 /* ---- inspection and lifetime ------------------------------------------ */
 int rt_bvh_info_get(const rt_bvh* b, rt_bvh_info* info); /* host struct */
 

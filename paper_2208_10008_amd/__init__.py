@@ -89,6 +89,11 @@ RECEPTION_DTYPE = np.dtype([("rx", "<i4"), ("ray", "<i4"), ("order", "<i4"), ("k
                             ("l", "<f8"), ("dist", "<f8")])
 assert RECEPTION_DTYPE.itemsize == 32
 
+# numpy view of rt_diffracted (64 bytes)
+DIFFRACTED_DTYPE = np.dtype([("ray", "<i4"), ("order", "<i4"), ("facet", "<i4"), ("edge", "<i4"),
+                             ("cone", "<i4"), ("pad", "<i4"), ("path", "<f8"), ("ray8", "<f4", 8)])
+assert DIFFRACTED_DTYPE.itemsize == 64
+
 BATCH_MODES = {"direct": 0, "queue": 1}
 BATCH_ORDERS = {"given": 0, "cost": 1}
 
@@ -104,7 +109,7 @@ EXPORTS = ("rt_split_params_default", "rt_build", "rt_rebuild", "rt_trace",
            "rt_batch_set", "rt_batch_configure", "rt_batch_get_config", "rt_batch_launch",
            "rt_batch_autotune", "rt_batch_destroy", "rt_rays_from_directions",
            "rt_trace_receive", "rt_receive_segments", "rt_receive_dedup_workspace",
-           "rt_receive_dedup", "rt_trace_energy")
+           "rt_receive_dedup", "rt_trace_energy", "rt_wedges", "rt_diffract_segments")
 PROBE_EXPORTS = ("rt_probe_read", "rt_probe_copy")  # include/rt_probe.h
 
 _lib = None
@@ -152,12 +157,16 @@ def load(path: str = LIB_PATH):
     lib.rt_receive_dedup_workspace.restype = i64
     lib.rt_receive_dedup.argtypes = [P, i64, i32, RX, P, i64, P]
     lib.rt_trace_energy.argtypes = [P, P, i64, i32, ctypes.POINTER(rt_energy), P, P, P, RX, P]
+    lib.rt_wedges.argtypes = [P, i64, P, P]
+    lib.rt_diffract_segments.argtypes = [P, i64, P, P, P, i64, i32, ctypes.c_double, P, i32, P,
+                                         i64, P, P]
     for name in ("rt_build", "rt_rebuild", "rt_trace", "rt_trace_bounces", "rt_trace_ex",
                  "rt_bvh_info_get", "rt_bvh_download", "rt_bvh_export_trace_nodes",
                  "rt_probe_read", "rt_probe_copy", "rt_batch_create", "rt_batch_set",
                  "rt_batch_configure", "rt_batch_get_config", "rt_batch_launch",
                  "rt_batch_autotune", "rt_rays_from_directions", "rt_trace_receive",
-                 "rt_receive_segments", "rt_receive_dedup", "rt_trace_energy"):
+                 "rt_receive_segments", "rt_receive_dedup", "rt_trace_energy", "rt_wedges",
+                 "rt_diffract_segments"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -367,6 +376,48 @@ def rt_trace_energy(handle, rays, max_bounces, energy: Energy, out, path_len, n_
     rx = None if receivers is None else ctypes.byref(receivers.c())
     _check(lib.rt_trace_energy(handle, _ptr(rays), rays.shape[0], max_bounces, ctypes.byref(e),
                                _ptr(out), _ptr(path_len), _ptr(n_hits), rx, _stream(stream)))
+
+
+def rt_wedges(tris, nbr=None, stream=None):
+    """Neighbour of every half-edge (int32 [n, 3] CUDA tensor): the other
+    facet of a wedge edge, -1 free, -2 not diffracting.  Synchronises."""
+    import torch
+    _dev(tris, torch.float32, 9, "tris")
+    if nbr is None:
+        nbr = torch.empty((tris.shape[0], 3), dtype=torch.int32, device=tris.device)
+    _check(load().rt_wedges(_ptr(tris), tris.shape[0], _ptr(nbr), _stream(stream)))
+    return nbr
+
+
+def rt_diffract_segments(tris, nbr, seg_rays, hits, max_bounces, delta, cone, cap, out=None,
+                         count=None, stream=None):
+    """Diffracted rays of stored chains; returns (records int32 [cap, 16]
+    tensor viewing rt_diffracted, count int64 [1] tensor).  cone: float64
+    [n_cone, 2] CUDA tensor of (cos, sin)."""
+    import torch
+    _dev(tris, torch.float32, 9, "tris")
+    if out is None:
+        out = torch.zeros((max(int(cap), 1), 16), dtype=torch.int32, device=tris.device)
+    if count is None:
+        count = torch.zeros(1, dtype=torch.int64, device=tris.device)
+    n = hits.shape[1]
+    _check(load().rt_diffract_segments(_ptr(tris), tris.shape[0], _ptr(nbr), _ptr(seg_rays),
+                                       _ptr(hits), n, max_bounces, float(delta), _ptr(cone),
+                                       cone.shape[0], _ptr(out), int(cap), _ptr(count),
+                                       _stream(stream)))
+    return out, count
+
+
+def diffracted_records(out, count, cap) -> np.ndarray:
+    """The stored rt_diffracted records as a numpy DIFFRACTED_DTYPE array."""
+    k = min(int(count.item()), int(cap))
+    return out[:k].cpu().numpy().view(DIFFRACTED_DTYPE).reshape(-1)
+
+
+def diffracted_rays(out, k):
+    """The first k diffracted rays as a contiguous float32 [k, 8] ray tensor."""
+    import torch
+    return out[:k, 8:16].contiguous().view(torch.float32)
 
 
 def rt_bvh_info_get(handle) -> rt_bvh_info:

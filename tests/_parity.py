@@ -4,8 +4,11 @@ Rule (closest hit): a ray is clean when the checker's margin exceeds 1e-4;
 clean rays must give the checker's facet id exactly and t within relative
 1e-5.  Every ray, clean or not, must give an answer in the acceptable set:
 the checker's winner, a facet crossed within 1e-4 of its edges no later than
-the winner's t (relative 1e-4), or a miss when the winner itself lies within
-1e-4 of an edge or of either end of the range.
+the winner's t (relative 1e-4), a miss when the winner itself lies within
+1e-4 of an edge or of either end of the range, or -- when the winner lies
+within 1e-4 of an edge, so that the ray may pass it -- the answer with the
+winner removed (the same rule again, up to four facets deep: a ray tangent
+to a thin slab passes both of its faces).
 """
 import numpy as np
 
@@ -19,6 +22,35 @@ BAND = 5e-3   # reception: relative distance from the Eq. (4) threshold treated 
 
 def _rel(a, s):
     return a / np.maximum(np.abs(s), 1e-3)
+
+
+def _edge_near(u, v):
+    return min(u, v, 1 - u - v) <= CLEAN
+
+
+def _passes_grazed(tris, ray, gid, winner, u, v, depth=4):
+    """True when the GPU answer gid for one ray is acceptable after removing
+    the checker's winners that the ray meets within CLEAN of an edge."""
+    if winner < 0 or not _edge_near(u, v):
+        return False
+    cut = np.array(tris, np.float32, copy=True).reshape(-1, 9)
+    removed = [winner]
+    for _ in range(depth):
+        cut[removed] = 0.0                     # zero-area facets are never hit
+        nxt = oracle.brute(cut, ray[None])
+        nid = int(nxt.id[0])
+        if gid == nid:
+            return True
+        if gid >= 0:
+            valid, tg, ug, vg = oracle.evaluate(tris, ray[None], np.array([gid], np.int32))
+            out = max(-ug[0], -vg[0], ug[0] + vg[0] - 1)
+            lim = nxt.t[0] * (1 + CLEAN) if nid >= 0 else np.inf
+            if valid[0] and out <= CLEAN and tg[0] <= lim:
+                return True
+        if nid < 0 or not _edge_near(nxt.u[0], nxt.v[0]):
+            return False
+        removed.append(nid)
+    return False
 
 
 def compare_hits(tris, rays, gid, gt, ref: "oracle.Hits", skip=None):
@@ -59,6 +91,13 @@ def compare_hits(tris, rays, gid, gt, ref: "oracle.Hits", skip=None):
             edge = np.minimum(np.minimum(u, v), 1 - u - v) <= CLEAN
             rng = np.minimum(_rel(t1 - tmin, t1), _rel(tmax - t1, t1)) <= CLEAN
             ok |= no_g & (edge | rng)
+        if not ok.all() and skip is None:
+            # a ray through an edge of the winner may pass it (a ray tangent to
+            # a thin slab passes both of its faces): then the answer is the
+            # one with that facet removed, the same rule applied again, up to
+            # four facets deep
+            for q in np.nonzero(~ok)[0]:
+                ok[q] = _passes_grazed(tris, r[q], g[q], w[q], ref.u[low][q], ref.v[low][q])
         assert ok.all(), f"{(~ok).sum()} low-margin rays outside the acceptable set, e.g. {low[~ok][:5]}"
     return {"rays": int(m), "clean": int(clean.sum()), "low_margin": int((~clean).sum()),
             "low_margin_differing": int(low.size), "hits": int((gid >= 0).sum())}

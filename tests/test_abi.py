@@ -69,13 +69,15 @@ int main(void) {
          offsetof(rt_receivers, cap), offsetof(rt_receivers, count));
   printf("%zu %zu %zu %zu\\n", sizeof(rt_energy), offsetof(rt_energy, k0),
          offsetof(rt_energy, min_power), offsetof(rt_energy, power));
+  printf("%zu %zu %zu\\n", sizeof(rt_diffracted), offsetof(rt_diffracted, path),
+         offsetof(rt_diffracted, ray8));
   return 0;
 }""")
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-D__HIP_PLATFORM_AMD__", "-I" + os.path.join(ROOT, "include"),
                     "-I/opt/rocm/include", str(src), "-o", str(exe)], check=True)
-    a, b, c, d, e = subprocess.run([str(exe)], capture_output=True, text=True,
-                                   check=True).stdout.split("\n")[:5]
+    a, b, c, d, e, g = subprocess.run([str(exe)], capture_output=True, text=True,
+                                      check=True).stdout.split("\n")[:6]
     sizes = [int(x) for x in a.split()]
     offs = [int(x) for x in b.split()]
     assert sizes == [ctypes.sizeof(R.rt_split_params), 16, ctypes.sizeof(R.rt_bvh_info),
@@ -92,6 +94,9 @@ int main(void) {
                                            R.rt_receivers.cap.offset, R.rt_receivers.count.offset]
     assert [int(x) for x in e.split()] == [ctypes.sizeof(R.rt_energy), R.rt_energy.k0.offset,
                                            R.rt_energy.min_power.offset, R.rt_energy.power.offset]
+    assert [int(x) for x in g.split()] == [R.DIFFRACTED_DTYPE.itemsize,
+                                           R.DIFFRACTED_DTYPE.fields["path"][1],
+                                           R.DIFFRACTED_DTYPE.fields["ray8"][1]]
 
 
 def test_defaults():
@@ -280,3 +285,31 @@ def test_energy_argument_checks():
     # a valid struct (refl may be NULL without materials) reaches the tree check
     assert f(None, p, 4, 2, en(refl=None, n_materials=0), p, None, None, None, None) == R.RT_EINVAL
     assert b"tree" in lib.rt_last_error()
+
+
+def test_diffraction_argument_checks():
+    """Checks that fail before any device call."""
+    lib = R.load()
+    buf = np.zeros(64, np.float64)
+    base = buf.ctypes.data + (-buf.ctypes.data) % 64
+    p = ctypes.c_void_p(base)
+    odd = ctypes.c_void_p(base + 2)
+    w = lib.rt_wedges
+    assert w(None, 4, p, None) == R.RT_EINVAL
+    assert w(p, 4, None, None) == R.RT_EINVAL
+    assert w(odd, 4, p, None) == R.RT_EINVAL
+    assert w(p, 0, p, None) == R.RT_EINVAL and w(p, 1 << 29, p, None) == R.RT_EINVAL
+    d = lib.rt_diffract_segments
+
+    def call(**kw):
+        a = dict(tris=p, n_tris=4, nbr=p, seg=p, hits=p, n=4, nb=2, delta=0.01, cone=p, n_cone=4,
+                 out=p, cap=4, count=p)
+        a.update(kw)
+        return d(a["tris"], a["n_tris"], a["nbr"], a["seg"], a["hits"], a["n"], a["nb"], a["delta"],
+                 a["cone"], a["n_cone"], a["out"], a["cap"], a["count"], None)
+
+    for kw in (dict(tris=None), dict(nbr=None), dict(count=None), dict(count=odd), dict(n_tris=0),
+               dict(n=-1), dict(n=1 << 31), dict(nb=0), dict(nb=65), dict(delta=-1.0),
+               dict(delta=float("inf")), dict(n_cone=-1), dict(n_cone=1025), dict(cone=None),
+               dict(cap=-1), dict(cap=1 << 31), dict(out=None), dict(seg=None), dict(hits=odd)):
+        assert call(**kw) == R.RT_EINVAL, kw
