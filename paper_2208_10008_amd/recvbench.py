@@ -1,17 +1,24 @@
-"""Receiving-sphere reception (Sec. III-C, Eq. (4)) on the city24k launch:
-2,000 buildings (about 24k facets), Tx (0, 0, 25), level-9 icosphere
-(2,621,442 rays), up to 6 segments, field points outside the buildings
-within 400 m of the Tx, delta = mean angle between adjacent launch
-directions.
+"""After-trace stages on the city24k launch: 2,000 buildings (about 24k
+facets), Tx (0, 0, 25), level-9 icosphere (2,621,442 rays), up to 6
+segments; delta = mean angle between adjacent launch directions.
 
     python -m paper_2208_10008_amd.recvbench [--receivers 1,16,64,256] [--reps 10]
 
 Times with HIP events on the launching stream:
   * the chains alone (rt_trace_bounces);
-  * the chains with every segment tested as it is traced (rt_trace_receive),
-    per number of field points;
-  * the stored-chain kernel (rt_receive_segments) over the tracer's segment
-    output, and the duplicate grouping (rt_receive_dedup).
+  * receiving spheres (Sec. III-C, Eq. (4)), field points outside the
+    buildings within 400 m of the Tx: the chains with every segment tested as
+    it is traced (rt_trace_receive) per number of field points; the
+    stored-chain kernel (rt_receive_segments) over the tracer's segment
+    output; the duplicate grouping (rt_receive_dedup);
+  * edge diffraction (Sec. III-B): wedge extraction (rt_wedges, host clock of
+    the synchronising call), the diffraction pass over the stored chains
+    (rt_diffract_segments, 16 cone directions) and one closest-hit segment
+    for every diffracted ray;
+  * the chains with the energy stop rule of Sec. III-B (rt_trace_energy) at
+    several thresholds: per-facet materials (ground concrete, other facets
+    concrete / glass / metal 0.8 / 0.15 / 0.05), illustrative power
+    reflection coefficients, free-space constant at 2.4 GHz.
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -19,6 +26,7 @@ from __future__ import annotations
 import argparse
 import json
 import sys
+import time
 
 import numpy as np
 
@@ -38,7 +46,8 @@ def main():
     a = ap.parse_args()
     import torch
 
-    from . import BVH, Energy, Receivers, SplitParams, rt_receive_segments
+    from . import (BVH, Energy, Receivers, SplitParams, diffracted_rays, rt_diffract_segments,
+                   rt_receive_segments, rt_wedges)
     from rtgen import icosphere, workloads
 
     def say(*m):
@@ -53,6 +62,11 @@ def main():
     out = bvh.hits_buffer(n, nb)
     pl = torch.empty(n, dtype=torch.float64, device="cuda")
     nh = torch.empty(n, dtype=torch.int32, device="cuda")
+
+    def timed_host(fn):  # host wall clock of a synchronising call, ms
+        t0 = time.perf_counter()
+        fn()
+        return (time.perf_counter() - t0) * 1e3
 
     def timed(fn):
         fn()
@@ -105,7 +119,30 @@ def main():
     res["dedup"] = {"field_points": k, "ms": round(t, 4), "receptions": int(rec.size),
                     "kept": int(rec["keep"].sum())}
     say(f"dedup, {k} field points: {t:.3f} ms, {rec.size} -> {int(rec['keep'].sum())}")
-    del seg
+    # diffraction over the stored chains
+    tris_d = torch.from_numpy(w.tris).cuda()
+    nbr = rt_wedges(tris_d)
+    t_w = min(timed_host(lambda: rt_wedges(tris_d, nbr)) for _ in range(3))
+    n_cone = 16
+    a_k = 2 * np.pi * (np.arange(n_cone) + 0.5) / n_cone
+    cone = torch.from_numpy(np.stack([np.cos(a_k), np.sin(a_k)], 1)).cuda()
+    cap = 1 << 24
+    dout = torch.zeros((cap, 16), dtype=torch.int32, device="cuda")
+    dcnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    t_d = timed(lambda: rt_diffract_segments(tris_d, nbr, seg, out, nb, delta, cone, cap, dout, dcnt))
+    nd = min(int(dcnt.item()), cap)
+    drays = diffracted_rays(dout, nd)
+    dhits = bvh.hits_buffer(nd, 1)[0]
+    t_dt = timed(lambda: bvh.trace(drays, dhits))
+    wedge_half_edges = int((nbr >= 0).sum().item())
+    res["diffraction"] = {"wedges_ms": round(t_w, 3), "wedge_half_edges": wedge_half_edges,
+                          "free_half_edges": int((nbr == -1).sum().item()), "cone_directions": n_cone,
+                          "pass_ms": round(t_d, 4), "diffracted_rays": nd,
+                          "trace_diffracted_ms": round(t_dt, 4),
+                          "diffracted_mrays_s": round(nd / (t_dt * 1e-3) / 1e6, 1)}
+    say(f"diffraction: wedges {t_w:.2f} ms ({wedge_half_edges} wedge half-edges), pass {t_d:.3f} ms, "
+        f"{nd} diffracted rays, traced in {t_dt:.3f} ms")
+    del seg, dout
     mat = torch.from_numpy(workloads.city_materials(w.n_tris, 0)).cuda()
     refl = torch.from_numpy(workloads.REFLECTION).cuda()
     res["energy"] = {"k0": workloads.free_space_k0(), "reflection": workloads.REFLECTION.tolist(),
