@@ -18,7 +18,10 @@ Times with HIP events on the launching stream:
   * the chains with the energy stop rule of Sec. III-B (rt_trace_energy) at
     several thresholds: per-facet materials (ground concrete, other facets
     concrete / glass / metal 0.8 / 0.15 / 0.05), illustrative power
-    reflection coefficients, free-space constant at 2.4 GHz.
+    reflection coefficients, free-space constant at 2.4 GHz;
+  * beside them, the CPU checker (test infrastructure, all host threads) on a
+    seeded 65,536-ray sample of the launch: its chains, its chains with the
+    energy rule, its reception test (64 field points) and its diffraction.
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -37,12 +40,63 @@ FP64_OPS_PER_TEST = 30
 BYTES_PER_SEGMENT = 32 + 16  # stored segment ray + its hit record
 
 
+def cpu_checker(w, delta, n_sample, say):
+    """The CPU checker (test infrastructure) on a seeded sample of the same
+    launch, all host threads: its float64 chains with the energy rule, its
+    receiving-sphere test of those chains against 64 field points, and its
+    diffraction of them (16 directions).  Rates in segments per second."""
+    import os
+    import time as _t
+
+    import oracle
+    from oracle import diffraction, reception
+    from rtgen import workloads
+    threads = min(16, os.cpu_count() or 1)
+    rng = np.random.default_rng(5)
+    pick = np.sort(rng.choice(w.n_rays, size=min(n_sample, w.n_rays), replace=False))
+    rays = w.rays[pick]
+    tree = oracle.build_tree(w.tris, oracle.SplitParams(alpha=0.4, src=w.tx))
+    out = {"threads": threads, "sample_rays": int(rays.shape[0])}
+    t0 = _t.perf_counter()
+    ch = oracle.bounces(w.tris, rays, w.max_bounces, tree=tree, nthreads=threads)
+    t_ch = _t.perf_counter() - t0
+    segs = int(np.sum(np.minimum(ch.n_hits + 1, w.max_bounces)))
+    out["chains_msegments_s"] = round(segs / t_ch / 1e6, 3)
+    mat = workloads.city_materials(w.n_tris, 0)
+    t0 = _t.perf_counter()
+    che, pw = oracle.bounces_energy(w.tris, rays, w.max_bounces, mat, workloads.REFLECTION,
+                                    workloads.free_space_k0(), 1e-10, tree=tree, nthreads=threads,
+                                    segments=False)
+    t_e = _t.perf_counter() - t0
+    stopped = (pw < 1e-10) & (che.n_hits > 0)
+    segs_e = int(np.sum(np.where(stopped, che.n_hits, np.minimum(che.n_hits + 1, w.max_bounces))))
+    out["energy_1e-10_msegments_s"] = round(segs_e / t_e / 1e6, 3)
+    pts = workloads.field_points(w.tris, 400.0, 64, 164)
+    t0 = _t.perf_counter()
+    reception.receive(ch.seg, ch.id, ch.t, pts, delta)
+    t_r = _t.perf_counter() - t0
+    out["reception_64_msegments_s"] = round(segs / t_r / 1e6, 3)
+    nbr = diffraction.wedges(w.tris)
+    t0 = _t.perf_counter()
+    nd = diffraction.diffract(w.tris, nbr, ch.seg, ch.id, ch.t, delta,
+                              diffraction.cone_table(16)).size
+    t_d = _t.perf_counter() - t0
+    out["diffraction_msegments_s"] = round(segs / t_d / 1e6, 3)
+    out["diffracted_rays"] = int(nd)
+    out["segments"] = segs
+    say("cpu checker:", out)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--receivers", default="1,16,64,256")
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--dedup-receivers", type=int, default=64)
     ap.add_argument("--thresholds", default="1e-9,1e-10,1e-11,0")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU checker's timings")
+    ap.add_argument("--cpu-rays", type=int, default=65536,
+                    help="seeded sample of the launch the CPU checker runs on")
     a = ap.parse_args()
     import torch
 
@@ -160,6 +214,8 @@ def main():
             "mrays_s": round(segs_e / (t * 1e-3) / 1e6, 1)}
         say(f"energy stop at {thr:g}: {t:.3f} ms, {segs_e} segments, "
             f"{float(stopped.double().mean().item()):.3f} stopped by energy")
+    if not a.no_cpu:
+        res["cpu_checker"] = cpu_checker(w, delta, a.cpu_rays, say)
     print(json.dumps(res), flush=True)
 
 

@@ -26,8 +26,13 @@ TRACE_SRC = os.path.join(HERE, "csrc", "rt_trace.hip")
 
 
 def source_sha1(path: str = TRACE_SRC) -> str:
-    with open(path, "rb") as f:
-        return hashlib.sha1(f.read()).hexdigest()[:12]
+    """SHA-1 (12 hex digits) of the trace kernel's source and of the internal
+    header it compiles with."""
+    h = hashlib.sha1()
+    for p in (path, os.path.join(os.path.dirname(path), "rt_internal.h")):
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:12]
 
 
 def counter_values(directory: str, counter: str) -> dict:
