@@ -185,12 +185,36 @@ __device__ int diffract_hit(const DiffArgs& A, int64_t ray, int order, int64_t f
   const double dn = sqrt(dot3(d, d));
   const double l = L + T * dn;
   const double rho = l * A.delta / sqrt(3.0);
+  // single-precision rejection: an edge whose float32 distance from the hit
+  // exceeds rho by 0.1 % plus 1e-4 of the coordinate scale (float32 rounding
+  // moves these distances by a few 1e-7 of it) cannot pass the float64 test
+  int maybe = 0;
+  {
+    const float px = fmaf(t, rb.x, ra.x), py = fmaf(t, rb.y, ra.y), pz = fmaf(t, rb.z, ra.z);
+    const float scale = fmaxf(fmaxf(fabsf(px), fabsf(py)), fabsf(pz)) + 1.0f;
+    const float r32 = (float)rho * 1.001f + 1e-4f * (scale + fmaxf(fmaxf(fabsf(tv[0]), fabsf(tv[1])),
+                                                                   fabsf(tv[2])));
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const float* ka = tv + 3 * k;
+      const float* kb = tv + 3 * ((k + 1) % 3);
+      const float ex = kb[0] - ka[0], ey = kb[1] - ka[1], ez = kb[2] - ka[2];
+      const float wx = px - ka[0], wy = py - ka[1], wz = pz - ka[2];
+      const float ee = ex * ex + ey * ey + ez * ez;
+      float sk = (wx * ex + wy * ey + wz * ez) / ee;
+      sk = fminf(fmaxf(sk, 0.0f), 1.0f);
+      const float qx = wx - sk * ex, qy = wy - sk * ey, qz = wz - sk * ez;
+      const bool far = qx * qx + qy * qy + qz * qz > r32 * r32;
+      if (!far) maybe |= 1 << k;   // NaN or overflow: kept for the float64 test
+    }
+  }
+  if (maybe == 0) return 0;
   int bk = -1;
   double bdist = 0.0;
   D3 q{}, e{}, a{};
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    if (A.nbr[3 * f + k] == -2) continue;
+    if (!((maybe >> k) & 1) || A.nbr[3 * f + k] == -2) continue;
     const D3 ak = pick(v0, v1, v2, k), bkv = pick(v0, v1, v2, (k + 1) % 3);
     const D3 ek = sub3(bkv, ak);
     double s = dot3(sub3(p, ak), ek) / dot3(ek, ek);
@@ -279,26 +303,47 @@ __device__ int diffract_hit(const DiffArgs& A, int64_t ray, int order, int64_t f
   return kept;
 }
 
+// One chain per lane; the wave steps through the segments together (lanes
+// whose chain has ended sit out), adds up its lanes' diffracted rays with a
+// wave scan and takes their slots with one atomic per wave and segment.
 __global__ __launch_bounds__(kDiffBlock) void k_diffract(const float4* __restrict__ seg,
                                                          const rt_hit* __restrict__ hits, int64_t n,
                                                          int max_b, DiffArgs A) {
   const int64_t i = (int64_t)blockIdx.x * kDiffBlock + threadIdx.x;
-  if (i >= n) return;
+  const int lane = threadIdx.x & 63;
+  bool alive = i < n;
   double L = 0.0;
   for (int b = 0; b < max_b; ++b) {
-    const int64_t k = (int64_t)b * n + i;
-    const int4 h = reinterpret_cast<const int4*>(hits)[k];
-    if (h.x < 0) break;
-    const float4 ra = seg[2 * k], rb = seg[2 * k + 1];
-    const float th = __int_as_float(h.y);
-    if (h.x < A.n_tris) {
-      const int kept = diffract_hit(A, i, b, h.x, ra, rb, th, L, false, 0);
-      if (kept > 0) {
-        const unsigned long long base = atomicAdd(A.count, (unsigned long long)kept);
-        diffract_hit(A, i, b, h.x, ra, rb, th, L, true, base);
+    if (__ballot(alive) == 0ull) break;
+    int kept = 0, fid = -1;
+    float4 ra = make_float4(0.f, 0.f, 0.f, 0.f), rb = ra;
+    float th = 0.f;
+    if (alive) {
+      const int64_t k = (int64_t)b * n + i;
+      const int4 h = reinterpret_cast<const int4*>(hits)[k];
+      if (h.x < 0) {
+        alive = false;
+      } else {
+        fid = h.x;
+        ra = seg[2 * k];
+        rb = seg[2 * k + 1];
+        th = __int_as_float(h.y);
+        if (fid < A.n_tris) kept = diffract_hit(A, i, b, fid, ra, rb, th, L, false, 0);
       }
     }
-    L += seg_path(th, rb.x, rb.y, rb.z);
+    int incl = kept;
+    for (int d = 1; d < 64; d <<= 1) {
+      const int y = __shfl_up(incl, d);
+      if (lane >= d) incl += y;
+    }
+    const int total = __shfl(incl, 63);
+    if (total > 0) {
+      unsigned long long base = 0;
+      if (lane == 63) base = atomicAdd(A.count, (unsigned long long)total);
+      base = __shfl(base, 63);
+      if (kept > 0) diffract_hit(A, i, b, fid, ra, rb, th, L, true, base + (incl - kept));
+    }
+    if (alive) L += seg_path(th, rb.x, rb.y, rb.z);
   }
 }
 
