@@ -174,3 +174,42 @@ def test_energy_receptions_are_those_of_the_launched_segments(city):
     assert kka == kkb and np.array_equal(ka["l"], kb["l"]) and np.array_equal(ka["dist"], kb["dist"])
     log(f"energy receptions: {a.size} of {rb.count()} fixed-order receptions")
     assert 0 < a.size < rb.count()
+
+
+def test_energy_edge_cases(city):
+    tris, _, src, mat = city
+    bvh = R.BVH(dev(tris), R.SplitParams(alpha=0.4, src=src))
+    # empty ray set
+    e = energy(mat, 1e-10, 0)
+    out, pl, nh = bvh.trace_energy(torch.empty((0, 8), dtype=torch.float32, device="cuda"), 4, e)
+    assert out.shape == (4, 0, 4)
+    # unknown materials reflect nothing: every chain stops at its first hit, as in the checker
+    rays = workloads.multiscene_rays(src, 4)
+    bad = np.full(tris.shape[0], 7, np.int32)
+    e = energy(bad, 1e-30, rays.shape[0])
+    out, pl, nh = bvh.trace_energy(dev(rays), 4, e)
+    hn = nh.cpu().numpy()
+    ch, pw = oracle.bounces_energy(tris, rays, 4, bad, workloads.REFLECTION, K0, 1e-30, nthreads=NTHREADS)
+    assert hn.max() == 1 and np.array_equal(hn, ch.n_hits)
+    assert np.all(e.power.cpu().numpy() == 0.0)
+
+
+@pytest.mark.slow
+def test_city24k_full_size_energy():
+    """The benchmark's launch (city24k, level 9, 6 segments) at the 1e-10
+    threshold: 20,000 sampled chains stop where the checker's stop."""
+    w = workloads.city24k()
+    mat = workloads.city_materials(w.n_tris, 0)
+    thr, nb = 1e-10, w.max_bounces
+    bvh = R.BVH(dev(w.tris), R.SplitParams(alpha=0.4, src=w.tx))
+    e = energy(mat, thr, w.n_rays)
+    d_rays = dev(w.rays)
+    out, _, nh = bvh.trace_energy(d_rays, nb, e)
+    out_f, _, _ = bvh.trace_bounces(d_rays, nb)
+    rng = np.random.default_rng(13)
+    pick = np.sort(rng.choice(w.n_rays, 20_000, replace=False))
+    st = stop_agreement(w.tris, w.rays[pick], mat, thr, nb, oracle.SplitParams(alpha=0.4, src=w.tx),
+                        out.cpu().numpy()[:, pick], nh.cpu().numpy()[pick],
+                        e.power.cpu().numpy()[pick], out_f.cpu().numpy()[:, pick])
+    log("city24k energy (sampled):", st)
+    assert st["agree"] > 0.98 * st["rays"] and st["stopped_by_energy"] > 0.05
