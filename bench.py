@@ -102,8 +102,9 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: the path has no multi-GPU mode "
-              "(rays are independent; see the sharding notes of the design)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the path has no multi-GPU mode (rays are "
+              "independent, so each GPU would trace its own slice of the rays with the whole "
+              "tree; no collective is needed)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
