@@ -71,6 +71,25 @@ def load_traffic(workload_name):
     return rec.get("hbm_bytes_per_launch")
 
 
+# Vector instruction issue of the chip: 256 CUs x 4 SIMDs, one wave64
+# instruction every 4 cycles per SIMD (16 lanes a cycle, no packed FP32), 2.4 GHz.
+VALU_ISSUE_PER_S = 256 * 4 * 2.4e9 / 4
+
+
+def load_sq(workload_name):
+    """Vector instructions per trace launch (binary nodes, the benchmark's
+    tree) from a committed SQ counter run on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "trace_sq_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_source_sha1") != kernel_source_hash() or rec.get("workload") != workload_name:
+        return None
+    g = rec["groups"][0]
+    return {"valu_wave_instr": g["SQ_INSTS_VALU"], "vmem_rd_wave_instr": g["SQ_INSTS_VMEM_RD"]}
+
+
 def probe_ceilings(R, torch):
     """Streaming-read bandwidth (GB/s) from working sets that stay in each
     XCD's L2 (2 MiB read whole by every work-group), in the Infinity Cache
@@ -175,6 +194,7 @@ def main():
     alg_bytes = segments * (RAY_BYTES + HIT_BYTES) + nodes_total * NODE_BYTES + tests_total * FACET_BYTES
     achieved = alg_bytes / (trace_mean_ms * 1e-3) / 1e9
     traffic = load_traffic(w.name)
+    sq = load_sq(w.name)
     info = bvh.info()
 
     if args.copy_mib:
@@ -214,6 +234,9 @@ def main():
             "alg_bytes_per_launch": alg_bytes,
             "measured_ceilings_gbs": ceilings,
             "frac_of_measured_l2": (round(achieved / ceilings["l2"], 4) if ceilings else None),
+            "valu_wave_instr_per_launch": (sq["valu_wave_instr"] if sq else None),
+            "valu_issue_frac": (round(sq["valu_wave_instr"] / (trace_mean_ms * 1e-3 * VALU_ISSUE_PER_S), 4)
+                                if sq else None),
         },
         "segments_per_step": segments,
         "trace_only_mrays_s": round(segments / (trace_mean_ms * 1e-3) / 1e6, 2),
