@@ -6,7 +6,10 @@
  * launched rays through it: a ray enters only the bounding volumes it meets
  * (Sec. III-B), keeps the nearest facet hit inside its action range
  * [tmin, tmax], and may be re-launched as a specular reflection up to a set
- * number of segments (Sec. III-B, reflection order).
+ * number of segments (Sec. III-B, reflection order).  Around the chains:
+ * batched launches of many queries (trees, ray sets), receiving spheres at
+ * field points (Sec. III-C, Eq. (4)), the energy stop rule and edge
+ * diffraction (Sec. III-B).
  *
  * Conventions shared by every call:
  *   - All array arguments are DEVICE pointers (HBM) unless a comment says

@@ -10,6 +10,18 @@ paper_2208_10008_amd._build``) -- there is no CPU fallback.
 
 Low-level functions keep the C names (:func:`rt_build`, :func:`rt_trace`,
 :func:`rt_trace_bounces`, ...); :class:`BVH` wraps a handle.
+
+Typical use (all tensors on the GPU)::
+
+    bvh = BVH(tris, SplitParams(alpha=0.4, src=tx))          # Eq. (2) tree for this Tx
+    out, path_len, n_hits = bvh.trace_bounces(rays, 6)       # reflection chains
+    rx = Receivers(points, delta, cap=1 << 16)               # receiving spheres, Eq. (4)
+    bvh.trace_receive(rays, 6, rx); rx.dedup(out, 6)         # ... and one record per path
+    e = Energy(material, refl, Energy.k0_for(2.4e9), 1e-10)  # energy stop rule
+    bvh.trace_energy(rays, 6, e, receivers=rx)
+    nbr = rt_wedges(tris)                                    # diffracting edges
+    rec, count = rt_diffract_segments(tris, nbr, seg, out, 6, delta, cone, cap)
+    batch = Batch(64); batch.set(queries); batch.autotune(); batch.launch()
 """
 from __future__ import annotations
 
