@@ -421,7 +421,7 @@ def test_quantized_bounds_are_conservative(city, tmp_path):
         checked = 0
         for b in internal[nodes["depth"][internal] % 2 == 0]:
             w = tidx[b]
-            meta = u[w, 3]
+            meta = int(u[w, 3])          # Python int: the exponent bytes minus 127 may be negative
             e = np.array([(meta & 255) - 127, ((meta >> 8) & 255) - 127, ((meta >> 16) & 255) - 127])
             mask = meta >> 24
             kids = []
