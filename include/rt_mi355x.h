@@ -369,7 +369,8 @@ int rt_bvh_download(const rt_bvh* b, rt_node_rec* nodes, int64_t node_cap, int32
  *   RT_NODE_Q4, 64 B: float ox, oy, oz; uint32 meta = (ex + 127) | (ey + 127) << 8 |
  *                 (ez + 127) << 16 | mask << 24; uint8 qlox[4], qloy[4], qloz[4], qhix[4],
  *                 qhiy[4], qhiz[4]; 8 bytes 0; int32 ref[4].  Child c's volume is
- *                 lo = fmaf(q_lo, 2^e, o), hi = fmaf(q_hi, 2^e, o) per axis (float32).
+ *                 lo = o + q_lo 2^e, hi = o + q_hi 2^e per axis in exact (real)
+ *                 arithmetic, which contains the child's float32 volume; e >= -64.
  * A reference r >= 0 is a node index, r < 0 a leaf whose facets start at
  * leaf-order position ~r.  Synchronises the device. */
 int rt_bvh_export_trace_nodes(const rt_bvh* b, void* host, int64_t* bytes);

@@ -1591,34 +1591,62 @@ __global__ void k_emit(const BNode* __restrict__ nodes, const BuildState* __rest
 
 __device__ inline float pow2f(int e) { return __int_as_float((e + 127) << 23); }  // e in [-126, 127]
 
-// Per-axis exponent: smallest e with fmaf(255, 2^e, lo) >= hi, the decode
-// expression of the traversal kernel.
+// The 8-bit bounds are exact: the child plane of code q is lo + q 2^e in real
+// arithmetic (the traversal crosses it with one fused multiply-add and an
+// outward-rounded node term, which encloses the exact plane).  Containment
+// is therefore decided on the exact sum, from its float32 rounding
+// r = fmaf(q, 2^e, lo): rounding to nearest is monotone and v is a float, so
+// r < v implies lo + q 2^e <= v and r > v implies >= v; when r == v the
+// comparison holds only if the sum is exact, i.e. r - lo == q 2^e, checked in
+// double with the subtraction's own rounding error (two-sum) required zero.
+// Exponents stay in [kQExpMin, 127] so that 2^e / d remains a normal float.
+constexpr int kQExpMin = -64;
+
+__device__ inline bool sum_exact(float q, float sc, float lo, float r) {
+  const double a = r, b = -(double)lo;
+  const double s = a + b;
+  const double bb = s - a;
+  const double err = (a - (s - bb)) + (b - bb);
+  return err == 0.0 && s == (double)q * (double)sc;
+}
+// lo + q sc <= v exactly
+__device__ inline bool dec_le(int q, float sc, float lo, float v) {
+  const float r = fmaf((float)q, sc, lo);
+  return r < v || (r == v && sum_exact((float)q, sc, lo, r));
+}
+// lo + q sc >= v exactly
+__device__ inline bool dec_ge(int q, float sc, float lo, float v) {
+  const float r = fmaf((float)q, sc, lo);
+  return r > v || (r == v && sum_exact((float)q, sc, lo, r));
+}
+
+// Per-axis exponent: smallest e with lo + 255 2^e >= hi.
 __device__ inline int quant_exp(float lo, float hi) {
-  int e = -126;
+  int e = kQExpMin;
   const float ext = hi - lo;
   if (ext > 0.f) {
     int x;
     frexpf(ext / 255.f, &x);  // ext / 255 < 2^x
-    e = max(-126, min(127, x - 1));
+    e = max(kQExpMin, min(127, x - 1));
   }
-  while (e < 127 && fmaf(255.f, pow2f(e), lo) < hi) ++e;
-  while (e > -126 && fmaf(255.f, pow2f(e - 1), lo) >= hi) --e;
+  while (e < 127 && !dec_ge(255, pow2f(e), lo, hi)) ++e;
+  while (e > kQExpMin && dec_ge(255, pow2f(e - 1), lo, hi)) --e;
   return e;
 }
-// Largest q with decode(q) <= v (q in [0, 255]); decode(0) = lo <= v.
+// Largest q with lo + q sc <= v (q in [0, 255]; q = 0 qualifies: lo <= v).
 __device__ inline unsigned quant_lo(float v, float lo, float sc) {
   int q = (int)floorf((v - lo) / sc);
   q = max(0, min(255, q));
-  while (q > 0 && fmaf((float)q, sc, lo) > v) --q;
-  while (q < 255 && fmaf((float)(q + 1), sc, lo) <= v) ++q;
+  while (q > 0 && !dec_le(q, sc, lo, v)) --q;
+  while (q < 255 && dec_le(q + 1, sc, lo, v)) ++q;
   return (unsigned)q;
 }
-// Smallest q with decode(q) >= v; decode(255) >= the parent's hi >= v.
+// Smallest q with lo + q sc >= v (q = 255 qualifies: it reaches the parent's hi).
 __device__ inline unsigned quant_hi(float v, float lo, float sc) {
   int q = (int)ceilf((v - lo) / sc);
   q = max(0, min(255, q));
-  while (q < 255 && fmaf((float)q, sc, lo) < v) ++q;
-  while (q > 0 && fmaf((float)(q - 1), sc, lo) >= v) --q;
+  while (q < 255 && !dec_ge(q, sc, lo, v)) ++q;
+  while (q > 0 && dec_ge(q - 1, sc, lo, v)) --q;
   return (unsigned)q;
 }
 

@@ -19,7 +19,9 @@
 namespace rt {
 namespace {
 
-constexpr float kBig = 1e30f;  // stand-in for 1/0 in the slab test
+// Stand-in for 1/0 in the slab test: a power of two, so that o * kBig is
+// exact and a zero direction component needs no rounding margin.
+constexpr float kBig = 0x1p100f;
 // Slab far distances grow by 2 * gamma(3) so rounding never rejects a volume
 // the exact ray meets (Ize, "Robust BVH ray traversal", JCGT 2013).
 constexpr float kFarGrow = 1.0f + 2.0f * (3.0f * 5.9604645e-8f) / (1.0f - 3.0f * 5.9604645e-8f);
@@ -27,6 +29,14 @@ constexpr float kFarGrow = 1.0f + 2.0f * (3.0f * 5.9604645e-8f) / (1.0f - 3.0f *
 struct RayPre {
   float ox, oy, oz, dx, dy, dz;
   float ix, iy, iz;  // 1/d (kBig for a zero component)
+  // Fused-slab offsets: a plane at coordinate p is crossed at
+  // fma(p, i, a), with a = -o * i rounded down for the plane the ray enters
+  // first and up for the one it leaves by, so the single rounding of the
+  // fused form can only widen the interval.  For the 4-wide float32 nodes
+  // a0 / a1 belong to the lo / hi planes; for the 8-bit nodes, which pick
+  // the entry and exit planes by the ray's signs, a0 is -o i rounded down
+  // and a1 rounded up.
+  float a0x, a1x, a0y, a1y, a0z, a1z;
   float tmin, tmax;
   int kx, ky, kz;    // axis permutation of the watertight test
   float sx, sy, sz;  // its shear constants
@@ -36,6 +46,25 @@ __device__ inline float sel(float x, float y, float z, int k) {
   return k == 0 ? x : (k == 1 ? y : z);
 }
 
+// Offsets of one axis.  a = fl(-o i) and its rounding error e = -o i - a,
+// which one fused multiply-add gives exactly; the lo-plane offset of a ray
+// with i > 0 is the float nearest below or at -o i and its hi-plane offset
+// the float nearest above or at it (the reverse for i < 0), so
+// fma(p, i, offset), rounded once, errs from the exact (p - o) i only by u
+// of its own size (u = 2^-24) -- the relative error the far-distance growth
+// already covers -- plus at most one ulp of o i toward the outside.  A zero
+// component has i = kBig, a power of two: the product is exact (e = 0).
+template <bool BY_SIGN>
+__device__ inline void offsets(float o, float i, float& a0, float& a1) {
+  const float a = -(o * i);
+  const float e = fmaf(-o, i, -a);
+  const float down = e < 0.f ? nextafterf(a, -INFINITY) : a;
+  const float up = e > 0.f ? nextafterf(a, INFINITY) : a;
+  a0 = BY_SIGN || i > 0.f ? down : up;
+  a1 = BY_SIGN || i > 0.f ? up : down;
+}
+
+template <int FMT>
 __device__ inline RayPre prepare(float ox, float oy, float oz, float dx, float dy, float dz,
                                  float tmin, float tmax) {
   RayPre r;
@@ -44,6 +73,12 @@ __device__ inline RayPre prepare(float ox, float oy, float oz, float dx, float d
   r.ix = dx != 0.f ? 1.f / dx : kBig;
   r.iy = dy != 0.f ? 1.f / dy : kBig;
   r.iz = dz != 0.f ? 1.f / dz : kBig;
+  if constexpr (FMT != RT_NODE_BIN2) {
+    constexpr bool kBySign = FMT == RT_NODE_Q4;
+    offsets<kBySign>(ox, r.ix, r.a0x, r.a1x);
+    offsets<kBySign>(oy, r.iy, r.a0y, r.a1y);
+    offsets<kBySign>(oz, r.iz, r.a0z, r.a1z);
+  }
   r.tmin = tmin;
   r.tmax = tmax;
   float ax = fabsf(dx), ay = fabsf(dy), az = fabsf(dz);
@@ -60,12 +95,24 @@ __device__ inline RayPre prepare(float ox, float oy, float oz, float dx, float d
 }
 
 // Closed slab test of one box against [tlo, thi]; returns the entry distance
-// through tnear.
+// through tnear.  FUSED crosses each plane with one fused multiply-add and
+// the ray's rounded offsets (six fewer operations per box, six more
+// registers per ray): the wide nodes, whose child tests dominate their
+// visits, use it; the binary nodes keep (p - o) / d, whose lower register
+// count keeps one more wave per SIMD resident.
+template <bool FUSED>
 __device__ inline bool slab(const RayPre& r, float lox, float hix, float loy, float hiy,
                             float loz, float hiz, float tlo, float thi, float& tnear) {
-  float x0 = (lox - r.ox) * r.ix, x1 = (hix - r.ox) * r.ix;
-  float y0 = (loy - r.oy) * r.iy, y1 = (hiy - r.oy) * r.iy;
-  float z0 = (loz - r.oz) * r.iz, z1 = (hiz - r.oz) * r.iz;
+  float x0, x1, y0, y1, z0, z1;
+  if constexpr (FUSED) {
+    x0 = fmaf(lox, r.ix, r.a0x); x1 = fmaf(hix, r.ix, r.a1x);
+    y0 = fmaf(loy, r.iy, r.a0y); y1 = fmaf(hiy, r.iy, r.a1y);
+    z0 = fmaf(loz, r.iz, r.a0z); z1 = fmaf(hiz, r.iz, r.a1z);
+  } else {
+    x0 = (lox - r.ox) * r.ix; x1 = (hix - r.ox) * r.ix;
+    y0 = (loy - r.oy) * r.iy; y1 = (hiy - r.oy) * r.iy;
+    z0 = (loz - r.oz) * r.iz; z1 = (hiz - r.oz) * r.iz;
+  }
   float tn = fmaxf(fmaxf(fminf(x0, x1), fminf(y0, y1)), fmaxf(fminf(z0, z1), tlo));
   float tf = fminf(fminf(fmaxf(x0, x1), fmaxf(y0, y1)), fmaxf(z0, z1)) * kFarGrow;
   tf = fminf(tf, thi);
@@ -242,8 +289,11 @@ __device__ inline void cswap(float& ka, int& ra, float& kb, int& rb) {
   }
 }
 
-__device__ inline float pow2f(int e) { return __int_as_float((e + 127) << 23); }
 __device__ inline float qbyte(unsigned w, int c) { return (float)((w >> (8 * c)) & 255u); }
+// x moved by at least one unit in the last place: down for step -2^-23, up
+// for +2^-23 (|x| 2^-23 is one ulp of x or more, and the rounding of the
+// fused result cannot come back past it); 0 stays 0.
+__device__ inline float outward(float x, float step) { return fmaf(fabsf(x), step, x); }
 
 // Tests the facets of one leaf (positions ~node .. the one tagged last).
 template <bool STATS>
@@ -293,8 +343,8 @@ __device__ __forceinline__ Hit closest(const void* __restrict__ nodes, const TFa
         if (STATS) ++nvis;
         const TNode nd = static_cast<const TNode*>(nodes)[node];
         float n0, n1;
-        const bool h0 = slab(r, nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.c.x, nd.c.y, r.tmin, h.t, n0);
-        const bool h1 = slab(r, nd.b.x, nd.b.y, nd.b.z, nd.b.w, nd.c.z, nd.c.w, r.tmin, h.t, n1);
+        const bool h0 = slab<false>(r, nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.c.x, nd.c.y, r.tmin, h.t, n0);
+        const bool h1 = slab<false>(r, nd.b.x, nd.b.y, nd.b.z, nd.b.w, nd.c.z, nd.c.w, r.tmin, h.t, n1);
         if (h0 && h1) {
           const bool first0 = n0 <= n1;
           st.push(first0 ? nd.d.y : nd.d.x);
@@ -346,31 +396,43 @@ __device__ __forceinline__ Hit closest(const void* __restrict__ nodes, const TFa
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           float tn;
-          const bool hit = ((mask >> c) & 1u) &&
-                           slab(r, lx[c], hx[c], ly[c], hy[c], lz[c], hz[c], r.tmin, h.t, tn);
-          key[c] = hit ? tn : INFINITY;
+          const bool in = slab<true>(r, lx[c], hx[c], ly[c], hy[c], lz[c], hz[c], r.tmin, h.t, tn);
+          key[c] = (in & (((mask >> c) & 1u) != 0u)) ? tn : INFINITY;
           ref[c] = rr[c];
         }
       } else {
         const QNode4 nd = static_cast<const QNode4*>(nodes)[node];
         const unsigned meta = __float_as_uint(nd.h.w);
         mask = meta >> 24;
-        const float sx = pow2f((int)(meta & 255u) - 127);
-        const float sy = pow2f((int)((meta >> 8) & 255u) - 127);
-        const float sz = pow2f((int)((meta >> 16) & 255u) - 127);
+        // The builder guarantees that the exact (unrounded) h + q 2^e encloses
+        // every child.  A child plane is crossed at q (2^e i) + (h i - o i):
+        // 2^e i is exact (a power of two times i), and the node term is formed
+        // once per axis from the ray's directed offsets and moved outward by
+        // one more unit in the last place for its own rounding, so one fused
+        // multiply-add per plane errs only by u of the crossing distance.
+        const float six = __uint_as_float((meta << 23) & 0x7f800000u) * r.ix;
+        const float siy = __uint_as_float((meta << 15) & 0x7f800000u) * r.iy;
+        const float siz = __uint_as_float((meta << 7) & 0x7f800000u) * r.iz;
+        const float cnx = outward(fmaf(nd.h.x, r.ix, r.a0x), -0x1p-23f);
+        const float cfx = outward(fmaf(nd.h.x, r.ix, r.a1x), 0x1p-23f);
+        const float cny = outward(fmaf(nd.h.y, r.iy, r.a0y), -0x1p-23f);
+        const float cfy = outward(fmaf(nd.h.y, r.iy, r.a1y), 0x1p-23f);
+        const float cnz = outward(fmaf(nd.h.z, r.iz, r.a0z), -0x1p-23f);
+        const float cfz = outward(fmaf(nd.h.z, r.iz, r.a1z), 0x1p-23f);
+        // the bytes of the plane each child is entered by and left by
+        const bool px = r.ix > 0.f, py = r.iy > 0.f, pz = r.iz > 0.f;
+        const unsigned enx = px ? nd.qa.x : nd.qa.w, exx = px ? nd.qa.w : nd.qa.x;
+        const unsigned eny = py ? nd.qa.y : nd.qb.x, exy = py ? nd.qb.x : nd.qa.y;
+        const unsigned enz = pz ? nd.qa.z : nd.qb.y, exz = pz ? nd.qb.y : nd.qa.z;
         const int rr[4] = {nd.ref.x, nd.ref.y, nd.ref.z, nd.ref.w};
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-          // decode exactly as the builder verified: fmaf(q, 2^e, origin)
-          const float lx = fmaf(qbyte(nd.qa.x, c), sx, nd.h.x);
-          const float ly = fmaf(qbyte(nd.qa.y, c), sy, nd.h.y);
-          const float lz = fmaf(qbyte(nd.qa.z, c), sz, nd.h.z);
-          const float hx = fmaf(qbyte(nd.qa.w, c), sx, nd.h.x);
-          const float hy = fmaf(qbyte(nd.qb.x, c), sy, nd.h.y);
-          const float hz = fmaf(qbyte(nd.qb.y, c), sz, nd.h.z);
-          float tn;
-          const bool hit = ((mask >> c) & 1u) && slab(r, lx, hx, ly, hy, lz, hz, r.tmin, h.t, tn);
-          key[c] = hit ? tn : INFINITY;
+          const float tnx = fmaf(qbyte(enx, c), six, cnx), tfx = fmaf(qbyte(exx, c), six, cfx);
+          const float tny = fmaf(qbyte(eny, c), siy, cny), tfy = fmaf(qbyte(exy, c), siy, cfy);
+          const float tnz = fmaf(qbyte(enz, c), siz, cnz), tfz = fmaf(qbyte(exz, c), siz, cfz);
+          const float tn = fmaxf(fmaxf(tnx, tny), fmaxf(tnz, r.tmin));
+          const float tf = fminf(fminf(fminf(tfx, tfy), tfz) * kFarGrow, h.t);
+          key[c] = ((tn <= tf) & (((mask >> c) & 1u) != 0u)) ? tn : INFINITY;
           ref[c] = rr[c];
         }
       }
@@ -479,7 +541,7 @@ __device__ __forceinline__ void trace_chains(const void* __restrict__ tn, const 
       seg[2 * ((int64_t)b * n + i)] = make_float4(ox, oy, oz, tmin);
       seg[2 * ((int64_t)b * n + i) + 1] = make_float4(dx, dy, dz, tmax);
     }
-    const RayPre r = prepare(ox, oy, oz, dx, dy, dz, tmin, tmax);
+    const RayPre r = prepare<FMT>(ox, oy, oz, dx, dy, dz, tmin, tmax);
     Hit h = closest<FMT, STATS>(tn, tf, r, skip, stack, nvis, ntest);
     N2 nrm;
     if (h.id >= 0) {
