@@ -8,6 +8,7 @@
 #include <new>
 #include <string>
 
+#include "rt_build_plan.h"
 #include "rt_internal.h"
 
 namespace rt {

@@ -32,6 +32,7 @@
 #include <string>
 #include <vector>
 
+#include "rt_build_plan.h"
 #include "rt_internal.h"
 
 namespace rt {

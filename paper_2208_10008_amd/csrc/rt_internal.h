@@ -120,14 +120,10 @@ struct Buffers {
   int64_t bytes = 0;
 };
 
-// build sizes shared by the allocator and the build
-constexpr int kChunk = 512;     // facets per big-node chunk
-constexpr int kBigNode = 1024;  // nodes above this many facets are split chunk-wise
-constexpr int kRegNode = 16;    // subtrees at or below this many facets stay in registers
+// build sizes shared by the allocator and the build (the phase thresholds
+// and the capacities derived from them are in rt_build_plan.h)
 constexpr int kScanBlock = 1024;
 constexpr int kBinReplicas = 8; // copies of a big node's bins that chunks add into
-inline int64_t item_capacity(int64_t n) { return n / kChunk + n / (kBigNode + 1) + 2; }
-inline int64_t anode_capacity(int64_t n) { return n / (kBigNode + 1) + 1; }
 // bytes of one bin set: counts, ordered-int boxes and (optionally) ordered-int64
 // centroid bounds for 3 axes of B bins
 __host__ __device__ inline size_t align8(size_t x) { return (x + 7) & ~size_t(7); }
