@@ -132,3 +132,25 @@ def test_check_request_limits():
     assert check_request(Request(0, 0, 65, 0.0, rays=rays(3)), {0: None})
     assert check_request(Request(0, 0, 1, 0.0, tx=(0, 0, 1), n_rays=11), {0: None}, 10)
     assert check_request(Request(0, 0, 1, 0.0, tx=(0, 0, 1), n_rays=10), {0: None}, 10) == ""
+
+
+def test_consumer_sees_every_finished_query_and_can_release_results():
+    from paper_2208_10008_amd.serve import count_segments, release_results
+    seen = []
+
+    def consumer(r):
+        assert r.status == DONE and r.out is not None
+        r.n_hits[:] = np.arange(r.n) % (r.max_bounces + 2)   # chains of every length
+        want = int(np.minimum(r.n_hits + 1, r.max_bounces).sum())
+        assert count_segments(r) == want
+        release_results(r)
+        assert r.segments == want and r.out is None and r.n_hits is None
+        seen.append(r.rid)
+
+    ex = HostExecutor(polls=2)
+    srv = Server(ex, 10 ** 9, 2, 3, on_done=consumer)
+    reqs = [srv.submit(0, 1 + k % 4, rays(10 + k)) for k in range(7)]
+    srv.run_until_idle()
+    assert sorted(seen) == [r.rid for r in reqs]
+    m = srv.metrics()
+    assert m["queries"] == 7 and m["segments"] == sum(r.segments for r in reqs)
