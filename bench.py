@@ -5,13 +5,18 @@ A step is one pass of the whole path for one transmitter: build the BVH of
 the scene with the Eq. (2) split for that transmitter (Sec. II-B, II-C), then
 trace the launched rays with up to 6 specular bounces (Sec. III-B).  Scene and
 rays are seeded synthetic inputs already resident in HBM.  The value is
-traced segments (primary + every re-launched segment) per second of step time,
-in millions.
+traced segments (primary + every re-launched segment) per second of the timed
+steps, in millions.  Consecutive steps alternate between two trees, output
+sets and streams (--pipeline 2, the default), so one transmitter's build runs
+while the previous transmitter's rays are traced; every step still builds its
+whole tree and traces all its rays.  The serial rate (--pipeline 1: each step
+waits for the previous one) is reported beside it.
 
 Prints one JSON line.  Extra fields: the trace kernel's roofline (algorithmic
 bytes from the instrumented kernel's node and facet counts), the CPU checker's
 rate on the same workload, the traditional (alpha = 1) vs improved split
-comparison, facet tests and nodes per ray, per-step latency percentiles.
+comparison, facet tests and nodes per ray, per-step latency percentiles
+(device time from a step's first kernel to its last).
 """
 from __future__ import annotations
 
@@ -42,8 +47,12 @@ def parse():
     ap.add_argument("--alpha", type=float, default=0.4)
     ap.add_argument("--max-leaf", type=int, default=4)
     ap.add_argument("--node-format", default="bin2", choices=["bin2", "f4", "q4"])
+    ap.add_argument("--pipeline", type=int, default=2, choices=[1, 2],
+                    help="trees / streams that consecutive steps alternate between")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--no-serial", action="store_true",
+                    help="skip the serial reference steps (profiling runs)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one plain device copy of this size (counter calibration)")
     ap.add_argument("--no-probe", action="store_true",
@@ -141,42 +150,49 @@ def main():
     tris = torch.from_numpy(w.tris).cuda()
     rays = torch.from_numpy(w.rays).cuda()
     n = w.n_rays
-    out = torch.empty((nb, n, 4), dtype=torch.int32, device="cuda")
-    path_len = torch.empty(n, dtype=torch.float64, device="cuda")
-    n_hits = torch.empty(n, dtype=torch.int32, device="cuda")
-    bvh = R.BVH(tris, params)
-    stream = torch.cuda.current_stream()
+    depth = args.pipeline
+    outs = [(torch.empty((nb, n, 4), dtype=torch.int32, device="cuda"),
+             torch.empty(n, dtype=torch.float64, device="cuda"),
+             torch.empty(n, dtype=torch.int32, device="cuda")) for _ in range(depth)]
+    out, path_len, n_hits = outs[0]
+    trees = [R.BVH(tris, params) for _ in range(depth)]
+    bvh = trees[0]
+    streams = [torch.cuda.Stream() for _ in range(depth)]  # default priority
 
-    def step(p, ev=None):
+    def step(k, p, d, ev=None):
+        """Step k on tree, outputs and stream k mod d: rebuild, then trace."""
+        i = k % d
+        s = streams[i]
         if ev is not None:
-            ev[0].record(stream)
-        R.rt_rebuild(bvh.handle, tris, p)
+            ev[0].record(s)
+        R.rt_rebuild(trees[i].handle, tris, p, stream=s)
         if ev is not None:
-            ev[1].record(stream)
-        R.rt_trace_bounces(bvh.handle, rays, nb, out, path_len, n_hits)
+            ev[1].record(s)
+        R.rt_trace_bounces(trees[i].handle, rays, nb, *outs[i], stream=s)
         if ev is not None:
-            ev[2].record(stream)
+            ev[2].record(s)
 
-    def timed(p, steps, warmup):
-        for _ in range(warmup):
-            step(p)
+    def timed(p, steps, warmup, d=1):
+        for k in range(warmup):
+            step(k, p, d)
         torch.cuda.synchronize()
         evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
-        wall = []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(steps):
-            s0 = time.perf_counter()
-            step(p, evs[k])
-            evs[k][2].synchronize()
-            wall.append(time.perf_counter() - s0)
+            step(k, p, d, evs[k])
         torch.cuda.synchronize()
         total = time.perf_counter() - t0
         build_ms = [e[0].elapsed_time(e[1]) for e in evs]
         trace_ms = [e[1].elapsed_time(e[2]) for e in evs]
-        return total, wall, build_ms, trace_ms
+        step_ms = [e[0].elapsed_time(e[2]) for e in evs]  # one step's latency on the device
+        return total, step_ms, build_ms, trace_ms
 
-    total, wall, build_ms, trace_ms = timed(params, args.steps, args.warmup)
+    total, step_lat, build_ms, trace_ms = timed(params, args.steps, args.warmup, depth)
+    serial = depth > 1 and not args.no_serial
+    if serial:
+        s_steps = max(5, args.steps // 3)
+        s_tot, _, s_build, s_trace = timed(params, s_steps, 1, 1)
     nh = n_hits.cpu().numpy()
     segments = int(np.minimum(nh + 1, nb).sum())
     ms_per_step = 1e3 * total / args.steps
@@ -225,6 +241,7 @@ def main():
             "tx": list(w.tx), "alpha": args.alpha, "max_leaf": args.max_leaf,
             "node_format": args.node_format,
             "step": "rt_rebuild (Eq. 2 BVH for this Tx) + rt_trace_bounces",
+            "pipeline": depth,
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -243,13 +260,20 @@ def main():
         "primary_mrays_s": round(n / (total / args.steps) / 1e6, 2),
         "build_ms": round(float(np.mean(build_ms)), 4),
         "trace_ms": round(trace_mean_ms, 4),
-        "latency_ms_p50": round(1e3 * float(np.percentile(wall, 50)), 4),
-        "latency_ms_p99": round(1e3 * float(np.percentile(wall, 99)), 4),
+        "latency_ms_p50": round(float(np.percentile(step_lat, 50)), 4),
+        "latency_ms_p99": round(float(np.percentile(step_lat, 99)), 4),
         "tri_tests_per_ray": round(tests_total / segments, 3),
         "nodes_per_ray": round(nodes_total / segments, 3),
         "tri_tests_per_primary_p50_p99": [int(np.percentile(st[:, 1], 50)), int(np.percentile(st[:, 1], 99))],
         "bvh": {"nodes": info.n_nodes, "depth": info.depth, "trace_bytes": info.trace_bytes},
     }
+    if serial:
+        result["serial"] = {
+            "steps": s_steps, "ms_per_step": round(1e3 * s_tot / s_steps, 4),
+            "mrays_s": round(segments / (s_tot / s_steps) / 1e6, 2),
+            "build_ms": round(float(np.mean(s_build)), 4),
+            "trace_ms": round(float(np.mean(s_trace)), 4),
+        }
 
     if not args.no_compare:
         fmts = {}
@@ -271,7 +295,7 @@ def main():
             "paper_claim": "20-35% less computation time than the traditional BVH "
                            "(hardware not stated in the paper)",
         }
-        step(params)  # leave the improved tree in place
+        step(0, params, 1)  # leave the improved tree in place
         torch.cuda.synchronize()
 
     if not args.no_cpu_baseline:
