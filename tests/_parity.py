@@ -21,7 +21,8 @@ BAND = 5e-3   # reception: relative distance from the Eq. (4) threshold treated 
 
 
 def _rel(a, s):
-    return a / np.maximum(np.abs(s), 1e-3)
+    with np.errstate(invalid="ignore"):  # inf - inf (two misses) gives nan, which compares false
+        return a / np.maximum(np.abs(s), 1e-3)
 
 
 def _edge_near(u, v):
