@@ -251,6 +251,7 @@ def main():
             "alg_bytes_per_launch": alg_bytes,
             "measured_ceilings_gbs": ceilings,
             "frac_of_measured_l2": (round(achieved / ceilings["l2"], 4) if ceilings else None),
+            "frac_of_measured_mall": (round(achieved / ceilings["mall"], 4) if ceilings else None),
             "valu_wave_instr_per_launch": (sq["valu_wave_instr"] if sq else None),
             "valu_issue_frac": (round(sq["valu_wave_instr"] / (trace_mean_ms * 1e-3 * VALU_ISSUE_PER_S), 4)
                                 if sq else None),

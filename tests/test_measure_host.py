@@ -100,3 +100,12 @@ def test_bench_reads_records_only_for_the_current_source(tmp_path, monkeypatch):
     with open(tmp_path / "profiles" / "trace_traffic.json", "w") as f:
         json.dump(rec, f)
     assert bench.load_traffic("w") is None
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr and r.stdout == ""
