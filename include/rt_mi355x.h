@@ -379,8 +379,9 @@ void rt_bvh_destroy(rt_bvh* b); /* NULL is a no-op; waits for the device */
 
 /* ---- batched trace (Sec. III-B for many transmitters and scenes) ---------
  * Many queries -- each a resident tree, a set of launched rays and a bounce
- * limit -- traced in one launch per node format.  Every query's results are
- * exactly those of rt_trace_bounces on the same tree and rays: they do not
+ * limit, optionally field points -- traced in one launch per node format and
+ * kind.  Every query's results are exactly those of rt_trace_bounces (with
+ * field points: rt_trace_receive) on the same tree and rays: they do not
  * depend on the other queries, their order or the launch shape. */
 typedef struct rt_query {
   const rt_bvh* bvh;    /* resident tree (built, not destroyed while a launch is pending) */
@@ -391,6 +392,11 @@ typedef struct rt_query {
   rt_hit* out;          /* device [max_bounces][n], 16-byte aligned */
   double* path_len;     /* device [n] (float64 path length per chain) or NULL */
   int32_t* n_hits;      /* device [n] (facets hit per chain) or NULL */
+  const rt_receivers* receivers; /* host struct of device buffers (Sec. III-C, Eq. (4)): every
+                                    traced segment is tested as in rt_trace_receive, the count
+                                    cleared by each launch; read by rt_batch_set (the buffers
+                                    must outlive the launches); NULL: no reception test.
+                                    With field points n must be < 2^31. */
 } rt_query;
 
 #define RT_BATCH_DIRECT 0 /* one work-group per 64-ray batch of every query */

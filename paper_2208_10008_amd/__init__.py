@@ -75,7 +75,7 @@ class rt_query(ctypes.Structure):
     _fields_ = [("bvh", ctypes.c_void_p), ("rays", ctypes.c_void_p), ("n", ctypes.c_int64),
                 ("max_bounces", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("out", ctypes.c_void_p), ("path_len", ctypes.c_void_p),
-                ("n_hits", ctypes.c_void_p)]
+                ("n_hits", ctypes.c_void_p), ("receivers", ctypes.c_void_p)]
 
 
 class rt_batch_config(ctypes.Structure):
@@ -604,8 +604,12 @@ class Batch:
         self.queries = []
 
     def set(self, queries):
+        """Queries: dicts with bvh, rays, max_bounces and optionally out,
+        path_len, n_hits (allocated when missing) and receivers (a Receivers:
+        the query's chains are traced with the reception test)."""
         import torch
         arr = (rt_query * max(len(queries), 1))()
+        held = []  # rt_receivers structs, alive until rt_batch_set has read them
         for k, q in enumerate(queries):
             rays = _dev(q["rays"], torch.float32, 8, "rays")
             n, nb = rays.shape[0], int(q["max_bounces"])
@@ -622,6 +626,9 @@ class Batch:
             arr[k].out = q["out"].data_ptr()
             arr[k].path_len = q["path_len"].data_ptr()
             arr[k].n_hits = q["n_hits"].data_ptr()
+            if q.get("receivers") is not None:
+                held.append(q["receivers"].c())
+                arr[k].receivers = ctypes.addressof(held[-1])
         _check(load().rt_batch_set(self.handle, arr, len(queries)))
         self.queries = queries
         return [arr[k].status for k in range(len(queries))]

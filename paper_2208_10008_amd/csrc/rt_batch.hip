@@ -1,6 +1,8 @@
 // Batched trace (declared in include/rt_mi355x.h): many queries -- trees,
-// ray sets, bounce limits -- in one launch per node format, optionally
-// through a captured hipGraph, with a small autotuner over launch shapes.
+// ray sets, bounce limits, optionally field points -- in one launch per node
+// format (and per kind: plain chains, or chains with the reception test),
+// optionally through a captured hipGraph, with a small autotuner over launch
+// shapes.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -15,8 +17,9 @@ namespace rt {
 namespace {
 
 constexpr int kFormats = 3;
+constexpr int kGroups = 2 * kFormats;  // group 2 f + r: node format f, r = 1 with field points
 
-struct Group {  // the queries of one node format, contiguous in the table
+struct Group {  // the queries of one node format and kind, contiguous in the table
   int first = 0, count = 0, depth = 0;
   int64_t batches = 0;
 };
@@ -32,6 +35,9 @@ int query_error(const rt_query& q) {
     if ((q.path_len && !aligned(q.path_len, 8)) || (q.n_hits && !aligned(q.n_hits, 4)))
       return RT_EINVAL;
   }
+  if (q.receivers) {  // reception records hold 32-bit ray numbers
+    if (check_rx(q.receivers, "rt_batch_set") != RT_OK || q.n > INT32_MAX) return RT_EINVAL;
+  }
   return RT_OK;
 }
 
@@ -45,15 +51,15 @@ struct rt_batch {
   int device = 0;
   BatchQuery* staging = nullptr;  // pinned host [cap]
   BatchQuery* table = nullptr;    // device [cap]
-  unsigned long long* queues = nullptr;  // device [kFormats]
+  unsigned long long* queues = nullptr;  // device [kGroups]
   hipEvent_t copied = nullptr;    // the last launch has read the staging table
   hipStream_t capture = nullptr;  // private stream the graph is captured on
   bool pending = false;
   std::vector<rt_query> queries;  // the valid queries, as given
-  Group groups[kFormats];
+  Group groups[kGroups];
   int nq = 0;
   rt_batch_config cfg{RT_BATCH_DIRECT, 0, RT_ORDER_COST, 0};
-  int grid[kFormats] = {0, 0, 0};  // persistent work-groups per format (QUEUE mode)
+  int grid[kGroups] = {0, 0, 0, 0, 0, 0};  // persistent work-groups per group (QUEUE mode)
   // captured graph and the shape it was captured for
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -74,8 +80,10 @@ void free_batch(rt_batch* b) {
   b->graph = nullptr;
 }
 
-// Lays the valid queries out in the staging table: grouped by node format,
-// in the configured order, each with its first work-group number.
+// Lays the valid queries out in the staging table: grouped by node format
+// and kind, in the configured order, each with its first work-group number.
+// A query with field points and no rays still takes its place (its count is
+// cleared by the launch).
 void layout(rt_batch* b) {
   std::vector<int> idx(b->queries.size());
   for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
@@ -87,13 +95,16 @@ void layout(rt_batch* b) {
     });
   }
   int pos = 0;
-  for (int f = 0; f < kFormats; ++f) {
-    Group& g = b->groups[f];
+  for (int gi = 0; gi < kGroups; ++gi) {
+    const int f = gi / 2;
+    const bool rv = gi % 2;
+    Group& g = b->groups[gi];
     g = Group();
     g.first = pos;
     for (int i : idx) {
       const rt_query& q = b->queries[i];
-      if (q.bvh->info.node_format != f || q.n == 0) continue;
+      if (q.bvh->info.node_format != f || (q.receivers != nullptr) != rv) continue;
+      if (q.n == 0 && !rv) continue;
       BatchQuery e;
       std::memset(&e, 0, sizeof(e));
       const Buffers& B = q.bvh->buf;
@@ -106,6 +117,7 @@ void layout(rt_batch* b) {
       e.n = q.n;
       e.first_batch = g.batches;
       e.max_b = q.max_bounces;
+      if (rv) e.recv = recv_args(q.receivers);
       b->staging[pos++] = e;
       ++g.count;
       g.batches += (q.n + 63) / 64;
@@ -117,36 +129,43 @@ void layout(rt_batch* b) {
 
 std::vector<int64_t> shape_key(const rt_batch* b) {
   std::vector<int64_t> k = {b->cfg.mode, b->cfg.grid, b->cfg.order, b->nq};
-  for (int f = 0; f < kFormats; ++f) {
-    k.push_back(b->groups[f].first);
-    k.push_back(b->groups[f].count);
-    k.push_back(b->groups[f].depth);
-    k.push_back(b->groups[f].batches);
+  for (int gi = 0; gi < kGroups; ++gi) {
+    k.push_back(b->groups[gi].first);
+    k.push_back(b->groups[gi].count);
+    k.push_back(b->groups[gi].depth);
+    k.push_back(b->groups[gi].batches);
   }
   return k;
 }
 
 // Persistent work-group counts for the QUEUE mode (before any capture).
 void plan_grids(rt_batch* b) {
-  for (int f = 0; f < kFormats; ++f) {
-    const Group& g = b->groups[f];
-    b->grid[f] = 0;
+  for (int gi = 0; gi < kGroups; ++gi) {
+    const Group& g = b->groups[gi];
+    b->grid[gi] = 0;
     if (b->cfg.mode == RT_BATCH_QUEUE && g.count)
-      b->grid[f] = b->cfg.grid > 0 ? b->cfg.grid : trace_resident_groups(f, g.depth);
+      b->grid[gi] = b->cfg.grid > 0 ? b->cfg.grid : trace_resident_groups(gi / 2, gi % 2, g.depth);
   }
 }
 
-// The table upload and one launch per node format present, on stream s.
+// The table upload, the reception counts cleared, and one launch per group
+// present, on stream s.
 int enqueue(rt_batch* b, hipStream_t s) {
   int rc = check_hip(hipMemcpyAsync(b->table, b->staging, sizeof(BatchQuery) * std::max(b->nq, 1),
                                     hipMemcpyHostToDevice, s),
                      "rt_batch_launch: table upload");
   if (rc != RT_OK) return rc;
-  for (int f = 0; f < kFormats; ++f) {
-    const Group& g = b->groups[f];
+  for (int gi = 1; gi < kGroups; gi += 2) {
+    const Group& g = b->groups[gi];
     if (g.count == 0) continue;
-    rc = launch_trace_batch(b->table + g.first, g.count, g.batches, f, g.depth, b->grid[f],
-                            b->queues + f, s);
+    rc = launch_batch_clear_counts(b->table + g.first, g.count, s);
+    if (rc != RT_OK) return rc;
+  }
+  for (int gi = 0; gi < kGroups; ++gi) {
+    const Group& g = b->groups[gi];
+    if (g.count == 0 || g.batches == 0) continue;
+    rc = launch_trace_batch(b->table + g.first, g.count, g.batches, gi / 2, gi % 2, g.depth,
+                            b->grid[gi], b->queues + gi, s);
     if (rc != RT_OK) return rc;
   }
   return RT_OK;
@@ -217,7 +236,7 @@ int rt_batch_create(int32_t max_queries, rt_batch** out) {
   if (rc == RT_OK)
     rc = check_hip(hipMalloc((void**)&b->table, sizeof(BatchQuery) * max_queries), "hipMalloc");
   if (rc == RT_OK)
-    rc = check_hip(hipMalloc((void**)&b->queues, sizeof(unsigned long long) * kFormats), "hipMalloc");
+    rc = check_hip(hipMalloc((void**)&b->queues, sizeof(unsigned long long) * kGroups), "hipMalloc");
   if (rc == RT_OK) rc = check_hip(hipEventCreateWithFlags(&b->copied, hipEventDisableTiming), "event");
   if (rc == RT_OK) rc = check_hip(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking), "stream");
   if (rc != RT_OK) {
@@ -283,8 +302,9 @@ int rt_batch_autotune(rt_batch* b, int32_t reps, hipStream_t s, float* ms) {
     cands.push_back({RT_BATCH_QUEUE, 0, order, 0});
   }
   int res = 0;
-  for (int f = 0; f < kFormats; ++f)
-    if (b->groups[f].count) res = std::max(res, trace_resident_groups(f, RT_MAX_DEPTH));
+  for (int gi = 0; gi < kGroups; ++gi)
+    if (b->groups[gi].count)
+      res = std::max(res, trace_resident_groups(gi / 2, gi % 2, RT_MAX_DEPTH));
   cands.push_back({RT_BATCH_QUEUE, 2 * std::max(res, 1), RT_ORDER_COST, 0});
   hipEvent_t e0 = nullptr, e1 = nullptr;
   int rc = check_hip(hipEventCreate(&e0), "event");

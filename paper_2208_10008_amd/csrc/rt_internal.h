@@ -158,7 +158,18 @@ __device__ __host__ inline double o2d(long long i) {
   return d;
 }
 
-// One query of a batched trace launch (device table entry, 64 bytes + pad).
+// ---- ray reception (Sec. III-C, Eq. (4)) ----
+struct RecvArgs {
+  const double* pos;            // [n_rx][3]
+  rt_reception* rec;            // [cap]
+  unsigned long long* count;    // receptions found
+  int64_t cap;
+  double delta;
+  int32_t n_rx;
+  int32_t pad;
+};
+
+// One query of a batched trace launch (device table entry).
 struct alignas(16) BatchQuery {
   const void* nodes;     // traversal nodes of the query's tree
   const TFacet* facets;  // its leaf-ordered facets
@@ -170,18 +181,9 @@ struct alignas(16) BatchQuery {
   int64_t first_batch;   // first work-group number of the query in the launch
   int32_t max_b;
   int32_t pad[3];
+  RecvArgs recv;         // field points of a reception launch (n_rx 0 otherwise)
 };
 
-// ---- ray reception (Sec. III-C, Eq. (4)) ----
-struct RecvArgs {
-  const double* pos;            // [n_rx][3]
-  rt_reception* rec;            // [cap]
-  unsigned long long* count;    // receptions found
-  int64_t cap;
-  double delta;
-  int32_t n_rx;
-  int32_t pad;
-};
 
 // Path length t |d| of a segment in float64, without contraction, so that
 // the tracer and the reception kernels accumulate the same bits.
@@ -292,10 +294,17 @@ int launch_trace(const Buffers& B, int node_format, int depth, const float* rays
 // Batched launch over table[0 .. nq) (device), all of one node format;
 // total_batches work-groups, or `grid` persistent work-groups taking batches
 // from `queue` when grid > 0.  depth: deepest tree of the queries.
+// recv: the queries carry field points, every traced segment is tested
+// (their counts must have been cleared, see launch_batch_clear_counts).
 int launch_trace_batch(const BatchQuery* table, int nq, int64_t total_batches, int node_format,
-                       int depth, int grid, unsigned long long* queue, hipStream_t s);
+                       bool recv, int depth, int grid, unsigned long long* queue, hipStream_t s);
+// Clears the reception counts of table[0 .. nq) (a kernel: safe in a captured graph).
+int launch_batch_clear_counts(const BatchQuery* table, int nq, hipStream_t s);
 // Work-groups of the trace kernel that fit the device at once for this format and depth.
-int trace_resident_groups(int node_format, int depth);
+int trace_resident_groups(int node_format, bool recv, int depth);
+// receive.hip: argument checks of a receivers struct and its kernel arguments.
+int check_rx(const rt_receivers* rx, const char* who);
+RecvArgs recv_args(const rt_receivers* rx);
 // Chains with the reception test of every segment (receive.hip zeroes the count first).
 int launch_trace_receive(const Buffers& B, int node_format, int depth, const float* rays,
                          int64_t n, int32_t max_bounces, rt_hit* out, double* path_len,

@@ -137,22 +137,6 @@ __global__ void k_dd_mark(rt_reception* __restrict__ rec, const unsigned long lo
   rec[k].keep = keep;
 }
 
-int check_rx(const rt_receivers* rx, const char* who) {
-  const std::string w(who);
-  if (!rx) return set_error(RT_EINVAL, w + ": receivers struct is NULL");
-  if (rx->n < 0 || rx->reserved != 0) return set_error(RT_EINVAL, w + ": n must be >= 0, reserved 0");
-  if (rx->n > 0 && (!rx->pos || !aligned_to(rx->pos, 8)))
-    return set_error(RT_EINVAL, w + ": pos must be non-NULL and 8-byte aligned");
-  if (!std::isfinite(rx->delta) || rx->delta < 0.0)
-    return set_error(RT_EINVAL, w + ": delta must be finite and >= 0");
-  if (rx->cap < 0 || rx->cap > INT32_MAX) return set_error(RT_EINVAL, w + ": cap outside 0..2^31-1");
-  if (rx->cap > 0 && (!rx->rec || !aligned_to(rx->rec, 16)))
-    return set_error(RT_EINVAL, w + ": rec must be non-NULL and 16-byte aligned");
-  if (!rx->count || !aligned_to(rx->count, 8))
-    return set_error(RT_EINVAL, w + ": count must be non-NULL and 8-byte aligned");
-  return RT_OK;
-}
-
 int check_energy(const rt_energy* e) {
   if (!e) return set_error(RT_EINVAL, "rt_trace_energy: energy struct is NULL");
   if (!e->material || !aligned_to(e->material, 4))
@@ -170,7 +154,25 @@ int check_energy(const rt_energy* e) {
   return RT_OK;
 }
 
-RecvArgs args_of(const rt_receivers* rx) {
+}  // namespace
+
+int check_rx(const rt_receivers* rx, const char* who) {
+  const std::string w(who);
+  if (!rx) return set_error(RT_EINVAL, w + ": receivers struct is NULL");
+  if (rx->n < 0 || rx->reserved != 0) return set_error(RT_EINVAL, w + ": n must be >= 0, reserved 0");
+  if (rx->n > 0 && (!rx->pos || !aligned_to(rx->pos, 8)))
+    return set_error(RT_EINVAL, w + ": pos must be non-NULL and 8-byte aligned");
+  if (!std::isfinite(rx->delta) || rx->delta < 0.0)
+    return set_error(RT_EINVAL, w + ": delta must be finite and >= 0");
+  if (rx->cap < 0 || rx->cap > INT32_MAX) return set_error(RT_EINVAL, w + ": cap outside 0..2^31-1");
+  if (rx->cap > 0 && (!rx->rec || !aligned_to(rx->rec, 16)))
+    return set_error(RT_EINVAL, w + ": rec must be non-NULL and 16-byte aligned");
+  if (!rx->count || !aligned_to(rx->count, 8))
+    return set_error(RT_EINVAL, w + ": count must be non-NULL and 8-byte aligned");
+  return RT_OK;
+}
+
+RecvArgs recv_args(const rt_receivers* rx) {
   RecvArgs a;
   a.pos = rx->pos;
   a.rec = rx->rec;
@@ -182,7 +184,6 @@ RecvArgs args_of(const rt_receivers* rx) {
   return a;
 }
 
-}  // namespace
 }  // namespace rt
 
 using namespace rt;
@@ -197,7 +198,7 @@ int rt_trace_receive(const rt_bvh* b, const float* rays, int64_t n, int32_t max_
   rc = check_rx(rx, "rt_trace_receive");
   if (rc != RT_OK) return rc;
   if (n > INT32_MAX) return set_error(RT_EINVAL, "rt_trace_receive: n must be < 2^31");
-  RecvArgs a = args_of(rx);
+  RecvArgs a = recv_args(rx);
   hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, s, a.count);
   rc = check_hip(hipGetLastError(), "reception count reset");
   if (rc != RT_OK || n == 0) return rc;
@@ -217,7 +218,7 @@ int rt_trace_energy(const rt_bvh* b, const float* rays, int64_t n, int32_t max_b
     rc = check_rx(rx, "rt_trace_energy");
     if (rc != RT_OK) return rc;
     if (n > INT32_MAX) return set_error(RT_EINVAL, "rt_trace_energy: n must be < 2^31 with receivers");
-    a = args_of(rx);
+    a = recv_args(rx);
     hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, s, a.count);
     rc = check_hip(hipGetLastError(), "reception count reset");
     if (rc != RT_OK) return rc;
@@ -244,7 +245,7 @@ int rt_receive_segments(const float* seg_rays, const rt_hit* hits, int64_t n, in
     return set_error(RT_EINVAL, "rt_receive_segments: max_bounces must lie in 1..64");
   if (n > 0 && (!seg_rays || !hits || !aligned_to(seg_rays, 16) || !aligned_to(hits, 16)))
     return set_error(RT_EINVAL, "rt_receive_segments: seg_rays and hits must be non-NULL, 16-byte aligned");
-  RecvArgs a = args_of(rx);
+  RecvArgs a = recv_args(rx);
   hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, s, a.count);
   rc = check_hip(hipGetLastError(), "reception count reset");
   if (rc != RT_OK || n == 0 || a.n_rx == 0) return rc;

@@ -648,8 +648,10 @@ __global__ __launch_bounds__(kBlock) void k_trace_energy(const void* __restrict_
 // Many queries (trees, ray sets, bounce limits) in one launch: work-group g
 // finds its query by binary search over the queries' first batch numbers and
 // traces that query's batch g - first.  Queries of one launch share the node
-// format; each brings its own tree.
-template <int FMT>
+// format and whether they carry field points (RECV: every traced segment is
+// tested against the query's own field points, as in k_trace_recv); each
+// brings its own tree.
+template <int FMT, bool RECV>
 __global__ __launch_bounds__(kBlock) void k_trace_batch(const BatchQuery* __restrict__ q, int nq) {
   extern __shared__ int s_stack[];
   const int64_t g = blockIdx.x;
@@ -662,14 +664,14 @@ __global__ __launch_bounds__(kBlock) void k_trace_batch(const BatchQuery* __rest
   const BatchQuery Q = q[lo];
   const int64_t local = g - Q.first_batch;
   if (local * kBlock >= Q.n) return;
-  trace_chains<FMT, true, false, false, false>(Q.nodes, Q.facets, Q.rays, Q.n, Q.max_b, Q.out,
-                                               Q.path_len, Q.n_hits, nullptr, nullptr, nullptr, 0,
-                                               local * kBlock, s_stack + threadIdx.x, RecvArgs{});
+  trace_chains<FMT, true, false, false, RECV>(Q.nodes, Q.facets, Q.rays, Q.n, Q.max_b, Q.out,
+                                              Q.path_len, Q.n_hits, nullptr, nullptr, nullptr, 0,
+                                              local * kBlock, s_stack + threadIdx.x, Q.recv);
 }
 
 // Persistent form of the batched launch: each wave takes batch numbers from
 // a global counter (one atomic per 64 rays) until all are done.
-template <int FMT>
+template <int FMT, bool RECV>
 __global__ __launch_bounds__(kBlock) void k_trace_batch_q(const BatchQuery* __restrict__ q, int nq,
                                                           int64_t total,
                                                           unsigned long long* __restrict__ queue) {
@@ -689,13 +691,19 @@ __global__ __launch_bounds__(kBlock) void k_trace_batch_q(const BatchQuery* __re
     const BatchQuery Q = q[lo];
     const int64_t local = (int64_t)g - Q.first_batch;
     if (local * kBlock >= Q.n) continue;
-    trace_chains<FMT, true, false, false, false>(Q.nodes, Q.facets, Q.rays, Q.n, Q.max_b, Q.out,
-                                                 Q.path_len, Q.n_hits, nullptr, nullptr, nullptr, 0,
-                                                 local * kBlock, s_stack + threadIdx.x, RecvArgs{});
+    trace_chains<FMT, true, false, false, RECV>(Q.nodes, Q.facets, Q.rays, Q.n, Q.max_b, Q.out,
+                                                Q.path_len, Q.n_hits, nullptr, nullptr, nullptr, 0,
+                                                local * kBlock, s_stack + threadIdx.x, Q.recv);
   }
 }
 
 __global__ void k_queue_reset(unsigned long long* q) { *q = 0ull; }
+
+// Clears the reception counts of the queries that have one.
+__global__ void k_batch_clear_counts(const BatchQuery* __restrict__ q, int nq) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nq && q[i].recv.count) *q[i].recv.count = 0ull;
+}
 
 // Stack entries a ray can need: one per binary level below the root, or up
 // to three per 4-wide level.  Sizing the LDS stack to the tree keeps the
@@ -748,47 +756,60 @@ void launch_fmt(const Buffers& B, int depth, const float* rays, int64_t n, int m
   }
 }
 
-template <int FMT>
+template <int FMT, bool RECV>
 void launch_batch_fmt(const BatchQuery* table, int nq, int64_t total, int depth, int grid,
                       unsigned long long* queue, hipStream_t s) {
   const size_t lds = stack_bytes<FMT>(depth);
   if (grid > 0) {
     hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(1), 0, s, queue);
-    hipLaunchKernelGGL((k_trace_batch_q<FMT>), dim3((unsigned)std::min<int64_t>(grid, total)),
+    hipLaunchKernelGGL((k_trace_batch_q<FMT, RECV>), dim3((unsigned)std::min<int64_t>(grid, total)),
                        dim3(kBlock), lds, s, table, nq, total, queue);
   } else {
-    hipLaunchKernelGGL((k_trace_batch<FMT>), dim3((unsigned)total), dim3(kBlock), lds, s, table, nq);
+    hipLaunchKernelGGL((k_trace_batch<FMT, RECV>), dim3((unsigned)total), dim3(kBlock), lds, s,
+                       table, nq);
   }
 }
 
-template <int FMT>
+template <int FMT, bool RECV>
 int resident_fmt(int depth) {
   int dev = 0, cus = 0, per_cu = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_trace_batch_q<FMT>, kBlock,
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_trace_batch_q<FMT, RECV>, kBlock,
                                                      stack_bytes<FMT>(depth));
   return std::max(1, cus * std::max(1, per_cu));
 }
 
 }  // namespace
 
-int launch_trace_batch(const BatchQuery* table, int nq, int64_t total, int node_format, int depth,
-                       int grid, unsigned long long* queue, hipStream_t s) {
+int launch_trace_batch(const BatchQuery* table, int nq, int64_t total, int node_format, bool recv,
+                       int depth, int grid, unsigned long long* queue, hipStream_t s) {
   if (nq <= 0 || total <= 0) return RT_OK;
-  switch (node_format) {
-    case RT_NODE_F4: launch_batch_fmt<RT_NODE_F4>(table, nq, total, depth, grid, queue, s); break;
-    case RT_NODE_Q4: launch_batch_fmt<RT_NODE_Q4>(table, nq, total, depth, grid, queue, s); break;
-    default: launch_batch_fmt<RT_NODE_BIN2>(table, nq, total, depth, grid, queue, s); break;
+  switch (node_format * 2 + (recv ? 1 : 0)) {
+    case 2 * RT_NODE_F4: launch_batch_fmt<RT_NODE_F4, false>(table, nq, total, depth, grid, queue, s); break;
+    case 2 * RT_NODE_F4 + 1: launch_batch_fmt<RT_NODE_F4, true>(table, nq, total, depth, grid, queue, s); break;
+    case 2 * RT_NODE_Q4: launch_batch_fmt<RT_NODE_Q4, false>(table, nq, total, depth, grid, queue, s); break;
+    case 2 * RT_NODE_Q4 + 1: launch_batch_fmt<RT_NODE_Q4, true>(table, nq, total, depth, grid, queue, s); break;
+    case 2 * RT_NODE_BIN2 + 1: launch_batch_fmt<RT_NODE_BIN2, true>(table, nq, total, depth, grid, queue, s); break;
+    default: launch_batch_fmt<RT_NODE_BIN2, false>(table, nq, total, depth, grid, queue, s); break;
   }
   return check_hip(hipGetLastError(), "batch trace launch");
 }
 
-int trace_resident_groups(int node_format, int depth) {
-  switch (node_format) {
-    case RT_NODE_F4: return resident_fmt<RT_NODE_F4>(depth);
-    case RT_NODE_Q4: return resident_fmt<RT_NODE_Q4>(depth);
-    default: return resident_fmt<RT_NODE_BIN2>(depth);
+int launch_batch_clear_counts(const BatchQuery* table, int nq, hipStream_t s) {
+  if (nq <= 0) return RT_OK;
+  hipLaunchKernelGGL(k_batch_clear_counts, dim3((nq + 255) / 256), dim3(256), 0, s, table, nq);
+  return check_hip(hipGetLastError(), "batch reception count reset");
+}
+
+int trace_resident_groups(int node_format, bool recv, int depth) {
+  switch (node_format * 2 + (recv ? 1 : 0)) {
+    case 2 * RT_NODE_F4: return resident_fmt<RT_NODE_F4, false>(depth);
+    case 2 * RT_NODE_F4 + 1: return resident_fmt<RT_NODE_F4, true>(depth);
+    case 2 * RT_NODE_Q4: return resident_fmt<RT_NODE_Q4, false>(depth);
+    case 2 * RT_NODE_Q4 + 1: return resident_fmt<RT_NODE_Q4, true>(depth);
+    case 2 * RT_NODE_BIN2 + 1: return resident_fmt<RT_NODE_BIN2, true>(depth);
+    default: return resident_fmt<RT_NODE_BIN2, false>(depth);
   }
 }
 

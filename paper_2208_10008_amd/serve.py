@@ -4,7 +4,9 @@ Scenes and their trees stay resident in HBM, and so does a table of launch
 directions (a level-9 icosphere, first-appearance order).  A query is
 (scene, transmitter, ray count, bounce depth) -- its rays are the first
 `count` table directions from the transmitter, made on the device -- or
-(scene, host rays, bounce depth); it is checked when it is
+(scene, host rays, bounce depth); it may also carry field points (Sec. III-C,
+Eq. (4)), and then only its receptions and hit counts come back instead of
+every hit record.  It is checked when it is
 submitted (a malformed query gets an error status and never enters the
 queue), waits in arrival order, and is admitted when an execution slot is
 free and its device memory (rays, hits, path lengths, hit counts) fits the
@@ -37,6 +39,7 @@ from typing import Callable, Optional
 
 import numpy as np
 
+from . import RECEPTION_DTYPE
 from . import rt_rays_from_directions as _rays_from_directions
 
 def _align(x: int, a: int = 256) -> int:
@@ -46,6 +49,8 @@ def _align(x: int, a: int = 256) -> int:
 # request states
 PENDING, RUNNING, DONE, FAILED, CANCELLED = "pending", "running", "done", "failed", "cancelled"
 MAX_RAYS = 1 << 26
+MAX_RECEIVERS = 1 << 16
+MAX_RECORDS = 1 << 24
 
 
 @dataclasses.dataclass
@@ -57,6 +62,9 @@ class Request:
     tx: Optional[tuple] = None            # transmitter of generated rays
     n_rays: int = 0                       # ... and their count
     rays: Optional[np.ndarray] = None     # or float32 [n, 8] host rays
+    receivers: Optional[np.ndarray] = None  # float64 [m, 3] field points: receptions come back
+    delta: float = 0.0                      # ... the launch's ray spacing (radians, Eq. (4))
+    rec_cap: int = 0                        # ... reception records kept (the count may exceed it)
     status: str = PENDING
     error: str = ""
     admitted: float = math.nan
@@ -65,6 +73,8 @@ class Request:
     path_len: Optional[np.ndarray] = None  # float64 [n]
     n_hits: Optional[np.ndarray] = None    # int32 [n]
     segments: int = -1                     # traced segments, once counted
+    receptions: Optional[np.ndarray] = None  # RECEPTION_DTYPE, the first min(count, rec_cap)
+    n_receptions: int = -1                   # receptions found (may exceed rec_cap)
 
     @property
     def n(self) -> int:
@@ -72,10 +82,17 @@ class Request:
 
     def device_bytes(self) -> int:
         """Device memory the query holds while it runs."""
-        return self.n * (32 + 16 * self.max_bounces + 8 + 4)
+        b = self.n * (32 + 16 * self.max_bounces + 8 + 4)
+        if self.receivers is not None:
+            b += self.receivers.shape[0] * 24 + max(self.rec_cap, 1) * 32 + 8
+        return b
 
     def result_bytes(self) -> int:
-        """Pinned host memory its results take: hits, path lengths, hit counts."""
+        """Pinned host memory its results take: hits, path lengths and hit
+        counts, or (with field points) reception records, their count and
+        the hit counts."""
+        if self.receivers is not None:
+            return _align(max(self.rec_cap, 1) * 32) + _align(8) + _align(self.n * 4)
         return _align(self.n * 16 * self.max_bounces) + _align(self.n * 8) + _align(self.n * 4)
 
     @property
@@ -102,6 +119,18 @@ def check_request(req: Request, scenes, max_generated: int = MAX_RAYS) -> str:
             return "rays must be finite"
     if not 1 <= req.max_bounces <= 64:
         return "bounce depth must lie in 1..64"
+    if req.receivers is not None:
+        p = req.receivers
+        if not isinstance(p, np.ndarray) or p.dtype != np.float64 or p.ndim != 2 or p.shape[1] != 3:
+            return "field points must be float64 [m, 3]"
+        if not 1 <= p.shape[0] <= MAX_RECEIVERS:
+            return f"field point count must lie in 1..{MAX_RECEIVERS}"
+        if not np.isfinite(p).all():
+            return "field points must be finite"
+        if not (math.isfinite(req.delta) and req.delta >= 0.0):
+            return "ray spacing delta must be finite and >= 0"
+        if not 0 <= req.rec_cap <= MAX_RECORDS:
+            return f"reception capacity must lie in 0..{MAX_RECORDS}"
     return ""
 
 
@@ -184,41 +213,128 @@ class GpuExecutor:
         self.work = [None] * slots
 
     def launch(self, slot: int, reqs):
+        """One batch on the slot's stream.  Per kind of array the batch takes
+        one device allocation and one pinned host buffer, and each query a
+        slice of them (16-byte aligned), so the host work per query is a ray
+        launch and a table entry; results are copied back with one copy per
+        array kind and handed out as numpy views of the pinned buffers."""
+        from . import rt_receivers
         torch = self.torch
         s = self.streams[slot]
-        qs, host = [], []
+        plain = [r for r in reqs if r.receivers is None]
+        recv = [r for r in reqs if r.receivers is not None]
+        dev = {}
         with torch.cuda.stream(s):
+            def pool(name, count, dtype):
+                dev[name] = torch.empty(max(count, 1), dtype=dtype, device="cuda")
+                return dev[name]
+
+            n_all = sum(r.n for r in reqs)
+            rays = pool("rays", 8 * n_all, torch.float32)
+            # plain queries: hits, path lengths, hit counts (all copied back)
+            p_out = pool("p_out", sum(4 * r.n * r.max_bounces for r in plain), torch.int32)
+            p_pl = pool("p_pl", sum(r.n for r in plain), torch.float64)
+            p_nh = pool("p_nh", sum(r.n for r in plain), torch.int32)
+            # queries with field points: hits and path lengths stay on the device
+            r_out = pool("r_out", sum(4 * r.n * r.max_bounces for r in recv), torch.int32)
+            r_pl = pool("r_pl", sum(r.n for r in recv), torch.float64)
+            r_nh = pool("r_nh", sum(r.n for r in recv), torch.int32)
+            r_rec = pool("r_rec", sum(8 * max(r.rec_cap, 1) for r in recv), torch.int32)
+            r_cnt = pool("r_cnt", len(recv), torch.int64)
+            if recv:
+                pos_host = torch.from_numpy(np.concatenate([r.receivers for r in recv])).pin_memory()
+                r_pos = pool("r_pos", pos_host.numel(), torch.float64)
+                r_pos.copy_(pos_host.view(-1), non_blocking=True)
+                dev["pos_host"] = pos_host
+            qs, off = [], {"rays": 0, "p": 0, "po": 0, "r": 0, "ro": 0, "rec": 0, "pos": 0}
+            keep = []  # rt_receivers structs, read by Batch.set
             for r in reqs:
+                n, nb = r.n, r.max_bounces
+                ray = rays[8 * off["rays"]:8 * (off["rays"] + n)].view(n, 8)
+                off["rays"] += n
                 if r.rays is None:
-                    rays = _rays_from_directions(self.dirs, r.n_rays, r.tx, self.tmin, self.tmax,
-                                                 stream=s)
+                    _rays_from_directions(self.dirs, n, r.tx, self.tmin, self.tmax, rays=ray,
+                                          stream=s)
                 else:
-                    rays = torch.from_numpy(r.rays).pin_memory().to("cuda", non_blocking=True)
-                qs.append({"bvh": self.scenes[r.scene], "rays": rays, "max_bounces": r.max_bounces})
+                    ray.copy_(torch.from_numpy(r.rays).pin_memory(), non_blocking=True)
+                q = {"bvh": self.scenes[r.scene], "rays": ray, "max_bounces": nb}
+                if r.receivers is None:
+                    q["out"] = p_out[4 * off["po"]:4 * (off["po"] + n * nb)].view(nb, n, 4)
+                    q["path_len"] = p_pl[off["p"]:off["p"] + n]
+                    q["n_hits"] = p_nh[off["p"]:off["p"] + n]
+                    off["po"] += n * nb
+                    off["p"] += n
+                else:
+                    k = len(keep)
+                    m, cap = r.receivers.shape[0], max(r.rec_cap, 1)
+                    q["out"] = r_out[4 * off["ro"]:4 * (off["ro"] + n * nb)].view(nb, n, 4)
+                    q["path_len"] = r_pl[off["r"]:off["r"] + n]
+                    q["n_hits"] = r_nh[off["r"]:off["r"] + n]
+                    c = rt_receivers()
+                    c.pos = dev["r_pos"].data_ptr() + 24 * off["pos"]
+                    c.n, c.reserved, c.delta = m, 0, r.delta
+                    c.rec = r_rec.data_ptr() + 32 * off["rec"]
+                    c.cap = r.rec_cap
+                    c.count = r_cnt.data_ptr() + 8 * k
+                    keep.append(c)
+                    q["receivers"] = _Fixed(c)
+                    off["ro"] += n * nb
+                    off["r"] += n
+                    off["rec"] += cap
+                    off["pos"] += m
+                qs.append(q)
             self.batches[slot].set(qs)
             self.batches[slot].launch(stream=s)
 
-            def to_host(t):  # the query's own pinned buffer, filled on the slot's stream
+            def to_host(t):
                 h = torch.empty(t.shape, dtype=t.dtype, pin_memory=True)
                 h.copy_(t, non_blocking=True)
                 return h
-            for q in qs:
-                host.append((to_host(q["out"]), to_host(q["path_len"]), to_host(q["n_hits"])))
+            host = {"p_out": to_host(p_out), "p_pl": to_host(p_pl), "p_nh": to_host(p_nh)}
+            if recv:
+                host.update(r_nh=to_host(r_nh), r_rec=to_host(r_rec), r_cnt=to_host(r_cnt))
             ev = torch.cuda.Event()
             ev.record(s)
         self.events[slot] = ev
-        self.work[slot] = (reqs, qs, host)
+        self.work[slot] = (plain, recv, host, dev, keep)
 
     def poll(self, slot: int) -> bool:
         return self.events[slot] is not None and self.events[slot].query()
 
     def collect(self, slot: int):
-        reqs, qs, host = self.work[slot]
-        for r, (out, pl, nh) in zip(reqs, host):  # views of the query's pinned buffers
-            r.out, r.path_len, r.n_hits = out.numpy(), pl.numpy(), nh.numpy()
+        plain, recv, host, dev, keep = self.work[slot]
+        p, po = 0, 0
+        for r in plain:  # views of the batch's pinned buffers (they keep them alive)
+            n, nb = r.n, r.max_bounces
+            r.out = host["p_out"][4 * po:4 * (po + n * nb)].view(nb, n, 4).numpy()
+            r.path_len = host["p_pl"][p:p + n].numpy()
+            r.n_hits = host["p_nh"][p:p + n].numpy()
+            p += n
+            po += n * nb
+        q, rec = 0, 0
+        for k, r in enumerate(recv):
+            n, cap = r.n, max(r.rec_cap, 1)
+            r.n_receptions = int(host["r_cnt"][k])
+            got = min(r.n_receptions, r.rec_cap)
+            recs = host["r_rec"][8 * rec:8 * (rec + got)].view(got, 8).numpy()
+            r.receptions = recs.view(RECEPTION_DTYPE).reshape(-1)
+            r.n_hits = host["r_nh"][q:q + n].numpy()
+            q += n
+            rec += cap
         self.events[slot] = None
         self.work[slot] = None
-        return reqs
+        return plain + recv
+
+
+class _Fixed:
+    """A receivers argument for Batch.set built from pointers into pooled
+    device buffers."""
+
+    def __init__(self, c):
+        self._c = c
+
+    def c(self):
+        return self._c
 
 
 class Server:
@@ -246,10 +362,13 @@ class Server:
         self.stop_flag = False
 
     def submit(self, scene: int, max_bounces: int, rays: Optional[np.ndarray] = None,
-               tx=None, n_rays: int = 0) -> Request:
-        """A query: host rays, or a transmitter and a ray count."""
+               tx=None, n_rays: int = 0, receivers: Optional[np.ndarray] = None,
+               delta: float = 0.0, rec_cap: int = 0) -> Request:
+        """A query: host rays, or a transmitter and a ray count; with field
+        points (and the ray spacing delta), only receptions come back."""
         req = Request(next(self.ids), scene, int(max_bounces), self.clock(), tx=tx,
-                      n_rays=int(n_rays), rays=rays)
+                      n_rays=int(n_rays), rays=rays, receivers=receivers, delta=float(delta),
+                      rec_cap=int(rec_cap))
         err = check_request(req, self.ex.scenes, getattr(self.ex, "max_generated", MAX_RAYS))
         if err:  # never enters the queue
             req.status, req.error = FAILED, err
@@ -342,7 +461,8 @@ class Server:
                 "queue_depth_mean": round(float(np.mean(self.depth_samples or [0])), 2),
                 "queue_depth_max": int(max(self.depth_samples or [0])),
                 "admission_waits": self.sched.admission_waits,
-                "max_batches_in_flight": self.max_running}
+                "max_batches_in_flight": self.max_running,
+                "receptions": sum(max(r.n_receptions, 0) for r in done)}
 
 
 def count_segments(r: Request) -> int:
@@ -355,17 +475,26 @@ def release_results(r: Request):
     """Consumer for throughput runs: counts the query's segments and drops its
     result arrays, returning their pinned buffers to the pool."""
     r.segments = count_segments(r)
-    r.out = r.path_len = r.n_hits = None
+    r.out = r.path_len = r.n_hits = r.receptions = None
 
 
-def poisson_queries(duration: float, rate: float, seed: int = 0, scenes=range(8)):
-    """Config-5 query stream: Poisson arrivals; per query a scene (uniform), a
+def poisson_queries(duration: float, rate: float, seed: int = 0, scenes=range(8),
+                    receivers: int = 0, rec_cap: int = 1 << 14):
+    """The serving query stream: Poisson arrivals; per query a scene (uniform), a
     transmitter uniform over the scene outside buildings at 5-40 m, a ray
     count log-uniform in 10k-1M (icosphere prefix) and a bounce depth uniform
-    in 1-6.  Returns [(arrival_s, scene, tx, n_rays, max_bounces)]."""
-    from rtgen import scenes as sc, workloads
+    in 1-6.  Returns [(arrival_s, scene, tx, n_rays, max_bounces)]; with
+    `receivers` > 0 each entry also carries that many field points (drawn from
+    a pool of points outside buildings, 1.5 m up), the ray spacing delta of the
+    launch (the mean edge angle of the smallest icosphere level that holds
+    the rays) and a record capacity, as keyword arguments of Server.submit."""
+    from rtgen import icosphere, scenes as sc, workloads
     rng = np.random.default_rng(seed)
     geo = {s: workloads.multiscene_scene(s) for s in scenes}
+    pool, deltas = {}, {}
+    if receivers:
+        prng = np.random.default_rng(seed + 1)
+        pool = {s: sc.free_points(prng, geo[s][1], geo[s][0], 1.5, 512) for s in scenes}
     out, t = [], 0.0
     scene_ids = list(scenes)
     while True:
@@ -377,7 +506,15 @@ def poisson_queries(duration: float, rate: float, seed: int = 0, scenes=range(8)
         tx = sc.free_point(rng, half, tris, float(rng.uniform(5.0, 40.0)))
         n = int(round(10 ** rng.uniform(4.0, 6.0)))
         nb = int(rng.integers(1, 7))
-        out.append((t, s, tuple(float(x) for x in tx), n, nb))
+        entry = (t, s, tuple(float(x) for x in tx), n, nb)
+        if receivers:
+            lv = next(L for L in range(16) if icosphere.vertex_count(L) >= n)
+            if lv not in deltas:
+                deltas[lv] = float(icosphere.edge_angles(lv).mean())
+            pts = pool[s][rng.choice(pool[s].shape[0], receivers, replace=False)]
+            entry += ({"receivers": np.ascontiguousarray(pts), "delta": deltas[lv],
+                       "rec_cap": rec_cap},)
+        out.append(entry)
     return out
 
 
@@ -410,10 +547,12 @@ def run_stream(server: Server, stream, clock=time.perf_counter, progress=None):
             print(f"[serve] t={last - t0:.1f}s finished={len(server.finished)} "
                   f"pending={len(server.sched.pending)} running={len(server.running)}",
                   file=sys.stderr, flush=True)
-    for at, s, tx, n, nb in stream:
+    for item in stream:
+        at, s, tx, n, nb = item[:5]
+        extra = item[5] if len(item) > 5 else {}
         while clock() - t0 < at:
             time.sleep(max(0.0, min(1e-3, at - (clock() - t0))))
-        server.submit(s, nb, tx=tx, n_rays=n)
+        server.submit(s, nb, tx=tx, n_rays=n, **extra)
         report()
     while not server.idle():
         time.sleep(1e-3)
@@ -429,11 +568,14 @@ def main():
     ap.add_argument("--max-batch", type=int, default=64)
     ap.add_argument("--budget-gib", type=float, default=16.0)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--receivers", type=int, default=0,
+                    help="field points per query: only receptions and hit counts come back")
+    ap.add_argument("--rec-cap", type=int, default=1 << 14)
     a = ap.parse_args()
     import sys
     import torch
     t0 = time.perf_counter()
-    stream = poisson_queries(a.duration, a.rate, a.seed)
+    stream = poisson_queries(a.duration, a.rate, a.seed, receivers=a.receivers, rec_cap=a.rec_cap)
     print(f"[serve] {len(stream)} queries drawn", file=sys.stderr, flush=True)
     scenes = resident_scenes()
     torch.cuda.synchronize()
@@ -450,7 +592,9 @@ def main():
     run_stream(srv, stream, progress=5.0)
     m = srv.metrics()
     m.update({"workload": f"poisson {a.rate:g}/s for {a.duration:g} s over 8 scenes "
-                          f"(1k-200k facets), 10k-1M rays, 1-6 bounces",
+                          f"(1k-200k facets), 10k-1M rays, 1-6 bounces"
+                          + (f", {a.receivers} field points per query (receptions only)"
+                             if a.receivers else ""),
               "slots": a.slots, "max_batch": a.max_batch, "budget_gib": a.budget_gib,
               "setup_s": round(setup, 1)})
     print(json.dumps(m), flush=True)

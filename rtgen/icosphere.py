@@ -158,6 +158,10 @@ def edge_angles(level: int) -> np.ndarray:
     v = directions(level)
     f = faces(level)
     e = np.concatenate([f[:, [0, 1]], f[:, [1, 2]], f[:, [2, 0]]])
-    e = np.unique(np.sort(e, axis=1), axis=0)
+    e = np.sort(e, axis=1)
+    # one key per undirected edge; sorted unique keys list the edges in
+    # lexicographic (lo, hi) order
+    key = np.unique(e[:, 0] * np.int64(v.shape[0]) + e[:, 1])
+    e = np.stack([key // v.shape[0], key % v.shape[0]], 1)
     c = np.clip((v[e[:, 0]] * v[e[:, 1]]).sum(1), -1.0, 1.0)
     return np.arccos(c)

@@ -245,6 +245,23 @@ def free_point(tris_seed_rng, half, tris: np.ndarray, z) -> tuple:
             return (float(x), float(y), float(z))
 
 
+def free_points(rng, half, tris: np.ndarray, z, count: int) -> np.ndarray:
+    """`count` points drawn like free_point (uniform (x, y) not inside a
+    building, height z), float64 [count, 3]."""
+    lo, hi = _roof_boxes(tris)
+    out = np.empty((0, 3))
+    while out.shape[0] < count:
+        xy = rng.uniform(-half * 0.95, half * 0.95, size=(2 * count, 2))
+        inside = np.zeros(xy.shape[0], bool)
+        for k in range(0, lo.shape[0], 256):
+            a, b = lo[k:k + 256], hi[k:k + 256]
+            inside |= ((a[None, :, 0] <= xy[:, None, 0]) & (xy[:, None, 0] <= b[None, :, 0]) &
+                       (a[None, :, 1] <= xy[:, None, 1]) & (xy[:, None, 1] <= b[None, :, 1])).any(1)
+        keep = xy[~inside]
+        out = np.concatenate([out, np.column_stack([keep, np.full(keep.shape[0], float(z))])])
+    return out[:count]
+
+
 # ---------------------------------------------------------------------------
 # Materials the paper names for its scenes (Sec. IV-A), as indices.
 MATERIALS = ("concrete", "wood", "metal", "glass")

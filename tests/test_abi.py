@@ -61,9 +61,9 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu %zu\\n", offsetof(rt_node_rec, cost), offsetof(rt_bvh_info, root_lo),
          offsetof(rt_split_params, max_leaf), offsetof(rt_trace_opts, block),
          offsetof(rt_split_params, node_format), offsetof(rt_bvh_info, n_trace_nodes));
-  printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(rt_query), offsetof(rt_query, max_bounces),
+  printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(rt_query), offsetof(rt_query, max_bounces),
          offsetof(rt_query, status), offsetof(rt_query, out), offsetof(rt_query, n_hits),
-         sizeof(rt_batch_config));
+         sizeof(rt_batch_config), offsetof(rt_query, receivers));
   printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(rt_reception), offsetof(rt_reception, l),
          offsetof(rt_reception, dist), sizeof(rt_receivers), offsetof(rt_receivers, delta),
          offsetof(rt_receivers, cap), offsetof(rt_receivers, count));
@@ -87,7 +87,8 @@ int main(void) {
                     R.rt_split_params.node_format.offset, R.rt_bvh_info.n_trace_nodes.offset]
     assert [int(x) for x in c.split()] == [ctypes.sizeof(R.rt_query), R.rt_query.max_bounces.offset,
                                            R.rt_query.status.offset, R.rt_query.out.offset,
-                                           R.rt_query.n_hits.offset, ctypes.sizeof(R.rt_batch_config)]
+                                           R.rt_query.n_hits.offset, ctypes.sizeof(R.rt_batch_config),
+                                           R.rt_query.receivers.offset]
     assert [int(x) for x in d.split()] == [R.RECEPTION_DTYPE.itemsize, R.RECEPTION_DTYPE.fields["l"][1],
                                            R.RECEPTION_DTYPE.fields["dist"][1],
                                            ctypes.sizeof(R.rt_receivers), R.rt_receivers.delta.offset,

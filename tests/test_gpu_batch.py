@@ -125,6 +125,73 @@ def test_batch_graph_replays(small_set):
     b.close()
 
 
+def field_points(bvh_tris_half, rng, m):
+    tris, half = bvh_tris_half
+    from rtgen import scenes
+    return dev(scenes.free_points(rng, half, tris, 1.5, m))
+
+
+@pytest.mark.parametrize("mode,graph", [("direct", False), ("queue", False), ("direct", True)])
+def test_batch_receptions_equal_each_query_alone(small_set, mode, graph):
+    """Queries with field points (every other query, both node formats) in
+    one batch with plain queries: each gets the reception count and records
+    of rt_trace_receive on the same rays alone, and the same chains; the
+    counts are cleared by every launch (graph replays included)."""
+    from rtgen import icosphere
+    trees, queries = small_set
+    rng = np.random.default_rng(17)
+    delta = float(icosphere.edge_angles(6).mean())
+    qs = fresh(queries)
+    for k, q in enumerate(qs):
+        if k % 2 == 0:
+            pos = field_points(workloads.multiscene_scene(k // 2), rng, 12)
+            q["receivers"] = R.Receivers(pos, delta, 1 << 16)
+    ref = []
+    for q in qs:
+        if "receivers" in q:
+            rcv = R.Receivers(q["receivers"].pos, delta, 1 << 16)
+            out, pl, nh = q["bvh"].trace_receive(q["rays"], q["max_bounces"], rcv)
+            ref.append((out, pl, nh, rcv))
+        else:
+            ref.append(alone(q) + (None,))
+    b = R.Batch(16)
+    assert b.set(qs) == [0] * len(qs)
+    b.configure(mode=mode, graph=graph)
+    total = 0
+    for rep in range(2 if graph else 1):
+        b.launch()
+        torch.cuda.synchronize()
+        for k, (q, (out, pl, nh, rcv)) in enumerate(zip(qs, ref)):
+            assert torch.equal(q["out"], out) and torch.equal(q["path_len"], pl), k
+            assert torch.equal(q["n_hits"], nh), k
+            if rcv is None:
+                continue
+            got = q["receivers"]
+            assert got.count() == rcv.count() <= got.cap, k
+            assert np.array_equal(np.sort(got.records(), order=("rx", "ray", "order")),
+                                  np.sort(rcv.records(), order=("rx", "ray", "order"))), k
+            total += got.count()
+    log(f"{mode} graph={graph}: {total} receptions")
+    assert total > 0
+    b.close()
+
+
+def test_batch_receivers_are_checked(small_set):
+    _, queries = small_set
+    qs = fresh(queries[:3])
+    pos = dev(np.zeros((4, 3)))
+    qs[0]["receivers"] = R.Receivers(pos, float("nan"), 16)    # bad delta
+    qs[1]["receivers"] = R.Receivers(pos, 0.01, 16)
+    b = R.Batch(4)
+    st = b.set(qs)
+    assert st[0] != 0 and st[1] == 0 and st[2] == 0
+    b.launch()
+    torch.cuda.synchronize()
+    ref = alone(qs[2])
+    assert torch.equal(qs[2]["out"], ref[0])
+    b.close()
+
+
 def test_batch_autotune_keeps_results(small_set):
     _, queries = small_set
     ref = [alone(q) for q in queries]

@@ -1,6 +1,7 @@
 """Serving on the GPU: a query's results through the continuous-batching
 server are the same, bit for bit, as the same query traced alone, while
-other batches share the device; a short Poisson stream reports latency."""
+other batches share the device -- full hit records, and receptions for
+queries with field points; a short Poisson stream reports latency."""
 import sys
 import time
 
@@ -85,3 +86,42 @@ def test_short_poisson_stream(scenes):
     assert m["queries"] == len(stream) and m["failed"] == 0
     assert 0 < m["latency_ms_p50"] <= m["latency_ms_p99"] < 5000
     assert m["mrays_s"] > 0
+
+
+def test_reception_queries_equal_alone_in_the_mix(scenes):
+    """Queries with field points come back as reception records and hit
+    counts only; each equals the fused reception trace of the same rays run
+    alone (same count, same records bit for bit), while plain queries share
+    the slots."""
+    rng = np.random.default_rng(23)
+    ex = serve.GpuExecutor(scenes, slots=3, max_batch=4)
+    srv = serve.Server(ex, budget_bytes=4 << 30, slots=3, max_batch=4)
+    stream = serve.poisson_queries(duration=0.2, rate=60.0, seed=9, scenes=range(3), receivers=24,
+                                   rec_cap=1 << 16)
+    assert len(stream) >= 6
+    reqs = []
+    for k, (_, s, tx, n, nb, extra) in enumerate(stream):
+        reqs.append(srv.submit(s, nb, tx=tx, n_rays=n, **extra))
+        if k % 2 == 0:                      # plain queries in between
+            reqs.append(srv.submit(s, nb, tx=tx, n_rays=int(rng.integers(1000, 50_000))))
+        srv.step()
+    srv.run_until_idle()
+    got_recv = 0
+    for r in reqs:
+        assert r.status == serve.DONE, r.error
+        if r.receivers is None:
+            assert r.out is not None and r.receptions is None
+            continue
+        assert r.out is None and r.n_receptions >= 0
+        rays = torch.from_numpy(icosphere.make_rays(r.tx, icosphere.directions_n(r.n_rays),
+                                                    1e-4, 2000.0)).cuda()
+        rcv = R.Receivers(torch.from_numpy(r.receivers).cuda(), r.delta, r.rec_cap)
+        _, _, nh = scenes[r.scene].trace_receive(rays, r.max_bounces, rcv)
+        assert r.n_receptions == rcv.count(), f"query {r.rid}: reception count differs"
+        assert r.n_receptions <= r.rec_cap   # every record stored: the set is deterministic
+        assert np.array_equal(np.sort(r.receptions, order=("rx", "ray", "order")),
+                              np.sort(rcv.records(), order=("rx", "ray", "order"))), r.rid
+        assert np.array_equal(nh.cpu().numpy(), r.n_hits), f"query {r.rid}: hit counts differ"
+        got_recv += r.n_receptions
+    log("receptions through the server:", got_recv)
+    assert got_recv > 0

@@ -154,3 +154,25 @@ def test_consumer_sees_every_finished_query_and_can_release_results():
     assert sorted(seen) == [r.rid for r in reqs]
     m = srv.metrics()
     assert m["queries"] == 7 and m["segments"] == sum(r.segments for r in reqs)
+
+
+def test_field_point_queries_are_checked_and_sized():
+    from paper_2208_10008_amd.serve import MAX_RECEIVERS
+    srv, ex = make()
+    pts = np.zeros((4, 3))
+    bad = [srv.submit(0, 2, rays(4), receivers=pts.astype(np.float32), delta=0.01, rec_cap=8),
+           srv.submit(0, 2, rays(4), receivers=np.zeros((4, 2)), delta=0.01, rec_cap=8),
+           srv.submit(0, 2, rays(4), receivers=np.zeros((0, 3)), delta=0.01, rec_cap=8),
+           srv.submit(0, 2, rays(4), receivers=np.full((4, 3), np.nan), delta=0.01, rec_cap=8),
+           srv.submit(0, 2, rays(4), receivers=pts, delta=float("nan"), rec_cap=8),
+           srv.submit(0, 2, rays(4), receivers=pts, delta=-1.0, rec_cap=8),
+           srv.submit(0, 2, rays(4), receivers=pts, delta=0.01, rec_cap=-1),
+           srv.submit(0, 2, rays(4), receivers=np.zeros((MAX_RECEIVERS + 1, 3)), delta=0.01)]
+    for r in bad:
+        assert r.status == FAILED and r.error
+    ok = Request(0, 0, 3, 0.0, rays=rays(100), receivers=pts, delta=0.01, rec_cap=50)
+    plain = Request(1, 0, 3, 0.0, rays=rays(100))
+    assert check_request(ok, {0: None}) == ""
+    # receptions replace the hit records in host memory, and add their records on the device
+    assert ok.result_bytes() < plain.result_bytes()
+    assert ok.device_bytes() == plain.device_bytes() + 4 * 24 + 50 * 32 + 8
