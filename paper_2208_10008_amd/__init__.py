@@ -633,6 +633,15 @@ class Batch:
         self.queries = queries
         return [arr[k].status for k in range(len(queries))]
 
+    def set_table(self, arr, count: int):
+        """Sets queries from a ctypes array of rt_query that the caller built
+        (device pointers and sizes as the C ABI takes them, e.g. slices of
+        pooled buffers); the caller keeps the buffers alive.  Returns the
+        statuses."""
+        _check(load().rt_batch_set(self.handle, arr, count))
+        self.queries = []
+        return [arr[k].status for k in range(count)]
+
     def configure(self, mode="direct", grid=0, order="cost", graph=False):
         c = rt_batch_config(BATCH_MODES[mode], grid, BATCH_ORDERS[order], int(bool(graph)))
         _check(load().rt_batch_configure(self.handle, ctypes.byref(c)))

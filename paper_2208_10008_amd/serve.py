@@ -28,6 +28,7 @@ queue depth, admission waits).
 from __future__ import annotations
 
 import argparse
+import ctypes
 import collections
 import dataclasses
 import itertools
@@ -40,7 +41,7 @@ from typing import Callable, Optional
 import numpy as np
 
 from . import RECEPTION_DTYPE
-from . import rt_rays_from_directions as _rays_from_directions
+
 
 def _align(x: int, a: int = 256) -> int:
     return (x + a - 1) // a * a
@@ -215,22 +216,24 @@ class GpuExecutor:
     def launch(self, slot: int, reqs):
         """One batch on the slot's stream.  Per kind of array the batch takes
         one device allocation and one pinned host buffer, and each query a
-        slice of them (16-byte aligned), so the host work per query is a ray
-        launch and a table entry; results are copied back with one copy per
-        array kind and handed out as numpy views of the pinned buffers."""
-        from . import rt_receivers
+        16-byte-aligned slice of them: the host work per query is a ray launch
+        and a table entry (pointers into the pools).  Results are copied back
+        with one copy per array kind and handed out as numpy views of the
+        pinned buffers."""
+        from . import load, rt_query, rt_receivers, _stream
         torch = self.torch
+        lib = load()
         s = self.streams[slot]
+        sp = _stream(s)
         plain = [r for r in reqs if r.receivers is None]
         recv = [r for r in reqs if r.receivers is not None]
         dev = {}
         with torch.cuda.stream(s):
             def pool(name, count, dtype):
                 dev[name] = torch.empty(max(count, 1), dtype=dtype, device="cuda")
-                return dev[name]
+                return dev[name].data_ptr()
 
-            n_all = sum(r.n for r in reqs)
-            rays = pool("rays", 8 * n_all, torch.float32)
+            base_rays = pool("rays", 8 * sum(r.n for r in reqs), torch.float32)
             # plain queries: hits, path lengths, hit counts (all copied back)
             p_out = pool("p_out", sum(4 * r.n * r.max_bounces for r in plain), torch.int32)
             p_pl = pool("p_pl", sum(r.n for r in plain), torch.float64)
@@ -241,58 +244,58 @@ class GpuExecutor:
             r_nh = pool("r_nh", sum(r.n for r in recv), torch.int32)
             r_rec = pool("r_rec", sum(8 * max(r.rec_cap, 1) for r in recv), torch.int32)
             r_cnt = pool("r_cnt", len(recv), torch.int64)
+            r_pos = 0
             if recv:
                 pos_host = torch.from_numpy(np.concatenate([r.receivers for r in recv])).pin_memory()
                 r_pos = pool("r_pos", pos_host.numel(), torch.float64)
-                r_pos.copy_(pos_host.view(-1), non_blocking=True)
+                dev["r_pos"].copy_(pos_host.view(-1), non_blocking=True)
                 dev["pos_host"] = pos_host
-            qs, off = [], {"rays": 0, "p": 0, "po": 0, "r": 0, "ro": 0, "rec": 0, "pos": 0}
-            keep = []  # rt_receivers structs, read by Batch.set
-            for r in reqs:
+            arr = (rt_query * max(len(reqs), 1))()
+            keep = []   # rt_receivers structs, read by rt_batch_set
+            dirs = self.dirs.data_ptr()
+            o_ray = o_p = o_po = o_r = o_ro = o_rec = o_pos = 0
+            for k, r in enumerate(reqs):
                 n, nb = r.n, r.max_bounces
-                ray = rays[8 * off["rays"]:8 * (off["rays"] + n)].view(n, 8)
-                off["rays"] += n
+                rays = base_rays + 32 * o_ray
+                o_ray += n
                 if r.rays is None:
-                    _rays_from_directions(self.dirs, n, r.tx, self.tmin, self.tmax, rays=ray,
-                                          stream=s)
+                    _check_rc(lib.rt_rays_from_directions(dirs, n, r.tx[0], r.tx[1], r.tx[2],
+                                                          self.tmin, self.tmax, rays, sp))
                 else:
-                    ray.copy_(torch.from_numpy(r.rays).pin_memory(), non_blocking=True)
-                q = {"bvh": self.scenes[r.scene], "rays": ray, "max_bounces": nb}
+                    dev[f"host_rays{k}"] = torch.from_numpy(r.rays).pin_memory()
+                    dev["rays"][8 * (o_ray - n):8 * o_ray].view(n, 8).copy_(
+                        dev[f"host_rays{k}"], non_blocking=True)
+                q = arr[k]
+                q.bvh, q.rays, q.n, q.max_bounces = self.scenes[r.scene].handle, rays, n, nb
                 if r.receivers is None:
-                    q["out"] = p_out[4 * off["po"]:4 * (off["po"] + n * nb)].view(nb, n, 4)
-                    q["path_len"] = p_pl[off["p"]:off["p"] + n]
-                    q["n_hits"] = p_nh[off["p"]:off["p"] + n]
-                    off["po"] += n * nb
-                    off["p"] += n
+                    q.out, q.path_len, q.n_hits = p_out + 16 * o_po, p_pl + 8 * o_p, p_nh + 4 * o_p
+                    o_po += n * nb
+                    o_p += n
                 else:
-                    k = len(keep)
                     m, cap = r.receivers.shape[0], max(r.rec_cap, 1)
-                    q["out"] = r_out[4 * off["ro"]:4 * (off["ro"] + n * nb)].view(nb, n, 4)
-                    q["path_len"] = r_pl[off["r"]:off["r"] + n]
-                    q["n_hits"] = r_nh[off["r"]:off["r"] + n]
+                    q.out, q.path_len, q.n_hits = r_out + 16 * o_ro, r_pl + 8 * o_r, r_nh + 4 * o_r
                     c = rt_receivers()
-                    c.pos = dev["r_pos"].data_ptr() + 24 * off["pos"]
-                    c.n, c.reserved, c.delta = m, 0, r.delta
-                    c.rec = r_rec.data_ptr() + 32 * off["rec"]
-                    c.cap = r.rec_cap
-                    c.count = r_cnt.data_ptr() + 8 * k
+                    c.pos, c.n, c.reserved, c.delta = r_pos + 24 * o_pos, m, 0, r.delta
+                    c.rec, c.cap, c.count = r_rec + 32 * o_rec, r.rec_cap, r_cnt + 8 * len(keep)
                     keep.append(c)
-                    q["receivers"] = _Fixed(c)
-                    off["ro"] += n * nb
-                    off["r"] += n
-                    off["rec"] += cap
-                    off["pos"] += m
-                qs.append(q)
-            self.batches[slot].set(qs)
+                    q.receivers = ctypes.addressof(c)
+                    o_ro += n * nb
+                    o_r += n
+                    o_rec += cap
+                    o_pos += m
+            st = self.batches[slot].set_table(arr, len(reqs))
+            if any(st):
+                raise RuntimeError(f"serving table entries rejected: {st}")
             self.batches[slot].launch(stream=s)
 
-            def to_host(t):
+            def to_host(name):
+                t = dev[name]
                 h = torch.empty(t.shape, dtype=t.dtype, pin_memory=True)
                 h.copy_(t, non_blocking=True)
                 return h
-            host = {"p_out": to_host(p_out), "p_pl": to_host(p_pl), "p_nh": to_host(p_nh)}
+            host = {k: to_host(k) for k in (("p_out", "p_pl", "p_nh") if plain else ())}
             if recv:
-                host.update(r_nh=to_host(r_nh), r_rec=to_host(r_rec), r_cnt=to_host(r_cnt))
+                host.update({k: to_host(k) for k in ("r_nh", "r_rec", "r_cnt")})
             ev = torch.cuda.Event()
             ev.record(s)
         self.events[slot] = ev
@@ -303,38 +306,36 @@ class GpuExecutor:
 
     def collect(self, slot: int):
         plain, recv, host, dev, keep = self.work[slot]
-        p, po = 0, 0
-        for r in plain:  # views of the batch's pinned buffers (they keep them alive)
-            n, nb = r.n, r.max_bounces
-            r.out = host["p_out"][4 * po:4 * (po + n * nb)].view(nb, n, 4).numpy()
-            r.path_len = host["p_pl"][p:p + n].numpy()
-            r.n_hits = host["p_nh"][p:p + n].numpy()
-            p += n
-            po += n * nb
-        q, rec = 0, 0
-        for k, r in enumerate(recv):
-            n, cap = r.n, max(r.rec_cap, 1)
-            r.n_receptions = int(host["r_cnt"][k])
-            got = min(r.n_receptions, r.rec_cap)
-            recs = host["r_rec"][8 * rec:8 * (rec + got)].view(got, 8).numpy()
-            r.receptions = recs.view(RECEPTION_DTYPE).reshape(-1)
-            r.n_hits = host["r_nh"][q:q + n].numpy()
-            q += n
-            rec += cap
+        if plain:  # numpy views of the batch's pinned buffers (they keep them alive)
+            out, pl, nh = host["p_out"].numpy(), host["p_pl"].numpy(), host["p_nh"].numpy()
+            p = po = 0
+            for r in plain:
+                n, nb = r.n, r.max_bounces
+                r.out = out[4 * po:4 * (po + n * nb)].reshape(nb, n, 4)
+                r.path_len, r.n_hits = pl[p:p + n], nh[p:p + n]
+                p += n
+                po += n * nb
+        if recv:
+            cnt, recs, nh = host["r_cnt"].numpy(), host["r_rec"].numpy(), host["r_nh"].numpy()
+            q = rec = 0
+            for k, r in enumerate(recv):
+                n = r.n
+                r.n_receptions = int(cnt[k])
+                got = min(r.n_receptions, r.rec_cap)
+                r.receptions = (recs[8 * rec:8 * (rec + got)].reshape(got, 8)
+                                .view(RECEPTION_DTYPE).reshape(-1))
+                r.n_hits = nh[q:q + n]
+                q += n
+                rec += max(r.rec_cap, 1)
         self.events[slot] = None
         self.work[slot] = None
         return plain + recv
 
 
-class _Fixed:
-    """A receivers argument for Batch.set built from pointers into pooled
-    device buffers."""
-
-    def __init__(self, c):
-        self._c = c
-
-    def c(self):
-        return self._c
+def _check_rc(rc: int):
+    if rc != 0:
+        from . import RtError, load
+        raise RtError(rc, load().rt_last_error().decode())
 
 
 class Server:
