@@ -287,19 +287,37 @@ class GpuExecutor:
             if any(st):
                 raise RuntimeError(f"serving table entries rejected: {st}")
             self.batches[slot].launch(stream=s)
+            # segments each query traced, counted on the device (a segment per
+            # hit plus the final miss, at most the bounce limit per chain)
+            dev["p_seg"] = self._segments(plain, dev["p_nh"])
+            dev["r_seg"] = self._segments(recv, dev["r_nh"])
 
             def to_host(name):
                 t = dev[name]
                 h = torch.empty(t.shape, dtype=t.dtype, pin_memory=True)
                 h.copy_(t, non_blocking=True)
                 return h
-            host = {k: to_host(k) for k in (("p_out", "p_pl", "p_nh") if plain else ())}
+            host = {k: to_host(k) for k in (("p_out", "p_pl", "p_nh", "p_seg") if plain else ())}
             if recv:
-                host.update({k: to_host(k) for k in ("r_nh", "r_rec", "r_cnt")})
+                host.update({k: to_host(k) for k in ("r_nh", "r_rec", "r_cnt", "r_seg")})
             ev = torch.cuda.Event()
             ev.record(s)
         self.events[slot] = ev
         self.work[slot] = (plain, recv, host, dev, keep)
+
+    def _segments(self, reqs, n_hits):
+        torch = self.torch
+        if not reqs:
+            return torch.zeros(1, dtype=torch.int64, device="cuda")
+        n = torch.tensor([r.n for r in reqs], dtype=torch.int64).to("cuda", non_blocking=True)
+        nb = torch.tensor([r.max_bounces for r in reqs], dtype=torch.int32).to("cuda",
+                                                                             non_blocking=True)
+        total = sum(r.n for r in reqs)
+        seg = torch.minimum(n_hits[:total] + 1, torch.repeat_interleave(nb, n, output_size=total))
+        c = torch.cumsum(seg, 0, dtype=torch.int64)
+        ends = torch.cumsum(n, 0) - 1
+        per = c[ends]
+        return torch.cat([per[:1], per[1:] - per[:-1]])
 
     def poll(self, slot: int) -> bool:
         return self.events[slot] is not None and self.events[slot].query()
@@ -309,10 +327,12 @@ class GpuExecutor:
         if plain:  # numpy views of the batch's pinned buffers (they keep them alive)
             out, pl, nh = host["p_out"].numpy(), host["p_pl"].numpy(), host["p_nh"].numpy()
             p = po = 0
-            for r in plain:
+            seg = host["p_seg"].numpy()
+            for k, r in enumerate(plain):
                 n, nb = r.n, r.max_bounces
                 r.out = out[4 * po:4 * (po + n * nb)].reshape(nb, n, 4)
                 r.path_len, r.n_hits = pl[p:p + n], nh[p:p + n]
+                r.segments = int(seg[k])
                 p += n
                 po += n * nb
         if recv:
@@ -325,6 +345,7 @@ class GpuExecutor:
                 r.receptions = (recs[8 * rec:8 * (rec + got)].reshape(got, 8)
                                 .view(RECEPTION_DTYPE).reshape(-1))
                 r.n_hits = nh[q:q + n]
+                r.segments = int(host["r_seg"][k])
                 q += n
                 rec += max(r.rec_cap, 1)
         self.events[slot] = None
@@ -473,9 +494,11 @@ def count_segments(r: Request) -> int:
 
 
 def release_results(r: Request):
-    """Consumer for throughput runs: counts the query's segments and drops its
-    result arrays, returning their pinned buffers to the pool."""
-    r.segments = count_segments(r)
+    """Consumer for throughput runs: keeps the query's segment count (counted
+    on the device by the executor, else here) and drops its result arrays,
+    returning their pinned buffers to the pool."""
+    if r.segments < 0:
+        r.segments = count_segments(r)
     r.out = r.path_len = r.n_hits = r.receptions = None
 
 

@@ -74,6 +74,7 @@ def test_results_equal_alone_in_the_mix(scenes):
         assert np.array_equal(out.cpu().numpy(), r.out), f"query {r.rid}: hits differ"
         assert np.array_equal(pl.cpu().numpy(), r.path_len), f"query {r.rid}: path lengths differ"
         assert np.array_equal(nh.cpu().numpy(), r.n_hits), f"query {r.rid}: hit counts differ"
+        assert r.segments == serve.count_segments(r), f"query {r.rid}: device segment count"
 
 
 def test_short_poisson_stream(scenes):
@@ -122,6 +123,7 @@ def test_reception_queries_equal_alone_in_the_mix(scenes):
         assert np.array_equal(np.sort(r.receptions, order=("rx", "ray", "order")),
                               np.sort(rcv.records(), order=("rx", "ray", "order"))), r.rid
         assert np.array_equal(nh.cpu().numpy(), r.n_hits), f"query {r.rid}: hit counts differ"
+        assert r.segments == serve.count_segments(r), f"query {r.rid}: device segment count"
         got_recv += r.n_receptions
     log("receptions through the server:", got_recv)
     assert got_recv > 0
