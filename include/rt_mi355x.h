@@ -196,6 +196,25 @@ int rt_trace_ex(const rt_bvh* b, const float* rays, int64_t n, int32_t max_bounc
 int rt_rays_from_directions(const float* dirs, int64_t n, float ox, float oy, float oz, float tmin,
                             float tmax, float* rays, hipStream_t s);
 
+/* Many launches with one kernel (a serving batch): launch j writes n rays from
+ * its source along the first n directions of dirs to rows first .. first + n - 1
+ * of rays, as rt_rays_from_directions does.  table: device array of `count`
+ * records sorted by `first`, whose row ranges do not overlap; a record with
+ * n > n_dirs, a negative first or n, or a range past `total` writes nothing.
+ * Rows that no record covers are left as they are.  rays: device float32
+ * [total][8], 16-byte aligned.  Enqueued on s.
+ * Errors: RT_EINVAL (NULL, misaligned, count or total or n_dirs < 0, tmin > tmax
+ * or not finite), RT_EHIP. */
+typedef struct rt_ray_launch {
+  float src[3];      /* source point */
+  int32_t reserved;  /* 0 */
+  int64_t first;     /* first row of rays */
+  int64_t n;         /* rays of this launch */
+} rt_ray_launch;     /* 32 bytes */
+int rt_rays_from_directions_many(const float* dirs, int64_t n_dirs, const rt_ray_launch* table,
+                                 int32_t count, float tmin, float tmax, float* rays, int64_t total,
+                                 hipStream_t s);
+
 /* ---- ray reception (Sec. III-C, Eq. (4)) ---------------------------------
  * A field point R receives segment b of a ray (b = 0: the launched ray, b = k:
  * after k reflections; origin o, direction d, range [tmin, t_end] with t_end

@@ -120,7 +120,7 @@ EXPORTS = ("rt_split_params_default", "rt_build", "rt_rebuild", "rt_trace",
            "rt_bvh_export_trace_nodes", "rt_bvh_destroy", "rt_last_error", "rt_batch_create",
            "rt_batch_set", "rt_batch_configure", "rt_batch_get_config", "rt_batch_launch",
            "rt_batch_autotune", "rt_batch_destroy", "rt_rays_from_directions",
-           "rt_trace_receive", "rt_receive_segments", "rt_receive_dedup_workspace",
+           "rt_rays_from_directions_many", "rt_trace_receive", "rt_receive_segments", "rt_receive_dedup_workspace",
            "rt_receive_dedup", "rt_trace_energy", "rt_wedges", "rt_diffract_segments")
 PROBE_EXPORTS = ("rt_probe_read", "rt_probe_copy")  # include/rt_probe.h
 
@@ -159,6 +159,7 @@ def load(path: str = LIB_PATH):
     lib.rt_batch_autotune.argtypes = [P, i32, P, ctypes.POINTER(ctypes.c_float)]
     f32 = ctypes.c_float
     lib.rt_rays_from_directions.argtypes = [P, i64, f32, f32, f32, f32, f32, P, P]
+    lib.rt_rays_from_directions_many.argtypes = [P, i64, P, i32, f32, f32, P, i64, P]
     lib.rt_batch_destroy.argtypes = [P]
     lib.rt_batch_destroy.restype = None
     lib.rt_probe_copy.argtypes = [P, P, i64, P]
@@ -176,7 +177,8 @@ def load(path: str = LIB_PATH):
                  "rt_bvh_info_get", "rt_bvh_download", "rt_bvh_export_trace_nodes",
                  "rt_probe_read", "rt_probe_copy", "rt_batch_create", "rt_batch_set",
                  "rt_batch_configure", "rt_batch_get_config", "rt_batch_launch",
-                 "rt_batch_autotune", "rt_rays_from_directions", "rt_trace_receive",
+                 "rt_batch_autotune", "rt_rays_from_directions", "rt_rays_from_directions_many",
+                 "rt_trace_receive",
                  "rt_receive_segments", "rt_receive_dedup", "rt_trace_energy", "rt_wedges",
                  "rt_diffract_segments"):
         getattr(lib, name).restype = ctypes.c_int
@@ -589,6 +591,29 @@ def rt_rays_from_directions(dirs, n, src, tmin, tmax, rays=None, stream=None):
     _check(load().rt_rays_from_directions(dirs.data_ptr(), n, float(src[0]), float(src[1]),
                                           float(src[2]), float(tmin), float(tmax),
                                           rays.data_ptr(), _stream(stream)))
+    return rays
+
+
+# numpy view of rt_ray_launch (32 bytes): one launch of rt_rays_from_directions_many
+RAY_LAUNCH_DTYPE = np.dtype([("src", "<f4", 3), ("reserved", "<i4"), ("first", "<i8"), ("n", "<i8")])
+assert RAY_LAUNCH_DTYPE.itemsize == 32
+
+
+def rt_rays_from_directions_many(dirs, table, tmin, tmax, rays, stream=None):
+    """Rays of many launches with one kernel: table is a CUDA tensor holding
+    RAY_LAUNCH_DTYPE records (e.g. uint8 [count * 32]) sorted by first; rays
+    float32 [total, 8] CUDA tensor.  Rows no record covers are left as they are."""
+    import torch
+    if not isinstance(dirs, torch.Tensor) or not dirs.is_cuda or dirs.dtype != torch.float32 \
+            or dirs.dim() != 2 or dirs.shape[1] != 3 or not dirs.is_contiguous():
+        raise RtError(RT_EINVAL, "dirs must be a contiguous float32 CUDA tensor [m, 3]")
+    if not table.is_cuda or not table.is_contiguous() or table.numel() * table.element_size() % 32:
+        raise RtError(RT_EINVAL, "table must be a contiguous CUDA tensor of 32-byte records")
+    _dev(rays, torch.float32, 8, "rays")
+    count = table.numel() * table.element_size() // 32
+    _check(load().rt_rays_from_directions_many(dirs.data_ptr(), dirs.shape[0], table.data_ptr(),
+                                               count, float(tmin), float(tmax), rays.data_ptr(),
+                                               rays.shape[0], _stream(stream)))
     return rays
 
 

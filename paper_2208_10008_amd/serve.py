@@ -40,7 +40,7 @@ from typing import Callable, Optional
 
 import numpy as np
 
-from . import RECEPTION_DTYPE
+from . import RAY_LAUNCH_DTYPE, RECEPTION_DTYPE
 
 
 def _align(x: int, a: int = 256) -> int:
@@ -252,16 +252,25 @@ class GpuExecutor:
                 dev["pos_host"] = pos_host
             arr = (rt_query * max(len(reqs), 1))()
             keep = []   # rt_receivers structs, read by rt_batch_set
-            dirs = self.dirs.data_ptr()
+            # the generated rays of the whole batch: one launch from a table
+            first = np.cumsum([0] + [r.n for r in reqs[:-1]])
+            gen = [k for k, r in enumerate(reqs) if r.rays is None]
+            if gen:
+                table = np.zeros(len(gen), RAY_LAUNCH_DTYPE)
+                table["src"] = [reqs[k].tx for k in gen]
+                table["first"] = first[gen]
+                table["n"] = [reqs[k].n for k in gen]
+                dev["table_host"] = torch.from_numpy(table.view(np.uint8)).pin_memory()
+                dev["table"] = dev["table_host"].to("cuda", non_blocking=True)
+                _check_rc(lib.rt_rays_from_directions_many(
+                    self.dirs.data_ptr(), self.dirs.shape[0], dev["table"].data_ptr(), len(gen),
+                    self.tmin, self.tmax, base_rays, sum(r.n for r in reqs), sp))
             o_ray = o_p = o_po = o_r = o_ro = o_rec = o_pos = 0
             for k, r in enumerate(reqs):
                 n, nb = r.n, r.max_bounces
                 rays = base_rays + 32 * o_ray
                 o_ray += n
-                if r.rays is None:
-                    _check_rc(lib.rt_rays_from_directions(dirs, n, r.tx[0], r.tx[1], r.tx[2],
-                                                          self.tmin, self.tmax, rays, sp))
-                else:
+                if r.rays is not None:
                     dev[f"host_rays{k}"] = torch.from_numpy(r.rays).pin_memory()
                     dev["rays"][8 * (o_ray - n):8 * o_ray].view(n, 8).copy_(
                         dev[f"host_rays{k}"], non_blocking=True)

@@ -71,13 +71,15 @@ int main(void) {
          offsetof(rt_energy, min_power), offsetof(rt_energy, power));
   printf("%zu %zu %zu\\n", sizeof(rt_diffracted), offsetof(rt_diffracted, path),
          offsetof(rt_diffracted, ray8));
+  printf("%zu %zu %zu\\n", sizeof(rt_ray_launch), offsetof(rt_ray_launch, first),
+         offsetof(rt_ray_launch, n));
   return 0;
 }""")
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-D__HIP_PLATFORM_AMD__", "-I" + os.path.join(ROOT, "include"),
                     "-I/opt/rocm/include", str(src), "-o", str(exe)], check=True)
-    a, b, c, d, e, g = subprocess.run([str(exe)], capture_output=True, text=True,
-                                      check=True).stdout.split("\n")[:6]
+    a, b, c, d, e, g, h = subprocess.run([str(exe)], capture_output=True, text=True,
+                                         check=True).stdout.split("\n")[:7]
     sizes = [int(x) for x in a.split()]
     offs = [int(x) for x in b.split()]
     assert sizes == [ctypes.sizeof(R.rt_split_params), 16, ctypes.sizeof(R.rt_bvh_info),
@@ -98,6 +100,9 @@ int main(void) {
     assert [int(x) for x in g.split()] == [R.DIFFRACTED_DTYPE.itemsize,
                                            R.DIFFRACTED_DTYPE.fields["path"][1],
                                            R.DIFFRACTED_DTYPE.fields["ray8"][1]]
+    assert [int(x) for x in h.split()] == [R.RAY_LAUNCH_DTYPE.itemsize,
+                                           R.RAY_LAUNCH_DTYPE.fields["first"][1],
+                                           R.RAY_LAUNCH_DTYPE.fields["n"][1]]
 
 
 def test_defaults():
@@ -212,6 +217,28 @@ def test_rays_from_directions_argument_checks():
     assert lib.rt_rays_from_directions(p, 2, float("nan"), 0, 0, 0, 1, p, None) == R.RT_EINVAL
     assert lib.rt_rays_from_directions(p, 2, 0, 0, 0, 0, 1, ctypes.c_void_p(buf.ctypes.data + 4),
                                        None) == R.RT_EINVAL
+
+
+def test_rays_from_directions_many_argument_checks():
+    lib = R.load()
+    buf = np.zeros(256, np.float32)
+    base = buf.ctypes.data
+    base += (-base) % 16
+    p = ctypes.c_void_p(base)
+    f = lib.rt_rays_from_directions_many
+    assert f(p, 4, p, 0, 0, 1, p, 2, None) == R.RT_OK                 # no launch: nothing to do
+    assert f(p, 4, p, 1, 0, 1, p, 0, None) == R.RT_OK                 # no rows
+    assert f(None, 4, p, 1, 0, 1, p, 2, None) == R.RT_EINVAL
+    assert f(p, 4, None, 1, 0, 1, p, 2, None) == R.RT_EINVAL
+    assert f(p, 4, p, 1, 0, 1, None, 2, None) == R.RT_EINVAL
+    assert f(p, 4, p, -1, 0, 1, p, 2, None) == R.RT_EINVAL
+    assert f(p, 4, p, 1, 0, 1, p, -2, None) == R.RT_EINVAL
+    assert f(p, -4, p, 1, 0, 1, p, 2, None) == R.RT_EINVAL
+    assert f(p, 4, p, 1, 2, 1, p, 2, None) == R.RT_EINVAL             # tmin > tmax
+    assert f(p, 4, p, 1, float("nan"), 1, p, 2, None) == R.RT_EINVAL
+    assert f(p, 4, ctypes.c_void_p(base + 8), 1, 0, 1, p, 2, None) == R.RT_EINVAL
+    assert f(p, 4, p, 1, 0, 1, ctypes.c_void_p(base + 4), 2, None) == R.RT_EINVAL
+    assert R.RAY_LAUNCH_DTYPE.itemsize == 32
 
 
 def test_reception_argument_checks():

@@ -34,6 +34,30 @@ def test_device_rays_equal_host_rays(scenes):
         assert np.array_equal(dev_rays.view(np.uint32), host.view(np.uint32))
 
 
+def test_many_launch_rays_equal_one_launch_each(scenes):
+    """rt_rays_from_directions_many: every valid record writes exactly the rays
+    of rt_rays_from_directions into its rows; records past the table or with
+    too many rays write nothing; rows no record covers keep their values."""
+    dirs = torch.from_numpy(icosphere.directions(6).astype(np.float32)).cuda()
+    launches = [((1.5, -2.0, 7.0), 0, 1000), ((300.0, 12.5, 33.0), 1000, 0),
+                ((-5.0, 8.0, 2.5), 1000, 40_962), ((0.0, 0.0, 25.0), 41_962, 64),
+                ((9.0, 9.0, 9.0), 42_100, 50_000),            # more rays than directions: skipped
+                ((1.0, 2.0, 3.0), 42_200, 17)]                # runs past total: skipped
+    total = 42_210
+    table = np.zeros(len(launches), R.RAY_LAUNCH_DTYPE)
+    for k, (src, first, n) in enumerate(launches):
+        table[k] = (src, 0, first, n)
+    rays = torch.full((total, 8), -3.0, dtype=torch.float32, device="cuda")
+    R.rt_rays_from_directions_many(dirs, torch.from_numpy(table.view(np.uint8)).cuda(), 1e-4,
+                                   2000.0, rays)
+    got = rays.cpu().numpy()
+    want = np.full((total, 8), -3.0, np.float32)
+    for src, first, n in launches[:4]:
+        if n:
+            want[first:first + n] = R.rt_rays_from_directions(dirs, n, src, 1e-4, 2000.0).cpu().numpy()
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+
+
 def test_results_equal_alone_in_the_mix(scenes):
     """Stepped by hand: a first group of large queries (several ms on the
     device) is launched, a second mixed group is admitted into other slots
