@@ -178,7 +178,14 @@ typedef struct rt_trace_opts {
                           taking batches of rays from an atomic queue */
   int32_t refill;      /* persistent mode: 0 = a wave takes 64 consecutive rays when all its
                           chains have ended; 1 = free lanes take new rays at every segment */
-  int32_t reserved;
+  int32_t lanes_per_ray; /* 0: chosen by the library; 1: one lane per ray; 4, 16 or 64: that
+                          many lanes trace each ray together and split every leaf's facets
+                          (for trees with large leaves and launches too small to fill the
+                          device); > 1 requires seg_rays and ray_stats NULL and grid 0.  The
+                          library chooses > 1 only for trees built with max_leaf >= 16: the
+                          largest G of 64, 16, 4 with G <= max_leaf and n G <= 41000 max_leaf,
+                          the same for rt_trace, rt_trace_bounces and rt_trace_receive.
+                          Results do not depend on it. */
 } rt_trace_opts;
 
 /* rt_trace_bounces with optional outputs (opts nullable). */

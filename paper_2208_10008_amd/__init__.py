@@ -68,7 +68,7 @@ class rt_bvh_info(ctypes.Structure):
 class rt_trace_opts(ctypes.Structure):
     _fields_ = [("seg_rays", ctypes.c_void_p), ("ray_stats", ctypes.c_void_p),
                 ("block", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("refill", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("refill", ctypes.c_int32), ("lanes_per_ray", ctypes.c_int32)]
 
 
 class rt_query(ctypes.Structure):
@@ -269,12 +269,12 @@ def rt_trace_bounces(handle, rays, max_bounces, out, path_len=None, n_hits=None,
 
 
 def rt_trace_ex(handle, rays, max_bounces, out, path_len=None, n_hits=None, seg_rays=None,
-                ray_stats=None, block=0, grid=0, refill=0, stream=None):
+                ray_stats=None, block=0, grid=0, refill=0, lanes_per_ray=0, stream=None):
     lib = load()
     o = rt_trace_opts()
     o.seg_rays = None if seg_rays is None else seg_rays.data_ptr()
     o.ray_stats = None if ray_stats is None else ray_stats.data_ptr()
-    o.block, o.grid, o.refill = block, grid, refill
+    o.block, o.grid, o.refill, o.lanes_per_ray = block, grid, refill, lanes_per_ray
     _check(lib.rt_trace_ex(handle, _ptr(rays), rays.shape[0], max_bounces, _ptr(out),
                            _ptr(path_len), _ptr(n_hits), ctypes.byref(o), _stream(stream)))
 
@@ -517,7 +517,8 @@ class BVH:
         return out
 
     def trace_bounces(self, rays, max_bounces, out=None, path_len=None, n_hits=None,
-                      seg_rays=None, ray_stats=None, block=0, grid=0, refill=0, stream=None):
+                      seg_rays=None, ray_stats=None, block=0, grid=0, refill=0, lanes_per_ray=0,
+                      stream=None):
         import torch
         _dev(rays, torch.float32, 8, "rays")
         n = rays.shape[0]
@@ -527,11 +528,12 @@ class BVH:
             path_len = torch.empty(n, dtype=torch.float64, device=rays.device)
         if n_hits is None:
             n_hits = torch.empty(n, dtype=torch.int32, device=rays.device)
-        if seg_rays is None and ray_stats is None and block == 0 and grid == 0 and refill == 0:
+        if (seg_rays is None and ray_stats is None and block == 0 and grid == 0 and refill == 0
+                and lanes_per_ray == 0):
             rt_trace_bounces(self.handle, rays, max_bounces, out, path_len, n_hits, stream)
         else:
             rt_trace_ex(self.handle, rays, max_bounces, out, path_len, n_hits, seg_rays,
-                        ray_stats, block, grid, refill, stream)
+                        ray_stats, block, grid, refill, lanes_per_ray, stream)
         return out, path_len, n_hits
 
     def trace_receive(self, rays, max_bounces, receivers: Receivers, out=None, path_len=None,

@@ -169,8 +169,24 @@ int check_trace_args(const rt_bvh* b, const float* rays, int64_t n, int32_t max_
     if ((opts->block != 0 && opts->block != 64) || opts->grid < 0 ||
         (opts->refill != 0 && opts->refill != 1))
       return set_error(RT_EINVAL, "trace: block must be 0 or 64, grid >= 0, refill 0 or 1");
+    const int g = opts->lanes_per_ray;
+    if (g != 0 && g != 1 && g != 4 && g != 16 && g != 64)
+      return set_error(RT_EINVAL, "trace: lanes_per_ray must be 0, 1, 4, 16 or 64");
+    if (g > 1 && (opts->seg_rays || opts->ray_stats || opts->grid > 0))
+      return set_error(RT_EINVAL,
+                       "trace: lanes_per_ray > 1 takes no seg_rays, ray_stats or grid");
+    if (g > 1 && n > (int64_t)INT32_MAX * (64 / g))
+      return set_error(RT_EINVAL, "trace: too many rays for lanes_per_ray");
   }
   return RT_OK;
+}
+
+// Lanes per ray of a trace call: the caller's choice, else the library's
+// (one lane per ray whenever segments or statistics are recorded).
+int lanes_of(const rt_bvh* b, int64_t n, const rt_trace_opts* opts) {
+  if (opts && opts->lanes_per_ray > 0) return opts->lanes_per_ray;
+  if (opts && (opts->seg_rays || opts->ray_stats || opts->grid > 0)) return 1;
+  return trace_lanes(n, b->params.max_leaf);
 }
 }  // namespace rt
 
@@ -224,7 +240,7 @@ int rt_trace(const rt_bvh* b, const float* rays, int64_t n, rt_hit* out, hipStre
   int rc = check_trace_args(b, rays, n, 1, out, nullptr, nullptr, nullptr);
   if (rc != RT_OK || n == 0) return rc;
   return launch_trace(b->buf, b->info.node_format, b->info.depth, rays, n, 1, out, nullptr, nullptr,
-                      nullptr, s);
+                      nullptr, lanes_of(b, n, nullptr), (int)b->info.n_tris, s);
 }
 
 int rt_trace_bounces(const rt_bvh* b, const float* rays, int64_t n, int32_t max_bounces,
@@ -237,7 +253,7 @@ int rt_trace_ex(const rt_bvh* b, const float* rays, int64_t n, int32_t max_bounc
   int rc = check_trace_args(b, rays, n, max_bounces, out, path_len, n_hits, opts);
   if (rc != RT_OK || n == 0) return rc;
   return launch_trace(b->buf, b->info.node_format, b->info.depth, rays, n, max_bounces, out,
-                      path_len, n_hits, opts, s);
+                      path_len, n_hits, opts, lanes_of(b, n, opts), (int)b->info.n_tris, s);
 }
 
 int rt_bvh_info_get(const rt_bvh* b, rt_bvh_info* info) {

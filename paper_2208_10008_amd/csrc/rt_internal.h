@@ -288,9 +288,13 @@ int check_trace_args(const rt_bvh* b, const float* rays, int64_t n, int32_t max_
 int build_tree(Buffers& B, const float* tris, int64_t n, const rt_split_params& p,
                hipStream_t s, rt_bvh_info* info);
 // trace.hip
+// lanes: 1, or 4 / 16 / 64 lanes tracing each ray together (then opts may not
+// ask for seg_rays, ray_stats or a persistent grid); n_tf: facets of the tree.
 int launch_trace(const Buffers& B, int node_format, int depth, const float* rays, int64_t n,
                  int32_t max_bounces, rt_hit* out, double* path_len, int32_t* n_hits,
-                 const rt_trace_opts* opts, hipStream_t s);
+                 const rt_trace_opts* opts, int lanes, int n_tf, hipStream_t s);
+// Lanes per ray the library picks for n rays on a tree built with max_leaf.
+int trace_lanes(int64_t n, int max_leaf);
 // Batched launch over table[0 .. nq) (device), all of one node format;
 // total_batches work-groups, or `grid` persistent work-groups taking batches
 // from `queue` when grid > 0.  depth: deepest tree of the queries.
@@ -308,7 +312,8 @@ RecvArgs recv_args(const rt_receivers* rx);
 // Chains with the reception test of every segment (receive.hip zeroes the count first).
 int launch_trace_receive(const Buffers& B, int node_format, int depth, const float* rays,
                          int64_t n, int32_t max_bounces, rt_hit* out, double* path_len,
-                         int32_t* n_hits, const RecvArgs& recv, hipStream_t s);
+                         int32_t* n_hits, const RecvArgs& recv, int lanes, int n_tf,
+                         hipStream_t s);
 // Chains stopped by energy, with the reception test when recv is not null.
 int launch_trace_energy(const Buffers& B, int node_format, int depth, const float* rays,
                         int64_t n, int32_t max_bounces, rt_hit* out, double* path_len,

@@ -203,7 +203,8 @@ int rt_trace_receive(const rt_bvh* b, const float* rays, int64_t n, int32_t max_
   rc = check_hip(hipGetLastError(), "reception count reset");
   if (rc != RT_OK || n == 0) return rc;
   return launch_trace_receive(b->buf, b->info.node_format, b->info.depth, rays, n, max_bounces,
-                              out, path_len, n_hits, a, s);
+                              out, path_len, n_hits, a, trace_lanes(n, b->params.max_leaf),
+                              (int)b->info.n_tris, s);
 }
 
 int rt_trace_energy(const rt_bvh* b, const float* rays, int64_t n, int32_t max_bounces,

@@ -320,10 +320,69 @@ __device__ inline void leaf_test(const TFacet* __restrict__ tf, const RayPre& r,
   }
 }
 
-template <int FMT, bool STATS>
+// The same leaf test shared by the G lanes that trace one ray: lane s of the
+// group takes positions first + s, first + s + G, ... .  The round in which a
+// lane of the group meets the facet tagged last ends the leaf (lanes after it
+// hold the next leaf's facets and drop them; the facet array ends with a
+// tagged facet, so no lane that tests reads past it).  The lanes' candidates
+// are then merged by the closest-hit rule (smaller t, then smaller facet id),
+// a total order, so every lane of the group ends with the hit the serial
+// test finds.
+template <int G>
+__device__ inline void leaf_test_group(const TFacet* __restrict__ tf, int n_tf, const RayPre& r,
+                                       int node, int skip_pos, Hit& h, int& best_id) {
+  const int lane = threadIdx.x & 63;
+  const int sub = lane & (G - 1);
+  const int group_lane0 = lane & ~(G - 1);
+  float bt = h.t, bu = h.u, bv = h.v;
+  int bid = best_id, bpos = h.pos;
+  for (int k0 = ~node;; k0 += G) {
+    const int k = k0 + sub;
+    const bool inside = k < n_tf;
+    const TFacet f = tf[inside ? k : n_tf - 1];
+    const uint32_t tag = __float_as_uint(f.p0.w);
+    const unsigned long long ends = __ballot(inside && (tag & kLastFacet) != 0u);
+    const unsigned long long mine =
+        G == 64 ? ends : (ends >> group_lane0) & ((1ull << (G & 63)) - 1ull);
+    const int last_sub = mine ? __ffsll((long long)mine) - 1 : G - 1;
+    if (inside && sub <= last_sub && k != skip_pos) {
+      const int id = (int)(tag & ~kLastFacet);
+      float t, u, v;
+      if (facet_test(r, f.p0, f.p1, f.p2, t, u, v) && t >= r.tmin &&
+          (t < bt || (t == bt && id < bid))) {
+        bt = t;
+        bu = u;
+        bv = v;
+        bpos = k;
+        bid = id;
+      }
+    }
+    if (mine) break;
+  }
+#pragma unroll
+  for (int off = 1; off < G; off <<= 1) {
+    const float ot = __shfl_xor(bt, off), ou = __shfl_xor(bu, off), ov = __shfl_xor(bv, off);
+    const int oid = __shfl_xor(bid, off), opos = __shfl_xor(bpos, off);
+    if (ot < bt || (ot == bt && oid < bid)) {
+      bt = ot;
+      bu = ou;
+      bv = ov;
+      bid = oid;
+      bpos = opos;
+    }
+  }
+  h.t = bt;
+  h.u = bu;
+  h.v = bv;
+  h.pos = bpos;
+  if (bpos >= 0) h.id = bid;
+  best_id = bid;
+}
+
+template <int FMT, bool STATS, int G = 1>
 __device__ __forceinline__ Hit closest(const void* __restrict__ nodes, const TFacet* __restrict__ tf,
                        const RayPre& r, int skip_pos, int* stack_col, uint32_t& nvis,
-                       uint32_t& ntest) {
+                       uint32_t& ntest, int n_tf = 0) {
   Stack st;
   st.col = stack_col;
   int node = 0;
@@ -363,7 +422,8 @@ __device__ __forceinline__ Hit closest(const void* __restrict__ nodes, const TFa
         if (__ballot(leaf == 0 && node != kDone) == 0ull) break;
       }
       while (leaf < 0) {
-        leaf_test<STATS>(tf, r, leaf, skip_pos, h, best_id, ntest);
+        if constexpr (G == 1) leaf_test<STATS>(tf, r, leaf, skip_pos, h, best_id, ntest);
+        else leaf_test_group<G>(tf, n_tf, r, leaf, skip_pos, h, best_id);
         leaf = 0;
         if (node < 0 && node != kDone) {
           leaf = node;
@@ -457,7 +517,8 @@ __device__ __forceinline__ Hit closest(const void* __restrict__ nodes, const TFa
       if (__ballot(leaf == 0 && node != kDone) == 0ull) break;
     }
     while (leaf < 0) {
-      leaf_test<STATS>(tf, r, leaf, skip_pos, h, best_id, ntest);
+      if constexpr (G == 1) leaf_test<STATS>(tf, r, leaf, skip_pos, h, best_id, ntest);
+      else leaf_test_group<G>(tf, n_tf, r, leaf, skip_pos, h, best_id);
       leaf = 0;
       if (node < 0 && node != kDone) {
         leaf = node;
@@ -488,15 +549,22 @@ constexpr int kBlock = 64;  // one wave per work-group: the LDS stack is per wav
 // wave's chains have ended, so a wave traces adjacent launch directions
 // together; with `refill` it tops up free lanes at every segment.  A wave
 // exits once its rays are done; no wave ever waits for another.
-template <int FMT, bool BOUNCE, bool SEG, bool STATS, bool RECV, bool ENERGY = false>
+// With G > 1 (default launch only) the G lanes of each aligned group trace
+// one chain together: every lane of the group holds the same chain state,
+// the facets of each leaf are split over them, and only the group's first
+// lane writes results; a wave then takes 64 / G consecutive rays.
+template <int FMT, bool BOUNCE, bool SEG, bool STATS, bool RECV, bool ENERGY = false, int G = 1>
 __device__ __forceinline__ void trace_chains(const void* __restrict__ tn, const TFacet* __restrict__ tf,
                              const float4* __restrict__ rays, int64_t n, int max_b,
                              rt_hit* __restrict__ out, double* __restrict__ path_len,
                              int32_t* __restrict__ n_hits, float4* __restrict__ seg,
                              uint32_t* __restrict__ stats, unsigned long long* __restrict__ queue,
                              int refill, int64_t batch_base, int* stack,
-                             const RecvArgs& recv, const EnergyArgs& en = EnergyArgs{}) {
+                             const RecvArgs& recv, const EnergyArgs& en = EnergyArgs{},
+                             int n_tf = 0) {
+  static_assert(G == 1 || !STATS, "per-ray statistics are kept by the one-lane form only");
   const int lane = threadIdx.x & 63;
+  const bool writer = G == 1 || (lane & (G - 1)) == 0;
   const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   int64_t i = -1;  // ray of this lane, -1 when free
   float ox = 0.f, oy = 0.f, oz = 0.f, dx = 0.f, dy = 0.f, dz = 0.f, tmin = 0.f, tmax = 0.f;
@@ -518,7 +586,9 @@ __device__ __forceinline__ void trace_chains(const void* __restrict__ tn, const 
       }
       if (base >= (unsigned long long)n) drained = true;
       if (i < 0) {
-        const unsigned long long j = base + __popcll(free_lanes & below);
+        const unsigned long long j =
+            base + (G == 1 ? (unsigned long long)__popcll(free_lanes & below)
+                           : (unsigned long long)(lane / G));
         if (j < (unsigned long long)n) {
           i = (int64_t)j;
           const float4 ra = rays[2 * i], rb = rays[2 * i + 1];
@@ -537,12 +607,12 @@ __device__ __forceinline__ void trace_chains(const void* __restrict__ tn, const 
     if (__ballot(i >= 0) == 0ull) break;
     if (i < 0) continue;
     // one segment of this lane's chain
-    if (SEG) {
+    if (SEG && writer) {
       seg[2 * ((int64_t)b * n + i)] = make_float4(ox, oy, oz, tmin);
       seg[2 * ((int64_t)b * n + i) + 1] = make_float4(dx, dy, dz, tmax);
     }
     const RayPre r = prepare<FMT>(ox, oy, oz, dx, dy, dz, tmin, tmax);
-    Hit h = closest<FMT, STATS>(tn, tf, r, skip, stack, nvis, ntest);
+    Hit h = closest<FMT, STATS, G>(tn, tf, r, skip, stack, nvis, ntest, n_tf);
     N2 nrm;
     if (h.id >= 0) {
       // the facet is decided; its distance is recomputed accurately
@@ -551,8 +621,8 @@ __device__ __forceinline__ void trace_chains(const void* __restrict__ tn, const 
       const float tp = plane_t(nrm, f.p0, ox, oy, oz, dx, dy, dz);
       if (isfinite(tp)) h.t = fminf(fmaxf(tp, tmin), tmax);
     }
-    store_hit(out, (int64_t)b * n + i, h);
-    if (RECV)  // receiving spheres (Sec. III-C): path holds the length before this segment
+    if (writer) store_hit(out, (int64_t)b * n + i, h);
+    if (RECV && writer)  // receiving spheres (Sec. III-C): path holds the length before this segment
       receive_segment(recv, i, b, ox, oy, oz, dx, dy, dz, tmin, h.id >= 0 ? h.t : tmax, path);
     bool more = false;
     if (BOUNCE && h.id >= 0) {
@@ -577,7 +647,7 @@ __device__ __forceinline__ void trace_chains(const void* __restrict__ tn, const 
       }
     }
     if (!more) {  // chain finished: segments never launched read as misses
-      if (BOUNCE) {
+      if (BOUNCE && writer) {
         Hit none;
         none.id = -1;
         for (int q = b + 1; q < max_b; ++q) store_hit(out, (int64_t)q * n + i, none);
@@ -595,8 +665,9 @@ __device__ __forceinline__ void trace_chains(const void* __restrict__ tn, const 
 }
 
 // The LDS stack (dynamic shared memory) holds exactly the entries the tree
-// can need: stack_need(depth) per lane, in lane-column layout.
-template <int FMT, bool BOUNCE, bool SEG, bool STATS>
+// can need: stack_need(depth) per lane, in lane-column layout.  With G > 1
+// lanes per ray a work-group takes the 64 / G rays from blockIdx.x * 64 / G.
+template <int FMT, bool BOUNCE, bool SEG, bool STATS, int G = 1>
 __global__ __launch_bounds__(kBlock) void k_trace(const void* __restrict__ tn,
                                                   const TFacet* __restrict__ tf,
                                                   const float4* __restrict__ rays, int64_t n,
@@ -606,26 +677,27 @@ __global__ __launch_bounds__(kBlock) void k_trace(const void* __restrict__ tn,
                                                   float4* __restrict__ seg,
                                                   uint32_t* __restrict__ stats,
                                                   unsigned long long* __restrict__ queue,
-                                                  int refill) {
+                                                  int refill, int n_tf) {
   extern __shared__ int s_stack[];
-  trace_chains<FMT, BOUNCE, SEG, STATS, false>(tn, tf, rays, n, max_b, out, path_len, n_hits, seg,
-                                               stats, queue, refill, (int64_t)blockIdx.x * kBlock,
-                                               s_stack + threadIdx.x, RecvArgs{});
+  trace_chains<FMT, BOUNCE, SEG, STATS, false, false, G>(
+      tn, tf, rays, n, max_b, out, path_len, n_hits, seg, stats, queue, refill,
+      (int64_t)blockIdx.x * (kBlock / G), s_stack + threadIdx.x, RecvArgs{}, EnergyArgs{}, n_tf);
 }
 
 // Reflection chains whose segments are tested against field points as they
 // are traced (Sec. III-C): nothing per segment is stored.
-template <int FMT>
+template <int FMT, int G = 1>
 __global__ __launch_bounds__(kBlock) void k_trace_recv(const void* __restrict__ tn,
                                                        const TFacet* __restrict__ tf,
                                                        const float4* __restrict__ rays, int64_t n,
                                                        int max_b, rt_hit* __restrict__ out,
                                                        double* __restrict__ path_len,
-                                                       int32_t* __restrict__ n_hits, RecvArgs recv) {
+                                                       int32_t* __restrict__ n_hits, RecvArgs recv,
+                                                       int n_tf) {
   extern __shared__ int s_stack[];
-  trace_chains<FMT, true, false, false, true>(tn, tf, rays, n, max_b, out, path_len, n_hits, nullptr,
-                                              nullptr, nullptr, 0, (int64_t)blockIdx.x * kBlock,
-                                              s_stack + threadIdx.x, recv);
+  trace_chains<FMT, true, false, false, true, false, G>(
+      tn, tf, rays, n, max_b, out, path_len, n_hits, nullptr, nullptr, nullptr, 0,
+      (int64_t)blockIdx.x * (kBlock / G), s_stack + threadIdx.x, recv, EnergyArgs{}, n_tf);
 }
 
 // Reflection chains that also stop by energy (Sec. III-B), with or without
@@ -721,7 +793,7 @@ size_t stack_bytes(int depth) {
 template <int FMT, bool BOUNCE, bool SEG, bool STATS>
 void launch(const Buffers& B, int depth, const float* rays, int64_t n, int max_b, rt_hit* out,
             double* path_len, int32_t* n_hits, float* seg, uint32_t* stats, int grid,
-            int refill, hipStream_t s) {
+            int refill, int n_tf, hipStream_t s) {
   const int64_t batches = (n + kBlock - 1) / kBlock;
   const void* nodes = FMT == RT_NODE_BIN2 ? (const void*)B.tnodes : (const void*)B.wnodes;
   unsigned long long* q = nullptr;
@@ -735,24 +807,43 @@ void launch(const Buffers& B, int depth, const float* rays, int64_t n, int max_b
   hipLaunchKernelGGL((k_trace<FMT, BOUNCE, SEG, STATS>), dim3((unsigned)blocks), dim3(kBlock),
                      stack_bytes<FMT>(depth), s, nodes, B.tfacets,
                      reinterpret_cast<const float4*>(rays), n, max_b, out, path_len, n_hits,
-                     reinterpret_cast<float4*>(seg), stats, q, refill);
+                     reinterpret_cast<float4*>(seg), stats, q, refill, n_tf);
+}
+
+// G lanes per ray: one work-group per 64 / G consecutive rays.
+template <int FMT, int G>
+void launch_group(const Buffers& B, int depth, const float* rays, int64_t n, int max_b,
+                  rt_hit* out, double* path_len, int32_t* n_hits, int n_tf, hipStream_t s) {
+  constexpr int per_wave = kBlock / G;
+  const int64_t blocks = (n + per_wave - 1) / per_wave;
+  const void* nodes = FMT == RT_NODE_BIN2 ? (const void*)B.tnodes : (const void*)B.wnodes;
+  hipLaunchKernelGGL((k_trace<FMT, true, false, false, G>), dim3((unsigned)blocks), dim3(kBlock),
+                     stack_bytes<FMT>(depth), s, nodes, B.tfacets,
+                     reinterpret_cast<const float4*>(rays), n, max_b, out, path_len, n_hits,
+                     nullptr, nullptr, nullptr, 0, n_tf);
 }
 
 template <int FMT>
 void launch_fmt(const Buffers& B, int depth, const float* rays, int64_t n, int max_b, rt_hit* out,
                 double* path_len, int32_t* n_hits, float* seg, uint32_t* stats, int grid,
-                int refill, hipStream_t s) {
+                int refill, int lanes, int n_tf, hipStream_t s) {
+  switch (lanes) {  // the caller allows lanes > 1 only without seg, stats and grid
+    case 4: return launch_group<FMT, 4>(B, depth, rays, n, max_b, out, path_len, n_hits, n_tf, s);
+    case 16: return launch_group<FMT, 16>(B, depth, rays, n, max_b, out, path_len, n_hits, n_tf, s);
+    case 64: return launch_group<FMT, 64>(B, depth, rays, n, max_b, out, path_len, n_hits, n_tf, s);
+    default: break;
+  }
   const bool bounce = max_b > 1 || path_len || n_hits;
   if (!bounce && !seg && !stats) {
-    launch<FMT, false, false, false>(B, depth, rays, n, 1, out, nullptr, nullptr, nullptr, nullptr, grid, refill, s);
+    launch<FMT, false, false, false>(B, depth, rays, n, 1, out, nullptr, nullptr, nullptr, nullptr, grid, refill, n_tf, s);
   } else if (!seg && !stats) {
-    launch<FMT, true, false, false>(B, depth, rays, n, max_b, out, path_len, n_hits, nullptr, nullptr, grid, refill, s);
+    launch<FMT, true, false, false>(B, depth, rays, n, max_b, out, path_len, n_hits, nullptr, nullptr, grid, refill, n_tf, s);
   } else if (seg && !stats) {
-    launch<FMT, true, true, false>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, nullptr, grid, refill, s);
+    launch<FMT, true, true, false>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, nullptr, grid, refill, n_tf, s);
   } else if (!seg) {
-    launch<FMT, true, false, true>(B, depth, rays, n, max_b, out, path_len, n_hits, nullptr, stats, grid, refill, s);
+    launch<FMT, true, false, true>(B, depth, rays, n, max_b, out, path_len, n_hits, nullptr, stats, grid, refill, n_tf, s);
   } else {
-    launch<FMT, true, true, true>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, stats, grid, refill, s);
+    launch<FMT, true, true, true>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, stats, grid, refill, n_tf, s);
   }
 }
 
@@ -813,27 +904,63 @@ int trace_resident_groups(int node_format, bool recv, int depth) {
   }
 }
 
+namespace {
+template <int FMT, int G>
+void launch_recv_fmt(const Buffers& B, int depth, const float4* rays, int64_t n, int max_b,
+                     rt_hit* out, double* path_len, int32_t* n_hits, const RecvArgs& recv,
+                     int n_tf, hipStream_t s) {
+  constexpr int per_wave = kBlock / G;
+  const unsigned blocks = (unsigned)((n + per_wave - 1) / per_wave);
+  const void* nodes = FMT == RT_NODE_BIN2 ? (const void*)B.tnodes : (const void*)B.wnodes;
+  hipLaunchKernelGGL((k_trace_recv<FMT, G>), dim3(blocks), dim3(kBlock), stack_bytes<FMT>(depth),
+                     s, nodes, B.tfacets, rays, n, max_b, out, path_len, n_hits, recv, n_tf);
+}
+
+template <int FMT>
+void launch_recv_lanes(const Buffers& B, int depth, const float4* rays, int64_t n, int max_b,
+                       rt_hit* out, double* path_len, int32_t* n_hits, const RecvArgs& recv,
+                       int lanes, int n_tf, hipStream_t s) {
+  switch (lanes) {
+    case 4: return launch_recv_fmt<FMT, 4>(B, depth, rays, n, max_b, out, path_len, n_hits, recv, n_tf, s);
+    case 16: return launch_recv_fmt<FMT, 16>(B, depth, rays, n, max_b, out, path_len, n_hits, recv, n_tf, s);
+    case 64: return launch_recv_fmt<FMT, 64>(B, depth, rays, n, max_b, out, path_len, n_hits, recv, n_tf, s);
+    default: return launch_recv_fmt<FMT, 1>(B, depth, rays, n, max_b, out, path_len, n_hits, recv, n_tf, s);
+  }
+}
+
+// Lanes per ray chosen by the library.  Sharing a ray among G lanes cuts the
+// serial leaf tests of a chain by about G but multiplies the traversal and
+// merge work by G, so it pays while the launch is small for the leaf size:
+// timed on the paper-size scenes (leaves of 16 to 820 facets, 642 to 2.6 M
+// rays, every G), the fastest G is close to the largest of 64, 16, 4 with
+// G <= max_leaf and n G <= kGroupLanesPerFacet max_leaf.  Trees with small
+// leaves keep one lane per ray.
+constexpr int kGroupLeaf = 16;
+constexpr int64_t kGroupLanesPerFacet = 41000;
+}  // namespace
+
+int trace_lanes(int64_t n, int max_leaf) {
+  if (max_leaf < kGroupLeaf || n <= 0) return 1;
+  for (int g = 64; g > 1; g /= 4)
+    if (g <= max_leaf && n * g <= kGroupLanesPerFacet * max_leaf) return g;
+  return 1;
+}
+
 int launch_trace_receive(const Buffers& B, int node_format, int depth, const float* rays,
                          int64_t n, int32_t max_b, rt_hit* out, double* path_len,
-                         int32_t* n_hits, const RecvArgs& recv, hipStream_t s) {
+                         int32_t* n_hits, const RecvArgs& recv, int lanes, int n_tf,
+                         hipStream_t s) {
   if (n == 0) return RT_OK;
-  const unsigned blocks = (unsigned)((n + kBlock - 1) / kBlock);
   const float4* r4 = reinterpret_cast<const float4*>(rays);
   switch (node_format) {
     case RT_NODE_F4:
-      hipLaunchKernelGGL(k_trace_recv<RT_NODE_F4>, dim3(blocks), dim3(kBlock),
-                         stack_bytes<RT_NODE_F4>(depth), s, (const void*)B.wnodes, B.tfacets, r4,
-                         n, max_b, out, path_len, n_hits, recv);
+      launch_recv_lanes<RT_NODE_F4>(B, depth, r4, n, max_b, out, path_len, n_hits, recv, lanes, n_tf, s);
       break;
     case RT_NODE_Q4:
-      hipLaunchKernelGGL(k_trace_recv<RT_NODE_Q4>, dim3(blocks), dim3(kBlock),
-                         stack_bytes<RT_NODE_Q4>(depth), s, (const void*)B.wnodes, B.tfacets, r4,
-                         n, max_b, out, path_len, n_hits, recv);
+      launch_recv_lanes<RT_NODE_Q4>(B, depth, r4, n, max_b, out, path_len, n_hits, recv, lanes, n_tf, s);
       break;
     default:
-      hipLaunchKernelGGL(k_trace_recv<RT_NODE_BIN2>, dim3(blocks), dim3(kBlock),
-                         stack_bytes<RT_NODE_BIN2>(depth), s, (const void*)B.tnodes, B.tfacets, r4,
-                         n, max_b, out, path_len, n_hits, recv);
+      launch_recv_lanes<RT_NODE_BIN2>(B, depth, r4, n, max_b, out, path_len, n_hits, recv, lanes, n_tf, s);
       break;
   }
   return check_hip(hipGetLastError(), "trace+receive launch");
@@ -878,7 +1005,7 @@ int launch_trace_energy(const Buffers& B, int node_format, int depth, const floa
 
 int launch_trace(const Buffers& B, int node_format, int depth, const float* rays, int64_t n,
                  int32_t max_b, rt_hit* out, double* path_len, int32_t* n_hits,
-                 const rt_trace_opts* opts, hipStream_t s) {
+                 const rt_trace_opts* opts, int lanes, int n_tf, hipStream_t s) {
   if (n == 0) return RT_OK;
   float* seg = opts ? opts->seg_rays : nullptr;
   uint32_t* stats = opts ? opts->ray_stats : nullptr;
@@ -886,13 +1013,13 @@ int launch_trace(const Buffers& B, int node_format, int depth, const float* rays
   const int refill = opts ? opts->refill : 0;
   switch (node_format) {
     case RT_NODE_F4:
-      launch_fmt<RT_NODE_F4>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, stats, grid, refill, s);
+      launch_fmt<RT_NODE_F4>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, stats, grid, refill, lanes, n_tf, s);
       break;
     case RT_NODE_Q4:
-      launch_fmt<RT_NODE_Q4>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, stats, grid, refill, s);
+      launch_fmt<RT_NODE_Q4>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, stats, grid, refill, lanes, n_tf, s);
       break;
     default:
-      launch_fmt<RT_NODE_BIN2>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, stats, grid, refill, s);
+      launch_fmt<RT_NODE_BIN2>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, stats, grid, refill, lanes, n_tf, s);
       break;
   }
   return check_hip(hipGetLastError(), "trace launch");
