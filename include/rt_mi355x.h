@@ -188,7 +188,10 @@ typedef struct rt_trace_opts {
                           Results do not depend on it. */
 } rt_trace_opts;
 
-/* rt_trace_bounces with optional outputs (opts nullable). */
+/* rt_trace_bounces with optional outputs (opts nullable).
+ * Errors: as rt_trace_bounces; RT_EINVAL for a misaligned seg_rays / ray_stats,
+ * block, grid, refill or lanes_per_ray outside their values, lanes_per_ray > 1
+ * with seg_rays, ray_stats or grid > 0, or n > (2^31 - 1) 64 / lanes_per_ray. */
 int rt_trace_ex(const rt_bvh* b, const float* rays, int64_t n, int32_t max_bounces,
                 rt_hit* out, double* path_len, int32_t* n_hits, const rt_trace_opts* opts,
                 hipStream_t s);
