@@ -184,7 +184,8 @@ typedef struct rt_trace_opts {
                           device); > 1 requires seg_rays and ray_stats NULL and grid 0.  The
                           library chooses > 1 only for trees built with max_leaf >= 16: the
                           largest G of 64, 16, 4 with G <= max_leaf and n G <= 41000 max_leaf,
-                          the same for rt_trace, rt_trace_bounces and rt_trace_receive.
+                          the same for rt_trace, rt_trace_bounces and rt_trace_receive
+                          (rt_trace_energy and batched launches trace one lane per ray).
                           Results do not depend on it. */
 } rt_trace_opts;
 
@@ -249,7 +250,9 @@ typedef struct rt_reception {
 } rt_reception; /* 32 bytes */
 
 typedef struct rt_receivers {
-  const double* pos;  /* device float64 [n][3] field points, 8-byte aligned */
+  const double* pos;  /* device float64 [n][3] field points, 8-byte aligned; read as constant
+                         data, so it may not overlap rec, count or any other output of the
+                         call (RT_EINVAL) and must not change while a launch runs */
   int32_t n;          /* number of field points, >= 0 */
   int32_t reserved;   /* must be 0 */
   double delta;       /* angle between adjacent launched rays, radians, finite, >= 0 */

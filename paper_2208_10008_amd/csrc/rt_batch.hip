@@ -36,7 +36,11 @@ int query_error(const rt_query& q) {
       return RT_EINVAL;
   }
   if (q.receivers) {  // reception records hold 32-bit ray numbers
-    if (check_rx(q.receivers, "rt_batch_set") != RT_OK || q.n > INT32_MAX) return RT_EINVAL;
+    if (check_rx(q.receivers, "rt_batch_set",
+                 {{q.out, (int64_t)q.max_bounces * q.n * 16}, {q.path_len, q.n * 8},
+                  {q.n_hits, q.n * 4}}) != RT_OK ||
+        q.n > INT32_MAX)
+      return RT_EINVAL;
   }
   return RT_OK;
 }

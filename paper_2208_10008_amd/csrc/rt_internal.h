@@ -2,6 +2,9 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <initializer_list>
+#include <utility>
 #include <stdint.h>
 
 #include <string>
@@ -200,29 +203,48 @@ __device__ __forceinline__ double seg_path(float t, float dx, float dy, float dz
 //
 // The decision is the float64 expression below.  Before it, a float32 test
 // rejects pairs that cannot pass: with w = R - o and c = |w x d|^2 =
-// dist^2 |d|^2, a received pair has dist <= (L + |w|) delta / sqrt(3); the
-// float32 values of w, c, |w| and |d|^2 are within a few 1e-7 of
-// |o|_1 + |w| + L of the exact ones, and the test allows 1e-4 of that sum
+// dist^2 |d|^2, a received pair has dist <= (L + |w|) delta / sqrt(3) <=
+// (L + |w|_1) delta / sqrt(3) (the 1-norm bounds |w| without a square root);
+// the float32 values of w, c, |w|_1 and |d|^2 are within a few 1e-7 of
+// |o|_1 + |w|_1 + L of the exact ones, and the test allows 1e-4 of that sum
 // plus 0.1 % of the radius, so every pair the float64 test would receive
 // passes it (a NaN or overflow in float32 also passes).  Most pairs are far
 // from the line and stop here; the float64 test runs when a lane needs it.
+// The field point's index is the same on every lane and the field points do
+// not overlap anything a kernel writes (the host checks it), so their
+// coordinates are read through the scalar cache as constant data.
 __device__ __forceinline__ void receive_segment(const RecvArgs& a, int64_t ray, int order,
                                                 float ox, float oy, float oz, float dx, float dy,
                                                 float dz, float t0, float t1, double L) {
   const int lane = threadIdx.x & 63;
   const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  const float ddf = dx * dx + dy * dy + dz * dz;
+  const float ddk = (dx * dx + dy * dy + dz * dz) * 1.001f;
   const float Lf = (float)L;
   const float base = fabsf(ox) + fabsf(oy) + fabsf(oz) + Lf;
   const float kd = (float)(a.delta * 0.57735026918962576) * 1.001f;  // delta / sqrt(3)
+  // radius (L + |w|_1) kd + 1e-4 (base + |w|_1) = rad0 + |w|_1 kw
+  const float rad0 = fmaf(Lf, kd, 1e-4f * base);
+  const float kw = kd + 1e-4f;
+  typedef __attribute__((address_space(4))) const double ConstDouble;
+  ConstDouble* pos = (ConstDouble*)a.pos;
+  // the next field point is loaded while this one is tested
+  double nx = 0.0, ny = 0.0, nz = 0.0;
+  if (a.n_rx > 0) {
+    nx = pos[0];
+    ny = pos[1];
+    nz = pos[2];
+  }
   for (int r = 0; r < a.n_rx; ++r) {
-    const double Rx = a.pos[3 * r], Ry = a.pos[3 * r + 1], Rz = a.pos[3 * r + 2];
+    const double Rx = nx, Ry = ny, Rz = nz;
+    const int rn = __builtin_amdgcn_readfirstlane(r + 1 < a.n_rx ? r + 1 : r);
+    nx = pos[3 * rn];
+    ny = pos[3 * rn + 1];
+    nz = pos[3 * rn + 2];
     const float wx = (float)Rx - ox, wy = (float)Ry - oy, wz = (float)Rz - oz;
     const float cx = wy * dz - wz * dy, cy = wz * dx - wx * dz, cz = wx * dy - wy * dx;
     const float c = cx * cx + cy * cy + cz * cz;
-    const float wl = sqrtf(wx * wx + wy * wy + wz * wz);
-    const float rad = (Lf + wl) * kd + 1e-4f * (base + wl);
-    const bool maybe = !(c > ddf * rad * rad * 1.001f);
+    const float rad = fmaf(fabsf(wx) + fabsf(wy) + fabsf(wz), kw, rad0);
+    const bool maybe = !(c > ddk * rad * rad);
     if (__ballot(maybe) == 0ull) continue;
     bool ok = false;
     double l = 0.0, dist2 = 0.0;
@@ -307,7 +329,9 @@ int launch_batch_clear_counts(const BatchQuery* table, int nq, hipStream_t s);
 // Work-groups of the trace kernel that fit the device at once for this format and depth.
 int trace_resident_groups(int node_format, bool recv, int depth);
 // receive.hip: argument checks of a receivers struct and its kernel arguments.
-int check_rx(const rt_receivers* rx, const char* who);
+// Ranges (pointer, bytes) a call writes besides the reception records.
+using WrittenRanges = std::initializer_list<std::pair<const void*, int64_t>>;
+int check_rx(const rt_receivers* rx, const char* who, WrittenRanges written = {});
 RecvArgs recv_args(const rt_receivers* rx);
 // Chains with the reception test of every segment (receive.hip zeroes the count first).
 int launch_trace_receive(const Buffers& B, int node_format, int depth, const float* rays,

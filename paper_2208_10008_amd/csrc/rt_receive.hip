@@ -156,7 +156,7 @@ int check_energy(const rt_energy* e) {
 
 }  // namespace
 
-int check_rx(const rt_receivers* rx, const char* who) {
+int check_rx(const rt_receivers* rx, const char* who, WrittenRanges written) {
   const std::string w(who);
   if (!rx) return set_error(RT_EINVAL, w + ": receivers struct is NULL");
   if (rx->n < 0 || rx->reserved != 0) return set_error(RT_EINVAL, w + ": n must be >= 0, reserved 0");
@@ -169,6 +169,20 @@ int check_rx(const rt_receivers* rx, const char* who) {
     return set_error(RT_EINVAL, w + ": rec must be non-NULL and 16-byte aligned");
   if (!rx->count || !aligned_to(rx->count, 8))
     return set_error(RT_EINVAL, w + ": count must be non-NULL and 8-byte aligned");
+  // the kernels read the field points as constant data: nothing the call
+  // writes may overlap them
+  if (rx->n > 0) {
+    const uintptr_t p0 = reinterpret_cast<uintptr_t>(rx->pos);
+    const uintptr_t p1 = p0 + static_cast<uintptr_t>(rx->n) * 3 * sizeof(double);
+    auto overlaps = [&](const void* q, int64_t bytes) {
+      const uintptr_t q0 = reinterpret_cast<uintptr_t>(q);
+      return q != nullptr && bytes > 0 && q0 < p1 && p0 < q0 + static_cast<uintptr_t>(bytes);
+    };
+    bool clash = overlaps(rx->rec, rx->cap * (int64_t)sizeof(rt_reception)) ||
+                 overlaps(rx->count, 8);
+    for (const auto& wr : written) clash = clash || overlaps(wr.first, wr.second);
+    if (clash) return set_error(RT_EINVAL, w + ": pos overlaps memory the call writes");
+  }
   return RT_OK;
 }
 
@@ -195,7 +209,8 @@ int rt_trace_receive(const rt_bvh* b, const float* rays, int64_t n, int32_t max_
                      hipStream_t s) {
   int rc = check_trace_args(b, rays, n, max_bounces, out, path_len, n_hits, nullptr);
   if (rc != RT_OK) return rc;
-  rc = check_rx(rx, "rt_trace_receive");
+  rc = check_rx(rx, "rt_trace_receive",
+                {{out, (int64_t)max_bounces * n * 16}, {path_len, n * 8}, {n_hits, n * 4}});
   if (rc != RT_OK) return rc;
   if (n > INT32_MAX) return set_error(RT_EINVAL, "rt_trace_receive: n must be < 2^31");
   RecvArgs a = recv_args(rx);
@@ -216,7 +231,8 @@ int rt_trace_energy(const rt_bvh* b, const float* rays, int64_t n, int32_t max_b
   if (rc != RT_OK) return rc;
   RecvArgs a{};
   if (rx) {
-    rc = check_rx(rx, "rt_trace_energy");
+    rc = check_rx(rx, "rt_trace_energy", {{out, (int64_t)max_bounces * n * 16}, {path_len, n * 8},
+                                          {n_hits, n * 4}, {e->power, n * 8}});
     if (rc != RT_OK) return rc;
     if (n > INT32_MAX) return set_error(RT_EINVAL, "rt_trace_energy: n must be < 2^31 with receivers");
     a = recv_args(rx);

@@ -250,7 +250,8 @@ def test_reception_argument_checks():
     p = ctypes.c_void_p(base)
 
     def rx(**kw):
-        r = R.rt_receivers(pos=base, n=2, reserved=0, delta=0.01, rec=base, cap=4, count=base)
+        r = R.rt_receivers(pos=base, n=2, reserved=0, delta=0.01, rec=base + 256, cap=4,
+                           count=base + 512)
         for k, v in kw.items():
             setattr(r, k, v)
         return ctypes.byref(r)
@@ -268,6 +269,11 @@ def test_reception_argument_checks():
     assert seg(p, p, 4, 2, rx(rec=None), None) == R.RT_EINVAL
     assert seg(p, p, 4, 2, rx(rec=base + 8), None) == R.RT_EINVAL
     assert seg(p, p, 4, 2, rx(count=None), None) == R.RT_EINVAL
+    # field points are read as constant data: nothing the call writes may overlap them
+    for kw in (dict(rec=base), dict(rec=base + 32), dict(count=base + 40), dict(pos=base + 512)):
+        assert seg(p, p, 4, 2, rx(**kw), None) == R.RT_EINVAL, kw
+        assert b"overlaps" in lib.rt_last_error(), kw
+    assert lib.rt_trace_receive(None, p, 4, 2, p, None, None, rx(), None) == R.RT_EINVAL
     assert seg(p, p, 4, 0, rx(), None) == R.RT_EINVAL                 # max_bounces
     assert seg(p, p, 4, 65, rx(), None) == R.RT_EINVAL
     assert seg(p, p, -1, 2, rx(), None) == R.RT_EINVAL
