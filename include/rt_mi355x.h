@@ -182,8 +182,9 @@ typedef struct rt_trace_opts {
                           many lanes trace each ray together and split every leaf's facets
                           (for trees with large leaves and launches too small to fill the
                           device); > 1 requires seg_rays and ray_stats NULL and grid 0.  The
-                          library chooses > 1 only for trees built with max_leaf >= 16: the
-                          largest G of 64, 16, 4 with G <= max_leaf and n G <= 41000 max_leaf,
+                          library chooses > 1 only for trees built with max_leaf >= 16: with
+                          G <= max_leaf, 64 for n <= 50 max_leaf, 16 for n <= 700 max_leaf,
+                          4 for n <= 12000 max_leaf,
                           the same for rt_trace, rt_trace_bounces and rt_trace_receive
                           (rt_trace_energy and batched launches trace one lane per ray).
                           Results do not depend on it. */

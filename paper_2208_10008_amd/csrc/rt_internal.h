@@ -315,7 +315,8 @@ int build_tree(Buffers& B, const float* tris, int64_t n, const rt_split_params& 
 int launch_trace(const Buffers& B, int node_format, int depth, const float* rays, int64_t n,
                  int32_t max_bounces, rt_hit* out, double* path_len, int32_t* n_hits,
                  const rt_trace_opts* opts, int lanes, int n_tf, hipStream_t s);
-// Lanes per ray the library picks for n rays on a tree built with max_leaf.
+// Lanes per ray the library picks for n rays on a tree built with max_leaf
+// (api.hip).
 int trace_lanes(int64_t n, int max_leaf);
 // Batched launch over table[0 .. nq) (device), all of one node format;
 // total_batches work-groups, or `grid` persistent work-groups taking batches

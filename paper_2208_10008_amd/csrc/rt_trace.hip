@@ -928,23 +928,7 @@ void launch_recv_lanes(const Buffers& B, int depth, const float4* rays, int64_t 
   }
 }
 
-// Lanes per ray chosen by the library.  Sharing a ray among G lanes cuts the
-// serial leaf tests of a chain by about G but multiplies the traversal and
-// merge work by G, so it pays while the launch is small for the leaf size:
-// timed on the paper-size scenes (leaves of 16 to 820 facets, 642 to 2.6 M
-// rays, every G), the fastest G is close to the largest of 64, 16, 4 with
-// G <= max_leaf and n G <= kGroupLanesPerFacet max_leaf.  Trees with small
-// leaves keep one lane per ray.
-constexpr int kGroupLeaf = 16;
-constexpr int64_t kGroupLanesPerFacet = 41000;
 }  // namespace
-
-int trace_lanes(int64_t n, int max_leaf) {
-  if (max_leaf < kGroupLeaf || n <= 0) return 1;
-  for (int g = 64; g > 1; g /= 4)
-    if (g <= max_leaf && n * g <= kGroupLanesPerFacet * max_leaf) return g;
-  return 1;
-}
 
 int launch_trace_receive(const Buffers& B, int node_format, int depth, const float* rays,
                          int64_t n, int32_t max_b, rt_hit* out, double* path_len,
