@@ -185,8 +185,8 @@ typedef struct rt_trace_opts {
                           library chooses > 1 only for trees built with max_leaf >= 16: with
                           G <= max_leaf, 64 for n <= 50 max_leaf, 16 for n <= 700 max_leaf,
                           4 for n <= 12000 max_leaf,
-                          the same for rt_trace, rt_trace_bounces and rt_trace_receive
-                          (rt_trace_energy and batched launches trace one lane per ray).
+                          the same for rt_trace, rt_trace_bounces, rt_trace_receive and
+                          rt_trace_energy (batched launches trace one lane per ray).
                           Results do not depend on it. */
 } rt_trace_opts;
 

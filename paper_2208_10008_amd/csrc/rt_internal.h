@@ -342,8 +342,8 @@ int launch_trace_receive(const Buffers& B, int node_format, int depth, const flo
 // Chains stopped by energy, with the reception test when recv is not null.
 int launch_trace_energy(const Buffers& B, int node_format, int depth, const float* rays,
                         int64_t n, int32_t max_bounces, rt_hit* out, double* path_len,
-                        int32_t* n_hits, const RecvArgs* recv, const EnergyArgs& en,
-                        hipStream_t s);
+                        int32_t* n_hits, const RecvArgs* recv, const EnergyArgs& en, int lanes,
+                        int n_tf, hipStream_t s);
 
 }  // namespace rt
 

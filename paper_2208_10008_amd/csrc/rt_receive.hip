@@ -250,7 +250,8 @@ int rt_trace_energy(const rt_bvh* b, const float* rays, int64_t n, int32_t max_b
   en.n_mat = e->n_materials;
   en.pad = 0;
   return launch_trace_energy(b->buf, b->info.node_format, b->info.depth, rays, n, max_bounces, out,
-                             path_len, n_hits, rx ? &a : nullptr, en, s);
+                             path_len, n_hits, rx ? &a : nullptr, en,
+                             trace_lanes(n, b->params.max_leaf), (int)b->info.n_tris, s);
 }
 
 int rt_receive_segments(const float* seg_rays, const rt_hit* hits, int64_t n, int32_t max_bounces,

@@ -702,19 +702,18 @@ __global__ __launch_bounds__(kBlock) void k_trace_recv(const void* __restrict__ 
 
 // Reflection chains that also stop by energy (Sec. III-B), with or without
 // the reception test of every segment.
-template <int FMT, bool RECV>
+template <int FMT, bool RECV, int G = 1>
 __global__ __launch_bounds__(kBlock) void k_trace_energy(const void* __restrict__ tn,
                                                          const TFacet* __restrict__ tf,
                                                          const float4* __restrict__ rays, int64_t n,
                                                          int max_b, rt_hit* __restrict__ out,
                                                          double* __restrict__ path_len,
                                                          int32_t* __restrict__ n_hits,
-                                                         RecvArgs recv, EnergyArgs en) {
+                                                         RecvArgs recv, EnergyArgs en, int n_tf) {
   extern __shared__ int s_stack[];
-  trace_chains<FMT, true, false, false, RECV, true>(tn, tf, rays, n, max_b, out, path_len, n_hits,
-                                                    nullptr, nullptr, nullptr, 0,
-                                                    (int64_t)blockIdx.x * kBlock,
-                                                    s_stack + threadIdx.x, recv, en);
+  trace_chains<FMT, true, false, false, RECV, true, G>(
+      tn, tf, rays, n, max_b, out, path_len, n_hits, nullptr, nullptr, nullptr, 0,
+      (int64_t)blockIdx.x * (kBlock / G), s_stack + threadIdx.x, recv, en, n_tf);
 }
 
 // Many queries (trees, ray sets, bounce limits) in one launch: work-group g
@@ -951,37 +950,51 @@ int launch_trace_receive(const Buffers& B, int node_format, int depth, const flo
 }
 
 namespace {
+template <int FMT, int G>
+void launch_energy_lanes(const Buffers& B, int depth, const float4* rays, int64_t n, int max_b,
+                         rt_hit* out, double* path_len, int32_t* n_hits, const RecvArgs* recv,
+                         const EnergyArgs& en, int n_tf, hipStream_t s) {
+  constexpr int per_wave = kBlock / G;
+  const unsigned blocks = (unsigned)((n + per_wave - 1) / per_wave);
+  const void* nodes = FMT == RT_NODE_BIN2 ? (const void*)B.tnodes : (const void*)B.wnodes;
+  if (recv)
+    hipLaunchKernelGGL((k_trace_energy<FMT, true, G>), dim3(blocks), dim3(kBlock),
+                       stack_bytes<FMT>(depth), s, nodes, B.tfacets, rays, n, max_b, out, path_len,
+                       n_hits, *recv, en, n_tf);
+  else
+    hipLaunchKernelGGL((k_trace_energy<FMT, false, G>), dim3(blocks), dim3(kBlock),
+                       stack_bytes<FMT>(depth), s, nodes, B.tfacets, rays, n, max_b, out, path_len,
+                       n_hits, RecvArgs{}, en, n_tf);
+}
+
 template <int FMT>
 void launch_energy_fmt(const Buffers& B, int depth, const float4* rays, int64_t n, int max_b,
                        rt_hit* out, double* path_len, int32_t* n_hits, const RecvArgs* recv,
-                       const EnergyArgs& en, hipStream_t s) {
-  const unsigned blocks = (unsigned)((n + kBlock - 1) / kBlock);
-  const void* nodes = FMT == RT_NODE_BIN2 ? (const void*)B.tnodes : (const void*)B.wnodes;
-  if (recv)
-    hipLaunchKernelGGL((k_trace_energy<FMT, true>), dim3(blocks), dim3(kBlock),
-                       stack_bytes<FMT>(depth), s, nodes, B.tfacets, rays, n, max_b, out, path_len,
-                       n_hits, *recv, en);
-  else
-    hipLaunchKernelGGL((k_trace_energy<FMT, false>), dim3(blocks), dim3(kBlock),
-                       stack_bytes<FMT>(depth), s, nodes, B.tfacets, rays, n, max_b, out, path_len,
-                       n_hits, RecvArgs{}, en);
+                       const EnergyArgs& en, int lanes, int n_tf, hipStream_t s) {
+  switch (lanes) {
+    case 4: return launch_energy_lanes<FMT, 4>(B, depth, rays, n, max_b, out, path_len, n_hits, recv, en, n_tf, s);
+    case 16: return launch_energy_lanes<FMT, 16>(B, depth, rays, n, max_b, out, path_len, n_hits, recv, en, n_tf, s);
+    case 64: return launch_energy_lanes<FMT, 64>(B, depth, rays, n, max_b, out, path_len, n_hits, recv, en, n_tf, s);
+    default: return launch_energy_lanes<FMT, 1>(B, depth, rays, n, max_b, out, path_len, n_hits, recv, en, n_tf, s);
+  }
 }
 }  // namespace
 
 int launch_trace_energy(const Buffers& B, int node_format, int depth, const float* rays, int64_t n,
                         int32_t max_b, rt_hit* out, double* path_len, int32_t* n_hits,
-                        const RecvArgs* recv, const EnergyArgs& en, hipStream_t s) {
+                        const RecvArgs* recv, const EnergyArgs& en, int lanes, int n_tf,
+                        hipStream_t s) {
   if (n == 0) return RT_OK;
   const float4* r4 = reinterpret_cast<const float4*>(rays);
   switch (node_format) {
     case RT_NODE_F4:
-      launch_energy_fmt<RT_NODE_F4>(B, depth, r4, n, max_b, out, path_len, n_hits, recv, en, s);
+      launch_energy_fmt<RT_NODE_F4>(B, depth, r4, n, max_b, out, path_len, n_hits, recv, en, lanes, n_tf, s);
       break;
     case RT_NODE_Q4:
-      launch_energy_fmt<RT_NODE_Q4>(B, depth, r4, n, max_b, out, path_len, n_hits, recv, en, s);
+      launch_energy_fmt<RT_NODE_Q4>(B, depth, r4, n, max_b, out, path_len, n_hits, recv, en, lanes, n_tf, s);
       break;
     default:
-      launch_energy_fmt<RT_NODE_BIN2>(B, depth, r4, n, max_b, out, path_len, n_hits, recv, en, s);
+      launch_energy_fmt<RT_NODE_BIN2>(B, depth, r4, n, max_b, out, path_len, n_hits, recv, en, lanes, n_tf, s);
       break;
   }
   return check_hip(hipGetLastError(), "trace+energy launch");

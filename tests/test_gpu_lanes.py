@@ -173,3 +173,24 @@ def test_lanes_argument_checks(indoor):
         assert call(lanes=ok) == R.RT_OK
     torch.cuda.synchronize()
     bvh.close()
+
+
+@pytest.mark.parametrize("level", [3, 5, 6])
+def test_library_choice_in_the_energy_path(indoor, level):
+    """rt_trace_energy on a 250-facet-leaf tree picks 64 (levels 3, 5) or 16
+    (level 6) lanes per ray; with a zero threshold no chain stops by energy,
+    so its chains must equal the one-lane fixed-order chains bit for bit, and
+    every chain with a hit reports a positive power."""
+    w = indoor
+    rays = dev(w.rays(level))
+    n, nb = rays.shape[0], 4
+    bvh = R.BVH(dev(w.tris), R.SplitParams(alpha=w.alpha, src=w.tx, max_leaf=w.max_leaf))
+    e = R.Energy(dev(w.material), dev(workloads.REFLECTION), workloads.free_space_k0(), 0.0,
+                 power=torch.full((n,), -1.0, dtype=torch.float64, device="cuda"))
+    out, pl, nh = bvh.trace_energy(rays, nb, e)
+    ref = chains(bvh, rays, nb, 1)
+    assert_same_chains((out.cpu().numpy(), pl.cpu().numpy(), nh.cpu().numpy()), ref,
+                       f"energy, level {level}")
+    pw, hn = e.power.cpu().numpy(), ref[2]
+    assert np.all(pw[hn == 0] == 0) and np.all(pw[hn > 0] > 0)
+    bvh.close()
