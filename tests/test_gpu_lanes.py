@@ -194,3 +194,19 @@ def test_library_choice_in_the_energy_path(indoor, level):
     pw, hn = e.power.cpu().numpy(), ref[2]
     assert np.all(pw[hn == 0] == 0) and np.all(pw[hn > 0] > 0)
     bvh.close()
+
+
+@pytest.mark.parametrize("which", ["indoor", "outdoor"])
+def test_lanes_at_full_size(request, which):
+    """Level 9 (2,621,442 rays, the paper regime's largest launch): 4 and 16
+    lanes per ray and the library's own choice equal one lane per ray bit for
+    bit on every chain."""
+    w = request.getfixturevalue(which)
+    bvh = R.BVH(dev(w.tris), R.SplitParams(alpha=w.alpha, src=w.tx, max_leaf=w.max_leaf))
+    rays = dev(w.rays(9))
+    nb = w.max_bounces
+    ref = chains(bvh, rays, nb, 1)
+    for g in (4, 16, 0):
+        assert_same_chains(chains(bvh, rays, nb, g), ref, f"{w.name} level 9 G={g}")
+    log(f"{w.name} level 9: {rays.shape[0]} chains equal for G = 4, 16 and the library's choice")
+    bvh.close()
