@@ -66,6 +66,7 @@ extern "C" {
 #define RT_MAX_BINS 64     /* largest nbins */
 #define RT_MAX_DEPTH 64    /* largest depth_limit: the traversal stack holds this many entries */
 #define RT_MAX_BOUNCES 64  /* largest max_bounces */
+#define RT_LEAF_HIST 16    /* buckets of the leaf-size histogram (rt_bvh_stats) */
 
 typedef struct rt_split_params {
   float alpha;       /* Eq. (2) weight in [0, 1]; 1 = surface area only (Eq. (1)), 0 = distance only */
@@ -111,6 +112,18 @@ typedef struct rt_bvh_info {
                             internal node whose children are left, left + 1 (wide formats:
                             only even-depth internal nodes have one, so some records are
                             unused) */
+  /* Filled by rt_bvh_stats (has_stats = 1); rt_bvh_info_get leaves them 0. */
+  int32_t has_stats;
+  int32_t max_leaf_count; /* facets of the largest leaf */
+  double tree_cost;     /* Eq. (1) cost of the whole tree (Sec. II-B): the sum over internal
+                           nodes n of S(n) / S(root) * t_trav plus the sum over leaves l of
+                           S(l) / S(root) * k_l * t_i, S the surface area 2 (wh + hd + dw) of
+                           the node's volume, k_l its facet count, t_i and t_trav the build's
+                           split parameters; float64.  When S(root) = 0 every ratio is 1. */
+  double root_area;     /* S(root) */
+  int64_t leaf_hist[RT_LEAF_HIST]; /* leaves by facet count c: bucket c - 1 for c <= 8,
+                           bucket 5 + floor(log2(c - 1)) for 9 <= c <= 1024 (9-16, 17-32,
+                           ..., 513-1024), bucket 15 for c > 1024 */
 } rt_bvh_info;
 
 /* One node of the binary tree.  Node 0 is the root; the two children of a
@@ -175,7 +188,9 @@ typedef struct rt_trace_opts {
   int32_t block;       /* reserved, must be 0 or 64 (one wave per work-group) */
   int32_t grid;        /* 0: one work-group (one wave) per 64 consecutive rays, scheduled by the
                           hardware (fastest measured); > 0: this many persistent work-groups
-                          taking batches of rays from an atomic queue */
+                          taking batches of rays from an atomic queue of the handle's own
+                          (each call takes the next of 64 queues, so up to 64 such calls may
+                          be in flight on one handle at once, on any streams) */
   int32_t refill;      /* persistent mode: 0 = a wave takes 64 consecutive rays when all its
                           chains have ended; 1 = free lanes take new rays at every segment */
   int32_t lanes_per_ray; /* 0: chosen by the library; 1: one lane per ray; 4, 16 or 64: that
@@ -384,7 +399,15 @@ int rt_diffract_segments(const float* tris, int64_t n_tris, const int32_t* nbr,
                          rt_diffracted* out, int64_t cap, int64_t* count, hipStream_t s);
 
 /* ---- inspection and lifetime ------------------------------------------ */
-int rt_bvh_info_get(const rt_bvh* b, rt_bvh_info* info); /* host struct */
+/* Sizes recorded by the last build (host struct, no device work). */
+int rt_bvh_info_get(const rt_bvh* b, rt_bvh_info* info);
+
+/* Tree statistics (Sec. II-B, Eq. (1) tree cost): everything rt_bvh_info_get
+ * gives plus the total cost of the tree and the leaf-size histogram, computed
+ * on the device from the built tree (float64 sums in a fixed order, so equal
+ * trees give equal bits).  info: host struct.  Synchronises the device.
+ * Errors: RT_EINVAL (NULL, tree not built), RT_EHIP. */
+int rt_bvh_stats(const rt_bvh* b, rt_bvh_info* info);
 
 /* Copies the binary tree (host buffers): nodes [info.n_nodes], perm [n_tris]
  * (leaf order of the caller's facet ids).  Synchronises the device.

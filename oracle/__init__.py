@@ -13,6 +13,10 @@ Functions and what pins them:
   ground and wall distances.
 * :func:`build_tree` -- the paper's top-down build with the Eq. (2) split.
   Pinned by tree invariants and hand-worked split choices.
+* :func:`tree_cost` -- Eq. (1) cost of a whole tree, summed node by node.
+  Pinned by hand-worked trees and by the recursive form of the same cost
+  (each node's cost is t_trav plus its children's costs weighted by their
+  surface-area ratio).
 * :func:`trace_bvh` -- Sec. III-B traversal of that tree; must equal
   :func:`brute` on every ray.
 * :func:`bounces` -- specular reflection chains; pinned by image-source
@@ -224,6 +228,21 @@ def build_tree(tris, params: SplitParams) -> Tree:
     left, right, first, count, depth, axis, plane, flags = ints
     return Tree(lo, hi, left, right, first, count, depth, axis, plane, flags, cost, perm,
                 handle=h, tris=tris)
+
+
+def tree_cost(tree: Tree, t_isect: float = 1.0, t_trav: float = 1.0) -> float:
+    """Eq. (1) cost of the whole tree (Sec. II-B), float64: every internal node
+    n adds S(n) / S(root) * t_trav, every leaf l adds S(l) / S(root) * k_l *
+    t_i, S being the surface area 2 (wh + hd + dw) of the node's volume and k_l
+    its facet count.  When S(root) is 0 every ratio is taken as 1."""
+    w = tree.hi - tree.lo
+    area = 2.0 * (w[:, 0] * w[:, 1] + w[:, 1] * w[:, 2] + w[:, 2] * w[:, 0])
+    leaf = tree.left < 0
+    if area[0] > 0.0:
+        ratio = area / area[0]
+    else:
+        ratio = np.ones_like(area)
+    return float(np.sum(ratio[~leaf]) * t_trav + np.sum(ratio[leaf] * tree.count[leaf]) * t_isect)
 
 
 def trace_bvh(tree: Tree, rays, skip=None, nthreads=0, stats=False) -> Hits:

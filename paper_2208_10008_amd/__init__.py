@@ -39,6 +39,7 @@ D_MODES = {"mean": 0, "sum": 1, "kweighted": 2, "parent": 3}
 D_NORMS = {"unit": 0, "raw": 1}
 NODE_FORMATS = {"bin2": 0, "f4": 1, "q4": 2}
 MAX_BOUNCES = 64
+LEAF_HIST = 16  # RT_LEAF_HIST
 
 
 class RtError(RuntimeError):
@@ -62,7 +63,10 @@ class rt_bvh_info(ctypes.Structure):
                 ("depth", ctypes.c_int32), ("n_levels", ctypes.c_int32),
                 ("device_bytes", ctypes.c_int64), ("trace_bytes", ctypes.c_int64),
                 ("root_lo", ctypes.c_float * 3), ("root_hi", ctypes.c_float * 3),
-                ("node_format", ctypes.c_int32), ("n_trace_nodes", ctypes.c_int32)]
+                ("node_format", ctypes.c_int32), ("n_trace_nodes", ctypes.c_int32),
+                ("has_stats", ctypes.c_int32), ("max_leaf_count", ctypes.c_int32),
+                ("tree_cost", ctypes.c_double), ("root_area", ctypes.c_double),
+                ("leaf_hist", ctypes.c_int64 * LEAF_HIST)]
 
 
 class rt_trace_opts(ctypes.Structure):
@@ -116,7 +120,7 @@ NODE_DTYPE = np.dtype([("lo", "<f4", 3), ("hi", "<f4", 3), ("left", "<i4"), ("fi
 assert NODE_DTYPE.itemsize == 64
 
 EXPORTS = ("rt_split_params_default", "rt_build", "rt_rebuild", "rt_trace",
-           "rt_trace_bounces", "rt_trace_ex", "rt_bvh_info_get", "rt_bvh_download",
+           "rt_trace_bounces", "rt_trace_ex", "rt_bvh_info_get", "rt_bvh_stats", "rt_bvh_download",
            "rt_bvh_export_trace_nodes", "rt_bvh_destroy", "rt_last_error", "rt_batch_create",
            "rt_batch_set", "rt_batch_configure", "rt_batch_get_config", "rt_batch_launch",
            "rt_batch_autotune", "rt_batch_destroy", "rt_rays_from_directions",
@@ -144,6 +148,7 @@ def load(path: str = LIB_PATH):
     lib.rt_trace_bounces.argtypes = [P, P, i64, i32, P, P, P, P]
     lib.rt_trace_ex.argtypes = [P, P, i64, i32, P, P, P, ctypes.POINTER(rt_trace_opts), P]
     lib.rt_bvh_info_get.argtypes = [P, ctypes.POINTER(rt_bvh_info)]
+    lib.rt_bvh_stats.argtypes = [P, ctypes.POINTER(rt_bvh_info)]
     lib.rt_bvh_download.argtypes = [P, P, i64, P, i64]
     lib.rt_bvh_export_trace_nodes.argtypes = [P, P, ctypes.POINTER(i64)]
     lib.rt_bvh_destroy.argtypes = [P]
@@ -174,8 +179,8 @@ def load(path: str = LIB_PATH):
     lib.rt_diffract_segments.argtypes = [P, i64, P, P, P, i64, i32, ctypes.c_double, P, i32, P,
                                          i64, P, P]
     for name in ("rt_build", "rt_rebuild", "rt_trace", "rt_trace_bounces", "rt_trace_ex",
-                 "rt_bvh_info_get", "rt_bvh_download", "rt_bvh_export_trace_nodes",
-                 "rt_probe_read", "rt_probe_copy", "rt_batch_create", "rt_batch_set",
+                 "rt_bvh_info_get", "rt_bvh_stats", "rt_bvh_download",
+                 "rt_bvh_export_trace_nodes", "rt_probe_read", "rt_probe_copy", "rt_batch_create", "rt_batch_set",
                  "rt_batch_configure", "rt_batch_get_config", "rt_batch_launch",
                  "rt_batch_autotune", "rt_rays_from_directions", "rt_rays_from_directions_many",
                  "rt_trace_receive",
@@ -440,6 +445,13 @@ def rt_bvh_info_get(handle) -> rt_bvh_info:
     return info
 
 
+def rt_bvh_stats(handle) -> rt_bvh_info:
+    """Sizes, Eq. (1) tree cost and leaf-size histogram (synchronises)."""
+    info = rt_bvh_info()
+    _check(load().rt_bvh_stats(handle, ctypes.byref(info)))
+    return info
+
+
 def rt_bvh_download(handle):
     info = rt_bvh_info_get(handle)
     nodes = np.zeros(info.n_nodes, dtype=NODE_DTYPE)
@@ -498,6 +510,9 @@ class BVH:
 
     def info(self) -> rt_bvh_info:
         return rt_bvh_info_get(self.handle)
+
+    def stats(self) -> rt_bvh_info:
+        return rt_bvh_stats(self.handle)
 
     def download(self):
         return rt_bvh_download(self.handle)

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librt_mi355x.so")
-SOURCES = ["rt_api.hip", "rt_build.hip", "rt_trace.hip", "rt_batch.hip", "rt_probe.hip",
+SOURCES = ["rt_api.hip", "rt_build.hip", "rt_trace.hip", "rt_batch.hip", "rt_rays.hip", "rt_probe.hip",
            "rt_receive.hip", "rt_diffract.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -34,7 +34,8 @@ bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) %
 void free_buffers(Buffers& B) {
   void* ptrs[] = {B.recs_a, B.recs_b, B.perm,   B.nodes,    B.cnodes,   B.used,
                   B.rank,   B.bsum,   B.mfront, B.sfront,   B.aitems,   B.accnt,   B.abins,
-                  B.counters, B.root_box, B.tnodes, B.tfacets, B.wnodes, B.queue};
+                  B.counters, B.root_box, B.tnodes, B.tfacets, B.wnodes, B.queue,
+                  B.stat_work};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   B = Buffers();
@@ -79,6 +80,7 @@ int ensure_buffers(Buffers& B, int64_t n) {
   if (rc == RT_OK) rc = alloc(B.tfacets, nn, bytes);
   if (rc == RT_OK) rc = alloc(B.wnodes, nn, bytes);
   if (rc == RT_OK) rc = alloc(B.queue, kQueueSlots, bytes);
+  if (rc == RT_OK) rc = alloc(B.stat_work, kStatWords, bytes);
   if (rc != RT_OK) {
     free_buffers(B);
     return rc;
@@ -205,6 +207,14 @@ int lanes_of(const rt_bvh* b, int64_t n, const rt_trace_opts* opts) {
   if (opts && (opts->seg_rays || opts->ray_stats || opts->grid > 0)) return 1;
   return trace_lanes(n, b->params.max_leaf);
 }
+
+// Queue head of a persistent trace call: the handle's next slot, whatever
+// kernel variant or node format the call launches (null without a grid).
+unsigned long long* queue_of(const rt_bvh* b, const rt_trace_opts* opts) {
+  if (!opts || opts->grid <= 0) return nullptr;
+  const unsigned k = b->queue_slot.fetch_add(1u, std::memory_order_relaxed) % kQueueSlots;
+  return b->buf.queue + k;
+}
 }  // namespace rt
 
 using namespace rt;
@@ -257,7 +267,7 @@ int rt_trace(const rt_bvh* b, const float* rays, int64_t n, rt_hit* out, hipStre
   int rc = check_trace_args(b, rays, n, 1, out, nullptr, nullptr, nullptr);
   if (rc != RT_OK || n == 0) return rc;
   return launch_trace(b->buf, b->info.node_format, b->info.depth, rays, n, 1, out, nullptr, nullptr,
-                      nullptr, lanes_of(b, n, nullptr), (int)b->info.n_tris, s);
+                      nullptr, lanes_of(b, n, nullptr), (int)b->info.n_tris, nullptr, s);
 }
 
 int rt_trace_bounces(const rt_bvh* b, const float* rays, int64_t n, int32_t max_bounces,
@@ -270,12 +280,23 @@ int rt_trace_ex(const rt_bvh* b, const float* rays, int64_t n, int32_t max_bounc
   int rc = check_trace_args(b, rays, n, max_bounces, out, path_len, n_hits, opts);
   if (rc != RT_OK || n == 0) return rc;
   return launch_trace(b->buf, b->info.node_format, b->info.depth, rays, n, max_bounces, out,
-                      path_len, n_hits, opts, lanes_of(b, n, opts), (int)b->info.n_tris, s);
+                      path_len, n_hits, opts, lanes_of(b, n, opts), (int)b->info.n_tris,
+                      queue_of(b, opts), s);
 }
 
 int rt_bvh_info_get(const rt_bvh* b, rt_bvh_info* info) {
   if (!b || !info) return set_error(RT_EINVAL, "rt_bvh_info_get: NULL argument");
   *info = b->info;
+  return RT_OK;
+}
+
+int rt_bvh_stats(const rt_bvh* b, rt_bvh_info* info) {
+  if (!b || !info) return set_error(RT_EINVAL, "rt_bvh_stats: NULL argument");
+  if (b->info.n_tris <= 0) return set_error(RT_EINVAL, "rt_bvh_stats: tree not built");
+  rt_bvh_info r = b->info;
+  int rc = tree_stats(b->buf, r.n_nodes, (double)b->params.t_isect, (double)b->params.t_trav, &r);
+  if (rc != RT_OK) return rc;
+  *info = r;
   return RT_OK;
 }
 

@@ -1896,3 +1896,125 @@ int build_tree(Buffers& B, const float* tris, int64_t n64, const rt_split_params
 }
 
 }  // namespace rt
+
+// ---- tree statistics (rt_bvh_stats) ----------------------------------------
+// Eq. (1) cost of the finished tree, Sec. II-B: internal nodes add
+// S(n) t_trav, leaves S(l) k_l t_i (S the surface area of the node's volume),
+// both sums divided by S(root) at the end; and the histogram of leaf sizes.
+// A fixed grid walks the nodes with a fixed stride and reduces in a fixed
+// order, so the same tree gives the same bits.
+namespace rt {
+namespace {
+
+constexpr int kStatThreads = 256;
+
+__device__ inline double box_area(const BNode& nd) {
+  const double wx = (double)nd.hi[0] - (double)nd.lo[0];
+  const double wy = (double)nd.hi[1] - (double)nd.lo[1];
+  const double wz = (double)nd.hi[2] - (double)nd.lo[2];
+  return 2.0 * (wx * wy + wy * wz + wz * wx);
+}
+
+__device__ inline int leaf_bucket(int c) {
+  if (c <= 8) return c - 1;
+  if (c > 1024) return RT_LEAF_HIST - 1;
+  return 5 + (31 - __clz(c - 1));
+}
+
+// part[blk][2]: this block's internal and leaf sums; hist[blk][kStatHist]:
+// its leaf counts per bucket and (last word) its largest leaf.
+__global__ __launch_bounds__(kStatThreads) void k_tree_stats(const BNode* __restrict__ nodes,
+                                                            int64_t nn, double t_i,
+                                                            double t_trav,
+                                                            double* __restrict__ part,
+                                                            double* __restrict__ hist) {
+  __shared__ double s_int[kStatThreads], s_leaf[kStatThreads];
+  __shared__ int s_hist[kStatHist];
+  if (threadIdx.x < kStatHist) s_hist[threadIdx.x] = 0;
+  __syncthreads();
+  double a_int = 0.0, a_leaf = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kStatThreads + threadIdx.x; i < nn;
+       i += (int64_t)kStatBlocks * kStatThreads) {
+    const BNode nd = nodes[i];
+    const double s = box_area(nd);
+    if (nd.left >= 0) {
+      a_int += s * t_trav;
+    } else {
+      a_leaf += s * ((double)nd.count * t_i);
+      atomicAdd(&s_hist[leaf_bucket(nd.count)], 1);
+      atomicMax(&s_hist[kStatHist - 1], nd.count);
+    }
+  }
+  s_int[threadIdx.x] = a_int;
+  s_leaf[threadIdx.x] = a_leaf;
+  __syncthreads();
+  for (int h = kStatThreads / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      s_int[threadIdx.x] += s_int[threadIdx.x + h];
+      s_leaf[threadIdx.x] += s_leaf[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = s_int[0];
+    part[2 * blockIdx.x + 1] = s_leaf[0];
+  }
+  if (threadIdx.x < kStatHist) hist[blockIdx.x * kStatHist + threadIdx.x] = (double)s_hist[threadIdx.x];
+}
+
+// out[0..1]: the internal and leaf sums over the blocks in block order;
+// out[2..]: the histogram summed, the largest leaf as a maximum.
+__global__ void k_tree_stats_sum(const double* __restrict__ part, const double* __restrict__ hist,
+                                 double* __restrict__ out) {
+  if (threadIdx.x == 0) {
+    double a = 0.0, b = 0.0;
+    for (int k = 0; k < kStatBlocks; ++k) {
+      a += part[2 * k];
+      b += part[2 * k + 1];
+    }
+    out[0] = a;
+    out[1] = b;
+  }
+  if (threadIdx.x < kStatHist) {
+    double h = 0.0;
+    for (int k = 0; k < kStatBlocks; ++k) {
+      const double v = hist[k * kStatHist + threadIdx.x];
+      h = threadIdx.x == kStatHist - 1 ? fmax(h, v) : h + v;
+    }
+    out[2 + threadIdx.x] = h;
+  }
+}
+
+}  // namespace
+
+int tree_stats(const Buffers& B, int64_t n_nodes, double t_isect, double t_trav,
+               rt_bvh_info* info) {
+  double* part = B.stat_work;
+  double* hist = part + 2 * kStatBlocks;
+  double* out = hist + kStatBlocks * kStatHist;
+  HIPCHECK(hipDeviceSynchronize());
+  hipLaunchKernelGGL(k_tree_stats, dim3(kStatBlocks), dim3(kStatThreads), 0, 0, B.cnodes, n_nodes,
+                     t_isect, t_trav, part, hist);
+  hipLaunchKernelGGL(k_tree_stats_sum, dim3(1), dim3(64), 0, 0, part, hist, out);
+  HIPCHECK(hipGetLastError());
+  BNode root;
+  double h[2 + kStatHist];
+  HIPCHECK(hipMemcpy(h, out, sizeof(h), hipMemcpyDeviceToHost));
+  HIPCHECK(hipMemcpy(&root, B.cnodes, sizeof(root), hipMemcpyDeviceToHost));
+  const double wx = (double)root.hi[0] - (double)root.lo[0];
+  const double wy = (double)root.hi[1] - (double)root.lo[1];
+  const double wz = (double)root.hi[2] - (double)root.lo[2];
+  const double s_root = 2.0 * (wx * wy + wy * wz + wz * wx);
+  info->has_stats = 1;
+  info->root_area = s_root;
+  if (s_root > 0.0) {
+    info->tree_cost = h[0] / s_root + h[1] / s_root;
+  } else {  // every volume degenerate: each ratio is taken as 1
+    info->tree_cost = t_trav * (double)info->n_internal + t_isect * (double)info->n_tris;
+  }
+  for (int k = 0; k < RT_LEAF_HIST; ++k) info->leaf_hist[k] = (int64_t)h[2 + k];
+  info->max_leaf_count = (int32_t)h[2 + RT_LEAF_HIST];
+  return RT_OK;
+}
+
+}  // namespace rt

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <initializer_list>
 #include <utility>
 #include <stdint.h>
@@ -62,7 +63,7 @@ struct alignas(16) TFacet {
   float4 p0, p1, p2;
 };
 constexpr uint32_t kLastFacet = 0x80000000u;
-constexpr int kQueueSlots = 64;  // trace calls that may be in flight on one handle at once
+constexpr int kQueueSlots = 64;  // persistent trace calls that may be in flight on one handle at once
 
 // ---- build-time facet record, kept in reference order: 32 bytes ----
 //   lo = (box lo xyz, caller's id bits), hi = (box hi xyz, 0)
@@ -117,11 +118,17 @@ struct Buffers {
   // traversal data
   TNode* tnodes = nullptr;  // [max(n_internal, 1)]
   FNode4* wnodes = nullptr; // [max(n_internal, 1)] wide nodes (QNode4 records use the first half)
-  unsigned long long* queue = nullptr;  // [kQueueSlots] ray queue heads, one per trace call in flight
+  unsigned long long* queue = nullptr;  // [kQueueSlots] ray queue heads of persistent launches
   TFacet* tfacets = nullptr;  // [n]
+  double* stat_work = nullptr;  // [kStatWords] tree statistics: per-block partial sums
   int64_t cap_n = 0;        // facets the buffers can hold
   int64_t bytes = 0;
 };
+
+// tree statistics (rt_bvh_stats): per-block cost sums and leaf histograms
+constexpr int kStatBlocks = 64;
+constexpr int kStatHist = RT_LEAF_HIST + 1;  // buckets + the largest leaf
+constexpr int kStatWords = kStatBlocks * (2 + kStatHist) + 2 + kStatHist;
 
 // build sizes shared by the allocator and the build (the phase thresholds
 // and the capacities derived from them are in rt_build_plan.h)
@@ -309,12 +316,17 @@ int check_trace_args(const rt_bvh* b, const float* rays, int64_t n, int32_t max_
 // build.hip
 int build_tree(Buffers& B, const float* tris, int64_t n, const rt_split_params& p,
                hipStream_t s, rt_bvh_info* info);
+// Eq. (1) tree cost and leaf histogram of the built tree into info (synchronous).
+int tree_stats(const Buffers& B, int64_t n_nodes, double t_isect, double t_trav,
+               rt_bvh_info* info);
 // trace.hip
 // lanes: 1, or 4 / 16 / 64 lanes tracing each ray together (then opts may not
-// ask for seg_rays, ray_stats or a persistent grid); n_tf: facets of the tree.
+// ask for seg_rays, ray_stats or a persistent grid); n_tf: facets of the tree;
+// queue: the call's own queue head when opts asks for a persistent grid.
 int launch_trace(const Buffers& B, int node_format, int depth, const float* rays, int64_t n,
                  int32_t max_bounces, rt_hit* out, double* path_len, int32_t* n_hits,
-                 const rt_trace_opts* opts, int lanes, int n_tf, hipStream_t s);
+                 const rt_trace_opts* opts, int lanes, int n_tf, unsigned long long* queue,
+                 hipStream_t s);
 // Lanes per ray the library picks for n rays on a tree built with max_leaf
 // (api.hip).
 int trace_lanes(int64_t n, int max_leaf);
@@ -352,4 +364,8 @@ struct rt_bvh {
   rt_bvh_info info;
   rt_split_params params;
   int device;
+  // Next of the handle's kQueueSlots queue heads: every persistent launch on
+  // the handle, whatever its kernel variant or node format, takes the next
+  // one, so calls in flight on different streams never share a head.
+  mutable std::atomic<unsigned> queue_slot{0};
 };

@@ -792,14 +792,13 @@ size_t stack_bytes(int depth) {
 template <int FMT, bool BOUNCE, bool SEG, bool STATS>
 void launch(const Buffers& B, int depth, const float* rays, int64_t n, int max_b, rt_hit* out,
             double* path_len, int32_t* n_hits, float* seg, uint32_t* stats, int grid,
-            int refill, int n_tf, hipStream_t s) {
+            int refill, int n_tf, unsigned long long* queue, hipStream_t s) {
   const int64_t batches = (n + kBlock - 1) / kBlock;
   const void* nodes = FMT == RT_NODE_BIN2 ? (const void*)B.tnodes : (const void*)B.wnodes;
   unsigned long long* q = nullptr;
   int64_t blocks = batches;  // default: one work-group per batch of 64 rays
-  if (grid > 0) {            // persistent work-groups pulling batches from a queue
-    static std::atomic<unsigned> next_slot{0};
-    q = B.queue + (next_slot.fetch_add(1) % kQueueSlots);
+  if (grid > 0) {            // persistent work-groups pulling batches from the call's queue
+    q = queue;
     blocks = std::min<int64_t>(grid, batches);
     hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(1), 0, s, q);
   }
@@ -825,7 +824,7 @@ void launch_group(const Buffers& B, int depth, const float* rays, int64_t n, int
 template <int FMT>
 void launch_fmt(const Buffers& B, int depth, const float* rays, int64_t n, int max_b, rt_hit* out,
                 double* path_len, int32_t* n_hits, float* seg, uint32_t* stats, int grid,
-                int refill, int lanes, int n_tf, hipStream_t s) {
+                int refill, int lanes, int n_tf, unsigned long long* q, hipStream_t s) {
   switch (lanes) {  // the caller allows lanes > 1 only without seg, stats and grid
     case 4: return launch_group<FMT, 4>(B, depth, rays, n, max_b, out, path_len, n_hits, n_tf, s);
     case 16: return launch_group<FMT, 16>(B, depth, rays, n, max_b, out, path_len, n_hits, n_tf, s);
@@ -834,15 +833,15 @@ void launch_fmt(const Buffers& B, int depth, const float* rays, int64_t n, int m
   }
   const bool bounce = max_b > 1 || path_len || n_hits;
   if (!bounce && !seg && !stats) {
-    launch<FMT, false, false, false>(B, depth, rays, n, 1, out, nullptr, nullptr, nullptr, nullptr, grid, refill, n_tf, s);
+    launch<FMT, false, false, false>(B, depth, rays, n, 1, out, nullptr, nullptr, nullptr, nullptr, grid, refill, n_tf, q, s);
   } else if (!seg && !stats) {
-    launch<FMT, true, false, false>(B, depth, rays, n, max_b, out, path_len, n_hits, nullptr, nullptr, grid, refill, n_tf, s);
+    launch<FMT, true, false, false>(B, depth, rays, n, max_b, out, path_len, n_hits, nullptr, nullptr, grid, refill, n_tf, q, s);
   } else if (seg && !stats) {
-    launch<FMT, true, true, false>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, nullptr, grid, refill, n_tf, s);
+    launch<FMT, true, true, false>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, nullptr, grid, refill, n_tf, q, s);
   } else if (!seg) {
-    launch<FMT, true, false, true>(B, depth, rays, n, max_b, out, path_len, n_hits, nullptr, stats, grid, refill, n_tf, s);
+    launch<FMT, true, false, true>(B, depth, rays, n, max_b, out, path_len, n_hits, nullptr, stats, grid, refill, n_tf, q, s);
   } else {
-    launch<FMT, true, true, true>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, stats, grid, refill, n_tf, s);
+    launch<FMT, true, true, true>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, stats, grid, refill, n_tf, q, s);
   }
 }
 
@@ -1002,7 +1001,8 @@ int launch_trace_energy(const Buffers& B, int node_format, int depth, const floa
 
 int launch_trace(const Buffers& B, int node_format, int depth, const float* rays, int64_t n,
                  int32_t max_b, rt_hit* out, double* path_len, int32_t* n_hits,
-                 const rt_trace_opts* opts, int lanes, int n_tf, hipStream_t s) {
+                 const rt_trace_opts* opts, int lanes, int n_tf, unsigned long long* q,
+                 hipStream_t s) {
   if (n == 0) return RT_OK;
   float* seg = opts ? opts->seg_rays : nullptr;
   uint32_t* stats = opts ? opts->ray_stats : nullptr;
@@ -1010,13 +1010,13 @@ int launch_trace(const Buffers& B, int node_format, int depth, const float* rays
   const int refill = opts ? opts->refill : 0;
   switch (node_format) {
     case RT_NODE_F4:
-      launch_fmt<RT_NODE_F4>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, stats, grid, refill, lanes, n_tf, s);
+      launch_fmt<RT_NODE_F4>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, stats, grid, refill, lanes, n_tf, q, s);
       break;
     case RT_NODE_Q4:
-      launch_fmt<RT_NODE_Q4>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, stats, grid, refill, lanes, n_tf, s);
+      launch_fmt<RT_NODE_Q4>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, stats, grid, refill, lanes, n_tf, q, s);
       break;
     default:
-      launch_fmt<RT_NODE_BIN2>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, stats, grid, refill, lanes, n_tf, s);
+      launch_fmt<RT_NODE_BIN2>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, stats, grid, refill, lanes, n_tf, q, s);
       break;
   }
   return check_hip(hipGetLastError(), "trace launch");

@@ -190,3 +190,48 @@ def agree_with_checker(tris, rays, rx, delta, nb, params, got, ids_g, t_g, nthre
     assert np.all(np.abs(lg - lr) <= 2e-5 * lr), "path lengths"
     assert np.all(np.abs(dg - dr) <= 2e-5 * lr), "distances"
     return {"gpu": len(gk), "checker": len(rk), "compared": len(both), "borderline": len(only)}
+
+
+U32 = 2.0 ** -24   # float32 unit roundoff
+
+
+def chain_error_bounds(tris, seg, ids, t):
+    """First-order bound on |t_gpu - t_64| for every segment of the checker's
+    float64 chains (Sec. III-B re-launch), from how the GPU's float32 chain
+    departs from them.  Both start from the same float32 rays.  At segment b
+    let the GPU's origin and direction differ from the checker's by at most
+    E_o and E_d (vector norms).  The exact hit of the GPU's ray on the same
+    facet plane (unit normal n, incidence cos c = |n.d| / |d|) then moves by
+    |dt| <= (E_o + t E_d) / (|d| c), and the hit point, which stays in the
+    plane, by (E_o + t E_d)(1 + 1 / c).  The GPU's own arithmetic adds, per
+    segment: its t for its float32 ray (compensated, one float32 rounding:
+    2u t |d| at the hit point), the origin rounding of fma(t, d, o) (u per
+    coordinate, sqrt(3) u max|p|), and the reflection (compensated, rounded
+    once per component: at most 2u each, 2 sqrt(3) u max|r|).  Reflection is
+    an isometry, so E_d only accumulates those roundings.  The allowed
+    deviation is that propagated term plus the 1e-5 relative tolerance of
+    the segment itself.  Returns allowed [max_b, m] (inf where the checker's
+    segment missed or was never traced)."""
+    v = tris.astype(np.float64).reshape(-1, 3, 3)
+    nrm = np.cross(v[:, 1] - v[:, 0], v[:, 2] - v[:, 0])
+    nrm /= np.maximum(np.linalg.norm(nrm, axis=1, keepdims=True), 1e-300)
+    nb, m = ids.shape
+    allowed = np.full((nb, m), np.inf)
+    e_o = np.zeros(m)
+    e_d = np.zeros(m)
+    for b in range(nb):
+        hit = ids[b] >= 0
+        o, d = seg[b, :, 0:3], seg[b, :, 4:7]
+        dn = np.linalg.norm(d, axis=1)
+        tb = np.where(hit, t[b], 0.0)
+        n = nrm[np.where(hit, ids[b], 0)]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            cos = np.abs(np.einsum("ij,ij->i", n, d)) / dn
+            w = e_o + tb * e_d
+            allowed[b] = np.where(hit, 1e-5 * tb + w / (dn * cos), np.inf)
+            p = o + tb[:, None] * d
+            e_o = w * (1.0 + 1.0 / cos) + 2 * U32 * tb * dn + np.sqrt(3) * U32 * np.abs(p).max(1)
+        if b + 1 < nb:
+            r = seg[b + 1, :, 4:7]
+            e_d = e_d + 2 * np.sqrt(3) * U32 * np.nan_to_num(np.abs(r).max(1))
+    return allowed

@@ -73,13 +73,15 @@ int main(void) {
          offsetof(rt_diffracted, ray8));
   printf("%zu %zu %zu\\n", sizeof(rt_ray_launch), offsetof(rt_ray_launch, first),
          offsetof(rt_ray_launch, n));
+  printf("%zu %zu %zu %zu\\n", offsetof(rt_bvh_info, has_stats), offsetof(rt_bvh_info, tree_cost),
+         offsetof(rt_bvh_info, root_area), offsetof(rt_bvh_info, leaf_hist));
   return 0;
 }""")
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-D__HIP_PLATFORM_AMD__", "-I" + os.path.join(ROOT, "include"),
                     "-I/opt/rocm/include", str(src), "-o", str(exe)], check=True)
-    a, b, c, d, e, g, h = subprocess.run([str(exe)], capture_output=True, text=True,
-                                         check=True).stdout.split("\n")[:7]
+    a, b, c, d, e, g, h, k = subprocess.run([str(exe)], capture_output=True, text=True,
+                                            check=True).stdout.split("\n")[:8]
     sizes = [int(x) for x in a.split()]
     offs = [int(x) for x in b.split()]
     assert sizes == [ctypes.sizeof(R.rt_split_params), 16, ctypes.sizeof(R.rt_bvh_info),
@@ -103,6 +105,10 @@ int main(void) {
     assert [int(x) for x in h.split()] == [R.RAY_LAUNCH_DTYPE.itemsize,
                                            R.RAY_LAUNCH_DTYPE.fields["first"][1],
                                            R.RAY_LAUNCH_DTYPE.fields["n"][1]]
+    assert [int(x) for x in k.split()] == [R.rt_bvh_info.has_stats.offset,
+                                           R.rt_bvh_info.tree_cost.offset,
+                                           R.rt_bvh_info.root_area.offset,
+                                           R.rt_bvh_info.leaf_hist.offset]
 
 
 def test_defaults():
@@ -154,6 +160,7 @@ def test_null_handles():
     lib = R.load()
     info = R.rt_bvh_info()
     assert lib.rt_bvh_info_get(None, ctypes.byref(info)) == R.RT_EINVAL
+    assert lib.rt_bvh_stats(None, ctypes.byref(info)) == R.RT_EINVAL
     assert lib.rt_trace(None, None, 0, None, None) == R.RT_EINVAL
     assert lib.rt_trace_bounces(None, None, 0, 1, None, None, None, None) == R.RT_EINVAL
     assert lib.rt_bvh_download(None, None, 0, None, 0) == R.RT_EINVAL

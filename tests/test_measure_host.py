@@ -10,7 +10,7 @@ import os
 
 import pytest
 
-from paper_2208_10008_amd import sqcount, traffic
+import counters
 
 FIELDS = ["Correlation_Id", "Dispatch_Id", "Agent_Id", "Queue_Id", "Process_Id", "Thread_Id",
           "Grid_Size", "Kernel_Id", "Kernel_Name", "Workgroup_Size", "LDS_Block_Size",
@@ -43,7 +43,7 @@ def test_traffic_scales_by_the_calibration_copy(tmp_path):
              row(3, "k_trace", "WRITE_SIZE", 70.0), row(4, "k_probe_copy", "WRITE_SIZE", 4096.0)]
     write_csv(tmp_path / "f", fetch)
     write_csv(tmp_path / "w", write)
-    rec = traffic.trace_traffic(str(tmp_path / "f"), str(tmp_path / "w"), copy_mib=4)
+    rec = counters.trace_traffic(str(tmp_path / "f"), str(tmp_path / "w"), copy_mib=4)
     # the first (warm-up) dispatch is dropped: fetch 200 KiB x 2, write 60 KiB x 1
     assert rec["fetch_kib_per_launch_raw"] == 200.0 and rec["write_kib_per_launch_raw"] == 60.0
     assert rec["calibration"]["fetch_scale"] == 2.0 and rec["calibration"]["write_scale"] == 1.0
@@ -54,7 +54,7 @@ def test_traffic_scales_by_the_calibration_copy(tmp_path):
 def sq_rows(disp, vgpr, valu, ns, sgpr=48, instances=2):
     """One dispatch: every SQ counter split over `instances` rows."""
     out = []
-    for c in sqcount.COUNTERS:
+    for c in counters.COUNTERS:
         v = valu if c == "SQ_INSTS_VALU" else 10.0
         for _ in range(instances):
             out.append(row(disp, "k_trace", c, v / instances, vgpr=vgpr, sgpr=sgpr, t1=ns))
@@ -69,18 +69,18 @@ def test_sq_groups_by_resources_and_by_explicit_runs(tmp_path):
         rows += sq_rows(i + 1, g, float(v), 1000 * (i + 1))
     rows.append(row(99, "k_build_something", "SQ_INSTS_VALU", 1e9))  # other kernels are ignored
     write_csv(tmp_path / "sq", rows)
-    ds = sqcount.dispatches(str(tmp_path / "sq"))
+    ds = counters.dispatches(str(tmp_path / "sq"))
     assert len(ds) == 8
     assert ds[0]["SQ_INSTS_VALU"] == 100.0          # instances summed
-    by_sig = sqcount.groups(ds)
+    by_sig = counters.groups(ds)
     # two formats with the same resources run back to back merge into one group
     assert [g["dispatches"] for g in by_sig] == [3, 4, 1]
-    runs = sqcount.groups(ds, [3, 2, 2, 1])
+    runs = counters.groups(ds, [3, 2, 2, 1])
     assert [g["dispatches"] for g in runs] == [3, 2, 2, 1]
     assert [g["SQ_INSTS_VALU"] for g in runs] == [101.0, 305.0, 510.0, 100.0]   # medians
     assert runs[1]["ns"] == 4500.0
     with pytest.raises(ValueError):
-        sqcount.groups(ds, [3, 2, 2])
+        counters.groups(ds, [3, 2, 2])
 
 
 def test_bench_reads_records_only_for_the_current_source(tmp_path, monkeypatch):

@@ -59,3 +59,68 @@ def test_tmax_per_segment():
     rays = np.array([[5, 0, 0, 1e-4, 1, 0.5, 0, 9.0]], dtype=np.float32)
     c = oracle.bounces(tris, rays, 4)
     assert c.n_hits[0] == 1
+
+
+def _float32_chain(tris, tree, rays, nb):
+    """Chains whose re-launched rays are rounded to float32, as the GPU stores
+    them: origin fl32(o + t d) and direction fl32(reflected d), every segment
+    the checker's exact closest hit of that float32 ray."""
+    v = tris.astype(np.float64).reshape(-1, 3, 3)
+    nrm = np.cross(v[:, 1] - v[:, 0], v[:, 2] - v[:, 0])
+    m = rays.shape[0]
+    ids = np.full((nb, m), -1, np.int32)
+    ts = np.full((nb, m), np.inf)
+    cur = rays.astype(np.float32).copy()
+    prev = np.full(m, -1, np.int32)
+    live = np.ones(m, bool)
+    for b in range(nb):
+        k = np.nonzero(live)[0]
+        if k.size == 0:
+            break
+        ref = oracle.trace_bvh(tree, cur[k], skip=prev[k], nthreads=8)
+        ids[b, k], ts[b, k] = ref.id, ref.t
+        hit = ref.id >= 0
+        kh, idh, th = k[hit], ref.id[hit], ref.t[hit]
+        o = cur[kh, 0:3].astype(np.float64)
+        d = cur[kh, 4:7].astype(np.float64)
+        n = nrm[idh]
+        r = d - (2 * np.einsum("ij,ij->i", d, n) / np.einsum("ij,ij->i", n, n))[:, None] * n
+        cur[kh, 0:3] = (o + th[:, None] * d).astype(np.float32)
+        cur[kh, 4:7] = r.astype(np.float32)
+        prev[kh] = idh
+        live[k[~hit]] = False
+    return ids, ts
+
+
+def test_float32_chain_error_model():
+    """The error model the GPU chains are gated with (tests/_parity.py,
+    chain_error_bounds): float32-rounded re-launched rays traced exactly must
+    stay within it of the float64 chains on every compared segment of a
+    100,000-ray sample of the city launch, while the segment tolerance alone
+    (1e-5 relative) is exceeded on some of them, so the propagated term is
+    needed."""
+    from _parity import chain_error_bounds
+    from rtgen import workloads
+    w = workloads.city24k()
+    rays = w.rays[np.sort(np.random.default_rng(7).choice(w.n_rays, 100_000, replace=False))]
+    tree = oracle.build_tree(w.tris, oracle.SplitParams(alpha=0.4, src=w.tx))
+    nb = w.max_bounces
+    ch = oracle.bounces(w.tris, rays, nb, tree=tree, nthreads=8)
+    ids32, t32 = _float32_chain(w.tris, tree, rays, nb)
+    allowed = chain_error_bounds(w.tris, ch.seg, ch.id, ch.t)
+    ok = np.ones(rays.shape[0], bool)
+    worst, over_segment_tol, compared = 0.0, 0, 0
+    for b in range(nb):
+        m = ok & (ch.margin[b] > 1e-4)
+        assert np.array_equal(ids32[b, m], ch.id[b, m]), b
+        hit = m & (ch.id[b] >= 0)
+        dt = np.abs(t32[b, hit] - ch.t[b, hit])
+        assert np.all(dt <= allowed[b, hit]), b
+        if dt.size:
+            worst = max(worst, float((dt / allowed[b, hit]).max()))
+            over_segment_tol += int(np.sum(dt > 1e-5 * ch.t[b, hit]))
+        compared += int(hit.sum())
+        ok = m & (ch.id[b] >= 0)
+    print("float32 chains: %d hits compared, worst deviation / bound %.3f, %d over 1e-5 "
+          "relative" % (compared, worst, over_segment_tol))
+    assert compared > 50_000 and over_segment_tol > 0

@@ -96,3 +96,55 @@ def test_rejects_bad_params():
     for kw in (dict(alpha=1.5), dict(alpha=-0.1), dict(max_leaf=0), dict(nbins=1)):
         with pytest.raises(ValueError):
             oracle.build_tree(tris, oracle.SplitParams(**kw))
+
+
+# ---------------------------------------------------------------- tree cost
+def _strip(x0, x1):
+    """A right triangle covering the box [x0, x1] x [0, 1] x {0}."""
+    return [x0, 0, 0, x1, 0, 0, x0, 1, 0]
+
+
+def test_tree_cost_hand_worked():
+    # two unit squares' triangles at x in [0, 1] and [9, 10]: leaf boxes of
+    # area 2 * 1 * 1 = 2, root box [0, 10] x [0, 1] of area 2 * 10 = 20
+    two = np.array([_strip(0, 1), _strip(9, 10)], np.float32)
+    t = oracle.build_tree(two, oracle.SplitParams(max_leaf=1))
+    assert t.n_nodes == 3
+    assert oracle.tree_cost(t) == pytest.approx(20 / 20 + 2 / 20 + 2 / 20, rel=1e-15)   # 1.2
+    assert oracle.tree_cost(t, t_isect=2.0, t_trav=0.5) == pytest.approx(0.5 + 0.4, rel=1e-15)
+    t = oracle.build_tree(two, oracle.SplitParams(max_leaf=2))      # root leaf of 2 facets
+    assert t.n_nodes == 1 and oracle.tree_cost(t) == pytest.approx(2.0, rel=1e-15)
+    # three: x in [0, 1], [2, 3], [9, 10].  Eq. (1) prefers {A, B} | {C}
+    # ((6 * 2 + 2 * 1) / 20 against (2 * 1 + 16 * 2) / 20), then A | B:
+    # internal areas 20 and 6, leaf areas 2, 2, 2
+    three = np.array([_strip(0, 1), _strip(2, 3), _strip(9, 10)], np.float32)
+    t = oracle.build_tree(three, oracle.SplitParams(max_leaf=1))
+    assert t.n_nodes == 5 and sorted(t.count[t.left < 0].tolist()) == [1, 1, 1]
+    assert oracle.tree_cost(t) == pytest.approx((20 + 6) / 20 + 6 / 20, rel=1e-15)      # 1.6
+    assert oracle.tree_cost(t, t_isect=2.0, t_trav=0.5) == pytest.approx(0.65 + 0.6, rel=1e-15)
+
+
+def _recursive_cost(tree, node, t_isect, t_trav):
+    """Eq. (1) per node: a leaf costs k t_i; an internal node t_trav plus each
+    child's cost weighted by the child's share of its surface area."""
+    w = tree.hi[node] - tree.lo[node]
+    s = 2.0 * (w[0] * w[1] + w[1] * w[2] + w[2] * w[0])
+    if tree.left[node] < 0:
+        return tree.count[node] * t_isect
+    c = t_trav
+    for ch in (tree.left[node], tree.right[node]):
+        wc = tree.hi[ch] - tree.lo[ch]
+        sc = 2.0 * (wc[0] * wc[1] + wc[1] * wc[2] + wc[2] * wc[0])
+        c += sc / s * _recursive_cost(tree, ch, t_isect, t_trav)
+    return c
+
+
+@pytest.mark.parametrize("alpha,max_leaf", [(1.0, 4), (0.4, 1), (0.7, 8)])
+def test_tree_cost_equals_recursive_form(alpha, max_leaf):
+    # summed node by node with root-relative areas, or recursively with
+    # parent-relative areas: the area ratios telescope to the same value
+    w = workloads.microcell()
+    t = oracle.build_tree(w.tris, oracle.SplitParams(alpha=alpha, src=w.tx, max_leaf=max_leaf))
+    for ti, tt in ((1.0, 1.0), (3.0, 0.25)):
+        assert oracle.tree_cost(t, ti, tt) == pytest.approx(_recursive_cost(t, 0, ti, tt),
+                                                            rel=1e-12)
