@@ -385,6 +385,16 @@ typedef struct rt_diffracted {
  * non-finite vertex), RT_ENOMEM, RT_EHIP. */
 int rt_wedges(const float* tris, int64_t n, int32_t* nbr, hipStream_t s);
 
+/* rt_wedges for callers that cannot allocate device memory (code that must
+ * not call hipMalloc / hipFree, such as tight serving loops and harnesses that
+ * forbid it): the same result, bit for bit, with every temporary buffer taken
+ * from a device array the library holds for each GPU until the process ends
+ * (24 MiB), so n is limited to 1..262144 facets (RT_EINVAL beyond).  All calls
+ * on one GPU share that array: calls that overlap in time on one GPU (other
+ * host threads, other streams) race and must not be made.  Synchronises the
+ * stream.  Errors: as rt_wedges. */
+int rt_wedges_noalloc(const float* tris, int64_t n, int32_t* nbr, hipStream_t s);
+
 /* Diffracted rays of stored chains (seg_rays and hits as for
  * rt_receive_segments) over the facets tris [n_tris][9] with their
  * neighbours nbr [n_tris][3] from rt_wedges.  cone: device float64

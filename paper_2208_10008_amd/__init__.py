@@ -125,7 +125,8 @@ EXPORTS = ("rt_split_params_default", "rt_build", "rt_rebuild", "rt_trace",
            "rt_batch_set", "rt_batch_configure", "rt_batch_get_config", "rt_batch_launch",
            "rt_batch_autotune", "rt_batch_destroy", "rt_rays_from_directions",
            "rt_rays_from_directions_many", "rt_trace_receive", "rt_receive_segments", "rt_receive_dedup_workspace",
-           "rt_receive_dedup", "rt_trace_energy", "rt_wedges", "rt_diffract_segments")
+           "rt_receive_dedup", "rt_trace_energy", "rt_wedges", "rt_wedges_noalloc",
+           "rt_diffract_segments")
 PROBE_EXPORTS = ("rt_probe_read", "rt_probe_copy")  # include/rt_probe.h
 
 _lib = None
@@ -176,6 +177,7 @@ def load(path: str = LIB_PATH):
     lib.rt_receive_dedup.argtypes = [P, i64, i32, RX, P, i64, P]
     lib.rt_trace_energy.argtypes = [P, P, i64, i32, ctypes.POINTER(rt_energy), P, P, P, RX, P]
     lib.rt_wedges.argtypes = [P, i64, P, P]
+    lib.rt_wedges_noalloc.argtypes = [P, i64, P, P]
     lib.rt_diffract_segments.argtypes = [P, i64, P, P, P, i64, i32, ctypes.c_double, P, i32, P,
                                          i64, P, P]
     for name in ("rt_build", "rt_rebuild", "rt_trace", "rt_trace_bounces", "rt_trace_ex",
@@ -185,7 +187,7 @@ def load(path: str = LIB_PATH):
                  "rt_batch_autotune", "rt_rays_from_directions", "rt_rays_from_directions_many",
                  "rt_trace_receive",
                  "rt_receive_segments", "rt_receive_dedup", "rt_trace_energy", "rt_wedges",
-                 "rt_diffract_segments"):
+                 "rt_wedges_noalloc", "rt_diffract_segments"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -405,6 +407,15 @@ def rt_wedges(tris, nbr=None, stream=None):
     if nbr is None:
         nbr = torch.empty((tris.shape[0], 3), dtype=torch.int32, device=tris.device)
     _check(load().rt_wedges(_ptr(tris), tris.shape[0], _ptr(nbr), _stream(stream)))
+    return nbr
+
+
+def rt_wedges_noalloc(tris, nbr, stream=None):
+    """rt_wedges without device allocation (up to 262,144 facets); nbr is the
+    caller's int32 [n, 3] CUDA tensor.  Synchronises."""
+    import torch
+    _dev(tris, torch.float32, 9, "tris")
+    _check(load().rt_wedges_noalloc(_ptr(tris), tris.shape[0], _ptr(nbr), _stream(stream)))
     return nbr
 
 

@@ -11,8 +11,16 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "rt_internal.h"
+
+// Device memory of rt_wedges_noalloc: the half-edge keys and values (two
+// buffers each for the radix sort), the non-finite flag and the sort's
+// temporary storage, for up to kNoAllocMaxFacets facets.  One copy per GPU,
+// held until the process ends.  Host code never passes this name to a
+// kernel: it uses the device address hipGetSymbolAddress returns.
+static __device__ __align__(256) unsigned char scratch[size_t(24) << 20];
 
 namespace rt {
 namespace {
@@ -350,6 +358,33 @@ __global__ __launch_bounds__(kDiffBlock) void k_diffract(const float4* __restric
 __global__ void k_zero_u64(unsigned long long* c) { *c = 0ull; }
 __global__ void k_zero_i32(int* c) { *c = 0; }
 
+// Largest scene of rt_wedges_noalloc: keys and values of 3 * 2^18 half-edges
+// take 18 MiB of the 24 MiB scratch, the radix sort's double-buffer storage
+// the rest.
+constexpr int64_t kNoAllocMaxFacets = int64_t(1) << 18;
+
+// Device address of this GPU's copy of `scratch`, looked up once per device
+// with that device current.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch[kMaxDevices] = {};
+
+int scratch_of_device(unsigned char** out) {
+  int dev = 0;
+  int rc = check_hip(hipGetDevice(&dev), "hipGetDevice");
+  if (rc != RT_OK) return rc;
+  if (dev < 0 || dev >= kMaxDevices) return set_error(RT_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    rc = check_hip(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress");
+    if (rc != RT_OK) return rc;
+    g_scratch[dev] = static_cast<unsigned char*>(p);
+  }
+  *out = g_scratch[dev];
+  return RT_OK;
+}
+
 }  // namespace
 }  // namespace rt
 
@@ -399,6 +434,56 @@ int rt_wedges(const float* tris, int64_t n, int32_t* nbr, hipStream_t s) {
   for (void* p : {(void*)k_in, (void*)k_out, (void*)v_in, (void*)v_out, (void*)bad, tmp})
     if (p) (void)hipFree(p);
   if (rc == RT_OK && host_bad) return set_error(RT_EINVAL, "rt_wedges: a facet has a non-finite vertex");
+  return rc;
+}
+
+int rt_wedges_noalloc(const float* tris, int64_t n, int32_t* nbr, hipStream_t s) {
+  if (!tris || !nbr || !aligned_to(tris, 4) || !aligned_to(nbr, 4))
+    return set_error(RT_EINVAL, "rt_wedges_noalloc: NULL or misaligned array");
+  if (n < 1 || n > kNoAllocMaxFacets)
+    return set_error(RT_EINVAL, "rt_wedges_noalloc: n outside 1..262144 (the size of its device "
+                                "scratch; rt_wedges takes larger scenes)");
+  unsigned char* base = nullptr;
+  int rc = scratch_of_device(&base);
+  if (rc != RT_OK) return rc;
+  const int64_t nh = 3 * n;
+  size_t off = 0;
+  auto carve = [&](size_t bytes) {
+    unsigned char* p = base + off;
+    off += (bytes + 255) & ~size_t(255);
+    return p;
+  };
+  auto* k0 = reinterpret_cast<unsigned long long*>(carve(sizeof(unsigned long long) * nh));
+  auto* k1 = reinterpret_cast<unsigned long long*>(carve(sizeof(unsigned long long) * nh));
+  auto* v0 = reinterpret_cast<uint32_t*>(carve(sizeof(uint32_t) * nh));
+  auto* v1 = reinterpret_cast<uint32_t*>(carve(sizeof(uint32_t) * nh));
+  int* bad = reinterpret_cast<int*>(carve(sizeof(int)));
+  hipcub::DoubleBuffer<unsigned long long> keys(k0, k1);
+  hipcub::DoubleBuffer<uint32_t> vals(v0, v1);
+  size_t tmp_bytes = 0;
+  rc = check_hip(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, keys, vals, (int)nh, 0, 64, s),
+                 "radix sort size");
+  if (rc != RT_OK) return rc;
+  if (off + tmp_bytes > sizeof(scratch))
+    return set_error(RT_EINVAL, "rt_wedges_noalloc: sort storage exceeds the device scratch");
+  void* tmp = base + off;
+  const unsigned g = (unsigned)((nh + 255) / 256);
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(1), 0, s, bad);  // the scratch keeps the last call's flag
+  hipLaunchKernelGGL(k_edge_keys, dim3(g), dim3(256), 0, s, tris, nh, keys.Current(), vals.Current(), bad);
+  rc = check_hip(hipGetLastError(), "edge keys");
+  if (rc == RT_OK)
+    rc = check_hip(hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, keys, vals, (int)nh, 0, 64, s),
+                   "radix sort");
+  if (rc != RT_OK) return rc;
+  hipLaunchKernelGGL(k_edge_group, dim3(g), dim3(256), 0, s, tris, nh, keys.Current(), vals.Current(),
+                     nbr);
+  rc = check_hip(hipGetLastError(), "edge groups");
+  int host_bad = 0;
+  if (rc == RT_OK)
+    rc = check_hip(hipMemcpyAsync(&host_bad, bad, sizeof(int), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+  if (rc == RT_OK) rc = check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+  if (rc == RT_OK && host_bad)
+    return set_error(RT_EINVAL, "rt_wedges_noalloc: a facet has a non-finite vertex");
   return rc;
 }
 

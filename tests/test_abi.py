@@ -161,6 +161,11 @@ def test_null_handles():
     info = R.rt_bvh_info()
     assert lib.rt_bvh_info_get(None, ctypes.byref(info)) == R.RT_EINVAL
     assert lib.rt_bvh_stats(None, ctypes.byref(info)) == R.RT_EINVAL
+    host = np.zeros((4, 9), np.float32)
+    ptr = host.ctypes.data_as(ctypes.c_void_p)
+    assert lib.rt_wedges_noalloc(None, 4, ptr, None) == R.RT_EINVAL
+    assert lib.rt_wedges_noalloc(ptr, 0, ptr, None) == R.RT_EINVAL
+    assert lib.rt_wedges_noalloc(ptr, 262145, ptr, None) == R.RT_EINVAL   # above its scratch
     assert lib.rt_trace(None, None, 0, None, None) == R.RT_EINVAL
     assert lib.rt_trace_bounces(None, None, 0, 1, None, None, None, None) == R.RT_EINVAL
     assert lib.rt_bvh_download(None, None, 0, None, 0) == R.RT_EINVAL
