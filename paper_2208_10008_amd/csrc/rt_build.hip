@@ -513,29 +513,36 @@ struct Ctx {
 
 __device__ inline void set_err(BuildState* st, int bit) { atomicOr(&st->error, bit); }
 
-// Adds a big node to level `lvl`: a bin slot and its chunks.  Returns the
-// slot (the caller clears its bins), -1 on overflow.
-__device__ int push_big(const Ctx& X, int lvl, int id, int k) {
-  const int slot = atomicAdd(&X.st->a_nodes[lvl], 1);
-  const int nit = (k + kChunk - 1) / kChunk;
-  const int base = atomicAdd(&X.st->a_items[lvl], nit);
-  if (slot >= X.anode_cap || base + nit > X.item_cap) {
+// Chunk items queued so far on big-node level `lvl`.
+__device__ inline int level_items(const Ctx& X, int lvl) {
+  return (int)(unsigned)X.st->a_pack[lvl];
+}
+// Takes bin slots for `nodes` big nodes of level `lvl` and `items` chunk
+// items with one atomic add.  Returns false (and flags the error) when the
+// capacities are exceeded.
+__device__ inline bool take_big(const Ctx& X, int lvl, int nodes, int items, int& slot, int& base) {
+  const unsigned long long old =
+      atomicAdd(&X.st->a_pack[lvl], ((unsigned long long)nodes << 32) | (unsigned)items);
+  slot = (int)(old >> 32);
+  base = (int)(unsigned)old;
+  if (slot + nodes > X.anode_cap || base + items > X.item_cap) {
     set_err(X.st, 1);
-    return -1;
+    return false;
   }
-  AItem* it = X.items[lvl & 1];
-  for (int j = 0; j < nit; ++j) {
-    AItem a;
-    a.node = id;
-    a.slot = slot;
-    a.begin = j * kChunk;
-    a.end = min(k, (j + 1) * kChunk);
-    a.first_item = base;
-    a.n_items = nit;
-    a.pad[0] = a.pad[1] = 0;
-    it[base + j] = a;
-  }
-  return slot;
+  return true;
+}
+// Chunk item j (of nit) of big node `id` (k facets) at list index base + j.
+__device__ inline void write_item(const Ctx& X, int lvl, int id, int k, int slot, int base, int nit,
+                                  int j) {
+  AItem a;
+  a.node = id;
+  a.slot = slot;
+  a.begin = j * kChunk;
+  a.end = min(k, (j + 1) * kChunk);
+  a.first_item = base;
+  a.n_items = nit;
+  a.pad[0] = a.pad[1] = 0;
+  X.items[lvl & 1][base + j] = a;
 }
 __device__ inline char* node_bins(const Ctx& X, int lvl, int slot, int rep) {
   return X.abins[lvl & 1] + ((size_t)slot * kBinReplicas + rep) * X.abin_stride;
@@ -666,7 +673,7 @@ __global__ __launch_bounds__(256) void k_prep(const float* __restrict__ tris, in
 // Root node from the reduced bounds; queues it for the first schedule that
 // takes it (nothing when it is a leaf or a facet is not finite).
 __global__ __launch_bounds__(256) void k_root(Ctx X, const long long* root) {
-  __shared__ int s_slot;
+  __shared__ int s_slot, s_base;
   if (threadIdx.x == 0) s_slot = -1;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -693,13 +700,23 @@ __global__ __launch_bounds__(256) void k_root(Ctx X, const long long* root) {
   X.st->inv_l2 = l2 > 0.0 ? 1.0 / l2 : 0.0;
   if (X.st->nonfinite == 0 && X.n > X.C.max_leaf) {
     const int to = classify(X.C, X.n, 0, r.cblo, r.cbhi, X.la > 0, X.lm > 0);
-    if (to == TO_A) s_slot = push_big(X, 0, 0, X.n);
+    if (to == TO_A) {
+      int slot, base;
+      if (take_big(X, 0, 1, (X.n + kChunk - 1) / kChunk, slot, base)) {
+        s_slot = slot;
+        s_base = base;
+      }
+    }
     else if (to == TO_M) push_m(X, 0, 0, 0);
     else push_s(X, 0, 0);
   }
   }
   __syncthreads();
-  if (s_slot >= 0) clear_node_bins(X, 0, s_slot, threadIdx.x, blockDim.x);
+  if (s_slot >= 0) {
+    const int nit = (X.n + kChunk - 1) / kChunk;
+    for (int j = threadIdx.x; j < nit; j += blockDim.x) write_item(X, 0, 0, X.n, s_slot, s_base, nit, j);
+    clear_node_bins(X, 0, s_slot, threadIdx.x, blockDim.x);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -749,7 +766,7 @@ __host__ __device__ inline int a_copies(int B) {
 
 __global__ __launch_bounds__(kAThreads) void k_a_bin(Ctx X, int lvl) {
   extern __shared__ __align__(16) char lds[];
-  if ((int)blockIdx.x >= min(X.st->a_items[lvl], X.item_cap)) return;
+  if ((int)blockIdx.x >= min(level_items(X, lvl), X.item_cap)) return;
   const int par = lvl & 1;
   const AItem it = X.items[par][blockIdx.x];
   const BNode nd = X.nodes[it.node];
@@ -831,7 +848,7 @@ __global__ __launch_bounds__(kAThreads) void k_a_split(Ctx X, int lvl) {
   __shared__ double s_best;
   __shared__ int s_red[kAThreads / 64];
   __shared__ int s_w[2][kAThreads / 64];
-  if ((int)blockIdx.x >= min(X.st->a_items[lvl], X.item_cap)) return;
+  if ((int)blockIdx.x >= min(level_items(X, lvl), X.item_cap)) return;
   const int par = lvl & 1;
   const AItem it = X.items[par][blockIdx.x];
   const BNode nd = X.nodes[it.node];
@@ -952,26 +969,48 @@ __global__ __launch_bounds__(kAThreads) void k_a_split(Ctx X, int lvl) {
     rb += tr;
   }
   if (it.begin != 0) return;  // the node's first chunk writes the children
+  // per side: bin slot (-1: not a big node), first chunk item, chunk items
+  __shared__ int s_big[2][3];
+  const int c0 = 2 * (nd.first + nleft - 1) + 1;
   if (tid == 0) {
     float lo[2][3], hi[2][3];
     double clo[2][3], chi[2][3];
     bins_union(S, B, axis, 0, plane, lo[0], hi[0], clo[0], chi[0]);
     bins_union(S, B, axis, plane, B, lo[1], hi[1], clo[1], chi[1]);
-    const int c0 = make_children(X, it.node, nd, axis, plane, u.flags, s_best, nleft, lo, hi, clo, chi);
+    make_children(X, it.node, nd, axis, plane, u.flags, s_best, nleft, lo, hi, clo, chi);
+    int nit[2] = {0, 0};
     for (int side = 0; side < 2; ++side) {
-      s_w[0][side] = -1;
+      s_big[side][0] = -1;
       const int kc = side == 0 ? nleft : k - nleft;
       if (kc <= C.max_leaf) continue;
       const int first = nd.first + (side == 0 ? 0 : nleft);
       const int to = classify(C, kc, nd.depth + 1, clo[side], chi[side], lvl + 1 < X.la, X.lm > 0);
-      if (to == TO_A) s_w[0][side] = push_big(X, lvl + 1, c0 + side, kc);
+      if (to == TO_A) nit[side] = (kc + kChunk - 1) / kChunk;
       else if (to == TO_M) push_m(X, 0, c0 + side, first);
       else push_s(X, c0 + side, first);
     }
+    // both big children's bin slots and chunk items in one atomic add
+    const int nbig = (nit[0] > 0) + (nit[1] > 0);
+    int slot, base;
+    if (nbig > 0 && take_big(X, lvl + 1, nbig, nit[0] + nit[1], slot, base)) {
+      for (int side = 0; side < 2; ++side) {
+        if (nit[side] == 0) continue;
+        s_big[side][0] = slot++;
+        s_big[side][1] = base;
+        s_big[side][2] = nit[side];
+        base += nit[side];
+      }
+    }
   }
   __syncthreads();
-  for (int side = 0; side < 2; ++side)
-    if (s_w[0][side] >= 0) clear_node_bins(X, lvl + 1, s_w[0][side], tid, kAThreads);
+  for (int side = 0; side < 2; ++side) {
+    const int slot = s_big[side][0];
+    if (slot < 0) continue;
+    const int kc = side == 0 ? nleft : k - nleft;
+    for (int j = tid; j < s_big[side][2]; j += kAThreads)
+      write_item(X, lvl + 1, c0 + side, kc, slot, s_big[side][1], s_big[side][2], j);
+    clear_node_bins(X, lvl + 1, slot, tid, kAThreads);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -979,6 +1018,35 @@ __global__ __launch_bounds__(kAThreads) void k_a_split(Ctx X, int lvl) {
 // left child id (wave-uniform) and the children's sizes and centroid bounds.
 constexpr int kPartE = 8;  // consecutive records per lane and partition round
 
+// Run of consecutive facets in one bin of one axis, counts and boxes only.
+struct RunB {
+  int bin, count;
+  float lo[3], hi[3];
+};
+__device__ inline void runb_reset(RunB& r, int bin) {
+  r.bin = bin;
+  r.count = 0;
+  for (int q = 0; q < 3; ++q) {
+    r.lo[q] = INFINITY;
+    r.hi[q] = -INFINITY;
+  }
+}
+__device__ inline void runb_flush(const RunB& r, const Bins& S, int a, int B) {
+  if (r.count == 0) return;
+  const int slot = a * B + r.bin;
+  atomicAdd(&S.cnt[slot], r.count);
+  for (int q = 0; q < 3; ++q) {
+    atomicMin(&S.box[6 * slot + q], f2o(r.lo[q]));
+    atomicMax(&S.box[6 * slot + 3 + q], f2o(r.hi[q]));
+  }
+}
+
+// The wave's bins count facets and unite their boxes per bin (the centroid
+// bounds region of S is not used as bins here: it holds the 12 + 12 child
+// accumulators, so S must come with centroid bounds).  The children's
+// volumes and centroid bounds are exact unions of their facets', taken while
+// partitioning: each lane unites its own facets, then adds them with ordered
+// integer min / max into the accumulators.
 __device__ int wave_split_global(const Ctx& X, int id, const Bins& S, int& kc0, int& kc1,
                                  double ccb[2][6]) {
   const int lane = lane_id();
@@ -990,17 +1058,25 @@ __device__ int wave_split_global(const Ctx& X, int id, const Bins& S, int& kc0, 
   const FacetRec* in = X.recs[nd.depth & 1] + nd.first;
   FacetRec* out = X.recs[(nd.depth + 1) & 1] + nd.first;
   int32_t* perm = X.perm + nd.first;
+  long long* cacc = S.cb;          // [side][centroid lo xyz, hi xyz]
+  int* bacc = (int*)(S.cb + 12);   // [side][box lo xyz, hi xyz]
+  if (lane < 12) {
+    cacc[lane] = lane % 6 < 3 ? d2o(INFINITY) : d2o(-INFINITY);
+    bacc[lane] = lane % 6 < 3 ? f2o(INFINITY) : f2o(-INFINITY);
+  }
   int axis = -1, plane = -1, flags = u.flags;
   double best = INFINITY;
   if (!u.forced) {
-    bins_clear(S, B, lane, 64);
+    Bins Sb = S;
+    Sb.cb = nullptr;
+    bins_clear(Sb, B, lane, 64);
     wave_sync();
     // each lane walks a contiguous run of the node's facets
     const int per = (k + 63) / 64;
     const int i0 = min(k, lane * per), i1 = min(k, i0 + per);
-    Run run[3];
+    RunB run[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) run_reset(run[a], -1);
+    for (int a = 0; a < 3; ++a) runb_reset(run[a], -1);
     constexpr int kBinU = 4;
     for (int i = i0; i < i1; i += kBinU) {
       float4 lo[kBinU], hi[kBinU];
@@ -1020,32 +1096,31 @@ __device__ int wave_split_global(const Ctx& X, int id, const Bins& S, int& kc0, 
           if (!u.axis_ok[a]) continue;
           const int b = bin_of(cu[a], nd.cblo[a], u.scale[a], B);
           if (b != run[a].bin) {
-            run_flush(run[a], S, a, B);
-            run_reset(run[a], b);
+            runb_flush(run[a], Sb, a, B);
+            runb_reset(run[a], b);
           }
-          Run& r = run[a];
+          RunB& r = run[a];
           r.count += 1;
           r.lo[0] = fminf(r.lo[0], lo[v].x); r.lo[1] = fminf(r.lo[1], lo[v].y); r.lo[2] = fminf(r.lo[2], lo[v].z);
           r.hi[0] = fmaxf(r.hi[0], hi[v].x); r.hi[1] = fmaxf(r.hi[1], hi[v].y); r.hi[2] = fmaxf(r.hi[2], hi[v].z);
-          r.clo[0] = fmin(r.clo[0], cu[0]); r.clo[1] = fmin(r.clo[1], cu[1]); r.clo[2] = fmin(r.clo[2], cu[2]);
-          r.chi[0] = fmax(r.chi[0], cu[0]); r.chi[1] = fmax(r.chi[1], cu[1]); r.chi[2] = fmax(r.chi[2], cu[2]);
         }
       }
     }
 #pragma unroll
-    for (int a = 0; a < 3; ++a) run_flush(run[a], S, a, B);
+    for (int a = 0; a < 3; ++a) runb_flush(run[a], Sb, a, B);
     wave_sync();
     const double clo[3] = {nd.lo[0], nd.lo[1], nd.lo[2]}, chi[3] = {nd.hi[0], nd.hi[1], nd.hi[2]};
     wave_eval(S.cnt, S.box, C, u, clo, chi, k, axis, plane, best);
     if (axis < 0) flags |= 2;
   }
+  wave_sync();  // the accumulators' initial values
   const bool by_position = axis < 0;
-  int nleft;
+  int nleft = 0;
   if (by_position) {
     nleft = k / 2;
   } else {
-    nleft = 0;
-    for (int b = 0; b < plane; ++b) nleft += S.cnt[axis * B + b];
+    for (int b = lane; b < plane; b += 64) nleft += S.cnt[axis * B + b];
+    nleft = wsum(nleft);
   }
   const bool leaf0 = nleft <= C.max_leaf, leaf1 = k - nleft <= C.max_leaf;
   const int ax = by_position ? 0 : axis;
@@ -1101,15 +1176,13 @@ __device__ int wave_split_global(const Ctx& X, int id, const Bins& S, int& kc0, 
         } else {
           set_err(X.st, 128);
         }
-        if (by_position) {  // no bins: child bounds from the facets themselves
-          const float4 lo = r[e].lo, hi = r[e].hi;
-          const double cx = centroid(lo.x, hi.x), cy = centroid(lo.y, hi.y), cz = centroid(lo.z, hi.z);
-          const int sd = gl[e] ? 0 : 1;
-          blo[sd][0] = fminf(blo[sd][0], lo.x); blo[sd][1] = fminf(blo[sd][1], lo.y); blo[sd][2] = fminf(blo[sd][2], lo.z);
-          bhi[sd][0] = fmaxf(bhi[sd][0], hi.x); bhi[sd][1] = fmaxf(bhi[sd][1], hi.y); bhi[sd][2] = fmaxf(bhi[sd][2], hi.z);
-          cbl[sd][0] = fmin(cbl[sd][0], cx); cbl[sd][1] = fmin(cbl[sd][1], cy); cbl[sd][2] = fmin(cbl[sd][2], cz);
-          cbh[sd][0] = fmax(cbh[sd][0], cx); cbh[sd][1] = fmax(cbh[sd][1], cy); cbh[sd][2] = fmax(cbh[sd][2], cz);
-        }
+        const float4 lo = r[e].lo, hi = r[e].hi;
+        const double cx = centroid(lo.x, hi.x), cy = centroid(lo.y, hi.y), cz = centroid(lo.z, hi.z);
+        const int sd = gl[e] ? 0 : 1;
+        blo[sd][0] = fminf(blo[sd][0], lo.x); blo[sd][1] = fminf(blo[sd][1], lo.y); blo[sd][2] = fminf(blo[sd][2], lo.z);
+        bhi[sd][0] = fmaxf(bhi[sd][0], hi.x); bhi[sd][1] = fmaxf(bhi[sd][1], hi.y); bhi[sd][2] = fmaxf(bhi[sd][2], hi.z);
+        cbl[sd][0] = fmin(cbl[sd][0], cx); cbl[sd][1] = fmin(cbl[sd][1], cy); cbl[sd][2] = fmin(cbl[sd][2], cz);
+        cbh[sd][0] = fmax(cbh[sd][0], cx); cbh[sd][1] = fmax(cbh[sd][1], cy); cbh[sd][2] = fmax(cbh[sd][2], cz);
       }
       offl += __popcll(ml[e]);
       offr += __popcll(mr[e]);
@@ -1117,20 +1190,27 @@ __device__ int wave_split_global(const Ctx& X, int id, const Bins& S, int& kc0, 
     lbase += offl;
     rbase += offr;
   }
+  // the children's volumes and centroid bounds (a lane with no facet on a
+  // side leaves that side's accumulators alone)
+  for (int side = 0; side < 2; ++side)
+    for (int q = 0; q < 3; ++q) {
+      if (blo[side][q] <= bhi[side][q]) {
+        atomicMin(&bacc[6 * side + q], f2o(blo[side][q]));
+        atomicMax(&bacc[6 * side + 3 + q], f2o(bhi[side][q]));
+        atomicMin(&cacc[6 * side + q], d2o(cbl[side][q]));
+        atomicMax(&cacc[6 * side + 3 + q], d2o(cbh[side][q]));
+      }
+    }
+  wave_sync();
   float lo[2][3], hi[2][3];
   double clo[2][3], chi[2][3];
-  if (by_position) {
-    for (int side = 0; side < 2; ++side)
-      for (int q = 0; q < 3; ++q) {
-        lo[side][q] = wmin(blo[side][q]);
-        hi[side][q] = wmax(bhi[side][q]);
-        clo[side][q] = wmin(cbl[side][q]);
-        chi[side][q] = wmax(cbh[side][q]);
-      }
-  } else {
-    bins_union(S, B, axis, 0, plane, lo[0], hi[0], clo[0], chi[0]);
-    bins_union(S, B, axis, plane, B, lo[1], hi[1], clo[1], chi[1]);
-  }
+  for (int side = 0; side < 2; ++side)
+    for (int q = 0; q < 3; ++q) {
+      lo[side][q] = o2f(bacc[6 * side + q]);
+      hi[side][q] = o2f(bacc[6 * side + 3 + q]);
+      clo[side][q] = o2d(cacc[6 * side + q]);
+      chi[side][q] = o2d(cacc[6 * side + 3 + q]);
+    }
   if (lane == 0)
     make_children(X, id, nd, axis, plane, flags, by_position ? 0.0 : best, nleft, lo, hi, clo, chi);
   const int c0 = 2 * (nd.first + nleft - 1) + 1;
@@ -1141,6 +1221,7 @@ __device__ int wave_split_global(const Ctx& X, int id, const Bins& S, int& kc0, 
       ccb[side][q] = clo[side][q];
       ccb[side][3 + q] = chi[side][q];
     }
+  wave_sync();  // the bins and accumulators are reused by the wave's next node
   return c0;
 }
 
@@ -1233,6 +1314,8 @@ __device__ inline void bins16_from_lanes(int r0, int cnt, int packed_bins, const
   if (lane >= 48) c = 0;
 }
 
+// S must come with centroid bounds: that region holds the children's
+// accumulators, the bins (any count but 16) are counts and boxes only.
 __device__ void wave_subtree_regs(const Ctx& X, int id, const Bins& S, RNode* stk) {
   const int lane = lane_id();
   const int B = X.C.nbins;
@@ -1287,7 +1370,9 @@ __device__ void wave_subtree_regs(const Ctx& X, int id, const Bins& S, RNode* st
         bins16_from_lanes(t.r0, t.cnt, mybins, lo, hi, c, bl, bh);
         eval16(c, bl, bh, C, u, clo, chi, t.cnt, axis, plane, best);
       } else {
-        bins_clear(S, B, lane, 64);
+        Bins Sb = S;
+        Sb.cb = nullptr;
+        bins_clear(Sb, B, lane, 64);
         wave_sync();
         if (inr) {
 #pragma unroll
@@ -1322,20 +1407,38 @@ __device__ void wave_subtree_regs(const Ctx& X, int id, const Bins& S, RNode* st
       hi[q] = __int_as_float(__builtin_amdgcn_ds_permute(dst * 4, __float_as_int(hi[q])));
     }
     fid = __builtin_amdgcn_ds_permute(dst * 4, fid);
-    // child volumes and centroid bounds
+    // child volumes and centroid bounds: exact unions through ordered-integer
+    // min / max into the accumulators, one facet per lane
     const int side = !inr ? -1 : (lane < t.r0 + nleft ? 0 : 1);
+    long long* cacc = S.cb;         // [side][centroid lo xyz, hi xyz]
+    int* bacc = (int*)(S.cb + 12);  // [side][box lo xyz, hi xyz]
+    wave_sync();  // the previous node's reads of the accumulators are done
+    if (lane < 12) {
+      cacc[lane] = lane % 6 < 3 ? d2o(INFINITY) : d2o(-INFINITY);
+      bacc[lane] = lane % 6 < 3 ? f2o(INFINITY) : f2o(-INFINITY);
+    }
+    wave_sync();
+    if (side >= 0) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        atomicMin(&bacc[6 * side + q], f2o(lo[q]));
+        atomicMax(&bacc[6 * side + 3 + q], f2o(hi[q]));
+        const long long c = d2o(centroid(lo[q], hi[q]));
+        atomicMin(&cacc[6 * side + q], c);
+        atomicMax(&cacc[6 * side + 3 + q], c);
+      }
+    }
+    wave_sync();
     float clo_f[2][3], chi_f[2][3];
     double ccl[2][3], cch[2][3];
 #pragma unroll
     for (int s = 0; s < 2; ++s)
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
-        const bool m = side == s;
-        const double c = centroid(lo[q], hi[q]);
-        clo_f[s][q] = rmin(m ? lo[q] : INFINITY);
-        chi_f[s][q] = rmax(m ? hi[q] : -INFINITY);
-        ccl[s][q] = rmin(m ? c : (double)INFINITY);
-        cch[s][q] = rmax(m ? c : -(double)INFINITY);
+        clo_f[s][q] = o2f(bacc[6 * s + q]);
+        chi_f[s][q] = o2f(bacc[6 * s + 3 + q]);
+        ccl[s][q] = o2d(cacc[6 * s + q]);
+        cch[s][q] = o2d(cacc[6 * s + 3 + q]);
       }
     BNode pn;
     pn.first = base + t.r0;
@@ -1403,9 +1506,7 @@ __global__ __launch_bounds__(kWaveThreads) void k_s(Ctx X) {
       const int id = gstk[--sp];
       const int k = X.nodes[id].count;
       if (k <= kRegNode) {
-        Bins Sr = S;  // counts and boxes only
-        Sr.cb = nullptr;
-        wave_subtree_regs(X, id, Sr, rstk);
+        wave_subtree_regs(X, id, S, rstk);
         continue;
       }
       int kc[2];

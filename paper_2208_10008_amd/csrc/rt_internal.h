@@ -91,8 +91,9 @@ struct BuildState {
   int32_t n;           // facets of the build
   int32_t pad[3];
   double inv_l2;       // 1 / squared root diagonal (0 if the root is a point)
-  int32_t a_items[kMaxPhaseLevels + 1];  // chunk items per big-node level
-  int32_t a_nodes[kMaxPhaseLevels + 1];  // big nodes per level
+  // per big-node level: (big nodes << 32) | chunk items, both taken by one
+  // atomic add per parent
+  unsigned long long a_pack[kMaxPhaseLevels + 1];
 };
 constexpr int kStateWords = 512;  // int32 words reserved for BuildState
 static_assert(sizeof(BuildState) <= kStateWords * 4, "BuildState too large");
