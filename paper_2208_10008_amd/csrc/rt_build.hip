@@ -758,30 +758,41 @@ __device__ inline void run_flush(const Run& r, const Bins& S, int a, int B) {
 
 // Big nodes, pass 1: one work-group bins one chunk into LDS (one bin copy per
 // wave while they fit) and stores the chunk's bins.
-constexpr int kAThreads = 256;
-__host__ __device__ inline int a_copies(int B) {
+constexpr int kAThreads = 256;     // threads of a chunk's split work-group
+constexpr int kABinThreads = 128;  // threads of a chunk's binning work-group (4 facets each)
+__host__ __device__ inline int a_copies(int B, int threads) {
   const int fit = (int)((40 * 1024) / bins_bytes(B, true));
-  return fit < 1 ? 1 : (fit < kAThreads / 64 ? fit : kAThreads / 64);
+  return fit < 1 ? 1 : (fit < threads / 64 ? fit : threads / 64);
 }
 
-__global__ __launch_bounds__(kAThreads) void k_a_bin(Ctx X, int lvl) {
+__global__ __launch_bounds__(kABinThreads) void k_a_bin(Ctx X, int lvl) {
   extern __shared__ __align__(16) char lds[];
-  if ((int)blockIdx.x >= min(level_items(X, lvl), X.item_cap)) return;
+  const int active = min(level_items(X, lvl), X.item_cap);
+  if ((int)blockIdx.x >= active) return;
+  {
+    // the next level's bins (at most two big children per big node here),
+    // cleared by this level's work-groups in turn: nothing reads or adds to
+    // them before the next level's binning
+    const int next_slots = min(X.anode_cap, 2 * (int)(X.st->a_pack[lvl] >> 32));
+    for (int pr = blockIdx.x; pr < next_slots * kBinReplicas; pr += active)
+      bins_clear(bins_at(node_bins(X, lvl + 1, pr / kBinReplicas, pr % kBinReplicas), X.C.nbins, true),
+                 X.C.nbins, threadIdx.x, kABinThreads);
+  }
   const int par = lvl & 1;
   const AItem it = X.items[par][blockIdx.x];
   const BNode nd = X.nodes[it.node];
   const int B = X.C.nbins;
-  const int ncopy = a_copies(B);
+  const int ncopy = a_copies(B, kABinThreads);
   const size_t cs = bins_bytes(B, true);
   const int tid = threadIdx.x;
-  for (int cp = 0; cp < ncopy; ++cp) bins_clear(bins_at(lds + cp * cs, B, true), B, tid, kAThreads);
+  for (int cp = 0; cp < ncopy; ++cp) bins_clear(bins_at(lds + cp * cs, B, true), B, tid, kABinThreads);
   __syncthreads();
   const NodeSetup u = node_setup(X.C, nd.depth, nd.count, nd.cblo, nd.cbhi);
   const Bins S = bins_at(lds + ((tid >> 6) % ncopy) * cs, B, true);
   const FacetRec* in = X.recs[nd.depth & 1] + nd.first;
   // each thread walks a contiguous run of the chunk; consecutive facets that
   // share a bin are merged in registers before they reach LDS
-  constexpr int kPer = kChunk / kAThreads;
+  constexpr int kPer = kChunk / kABinThreads;
   const int i0 = it.begin + tid * kPer;
   FacetRec rr[kPer];
 #pragma unroll
@@ -811,7 +822,7 @@ __global__ __launch_bounds__(kAThreads) void k_a_bin(Ctx X, int lvl) {
   // this chunk's counts, and its bins added to one replica of the node's bins
   const Bins G = bins_at(node_bins(X, lvl, it.slot, blockIdx.x % kBinReplicas), B, true);
   int32_t* cc = X.ccnt[par] + (size_t)blockIdx.x * 3 * RT_MAX_BINS;
-  for (int c = tid; c < 3 * B; c += kAThreads) {
+  for (int c = tid; c < 3 * B; c += kABinThreads) {
     int cnt = 0;
     int bx[6] = {f2o(INFINITY), f2o(INFINITY), f2o(INFINITY), f2o(-INFINITY), f2o(-INFINITY), f2o(-INFINITY)};
     long long cb[6] = {d2o(INFINITY), d2o(INFINITY), d2o(INFINITY), d2o(-INFINITY), d2o(-INFINITY), d2o(-INFINITY)};
@@ -971,12 +982,39 @@ __global__ __launch_bounds__(kAThreads) void k_a_split(Ctx X, int lvl) {
   if (it.begin != 0) return;  // the node's first chunk writes the children
   // per side: bin slot (-1: not a big node), first chunk item, chunk items
   __shared__ int s_big[2][3];
+  // the children's volumes and centroid bounds: the node's bins on the split
+  // axis united per side, one bin per lane of the first wave
+  __shared__ int s_bacc[12];
+  __shared__ long long s_cacc[12];
   const int c0 = 2 * (nd.first + nleft - 1) + 1;
+  if (wave == 0) {
+    if (lane < 12) {
+      s_bacc[lane] = lane % 6 < 3 ? f2o(INFINITY) : f2o(-INFINITY);
+      s_cacc[lane] = lane % 6 < 3 ? d2o(INFINITY) : d2o(-INFINITY);
+    }
+    wave_sync();
+    for (int b = lane; b < B; b += 64) {
+      const int slot = axis * B + b, sd = b < plane ? 0 : 1;
+      if (S.cnt[slot] == 0) continue;
+      for (int q = 0; q < 3; ++q) {
+        atomicMin(&s_bacc[6 * sd + q], S.box[6 * slot + q]);
+        atomicMax(&s_bacc[6 * sd + 3 + q], S.box[6 * slot + 3 + q]);
+        atomicMin(&s_cacc[6 * sd + q], S.cb[6 * slot + q]);
+        atomicMax(&s_cacc[6 * sd + 3 + q], S.cb[6 * slot + 3 + q]);
+      }
+    }
+    wave_sync();
+  }
   if (tid == 0) {
     float lo[2][3], hi[2][3];
     double clo[2][3], chi[2][3];
-    bins_union(S, B, axis, 0, plane, lo[0], hi[0], clo[0], chi[0]);
-    bins_union(S, B, axis, plane, B, lo[1], hi[1], clo[1], chi[1]);
+    for (int sd = 0; sd < 2; ++sd)
+      for (int q = 0; q < 3; ++q) {
+        lo[sd][q] = o2f(s_bacc[6 * sd + q]);
+        hi[sd][q] = o2f(s_bacc[6 * sd + 3 + q]);
+        clo[sd][q] = o2d(s_cacc[6 * sd + q]);
+        chi[sd][q] = o2d(s_cacc[6 * sd + 3 + q]);
+      }
     make_children(X, it.node, nd, axis, plane, u.flags, s_best, nleft, lo, hi, clo, chi);
     int nit[2] = {0, 0};
     for (int side = 0; side < 2; ++side) {
@@ -1009,7 +1047,6 @@ __global__ __launch_bounds__(kAThreads) void k_a_split(Ctx X, int lvl) {
     const int kc = side == 0 ? nleft : k - nleft;
     for (int j = tid; j < s_big[side][2]; j += kAThreads)
       write_item(X, lvl + 1, c0 + side, kc, slot, s_big[side][1], s_big[side][2], j);
-    clear_node_bins(X, lvl + 1, slot, tid, kAThreads);
   }
 }
 
@@ -1038,6 +1075,74 @@ __device__ inline void runb_flush(const RunB& r, const Bins& S, int a, int B) {
   for (int q = 0; q < 3; ++q) {
     atomicMin(&S.box[6 * slot + q], f2o(r.lo[q]));
     atomicMax(&S.box[6 * slot + 3 + q], f2o(r.hi[q]));
+  }
+}
+
+// Stable partition of a node's records (global memory) by the split: left
+// side first, each side in input order; leaf children's facets go to perm.
+// Each lane unites the boxes and centroids of the facets it moves, per side.
+// PE records per lane and round.
+template <int PE>
+__device__ __forceinline__ void split_partition(BuildState* st, const FacetRec* in, FacetRec* out,
+                                                int32_t* perm, int k, int nleft, bool by_position, int ax,
+                                                double ax_lo, double ax_scale, int B, int plane,
+                                                bool leaf0, bool leaf1, float blo[2][3], float bhi[2][3],
+                                                double cbl[2][3], double cbh[2][3]) {
+  const int lane = lane_id();
+  const unsigned long long below = lanes_below();
+  int lbase = 0, rbase = 0;
+  for (int base = 0; base < k; base += 64 * PE) {
+    FacetRec r[PE];
+    bool gl[PE], valid[PE];
+    unsigned long long ml[PE], mr[PE];
+#pragma unroll
+    for (int e = 0; e < PE; ++e) {
+      const int i = base + e * 64 + lane;
+      valid[e] = i < k;
+      r[e] = in[min(i, k - 1)];
+    }
+#pragma unroll
+    for (int e = 0; e < PE; ++e) {
+      const int i = base + e * 64 + lane;
+      bool g = false;
+      if (valid[e]) {
+        if (by_position) {
+          g = i < nleft;
+        } else {
+          const float l = ax == 0 ? r[e].lo.x : (ax == 1 ? r[e].lo.y : r[e].lo.z);
+          const float h = ax == 0 ? r[e].hi.x : (ax == 1 ? r[e].hi.y : r[e].hi.z);
+          g = bin_of(centroid(l, h), ax_lo, ax_scale, B) < plane;
+        }
+      }
+      gl[e] = g;
+      ml[e] = __ballot(valid[e] && g);
+      mr[e] = __ballot(valid[e] && !g);
+    }
+    int offl = 0, offr = 0;
+#pragma unroll
+    for (int e = 0; e < PE; ++e) {
+      if (valid[e]) {
+        const int dst = gl[e] ? lbase + offl + __popcll(ml[e] & below)
+                              : nleft + rbase + offr + __popcll(mr[e] & below);
+        if (dst >= 0 && dst < k) {
+          out[dst] = r[e];
+          if (gl[e] ? leaf0 : leaf1) perm[dst] = __float_as_int(r[e].lo.w);
+        } else {
+          set_err(st, 128);
+        }
+        const float4 lo = r[e].lo, hi = r[e].hi;
+        const double cx = centroid(lo.x, hi.x), cy = centroid(lo.y, hi.y), cz = centroid(lo.z, hi.z);
+        const int sd = gl[e] ? 0 : 1;
+        blo[sd][0] = fminf(blo[sd][0], lo.x); blo[sd][1] = fminf(blo[sd][1], lo.y); blo[sd][2] = fminf(blo[sd][2], lo.z);
+        bhi[sd][0] = fmaxf(bhi[sd][0], hi.x); bhi[sd][1] = fmaxf(bhi[sd][1], hi.y); bhi[sd][2] = fmaxf(bhi[sd][2], hi.z);
+        cbl[sd][0] = fmin(cbl[sd][0], cx); cbl[sd][1] = fmin(cbl[sd][1], cy); cbl[sd][2] = fmin(cbl[sd][2], cz);
+        cbh[sd][0] = fmax(cbh[sd][0], cx); cbh[sd][1] = fmax(cbh[sd][1], cy); cbh[sd][2] = fmax(cbh[sd][2], cz);
+      }
+      offl += __popcll(ml[e]);
+      offr += __popcll(mr[e]);
+    }
+    lbase += offl;
+    rbase += offr;
   }
 }
 
@@ -1135,61 +1240,12 @@ __device__ int wave_split_global(const Ctx& X, int id, const Bins& S, int& kc0, 
       cbl[side][q] = INFINITY;
       cbh[side][q] = -INFINITY;
     }
-  const unsigned long long below = lanes_below();
-  int lbase = 0, rbase = 0;
-  for (int base = 0; base < k; base += 64 * kPartE) {
-    FacetRec r[kPartE];
-    bool gl[kPartE], valid[kPartE];
-    unsigned long long ml[kPartE], mr[kPartE];
-#pragma unroll
-    for (int e = 0; e < kPartE; ++e) {
-      const int i = base + e * 64 + lane;
-      valid[e] = i < k;
-      r[e] = in[min(i, k - 1)];
-    }
-#pragma unroll
-    for (int e = 0; e < kPartE; ++e) {
-      const int i = base + e * 64 + lane;
-      bool g = false;
-      if (valid[e]) {
-        if (by_position) {
-          g = i < nleft;
-        } else {
-          const float l = ax == 0 ? r[e].lo.x : (ax == 1 ? r[e].lo.y : r[e].lo.z);
-          const float h = ax == 0 ? r[e].hi.x : (ax == 1 ? r[e].hi.y : r[e].hi.z);
-          g = bin_of(centroid(l, h), ax_lo, ax_scale, B) < plane;
-        }
-      }
-      gl[e] = g;
-      ml[e] = __ballot(valid[e] && g);
-      mr[e] = __ballot(valid[e] && !g);
-    }
-    int offl = 0, offr = 0;
-#pragma unroll
-    for (int e = 0; e < kPartE; ++e) {
-      if (valid[e]) {
-        const int dst = gl[e] ? lbase + offl + __popcll(ml[e] & below)
-                              : nleft + rbase + offr + __popcll(mr[e] & below);
-        if (dst >= 0 && dst < k) {
-          out[dst] = r[e];
-          if (gl[e] ? leaf0 : leaf1) perm[dst] = __float_as_int(r[e].lo.w);
-        } else {
-          set_err(X.st, 128);
-        }
-        const float4 lo = r[e].lo, hi = r[e].hi;
-        const double cx = centroid(lo.x, hi.x), cy = centroid(lo.y, hi.y), cz = centroid(lo.z, hi.z);
-        const int sd = gl[e] ? 0 : 1;
-        blo[sd][0] = fminf(blo[sd][0], lo.x); blo[sd][1] = fminf(blo[sd][1], lo.y); blo[sd][2] = fminf(blo[sd][2], lo.z);
-        bhi[sd][0] = fmaxf(bhi[sd][0], hi.x); bhi[sd][1] = fmaxf(bhi[sd][1], hi.y); bhi[sd][2] = fmaxf(bhi[sd][2], hi.z);
-        cbl[sd][0] = fmin(cbl[sd][0], cx); cbl[sd][1] = fmin(cbl[sd][1], cy); cbl[sd][2] = fmin(cbl[sd][2], cz);
-        cbh[sd][0] = fmax(cbh[sd][0], cx); cbh[sd][1] = fmax(cbh[sd][1], cy); cbh[sd][2] = fmax(cbh[sd][2], cz);
-      }
-      offl += __popcll(ml[e]);
-      offr += __popcll(mr[e]);
-    }
-    lbase += offl;
-    rbase += offr;
-  }
+  if (k <= 64)
+    split_partition<1>(X.st, in, out, perm, k, nleft, by_position, ax, ax_lo, ax_scale, B, plane, leaf0,
+                       leaf1, blo, bhi, cbl, cbh);
+  else
+    split_partition<kPartE>(X.st, in, out, perm, k, nleft, by_position, ax, ax_lo, ax_scale, B, plane,
+                            leaf0, leaf1, blo, bhi, cbl, cbh);
   // the children's volumes and centroid bounds (a lane with no facet on a
   // side leaves that side's accumulators alone)
   for (int side = 0; side < 2; ++side)
@@ -1933,10 +1989,10 @@ int build_tree(Buffers& B, const float* tris, int64_t n64, const rt_split_params
   hipLaunchKernelGGL(k_prep, dim3((n + pb - 1) / pb), dim3(pb), 0, s, tris, n, B.recs_a, B.perm, st,
                      B.root_box, B.used, B.mfront, B.sfront);
   hipLaunchKernelGGL(k_root, dim3(1), dim3(256), 0, s, X, (const long long*)B.root_box);
-  const size_t lds_abin = a_copies(Bn) * bins_bytes(Bn, true);
+  const size_t lds_abin = a_copies(Bn, kABinThreads) * bins_bytes(Bn, true);
   const size_t lds_asplit = bins_bytes(Bn, true);
   for (int l = 0; l < la; ++l) {
-    hipLaunchKernelGGL(k_a_bin, dim3(X.item_cap), dim3(kAThreads), lds_abin, s, X, l);
+    hipLaunchKernelGGL(k_a_bin, dim3(X.item_cap), dim3(kABinThreads), lds_abin, s, X, l);
     hipLaunchKernelGGL(k_a_split, dim3(X.item_cap), dim3(kAThreads), lds_asplit, s, X, l);
   }
   // one wave per window of facet positions
