@@ -72,6 +72,9 @@ def parse():
     ap.add_argument("--node-format", default="bin2", choices=["bin2", "f4", "q4"])
     ap.add_argument("--pipeline", type=int, default=2, choices=[1, 2],
                     help="trees / streams that consecutive steps alternate between")
+    ap.add_argument("--cut", type=int, default=0,
+                    help="two-launch trace: chains alive after this many segments are traced by a "
+                         "second launch in full waves (rt_trace_opts.cut; 0: one launch)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the alpha / d_norm sweep")
@@ -239,6 +242,7 @@ def main_step(args):
     trees = [R.BVH(tris, params) for _ in range(depth)]
     bvh = trees[0]
     streams = [torch.cuda.Stream() for _ in range(depth)]  # default priority
+    wss = [R.chain_workspace(n) for _ in range(depth)] if args.cut > 0 else [None] * depth
 
     def step(k, p, d, ev=None):
         """Step k on tree, outputs and stream k mod d: rebuild, then trace."""
@@ -249,7 +253,10 @@ def main_step(args):
         R.rt_rebuild(trees[i].handle, tris, p, stream=s)
         if ev is not None:
             ev[1].record(s)
-        R.rt_trace_bounces(trees[i].handle, rays, nb, *outs[i], stream=s)
+        if args.cut > 0:
+            R.rt_trace_ex(trees[i].handle, rays, nb, *outs[i], cut=args.cut, chain_ws=wss[i], stream=s)
+        else:
+            R.rt_trace_bounces(trees[i].handle, rays, nb, *outs[i], stream=s)
         if ev is not None:
             ev[2].record(s)
 
@@ -326,7 +333,8 @@ def main_step(args):
             "workload": w.name, "tris": w.n_tris, "rays": n, "max_bounces": nb,
             "tx": list(w.tx), "alpha": args.alpha, "max_leaf": args.max_leaf,
             "node_format": args.node_format,
-            "step": "rt_rebuild (Eq. 2 BVH for this Tx) + rt_trace_bounces",
+            "step": "rt_rebuild (Eq. 2 BVH for this Tx) + " + (
+                f"rt_trace_ex (two launches, cut {args.cut})" if args.cut > 0 else "rt_trace_bounces"),
             "pipeline": depth,
         },
         "roofline": roofline(trace_mean_ms, segments, nodes_total, tests_total,

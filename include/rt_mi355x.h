@@ -203,12 +203,35 @@ typedef struct rt_trace_opts {
                           the same for rt_trace, rt_trace_bounces, rt_trace_receive and
                           rt_trace_energy (batched launches trace one lane per ray).
                           Results do not depend on it. */
+  int32_t cut;         /* 0: every chain is traced to its end in one launch; k >= 1: two
+                          launches (Sec. III-B re-launch, late segments regrouped): the
+                          first traces every chain's first k segments and appends the chains
+                          still alive after them to chain_ws (one atomic add per wave), the
+                          second traces those from segment k on, 64 per wave.  Needs chain_ws,
+                          grid 0 and one lane per
+                          ray; no effect when max_bounces <= k.  Each chain's hits, path
+                          length and hit count are those of the one-launch trace up to the
+                          order in which a wave's lanes test leaves (a chain whose closest
+                          hit is decided within rounding may differ) */
+  int32_t reserved2;   /* must be 0 */
+  void* chain_ws;      /* cut >= 1: caller-owned device workspace of at least
+                          rt_trace_chain_ws_bytes(n) bytes, 256-byte aligned, used by this
+                          call only (calls that overlap need workspaces of their own) */
+  int64_t chain_ws_bytes;
 } rt_trace_opts;
+
+/* Workspace of a two-launch trace (rt_trace_opts.cut >= 1) of n rays: a
+ * 256-byte header (the live-chain count) and a 64-byte chain state per ray.
+ * n < 0: 0. */
+int64_t rt_trace_chain_ws_bytes(int64_t n);
 
 /* rt_trace_bounces with optional outputs (opts nullable).
  * Errors: as rt_trace_bounces; RT_EINVAL for a misaligned seg_rays / ray_stats,
  * block, grid, refill or lanes_per_ray outside their values, lanes_per_ray > 1
- * with seg_rays, ray_stats or grid > 0, or n > (2^31 - 1) 64 / lanes_per_ray. */
+ * with seg_rays, ray_stats or grid > 0, n > (2^31 - 1) 64 / lanes_per_ray,
+ * cut < 0, reserved2 != 0, or cut >= 1 with seg_rays, ray_stats, grid > 0,
+ * lanes_per_ray > 1, n >= 2^31, or chain_ws NULL, misaligned or smaller than
+ * rt_trace_chain_ws_bytes(n). */
 int rt_trace_ex(const rt_bvh* b, const float* rays, int64_t n, int32_t max_bounces,
                 rt_hit* out, double* path_len, int32_t* n_hits, const rt_trace_opts* opts,
                 hipStream_t s);

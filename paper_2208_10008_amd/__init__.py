@@ -72,7 +72,9 @@ class rt_bvh_info(ctypes.Structure):
 class rt_trace_opts(ctypes.Structure):
     _fields_ = [("seg_rays", ctypes.c_void_p), ("ray_stats", ctypes.c_void_p),
                 ("block", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("refill", ctypes.c_int32), ("lanes_per_ray", ctypes.c_int32)]
+                ("refill", ctypes.c_int32), ("lanes_per_ray", ctypes.c_int32),
+                ("cut", ctypes.c_int32), ("reserved2", ctypes.c_int32),
+                ("chain_ws", ctypes.c_void_p), ("chain_ws_bytes", ctypes.c_int64)]
 
 
 class rt_query(ctypes.Structure):
@@ -126,7 +128,7 @@ EXPORTS = ("rt_split_params_default", "rt_build", "rt_rebuild", "rt_trace",
            "rt_batch_autotune", "rt_batch_destroy", "rt_rays_from_directions",
            "rt_rays_from_directions_many", "rt_trace_receive", "rt_receive_segments", "rt_receive_dedup_workspace",
            "rt_receive_dedup", "rt_trace_energy", "rt_wedges", "rt_wedges_noalloc",
-           "rt_diffract_segments")
+           "rt_diffract_segments", "rt_trace_chain_ws_bytes")
 PROBE_EXPORTS = ("rt_probe_read", "rt_probe_copy")  # include/rt_probe.h
 
 _lib = None
@@ -148,6 +150,8 @@ def load(path: str = LIB_PATH):
     lib.rt_trace.argtypes = [P, P, i64, P, P]
     lib.rt_trace_bounces.argtypes = [P, P, i64, i32, P, P, P, P]
     lib.rt_trace_ex.argtypes = [P, P, i64, i32, P, P, P, ctypes.POINTER(rt_trace_opts), P]
+    lib.rt_trace_chain_ws_bytes.argtypes = [i64]
+    lib.rt_trace_chain_ws_bytes.restype = i64
     lib.rt_bvh_info_get.argtypes = [P, ctypes.POINTER(rt_bvh_info)]
     lib.rt_bvh_stats.argtypes = [P, ctypes.POINTER(rt_bvh_info)]
     lib.rt_bvh_download.argtypes = [P, P, i64, P, i64]
@@ -275,13 +279,22 @@ def rt_trace_bounces(handle, rays, max_bounces, out, path_len=None, n_hits=None,
                                 _ptr(path_len), _ptr(n_hits), _stream(stream)))
 
 
+def rt_trace_chain_ws_bytes(n: int) -> int:
+    return int(load().rt_trace_chain_ws_bytes(n))
+
+
 def rt_trace_ex(handle, rays, max_bounces, out, path_len=None, n_hits=None, seg_rays=None,
-                ray_stats=None, block=0, grid=0, refill=0, lanes_per_ray=0, stream=None):
+                ray_stats=None, block=0, grid=0, refill=0, lanes_per_ray=0, cut=0, chain_ws=None,
+                stream=None):
     lib = load()
     o = rt_trace_opts()
     o.seg_rays = None if seg_rays is None else seg_rays.data_ptr()
     o.ray_stats = None if ray_stats is None else ray_stats.data_ptr()
     o.block, o.grid, o.refill, o.lanes_per_ray = block, grid, refill, lanes_per_ray
+    o.cut, o.reserved2 = cut, 0
+    if chain_ws is not None:
+        o.chain_ws = chain_ws.data_ptr()
+        o.chain_ws_bytes = chain_ws.numel() * chain_ws.element_size()
     _check(lib.rt_trace_ex(handle, _ptr(rays), rays.shape[0], max_bounces, _ptr(out),
                            _ptr(path_len), _ptr(n_hits), ctypes.byref(o), _stream(stream)))
 
@@ -507,6 +520,13 @@ def rt_bvh_destroy(handle):
 
 
 # ---- handle wrapper ---------------------------------------------------------
+def chain_workspace(n: int, device="cuda"):
+    """Device workspace of a two-launch trace of n rays (torch uint8, 256-byte
+    aligned by the caching allocator)."""
+    import torch
+    return torch.empty(rt_trace_chain_ws_bytes(n), dtype=torch.uint8, device=device)
+
+
 class BVH:
     """Owns one rt_bvh handle; tensors passed in stay owned by the caller."""
 
@@ -544,10 +564,14 @@ class BVH:
 
     def trace_bounces(self, rays, max_bounces, out=None, path_len=None, n_hits=None,
                       seg_rays=None, ray_stats=None, block=0, grid=0, refill=0, lanes_per_ray=0,
-                      stream=None):
+                      cut=0, chain_ws=None, stream=None):
+        """cut >= 1: two launches (see rt_trace_opts.cut); chain_ws is made
+        (rt_trace_chain_ws_bytes(n) bytes) when not given."""
         import torch
         _dev(rays, torch.float32, 8, "rays")
         n = rays.shape[0]
+        if cut > 0 and chain_ws is None:
+            chain_ws = chain_workspace(n, rays.device)
         if out is None:
             out = self.hits_buffer(n, max_bounces)
         if path_len is None:
@@ -555,11 +579,11 @@ class BVH:
         if n_hits is None:
             n_hits = torch.empty(n, dtype=torch.int32, device=rays.device)
         if (seg_rays is None and ray_stats is None and block == 0 and grid == 0 and refill == 0
-                and lanes_per_ray == 0):
+                and lanes_per_ray == 0 and cut == 0):
             rt_trace_bounces(self.handle, rays, max_bounces, out, path_len, n_hits, stream)
         else:
             rt_trace_ex(self.handle, rays, max_bounces, out, path_len, n_hits, seg_rays,
-                        ray_stats, block, grid, refill, lanes_per_ray, stream)
+                        ray_stats, block, grid, refill, lanes_per_ray, cut, chain_ws, stream)
         return out, path_len, n_hits
 
     def trace_receive(self, rays, max_bounces, receivers: Receivers, out=None, path_len=None,

@@ -179,6 +179,18 @@ int check_trace_args(const rt_bvh* b, const float* rays, int64_t n, int32_t max_
                        "trace: lanes_per_ray > 1 takes no seg_rays, ray_stats or grid");
     if (g > 1 && n > (int64_t)INT32_MAX * (64 / g))
       return set_error(RT_EINVAL, "trace: too many rays for lanes_per_ray");
+    if (opts->cut < 0 || opts->reserved2 != 0)
+      return set_error(RT_EINVAL, "trace: cut must be >= 0 and reserved2 0");
+    if (opts->cut > 0) {
+      if (opts->seg_rays || opts->ray_stats || opts->grid > 0 || g > 1)
+        return set_error(RT_EINVAL,
+                         "trace: cut >= 1 takes no seg_rays, ray_stats, grid or lanes_per_ray > 1");
+      if (n > INT32_MAX) return set_error(RT_EINVAL, "trace: cut >= 1 takes n < 2^31");
+      if (!opts->chain_ws || !aligned(opts->chain_ws, 256) ||
+          opts->chain_ws_bytes < rt_trace_chain_ws_bytes(n))
+        return set_error(RT_EINVAL, "trace: cut >= 1 needs a 256-byte aligned chain_ws of "
+                                    "rt_trace_chain_ws_bytes(n) bytes");
+    }
   }
   return RT_OK;
 }
@@ -204,7 +216,7 @@ int trace_lanes(int64_t n, int max_leaf) {
 // (one lane per ray whenever segments or statistics are recorded).
 int lanes_of(const rt_bvh* b, int64_t n, const rt_trace_opts* opts) {
   if (opts && opts->lanes_per_ray > 0) return opts->lanes_per_ray;
-  if (opts && (opts->seg_rays || opts->ray_stats || opts->grid > 0)) return 1;
+  if (opts && (opts->seg_rays || opts->ray_stats || opts->grid > 0 || opts->cut > 0)) return 1;
   return trace_lanes(n, b->params.max_leaf);
 }
 
@@ -268,6 +280,10 @@ int rt_trace(const rt_bvh* b, const float* rays, int64_t n, rt_hit* out, hipStre
   if (rc != RT_OK || n == 0) return rc;
   return launch_trace(b->buf, b->info.node_format, b->info.depth, rays, n, 1, out, nullptr, nullptr,
                       nullptr, lanes_of(b, n, nullptr), (int)b->info.n_tris, nullptr, s);
+}
+
+int64_t rt_trace_chain_ws_bytes(int64_t n) {
+  return n < 0 ? 0 : chain_ws_bytes(n);
 }
 
 int rt_trace_bounces(const rt_bvh* b, const float* rays, int64_t n, int32_t max_bounces,

@@ -65,6 +65,24 @@ struct alignas(16) TFacet {
 constexpr uint32_t kLastFacet = 0x80000000u;
 constexpr int kQueueSlots = 64;  // persistent trace calls that may be in flight on one handle at once
 
+// ---- a chain left alive by the first launch of a two-launch trace: 64 bytes ----
+// The state its next segment starts from (Sec. III-B re-launch).
+struct ChainCont {
+  float4 o_tmin;   // reflected origin, tmin
+  float4 d_tmax;   // reflected direction, tmax
+  double path;     // path length of the segments traced so far
+  int32_t ray;     // ray index
+  int32_t skip;    // facet position the chain just left
+  int32_t b;       // index of its next segment
+  int32_t hits;    // hits so far
+  int32_t pad[2];
+};
+static_assert(sizeof(ChainCont) == 64, "ChainCont is 64 bytes");
+// Workspace of a two-launch trace: the live-chain count (a 256-byte header),
+// then the records of the live chains in the order they were appended.
+constexpr int64_t kChainWsHeader = 256;
+inline int64_t chain_ws_bytes(int64_t n) { return kChainWsHeader + (int64_t)sizeof(ChainCont) * n; }
+
 // ---- build-time facet record, kept in reference order: 32 bytes ----
 //   lo = (box lo xyz, caller's id bits), hi = (box hi xyz, 0)
 struct alignas(16) FacetRec {

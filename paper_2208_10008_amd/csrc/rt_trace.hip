@@ -553,7 +553,12 @@ constexpr int kBlock = 64;  // one wave per work-group: the LDS stack is per wav
 // one chain together: every lane of the group holds the same chain state,
 // the facets of each leaf are split over them, and only the group's first
 // lane writes results; a wave then takes 64 / G consecutive rays.
-template <int FMT, bool BOUNCE, bool SEG, bool STATS, bool RECV, bool ENERGY = false, int G = 1>
+// PHASE 1 (first launch of a two-launch trace, default launch shape): a
+// chain still alive after `cut` segments is appended to `cont` (one atomic
+// add on *cont_n per wave) instead of going on.  PHASE 2: the lanes take the
+// records cont[batch_base ..) below n_src and go on from their saved state.
+template <int FMT, bool BOUNCE, bool SEG, bool STATS, bool RECV, bool ENERGY = false, int G = 1,
+          int PHASE = 0>
 __device__ __forceinline__ void trace_chains(const void* __restrict__ tn, const TFacet* __restrict__ tf,
                              const float4* __restrict__ rays, int64_t n, int max_b,
                              rt_hit* __restrict__ out, double* __restrict__ path_len,
@@ -561,8 +566,13 @@ __device__ __forceinline__ void trace_chains(const void* __restrict__ tn, const 
                              uint32_t* __restrict__ stats, unsigned long long* __restrict__ queue,
                              int refill, int64_t batch_base, int* stack,
                              const RecvArgs& recv, const EnergyArgs& en = EnergyArgs{},
-                             int n_tf = 0) {
+                             int n_tf = 0, ChainCont* __restrict__ cont = nullptr,
+                             unsigned long long* __restrict__ cont_n = nullptr, int cut = 0,
+                             int64_t n_src = -1) {
   static_assert(G == 1 || !STATS, "per-ray statistics are kept by the one-lane form only");
+  static_assert(PHASE == 0 || (BOUNCE && !SEG && !STATS && !RECV && !ENERGY && G == 1),
+                "the two-launch trace is the plain chain trace");
+  if (PHASE != 2) n_src = n;
   const int lane = threadIdx.x & 63;
   const bool writer = G == 1 || (lane & (G - 1)) == 0;
   const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
@@ -584,20 +594,31 @@ __device__ __forceinline__ void trace_chains(const void* __restrict__ tn, const 
         if (lane == leader) base = atomicAdd(queue, (unsigned long long)__popcll(free_lanes));
         base = __shfl(base, leader);
       }
-      if (base >= (unsigned long long)n) drained = true;
+      if (base >= (unsigned long long)n_src) drained = true;
       if (i < 0) {
         const unsigned long long j =
             base + (G == 1 ? (unsigned long long)__popcll(free_lanes & below)
                            : (unsigned long long)(lane / G));
-        if (j < (unsigned long long)n) {
-          i = (int64_t)j;
-          const float4 ra = rays[2 * i], rb = rays[2 * i + 1];
-          ox = ra.x; oy = ra.y; oz = ra.z; tmin = ra.w;
-          dx = rb.x; dy = rb.y; dz = rb.z; tmax = rb.w;
-          skip = -1;
-          b = 0;
-          hits = 0;
-          path = 0.0;
+        if (j < (unsigned long long)n_src) {
+          if (PHASE == 2) {
+            const ChainCont c = cont[j];
+            i = c.ray;
+            ox = c.o_tmin.x; oy = c.o_tmin.y; oz = c.o_tmin.z; tmin = c.o_tmin.w;
+            dx = c.d_tmax.x; dy = c.d_tmax.y; dz = c.d_tmax.z; tmax = c.d_tmax.w;
+            skip = c.skip;
+            b = c.b;
+            hits = c.hits;
+            path = c.path;
+          } else {
+            i = (int64_t)j;
+            const float4 ra = rays[2 * i], rb = rays[2 * i + 1];
+            ox = ra.x; oy = ra.y; oz = ra.z; tmin = ra.w;
+            dx = rb.x; dy = rb.y; dz = rb.z; tmax = rb.w;
+            skip = -1;
+            b = 0;
+            hits = 0;
+            path = 0.0;
+          }
           gain = 1.0;
           last_power = 0.0;
           nvis = ntest = 0;
@@ -646,6 +667,30 @@ __device__ __forceinline__ void trace_chains(const void* __restrict__ tn, const 
         more = true;
       }
     }
+    if (PHASE == 1) {  // chains alive after `cut` segments wait for the second launch
+      const bool push = more && b == cut;
+      const unsigned long long pm = __ballot(push);
+      if (pm != 0ull) {
+        const int leader = __ffsll((long long)pm) - 1;
+        unsigned long long at = 0;
+        if (lane == leader) at = atomicAdd(cont_n, (unsigned long long)__popcll(pm));
+        at = __shfl(at, leader);
+        if (push) {
+          ChainCont c;
+          c.o_tmin = make_float4(ox, oy, oz, tmin);
+          c.d_tmax = make_float4(dx, dy, dz, tmax);
+          c.path = path;
+          c.ray = (int32_t)i;
+          c.skip = skip;
+          c.b = b;
+          c.hits = hits;
+          c.pad[0] = c.pad[1] = 0;
+          cont[at + __popcll(pm & below)] = c;
+          i = -1;
+        }
+      }
+      if (i < 0) continue;
+    }
     if (!more) {  // chain finished: segments never launched read as misses
       if (BOUNCE && writer) {
         Hit none;
@@ -667,7 +712,7 @@ __device__ __forceinline__ void trace_chains(const void* __restrict__ tn, const 
 // The LDS stack (dynamic shared memory) holds exactly the entries the tree
 // can need: stack_need(depth) per lane, in lane-column layout.  With G > 1
 // lanes per ray a work-group takes the 64 / G rays from blockIdx.x * 64 / G.
-template <int FMT, bool BOUNCE, bool SEG, bool STATS, int G = 1>
+template <int FMT, bool BOUNCE, bool SEG, bool STATS, int G = 1, int PHASE = 0>
 __global__ __launch_bounds__(kBlock) void k_trace(const void* __restrict__ tn,
                                                   const TFacet* __restrict__ tf,
                                                   const float4* __restrict__ rays, int64_t n,
@@ -677,11 +722,35 @@ __global__ __launch_bounds__(kBlock) void k_trace(const void* __restrict__ tn,
                                                   float4* __restrict__ seg,
                                                   uint32_t* __restrict__ stats,
                                                   unsigned long long* __restrict__ queue,
-                                                  int refill, int n_tf) {
+                                                  int refill, int n_tf,
+                                                  ChainCont* __restrict__ cont = nullptr,
+                                                  unsigned long long* __restrict__ cont_n = nullptr,
+                                                  int cut = 0) {
   extern __shared__ int s_stack[];
-  trace_chains<FMT, BOUNCE, SEG, STATS, false, false, G>(
+  trace_chains<FMT, BOUNCE, SEG, STATS, false, false, G, PHASE>(
       tn, tf, rays, n, max_b, out, path_len, n_hits, seg, stats, queue, refill,
-      (int64_t)blockIdx.x * (kBlock / G), s_stack + threadIdx.x, RecvArgs{}, EnergyArgs{}, n_tf);
+      (int64_t)blockIdx.x * (kBlock / G), s_stack + threadIdx.x, RecvArgs{}, EnergyArgs{}, n_tf,
+      cont, cont_n, cut);
+}
+
+// Second launch of a two-launch trace: work-group g resumes the live chains
+// cont[64 g, 64 g + 64) of the *cont_n the first launch left.
+template <int FMT>
+__global__ __launch_bounds__(kBlock) void k_trace_resume(const void* __restrict__ tn,
+                                                         const TFacet* __restrict__ tf, int64_t n,
+                                                         int max_b, rt_hit* __restrict__ out,
+                                                         double* __restrict__ path_len,
+                                                         int32_t* __restrict__ n_hits, int n_tf,
+                                                         const ChainCont* __restrict__ cont,
+                                                         const unsigned long long* __restrict__ cont_n) {
+  extern __shared__ int s_stack[];
+  const int64_t total = (int64_t)*cont_n;
+  const int64_t base = (int64_t)blockIdx.x * kBlock;
+  if (base >= total) return;
+  trace_chains<FMT, true, false, false, false, false, 1, 2>(
+      tn, tf, nullptr, n, max_b, out, path_len, n_hits, nullptr, nullptr, nullptr, 0, base,
+      s_stack + threadIdx.x, RecvArgs{}, EnergyArgs{}, n_tf, const_cast<ChainCont*>(cont), nullptr, 0,
+      total);
 }
 
 // Reflection chains whose segments are tested against field points as they
@@ -792,9 +861,24 @@ size_t stack_bytes(int depth) {
 template <int FMT, bool BOUNCE, bool SEG, bool STATS>
 void launch(const Buffers& B, int depth, const float* rays, int64_t n, int max_b, rt_hit* out,
             double* path_len, int32_t* n_hits, float* seg, uint32_t* stats, int grid,
-            int refill, int n_tf, unsigned long long* queue, hipStream_t s) {
+            int refill, int n_tf, unsigned long long* queue, int cut, void* ws, hipStream_t s) {
   const int64_t batches = (n + kBlock - 1) / kBlock;
   const void* nodes = FMT == RT_NODE_BIN2 ? (const void*)B.tnodes : (const void*)B.wnodes;
+  if constexpr (BOUNCE && !SEG && !STATS) {
+    if (cut > 0 && cut < max_b && grid == 0) {  // two launches, regrouping the live chains
+      unsigned long long* cont_n = reinterpret_cast<unsigned long long*>(ws);
+      ChainCont* cont = reinterpret_cast<ChainCont*>(reinterpret_cast<char*>(ws) + kChainWsHeader);
+      hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(1), 0, s, cont_n);
+      hipLaunchKernelGGL((k_trace<FMT, true, false, false, 1, 1>), dim3((unsigned)batches),
+                         dim3(kBlock), stack_bytes<FMT>(depth), s, nodes, B.tfacets,
+                         reinterpret_cast<const float4*>(rays), n, max_b, out, path_len, n_hits,
+                         nullptr, nullptr, nullptr, 0, n_tf, cont, cont_n, cut);
+      hipLaunchKernelGGL((k_trace_resume<FMT>), dim3((unsigned)batches), dim3(kBlock),
+                         stack_bytes<FMT>(depth), s, nodes, B.tfacets, n, max_b, out, path_len,
+                         n_hits, n_tf, cont, cont_n);
+      return;
+    }
+  }
   unsigned long long* q = nullptr;
   int64_t blocks = batches;  // default: one work-group per batch of 64 rays
   if (grid > 0) {            // persistent work-groups pulling batches from the call's queue
@@ -824,7 +908,8 @@ void launch_group(const Buffers& B, int depth, const float* rays, int64_t n, int
 template <int FMT>
 void launch_fmt(const Buffers& B, int depth, const float* rays, int64_t n, int max_b, rt_hit* out,
                 double* path_len, int32_t* n_hits, float* seg, uint32_t* stats, int grid,
-                int refill, int lanes, int n_tf, unsigned long long* q, hipStream_t s) {
+                int refill, int lanes, int n_tf, unsigned long long* q, int cut, void* ws,
+                hipStream_t s) {
   switch (lanes) {  // the caller allows lanes > 1 only without seg, stats and grid
     case 4: return launch_group<FMT, 4>(B, depth, rays, n, max_b, out, path_len, n_hits, n_tf, s);
     case 16: return launch_group<FMT, 16>(B, depth, rays, n, max_b, out, path_len, n_hits, n_tf, s);
@@ -833,15 +918,15 @@ void launch_fmt(const Buffers& B, int depth, const float* rays, int64_t n, int m
   }
   const bool bounce = max_b > 1 || path_len || n_hits;
   if (!bounce && !seg && !stats) {
-    launch<FMT, false, false, false>(B, depth, rays, n, 1, out, nullptr, nullptr, nullptr, nullptr, grid, refill, n_tf, q, s);
+    launch<FMT, false, false, false>(B, depth, rays, n, 1, out, nullptr, nullptr, nullptr, nullptr, grid, refill, n_tf, q, cut, ws, s);
   } else if (!seg && !stats) {
-    launch<FMT, true, false, false>(B, depth, rays, n, max_b, out, path_len, n_hits, nullptr, nullptr, grid, refill, n_tf, q, s);
+    launch<FMT, true, false, false>(B, depth, rays, n, max_b, out, path_len, n_hits, nullptr, nullptr, grid, refill, n_tf, q, cut, ws, s);
   } else if (seg && !stats) {
-    launch<FMT, true, true, false>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, nullptr, grid, refill, n_tf, q, s);
+    launch<FMT, true, true, false>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, nullptr, grid, refill, n_tf, q, cut, ws, s);
   } else if (!seg) {
-    launch<FMT, true, false, true>(B, depth, rays, n, max_b, out, path_len, n_hits, nullptr, stats, grid, refill, n_tf, q, s);
+    launch<FMT, true, false, true>(B, depth, rays, n, max_b, out, path_len, n_hits, nullptr, stats, grid, refill, n_tf, q, cut, ws, s);
   } else {
-    launch<FMT, true, true, true>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, stats, grid, refill, n_tf, q, s);
+    launch<FMT, true, true, true>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, stats, grid, refill, n_tf, q, cut, ws, s);
   }
 }
 
@@ -1008,15 +1093,17 @@ int launch_trace(const Buffers& B, int node_format, int depth, const float* rays
   uint32_t* stats = opts ? opts->ray_stats : nullptr;
   const int grid = opts ? opts->grid : 0;
   const int refill = opts ? opts->refill : 0;
+  const int cut = opts ? opts->cut : 0;
+  void* ws = opts ? opts->chain_ws : nullptr;
   switch (node_format) {
     case RT_NODE_F4:
-      launch_fmt<RT_NODE_F4>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, stats, grid, refill, lanes, n_tf, q, s);
+      launch_fmt<RT_NODE_F4>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, stats, grid, refill, lanes, n_tf, q, cut, ws, s);
       break;
     case RT_NODE_Q4:
-      launch_fmt<RT_NODE_Q4>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, stats, grid, refill, lanes, n_tf, q, s);
+      launch_fmt<RT_NODE_Q4>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, stats, grid, refill, lanes, n_tf, q, cut, ws, s);
       break;
     default:
-      launch_fmt<RT_NODE_BIN2>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, stats, grid, refill, lanes, n_tf, q, s);
+      launch_fmt<RT_NODE_BIN2>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, stats, grid, refill, lanes, n_tf, q, cut, ws, s);
       break;
   }
   return check_hip(hipGetLastError(), "trace launch");

@@ -235,3 +235,27 @@ def chain_error_bounds(tris, seg, ids, t):
             r = seg[b + 1, :, 4:7]
             e_d = e_d + 2 * np.sqrt(3) * U32 * np.nan_to_num(np.abs(r).max(1))
     return allowed
+
+
+def check_differing(city, tree, bvh, rays, nb, base, got, differ, tag):
+    """Chains of a launch (lanes refilled, or live chains regrouped) that
+    differ from the default launch: before
+    the first differing segment both launches traced the same segment rays
+    (same facets, same float32 arithmetic), so that segment's input is known
+    from either launch; its checker margin must be at most 1e-4 and the
+    other launch's answer must pass the closest-hit rule.  base and got are
+    (hits, path lengths, hit counts) as numpy arrays; rays is on the device."""
+    assert differ.size <= 1e-4 * rays.shape[0], f"{tag}: {differ.size} chains differ"
+    import torch
+    seg = torch.empty((nb, rays.shape[0], 8), dtype=torch.float32, device="cuda")
+    bvh.trace_bounces(rays, nb, seg_rays=seg)
+    torch.cuda.synchronize()
+    seg_np = seg.cpu().numpy()
+    first = np.argmax(np.any(got[0][:, differ] != base[0][:, differ], axis=2), axis=0)
+    for j, b in zip(differ.tolist(), first.tolist()):
+        ray = seg_np[b, j][None]
+        skip = np.array([base[0][b - 1, j, 0] if b > 0 else -1], np.int32)
+        ref = oracle.trace_bvh(tree, ray, skip=skip, nthreads=1)
+        assert ref.margin[0] <= CLEAN, (tag, j, b, float(ref.margin[0]))
+        t = got[0][b, j, 1:2].view(np.float32).astype(np.float64)
+        compare_hits(city.tris, ray, got[0][b, j, 0:1], t, ref, skip=skip)

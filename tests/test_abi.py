@@ -75,13 +75,15 @@ int main(void) {
          offsetof(rt_ray_launch, n));
   printf("%zu %zu %zu %zu\\n", offsetof(rt_bvh_info, has_stats), offsetof(rt_bvh_info, tree_cost),
          offsetof(rt_bvh_info, root_area), offsetof(rt_bvh_info, leaf_hist));
+  printf("%zu %zu %zu %zu\\n", offsetof(rt_trace_opts, cut), offsetof(rt_trace_opts, reserved2),
+         offsetof(rt_trace_opts, chain_ws), offsetof(rt_trace_opts, chain_ws_bytes));
   return 0;
 }""")
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-D__HIP_PLATFORM_AMD__", "-I" + os.path.join(ROOT, "include"),
                     "-I/opt/rocm/include", str(src), "-o", str(exe)], check=True)
-    a, b, c, d, e, g, h, k = subprocess.run([str(exe)], capture_output=True, text=True,
-                                            check=True).stdout.split("\n")[:8]
+    a, b, c, d, e, g, h, k, m = subprocess.run([str(exe)], capture_output=True, text=True,
+                                               check=True).stdout.split("\n")[:9]
     sizes = [int(x) for x in a.split()]
     offs = [int(x) for x in b.split()]
     assert sizes == [ctypes.sizeof(R.rt_split_params), 16, ctypes.sizeof(R.rt_bvh_info),
@@ -109,6 +111,18 @@ int main(void) {
                                            R.rt_bvh_info.tree_cost.offset,
                                            R.rt_bvh_info.root_area.offset,
                                            R.rt_bvh_info.leaf_hist.offset]
+    assert [int(x) for x in m.split()] == [R.rt_trace_opts.cut.offset,
+                                           R.rt_trace_opts.reserved2.offset,
+                                           R.rt_trace_opts.chain_ws.offset,
+                                           R.rt_trace_opts.chain_ws_bytes.offset]
+
+
+def test_chain_workspace_size():
+    # a 256-byte header (the live-chain count) and one 64-byte chain state per ray
+    assert R.rt_trace_chain_ws_bytes(0) == 256
+    assert R.rt_trace_chain_ws_bytes(1) == 256 + 64
+    assert R.rt_trace_chain_ws_bytes(2621442) == 256 + 64 * 2621442
+    assert R.rt_trace_chain_ws_bytes(-1) == 0
 
 
 def test_defaults():

@@ -28,7 +28,7 @@ import oracle
 import paper_2208_10008_amd as R
 from rtgen import workloads
 
-from _parity import CLEAN, compare_hits
+from _parity import check_differing, compare_hits
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -126,24 +126,3 @@ def test_persistent_and_refill_launches(city, fmt):
             log(f"{tag}: sample {counts}")
             assert counts["clean"] > 0.99 * counts["segments"]
     bvh.close()
-
-
-def check_differing(city, tree, bvh, rays, nb, base, got, differ, tag):
-    """Chains of a refill launch that differ from the default launch: before
-    the first differing segment both launches traced the same segment rays
-    (same facets, same float32 arithmetic), so that segment's input is known
-    from either launch; its checker margin must be at most 1e-4 and the
-    refill launch's answer must pass the closest-hit rule."""
-    assert differ.size <= 1e-4 * rays.shape[0], f"{tag}: {differ.size} chains differ"
-    seg = torch.empty((nb, rays.shape[0], 8), dtype=torch.float32, device="cuda")
-    bvh.trace_bounces(rays, nb, seg_rays=seg)
-    torch.cuda.synchronize()
-    seg_np = seg.cpu().numpy()
-    first = np.argmax(np.any(got[0][:, differ] != base[0][:, differ], axis=2), axis=0)
-    for j, b in zip(differ.tolist(), first.tolist()):
-        ray = seg_np[b, j][None]
-        skip = np.array([base[0][b - 1, j, 0] if b > 0 else -1], np.int32)
-        ref = oracle.trace_bvh(tree, ray, skip=skip, nthreads=1)
-        assert ref.margin[0] <= CLEAN, (tag, j, b, float(ref.margin[0]))
-        t = got[0][b, j, 1:2].view(np.float32).astype(np.float64)
-        compare_hits(city.tris, ray, got[0][b, j, 0:1], t, ref, skip=skip)
