@@ -89,6 +89,7 @@ int ensure_buffers(Buffers& B, int64_t n) {
   B.item_cap = icap;
   B.anode_cap = acap;
   B.bytes = bytes;
+  B.state_ready = false;
   return RT_OK;
 }
 

@@ -613,12 +613,73 @@ __global__ void k_init(int32_t* words, long long* root, int n) {
   }
 }
 
-__global__ __launch_bounds__(256) void k_prep(const float* __restrict__ tris, int n,
-                                              FacetRec* __restrict__ recs, int32_t* __restrict__ perm,
-                                              BuildState* __restrict__ st,
-                                              long long* __restrict__ root, int32_t* __restrict__ used,
-                                              int32_t* __restrict__ mfront,
-                                              int32_t* __restrict__ sfront) {
+// Root node from the reduced bounds; queues it for the first schedule that
+// takes it (nothing when it is a leaf or a facet is not finite).  Every
+// thread of one work-group; the bounds and the non-finite flag were reduced
+// by atomics of the whole grid, so they are read at device scope.
+__device__ inline long long ld_dev(const long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ void setup_root(const Ctx& X, const long long* root) {
+  __shared__ int s_slot, s_base;
+  if (threadIdx.x == 0) s_slot = -1;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+  BNode r;
+  for (int a = 0; a < 3; ++a) {
+    r.lo[a] = o2f((int32_t)ld_dev(&root[a]));
+    r.hi[a] = o2f((int32_t)ld_dev(&root[3 + a]));
+    r.cblo[a] = o2d(ld_dev(&root[6 + a]));
+    r.cbhi[a] = o2d(ld_dev(&root[9 + a]));
+  }
+  r.left = -1;
+  r.first = 0;
+  r.count = X.n;
+  r.depth = 0;
+  r.axis = r.plane = -1;
+  r.flags = 0;
+  r.tidx = -1;
+  r.cost = 0.0;
+  X.nodes[0] = r;
+  double ex = (double)r.hi[0] - (double)r.lo[0];
+  double ey = (double)r.hi[1] - (double)r.lo[1];
+  double ez = (double)r.hi[2] - (double)r.lo[2];
+  double l2 = (ex * ex + ey * ey) + ez * ez;
+  X.st->inv_l2 = l2 > 0.0 ? 1.0 / l2 : 0.0;
+  const int nonfinite = __hip_atomic_load(&X.st->nonfinite, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (nonfinite == 0 && X.n > X.C.max_leaf) {
+    const int to = classify(X.C, X.n, 0, r.cblo, r.cbhi, X.la > 0, X.lm > 0);
+    if (to == TO_A) {
+      int slot, base;
+      if (take_big(X, 0, 1, (X.n + kChunk - 1) / kChunk, slot, base)) {
+        s_slot = slot;
+        s_base = base;
+      }
+    }
+    else if (to == TO_M) push_m(X, 0, 0, 0);
+    else push_s(X, 0, 0);
+  }
+  }
+  __syncthreads();
+  if (s_slot >= 0) {
+    const int nit = (X.n + kChunk - 1) / kChunk;
+    for (int j = threadIdx.x; j < nit; j += blockDim.x) write_item(X, 0, 0, X.n, s_slot, s_base, nit, j);
+    clear_node_bins(X, 0, s_slot, threadIdx.x, blockDim.x);
+  }
+}
+
+// Facet records, root bounds (ordered-int atomics), and the scratch the
+// later passes expect; the last work-group to finish sets up the root.
+__global__ __launch_bounds__(256) void k_prep(Ctx X, const float* __restrict__ tris,
+                                              long long* __restrict__ root) {
+  const int n = X.n;
+  FacetRec* __restrict__ recs = X.recs[0];
+  int32_t* __restrict__ perm = X.perm;
+  BuildState* st = X.st;
+  int32_t* __restrict__ used = X.used;
+  int32_t* __restrict__ mfront = X.mfront[0];
+  int32_t* __restrict__ sfront = X.sfront;
+  if (blockIdx.x == 0 && threadIdx.x == 0) st->n = n;
   __shared__ int s_box[6];
   __shared__ long long s_cb[6];
   if (threadIdx.x < 6) {
@@ -668,56 +729,19 @@ __global__ __launch_bounds__(256) void k_prep(const float* __restrict__ tris, in
     atomicMin(&root[6 + threadIdx.x], s_cb[threadIdx.x]);
     atomicMax(&root[9 + threadIdx.x], s_cb[3 + threadIdx.x]);
   }
-}
-
-// Root node from the reduced bounds; queues it for the first schedule that
-// takes it (nothing when it is a leaf or a facet is not finite).
-__global__ __launch_bounds__(256) void k_root(Ctx X, const long long* root) {
-  __shared__ int s_slot, s_base;
-  if (threadIdx.x == 0) s_slot = -1;
+  // the last work-group to get here sees every other one's root bounds
+  __shared__ int s_last;
   __syncthreads();
   if (threadIdx.x == 0) {
-  BNode r;
-  for (int a = 0; a < 3; ++a) {
-    r.lo[a] = o2f((int32_t)root[a]);
-    r.hi[a] = o2f((int32_t)root[3 + a]);
-    r.cblo[a] = o2d(root[6 + a]);
-    r.cbhi[a] = o2d(root[9 + a]);
-  }
-  r.left = -1;
-  r.first = 0;
-  r.count = X.n;
-  r.depth = 0;
-  r.axis = r.plane = -1;
-  r.flags = 0;
-  r.tidx = -1;
-  r.cost = 0.0;
-  X.nodes[0] = r;
-  double ex = (double)r.hi[0] - (double)r.lo[0];
-  double ey = (double)r.hi[1] - (double)r.lo[1];
-  double ez = (double)r.hi[2] - (double)r.lo[2];
-  double l2 = (ex * ex + ey * ey) + ez * ez;
-  X.st->inv_l2 = l2 > 0.0 ? 1.0 / l2 : 0.0;
-  if (X.st->nonfinite == 0 && X.n > X.C.max_leaf) {
-    const int to = classify(X.C, X.n, 0, r.cblo, r.cbhi, X.la > 0, X.lm > 0);
-    if (to == TO_A) {
-      int slot, base;
-      if (take_big(X, 0, 1, (X.n + kChunk - 1) / kChunk, slot, base)) {
-        s_slot = slot;
-        s_base = base;
-      }
-    }
-    else if (to == TO_M) push_m(X, 0, 0, 0);
-    else push_s(X, 0, 0);
-  }
+    __threadfence();
+    s_last = atomicAdd(&st->prep_done, 1) == (int)gridDim.x - 1;
   }
   __syncthreads();
-  if (s_slot >= 0) {
-    const int nit = (X.n + kChunk - 1) / kChunk;
-    for (int j = threadIdx.x; j < nit; j += blockDim.x) write_item(X, 0, 0, X.n, s_slot, s_base, nit, j);
-    clear_node_bins(X, 0, s_slot, threadIdx.x, blockDim.x);
-  }
+  if (!s_last) return;
+  __threadfence();
+  setup_root(X, root);
 }
+
 
 // ---------------------------------------------------------------------------
 // Run of consecutive facets that fall in one bin of one axis, kept in
@@ -1656,20 +1680,39 @@ __global__ __launch_bounds__(kScanBlock) void k_rank(const int32_t* __restrict__
   }
 }
 
-// Host record at the end of the build: {sequence, nodes, depth, non-finite,
-// error, root lo xyz, root hi xyz}.
-__global__ void k_finish(const BuildState* st, const BNode* nodes, int32_t* host_out, int seq) {
-  if (threadIdx.x != 0) return;
-  host_out[1] = st->total;
-  host_out[2] = st->depth;
-  host_out[3] = st->nonfinite;
-  host_out[4] = st->error;
-  for (int q = 0; q < 3; ++q) {
-    host_out[5 + q] = __float_as_int(nodes[0].lo[q]);
-    host_out[8 + q] = __float_as_int(nodes[0].hi[q]);
+// End of a build, by every thread of one work-group after the build's other
+// work: the host record {sequence, nodes, depth, non-finite, error, root lo
+// xyz, root hi xyz}, then BuildState and the root bounds set back to their
+// starting values for the next build on these buffers (nothing of this build
+// reads them afterwards).
+__device__ void finish_build(BuildState* st, long long* root, const BNode* nodes,
+                             int32_t* host_out, int seq) {
+  if (threadIdx.x == 0) {
+    host_out[1] = st->total;
+    host_out[2] = st->depth;
+    host_out[3] = st->nonfinite;
+    host_out[4] = st->error;
+    for (int q = 0; q < 3; ++q) {
+      host_out[5 + q] = __float_as_int(nodes[0].lo[q]);
+      host_out[8 + q] = __float_as_int(nodes[0].hi[q]);
+    }
+    __threadfence_system();
+    __atomic_store_n(&host_out[0], seq, __ATOMIC_RELEASE);
   }
-  __threadfence_system();
-  __atomic_store_n(&host_out[0], seq, __ATOMIC_RELEASE);
+  __syncthreads();
+  int32_t* words = reinterpret_cast<int32_t*>(st);
+  for (int i = threadIdx.x; i < kStateWords; i += blockDim.x) words[i] = 0;
+  if (threadIdx.x < 3) {
+    const int t = threadIdx.x;
+    root[t] = f2o(INFINITY);
+    root[3 + t] = f2o(-INFINITY);
+    root[6 + t] = d2o(INFINITY);
+    root[9 + t] = d2o(-INFINITY);
+  }
+}
+__global__ void k_finish(BuildState* st, long long* root, const BNode* nodes, int32_t* host_out,
+                         int seq) {
+  finish_build(st, root, nodes, host_out, seq);
 }
 
 __device__ inline float4 f4(float x, float y, float z, float w) { return make_float4(x, y, z, w); }
@@ -1698,10 +1741,10 @@ __device__ inline int compact_left(int left, const int32_t* __restrict__ rank, i
   return left < 0 ? -1 : 2 * remap(rank[(left - 1) >> 1], rr) + 1;
 }
 
-__global__ void k_emit(const BNode* __restrict__ nodes, const BuildState* __restrict__ st,
-                       const int32_t* __restrict__ used, const int32_t* __restrict__ rank,
-                       const int32_t* __restrict__ perm, const float* __restrict__ tris,
-                       BNode* __restrict__ cn, TNode* __restrict__ tn, TFacet* __restrict__ tf) {
+__device__ void emit_one(const BNode* __restrict__ nodes, const BuildState* __restrict__ st,
+                         const int32_t* __restrict__ used, const int32_t* __restrict__ rank,
+                         const int32_t* __restrict__ perm, const float* __restrict__ tris,
+                         BNode* __restrict__ cn, TNode* __restrict__ tn, TFacet* __restrict__ tf) {
   const int n = st->n;
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (st->error || b >= n) return;
@@ -1740,6 +1783,26 @@ __global__ void k_emit(const BNode* __restrict__ nodes, const BuildState* __rest
   t.c = f4(l.lo[2], l.hi[2], q.lo[2], q.hi[2]);
   t.d = make_int4(l.left < 0 ? ~l.first : pair_index(l), q.left < 0 ? ~q.first : pair_index(q), 0, 0);
   tn[r] = t;
+}
+// With host_out (binary nodes only: nothing runs after it), the last
+// work-group to finish also ends the build (finish_build).
+__global__ void k_emit(const BNode* __restrict__ nodes, BuildState* __restrict__ st,
+                       const int32_t* __restrict__ used, const int32_t* __restrict__ rank,
+                       const int32_t* __restrict__ perm, const float* __restrict__ tris,
+                       BNode* __restrict__ cn, TNode* __restrict__ tn, TFacet* __restrict__ tf,
+                       long long* __restrict__ root, int32_t* host_out, int seq) {
+  emit_one(nodes, st, used, rank, perm, tris, cn, tn, tf);
+  if (host_out == nullptr) return;
+  __shared__ int s_last;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    s_last = atomicAdd(&st->emit_done, 1) == (int)gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  finish_build(st, root, cn, host_out, seq);
 }
 
 // ---------------------------------------------------------------------------
@@ -1984,11 +2047,12 @@ int build_tree(Buffers& B, const float* tris, int64_t n64, const rt_split_params
   C.depth_limit = p.depth_limit;
   const int Bn = p.nbins;
 
-  hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, s, B.counters, B.root_box, n);
+  // the state's starting values: set once on new buffers, then by the end of
+  // every build (finish_build)
+  if (!B.state_ready) hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, s, B.counters, B.root_box, n);
+  B.state_ready = false;  // until this build has ended
   const int pb = 256;
-  hipLaunchKernelGGL(k_prep, dim3((n + pb - 1) / pb), dim3(pb), 0, s, tris, n, B.recs_a, B.perm, st,
-                     B.root_box, B.used, B.mfront, B.sfront);
-  hipLaunchKernelGGL(k_root, dim3(1), dim3(256), 0, s, X, (const long long*)B.root_box);
+  hipLaunchKernelGGL(k_prep, dim3((n + pb - 1) / pb), dim3(pb), 0, s, X, tris, B.root_box);
   const size_t lds_abin = a_copies(Bn, kABinThreads) * bins_bytes(Bn, true);
   const size_t lds_asplit = bins_bytes(Bn, true);
   for (int l = 0; l < la; ++l) {
@@ -2012,8 +2076,10 @@ int build_tree(Buffers& B, const float* tris, int64_t n64, const rt_split_params
   hipLaunchKernelGGL(k_count, dim3(nblk), dim3(kScanBlock), 0, s, B.used, nb, bsum, bmax);
   hipLaunchKernelGGL(k_rank, dim3(nblk), dim3(kScanBlock), 0, s, B.used, nb, bsum, bmax, B.rank, st);
   const int eb = 256;
+  const bool wide = p.node_format == RT_NODE_F4 || p.node_format == RT_NODE_Q4;
   hipLaunchKernelGGL(k_emit, dim3((n + eb - 1) / eb), dim3(eb), 0, s, B.nodes, st, B.used, B.rank,
-                     B.perm, tris, B.cnodes, B.tnodes, B.tfacets);
+                     B.perm, tris, B.cnodes, B.tnodes, B.tfacets, B.root_box,
+                     wide ? nullptr : rec.dev, seq);
   const int max_nodes = std::max(1, 2 * n - 1);
   if (p.node_format == RT_NODE_F4)
     hipLaunchKernelGGL(k_collapse<RT_NODE_F4>, dim3((max_nodes + eb - 1) / eb), dim3(eb), 0, s,
@@ -2021,12 +2087,13 @@ int build_tree(Buffers& B, const float* tris, int64_t n64, const rt_split_params
   else if (p.node_format == RT_NODE_Q4)
     hipLaunchKernelGGL(k_collapse<RT_NODE_Q4>, dim3((max_nodes + eb - 1) / eb), dim3(eb), 0, s,
                        B.cnodes, st, B.wnodes);
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, st, B.cnodes, rec.dev, seq);
+  if (wide) hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, st, B.root_box, B.cnodes, rec.dev, seq);
   HIPCHECK(hipGetLastError());
   {
     int rc = wait_record(rec, seq, s);
     if (rc != RT_OK) return rc;
   }
+  B.state_ready = true;  // the build's end set the state back
   const int32_t* h = rec.host;
   if (h[3]) return set_error(RT_EINVAL, "rt_build: a facet has a non-finite vertex");
   if (h[4]) return set_error(RT_EHIP, "rt_build: internal capacity check failed (code " +

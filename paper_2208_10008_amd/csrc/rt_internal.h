@@ -107,7 +107,9 @@ struct BuildState {
   int32_t depth;       // deepest node
   int32_t error;       // an internal capacity check failed
   int32_t n;           // facets of the build
-  int32_t pad[3];
+  int32_t prep_done;   // work-groups of the facet pass that have finished
+  int32_t emit_done;   // work-groups of the emit pass that have finished
+  int32_t pad;
   double inv_l2;       // 1 / squared root diagonal (0 if the root is a point)
   // per big-node level: (big nodes << 32) | chunk items, both taken by one
   // atomic add per parent
@@ -140,6 +142,9 @@ struct Buffers {
   unsigned long long* queue = nullptr;  // [kQueueSlots] ray queue heads of persistent launches
   TFacet* tfacets = nullptr;  // [n]
   double* stat_work = nullptr;  // [kStatWords] tree statistics: per-block partial sums
+  // BuildState and root bounds hold their starting values (set once after
+  // allocation; every build's last kernel sets them again for the next one)
+  bool state_ready = false;
   int64_t cap_n = 0;        // facets the buffers can hold
   int64_t bytes = 0;
 };
