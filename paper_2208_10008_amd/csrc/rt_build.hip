@@ -1170,12 +1170,16 @@ __device__ __forceinline__ void split_partition(BuildState* st, const FacetRec* 
   }
 }
 
+// PE_MAX: records per lane and partition round for nodes above 64 facets (and
+// binning loads in flight); k_s, whose nodes are mostly small, takes 1 to
+// keep its registers (and so its waves per SIMD) down.
 // The wave's bins count facets and unite their boxes per bin (the centroid
 // bounds region of S is not used as bins here: it holds the 12 + 12 child
 // accumulators, so S must come with centroid bounds).  The children's
 // volumes and centroid bounds are exact unions of their facets', taken while
 // partitioning: each lane unites its own facets, then adds them with ordered
 // integer min / max into the accumulators.
+template <int PE_MAX>
 __device__ int wave_split_global(const Ctx& X, int id, const Bins& S, int& kc0, int& kc1,
                                  double ccb[2][6]) {
   const int lane = lane_id();
@@ -1206,7 +1210,7 @@ __device__ int wave_split_global(const Ctx& X, int id, const Bins& S, int& kc0, 
     RunB run[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) runb_reset(run[a], -1);
-    constexpr int kBinU = 4;
+    constexpr int kBinU = PE_MAX == 1 ? 1 : 4;
     for (int i = i0; i < i1; i += kBinU) {
       float4 lo[kBinU], hi[kBinU];
 #pragma unroll
@@ -1264,11 +1268,11 @@ __device__ int wave_split_global(const Ctx& X, int id, const Bins& S, int& kc0, 
       cbl[side][q] = INFINITY;
       cbh[side][q] = -INFINITY;
     }
-  if (k <= 64)
+  if (PE_MAX == 1 || k <= 64)
     split_partition<1>(X.st, in, out, perm, k, nleft, by_position, ax, ax_lo, ax_scale, B, plane, leaf0,
                        leaf1, blo, bhi, cbl, cbh);
   else
-    split_partition<kPartE>(X.st, in, out, perm, k, nleft, by_position, ax, ax_lo, ax_scale, B, plane,
+    split_partition<PE_MAX>(X.st, in, out, perm, k, nleft, by_position, ax, ax_lo, ax_scale, B, plane,
                             leaf0, leaf1, blo, bhi, cbl, cbh);
   // the children's volumes and centroid bounds (a lane with no facet on a
   // side leaves that side's accumulators alone)
@@ -1329,7 +1333,7 @@ __global__ __launch_bounds__(kWaveThreads) void k_m(Ctx X, int pass) {
     const int depth = X.nodes[id].depth, first0 = X.nodes[id].first;
     int kc[2];
     double ccb[2][6];
-    const int c0 = wave_split_global(X, id, S, kc[0], kc[1], ccb);
+    const int c0 = wave_split_global<kPartE>(X, id, S, kc[0], kc[1], ccb);
     if (lane < 2 && kc[lane] > X.C.max_leaf) {
       const double* cb = lane == 0 ? ccb[0] : ccb[1];
       const int to = classify(X.C, kc[lane], depth + 1, cb, cb + 3, false, pass + 1 < X.lm);
@@ -1591,7 +1595,7 @@ __global__ __launch_bounds__(kWaveThreads) void k_s(Ctx X) {
       }
       int kc[2];
       double ccb[2][6];
-      const int c0 = wave_split_global(X, id, S, kc[0], kc[1], ccb);
+      const int c0 = wave_split_global<1>(X, id, S, kc[0], kc[1], ccb);
       // the children's records and nodes were written by this wave
       wave_global_sync();
       for (int sd = 1; sd >= 0; --sd) {
