@@ -1571,8 +1571,10 @@ __global__ __launch_bounds__(kWaveThreads) void k_s(Ctx X) {
   RNode* rstk = (RNode*)(mine + bins_bytes(B, true));
   int* gstk = (int*)(mine + bins_bytes(B, true) + align8(sizeof(RNode) * kRStack));
   // subtree roots hold more than max_leaf facets, so a window of
-  // min(64, max_leaf + 1) facet positions holds at most one of them
-  const int win = min(64, X.C.max_leaf + 1);
+  // min(64, 2 (max_leaf + 1)) facet positions holds at most two of them,
+  // taken in turn (half as many waves as one-root windows: fewer rounds of
+  // resident waves)
+  const int win = min(64, 2 * (X.C.max_leaf + 1));
   const int wbase = (blockIdx.x * (blockDim.x >> 6) + w) * win;
   if (wbase >= X.n) return;
   const int slot = wbase + lane;
@@ -2068,7 +2070,7 @@ int build_tree(Buffers& B, const float* tris, int64_t n64, const rt_split_params
   for (int m = 0; m < lm; ++m)
     hipLaunchKernelGGL(k_m, dim3((m_windows + 3) / 4), dim3(256), 4 * bins_bytes(Bn, true), s, X, m);
   const int s_waves = (int)std::max<size_t>(1, std::min<size_t>(4, (60 * 1024) / s_wave_bytes(Bn)));
-  const int s_win = std::min(64, p.max_leaf + 1);
+  const int s_win = std::min(64, 2 * (p.max_leaf + 1));
   const int s_windows = (n + s_win - 1) / s_win;
   hipLaunchKernelGGL(k_s, dim3((s_windows + s_waves - 1) / s_waves), dim3(64 * s_waves),
                      s_waves * s_wave_bytes(Bn), s, X);
