@@ -1077,7 +1077,7 @@ __global__ __launch_bounds__(kAThreads) void k_a_split(Ctx X, int lvl) {
 // ---------------------------------------------------------------------------
 // One node split by one wave, facet records in global memory.  Returns the
 // left child id (wave-uniform) and the children's sizes and centroid bounds.
-constexpr int kPartE = 8;  // consecutive records per lane and partition round
+constexpr int kPartE = 4;  // records per lane and partition round of a medium node above 64 facets (147 VGPRs, 3 waves per SIMD)
 
 // Run of consecutive facets in one bin of one axis, counts and boxes only.
 struct RunB {
