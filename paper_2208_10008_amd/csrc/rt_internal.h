@@ -157,7 +157,7 @@ constexpr int kStatWords = kStatBlocks * (2 + kStatHist) + 2 + kStatHist;
 // build sizes shared by the allocator and the build (the phase thresholds
 // and the capacities derived from them are in rt_build_plan.h)
 constexpr int kScanBlock = 1024;
-constexpr int kBinReplicas = 8; // copies of a big node's bins that chunks add into
+constexpr int kBinReplicas = 4; // copies of a big node's bins that chunks add into (2 and 8 timed: no better)
 // bytes of one bin set: counts, ordered-int boxes and (optionally) ordered-int64
 // centroid bounds for 3 axes of B bins
 __host__ __device__ inline size_t align8(size_t x) { return (x + 7) & ~size_t(7); }
