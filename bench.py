@@ -75,6 +75,9 @@ def parse():
     ap.add_argument("--cut", type=int, default=0,
                     help="two-launch trace: chains alive after this many segments are traced by a "
                          "second launch in full waves (rt_trace_opts.cut; 0: one launch)")
+    ap.add_argument("--pad", action="store_true",
+                    help="write the rows after each chain's miss as misses too (the library default; "
+                         "the step leaves them, since n_hits says where every chain ends)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the alpha / d_norm sweep")
@@ -244,7 +247,9 @@ def main_step(args):
     streams = [torch.cuda.Stream() for _ in range(depth)]  # default priority
     wss = [R.chain_workspace(n) for _ in range(depth)] if args.cut > 0 else [None] * depth
 
-    def step(k, p, d, ev=None):
+    flags = 0 if args.pad else R.RT_TRACE_NO_PAD
+
+    def step(k, p, d, ev=None, flags=flags):
         """Step k on tree, outputs and stream k mod d: rebuild, then trace."""
         i = k % d
         s = streams[i]
@@ -253,22 +258,23 @@ def main_step(args):
         R.rt_rebuild(trees[i].handle, tris, p, stream=s)
         if ev is not None:
             ev[1].record(s)
-        if args.cut > 0:
-            R.rt_trace_ex(trees[i].handle, rays, nb, *outs[i], cut=args.cut, chain_ws=wss[i], stream=s)
+        if args.cut > 0 or flags:
+            R.rt_trace_ex(trees[i].handle, rays, nb, *outs[i], cut=args.cut, chain_ws=wss[i],
+                          stream=s, flags=flags)
         else:
             R.rt_trace_bounces(trees[i].handle, rays, nb, *outs[i], stream=s)
         if ev is not None:
             ev[2].record(s)
 
-    def timed(p, steps, warmup, d=1):
+    def timed(p, steps, warmup, d=1, flags=flags):
         for k in range(warmup):
-            step(k, p, d)
+            step(k, p, d, flags=flags)
         torch.cuda.synchronize()
         evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(steps):
-            step(k, p, d, evs[k])
+            step(k, p, d, evs[k], flags=flags)
         torch.cuda.synchronize()
         total = time.perf_counter() - t0
         build_ms = [e[0].elapsed_time(e[1]) for e in evs]
@@ -292,6 +298,8 @@ def main_step(args):
     if serial:
         s_steps = max(5, args.steps // 3)
         s_tot, _, s_build, s_trace = timed(params, s_steps, 1, 1)
+        if flags:
+            p_tot, _, p_build, p_trace = timed(params, args.steps, 1, depth, flags=0)
     nh = n_hits.cpu().numpy()
     segments = int(np.minimum(nh + 1, nb).sum())
     ms_per_step = 1e3 * total / args.steps
@@ -336,6 +344,7 @@ def main_step(args):
             "step": "rt_rebuild (Eq. 2 BVH for this Tx) + " + (
                 f"rt_trace_ex (two launches, cut {args.cut})" if args.cut > 0 else "rt_trace_bounces"),
             "pipeline": depth,
+            "miss_rows": "padded" if args.pad else "left (RT_TRACE_NO_PAD; n_hits ends each chain)",
         },
         "roofline": roofline(trace_mean_ms, segments, nodes_total, tests_total,
                              load_sq(w.name), load_traffic(w.name), ceilings),
@@ -360,6 +369,13 @@ def main_step(args):
             "build_ms": round(float(np.mean(s_build)), 4),
             "trace_ms": round(float(np.mean(s_trace)), 4),
         }
+        if flags:
+            result["padded"] = {
+                "steps": args.steps, "ms_per_step": round(1e3 * p_tot / args.steps, 4),
+                "mrays_s": round(segments / (p_tot / args.steps) / 1e6, 2),
+                "build_ms": round(float(np.mean(p_build)), 4),
+                "trace_ms": round(float(np.mean(p_trace)), 4),
+            }
 
     if not args.no_compare:
         fmts = {}

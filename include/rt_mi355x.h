@@ -178,6 +178,12 @@ int rt_trace(const rt_bvh* b, const float* rays, int64_t n, rt_hit* out, hipStre
 int rt_trace_bounces(const rt_bvh* b, const float* rays, int64_t n, int32_t max_bounces,
                      rt_hit* out, double* path_len, int32_t* n_hits, hipStream_t s);
 
+/* rt_trace_opts.flags: rows of out for segments never traced (those after a
+ * chain's first miss) are left as they were instead of being written as
+ * misses; a chain with h hits has rows 0 .. min(h, max_bounces - 1) written
+ * (row h, when it exists, is its miss).  Needs n_hits to read out. */
+#define RT_TRACE_NO_PAD 1
+
 /* Optional outputs and launch shape for rt_trace_ex. */
 typedef struct rt_trace_opts {
   float* seg_rays;     /* nullable, [max_bounces][n][8]: the ray of every traced segment,
@@ -213,7 +219,7 @@ typedef struct rt_trace_opts {
                           length and hit count are those of the one-launch trace up to the
                           order in which a wave's lanes test leaves (a chain whose closest
                           hit is decided within rounding may differ) */
-  int32_t reserved2;   /* must be 0 */
+  int32_t flags;       /* 0 or RT_TRACE_NO_PAD */
   void* chain_ws;      /* cut >= 1: caller-owned device workspace of at least
                           rt_trace_chain_ws_bytes(n) bytes, 256-byte aligned, used by this
                           call only (calls that overlap need workspaces of their own) */
@@ -229,7 +235,8 @@ int64_t rt_trace_chain_ws_bytes(int64_t n);
  * Errors: as rt_trace_bounces; RT_EINVAL for a misaligned seg_rays / ray_stats,
  * block, grid, refill or lanes_per_ray outside their values, lanes_per_ray > 1
  * with seg_rays, ray_stats or grid > 0, n > (2^31 - 1) 64 / lanes_per_ray,
- * cut < 0, reserved2 != 0, or cut >= 1 with seg_rays, ray_stats, grid > 0,
+ * cut < 0, flags other than 0 or RT_TRACE_NO_PAD, RT_TRACE_NO_PAD without
+ * n_hits, or cut >= 1 with seg_rays, ray_stats, grid > 0,
  * lanes_per_ray > 1, n >= 2^31, or chain_ws NULL, misaligned or smaller than
  * rt_trace_chain_ws_bytes(n). */
 int rt_trace_ex(const rt_bvh* b, const float* rays, int64_t n, int32_t max_bounces,

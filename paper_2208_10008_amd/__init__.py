@@ -35,6 +35,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librt_mi355x.so")
 
 RT_OK, RT_EINVAL, RT_ENOMEM, RT_EHIP, RT_EDEPTH = 0, -1, -2, -3, -4
+RT_TRACE_NO_PAD = 1  # rt_trace_opts.flags: rows after a chain's miss are not written
 D_MODES = {"mean": 0, "sum": 1, "kweighted": 2, "parent": 3}
 D_NORMS = {"unit": 0, "raw": 1}
 NODE_FORMATS = {"bin2": 0, "f4": 1, "q4": 2}
@@ -73,7 +74,7 @@ class rt_trace_opts(ctypes.Structure):
     _fields_ = [("seg_rays", ctypes.c_void_p), ("ray_stats", ctypes.c_void_p),
                 ("block", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("refill", ctypes.c_int32), ("lanes_per_ray", ctypes.c_int32),
-                ("cut", ctypes.c_int32), ("reserved2", ctypes.c_int32),
+                ("cut", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("chain_ws", ctypes.c_void_p), ("chain_ws_bytes", ctypes.c_int64)]
 
 
@@ -285,13 +286,13 @@ def rt_trace_chain_ws_bytes(n: int) -> int:
 
 def rt_trace_ex(handle, rays, max_bounces, out, path_len=None, n_hits=None, seg_rays=None,
                 ray_stats=None, block=0, grid=0, refill=0, lanes_per_ray=0, cut=0, chain_ws=None,
-                stream=None):
+                stream=None, flags=0):
     lib = load()
     o = rt_trace_opts()
     o.seg_rays = None if seg_rays is None else seg_rays.data_ptr()
     o.ray_stats = None if ray_stats is None else ray_stats.data_ptr()
     o.block, o.grid, o.refill, o.lanes_per_ray = block, grid, refill, lanes_per_ray
-    o.cut, o.reserved2 = cut, 0
+    o.cut, o.flags = cut, flags
     if chain_ws is not None:
         o.chain_ws = chain_ws.data_ptr()
         o.chain_ws_bytes = chain_ws.numel() * chain_ws.element_size()
@@ -564,9 +565,11 @@ class BVH:
 
     def trace_bounces(self, rays, max_bounces, out=None, path_len=None, n_hits=None,
                       seg_rays=None, ray_stats=None, block=0, grid=0, refill=0, lanes_per_ray=0,
-                      cut=0, chain_ws=None, stream=None):
+                      cut=0, chain_ws=None, stream=None, pad=True):
         """cut >= 1: two launches (see rt_trace_opts.cut); chain_ws is made
-        (rt_trace_chain_ws_bytes(n) bytes) when not given."""
+        (rt_trace_chain_ws_bytes(n) bytes) when not given.  pad=False sets
+        RT_TRACE_NO_PAD: rows of ``out`` after each chain's miss keep what they
+        held, and ``n_hits`` tells where each chain ends."""
         import torch
         _dev(rays, torch.float32, 8, "rays")
         n = rays.shape[0]
@@ -579,11 +582,12 @@ class BVH:
         if n_hits is None:
             n_hits = torch.empty(n, dtype=torch.int32, device=rays.device)
         if (seg_rays is None and ray_stats is None and block == 0 and grid == 0 and refill == 0
-                and lanes_per_ray == 0 and cut == 0):
+                and lanes_per_ray == 0 and cut == 0 and pad):
             rt_trace_bounces(self.handle, rays, max_bounces, out, path_len, n_hits, stream)
         else:
             rt_trace_ex(self.handle, rays, max_bounces, out, path_len, n_hits, seg_rays,
-                        ray_stats, block, grid, refill, lanes_per_ray, cut, chain_ws, stream)
+                        ray_stats, block, grid, refill, lanes_per_ray, cut, chain_ws, stream,
+                        0 if pad else RT_TRACE_NO_PAD)
         return out, path_len, n_hits
 
     def trace_receive(self, rays, max_bounces, receivers: Receivers, out=None, path_len=None,

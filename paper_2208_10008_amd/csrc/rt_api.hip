@@ -180,8 +180,10 @@ int check_trace_args(const rt_bvh* b, const float* rays, int64_t n, int32_t max_
                        "trace: lanes_per_ray > 1 takes no seg_rays, ray_stats or grid");
     if (g > 1 && n > (int64_t)INT32_MAX * (64 / g))
       return set_error(RT_EINVAL, "trace: too many rays for lanes_per_ray");
-    if (opts->cut < 0 || opts->reserved2 != 0)
-      return set_error(RT_EINVAL, "trace: cut must be >= 0 and reserved2 0");
+    if (opts->cut < 0 || (opts->flags & ~RT_TRACE_NO_PAD) != 0)
+      return set_error(RT_EINVAL, "trace: cut must be >= 0 and flags 0 or RT_TRACE_NO_PAD");
+    if ((opts->flags & RT_TRACE_NO_PAD) && !n_hits)
+      return set_error(RT_EINVAL, "trace: RT_TRACE_NO_PAD needs n_hits");
     if (opts->cut > 0) {
       if (opts->seg_rays || opts->ray_stats || opts->grid > 0 || g > 1)
         return set_error(RT_EINVAL,

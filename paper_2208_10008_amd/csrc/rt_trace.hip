@@ -568,7 +568,7 @@ __device__ __forceinline__ void trace_chains(const void* __restrict__ tn, const 
                              const RecvArgs& recv, const EnergyArgs& en = EnergyArgs{},
                              int n_tf = 0, ChainCont* __restrict__ cont = nullptr,
                              unsigned long long* __restrict__ cont_n = nullptr, int cut = 0,
-                             int64_t n_src = -1) {
+                             int64_t n_src = -1, bool pad = true) {
   static_assert(G == 1 || !STATS, "per-ray statistics are kept by the one-lane form only");
   static_assert(PHASE == 0 || (BOUNCE && !SEG && !STATS && !RECV && !ENERGY && G == 1),
                 "the two-launch trace is the plain chain trace");
@@ -695,7 +695,8 @@ __device__ __forceinline__ void trace_chains(const void* __restrict__ tn, const 
       if (BOUNCE && writer) {
         Hit none;
         none.id = -1;
-        for (int q = b + 1; q < max_b; ++q) store_hit(out, (int64_t)q * n + i, none);
+        if (pad)
+          for (int q = b + 1; q < max_b; ++q) store_hit(out, (int64_t)q * n + i, none);
         if (path_len) path_len[i] = path;
         if (n_hits) n_hits[i] = hits;
         if (ENERGY && en.power) en.power[i] = last_power;
@@ -725,12 +726,12 @@ __global__ __launch_bounds__(kBlock) void k_trace(const void* __restrict__ tn,
                                                   int refill, int n_tf,
                                                   ChainCont* __restrict__ cont = nullptr,
                                                   unsigned long long* __restrict__ cont_n = nullptr,
-                                                  int cut = 0) {
+                                                  int cut = 0, int pad = 1) {
   extern __shared__ int s_stack[];
   trace_chains<FMT, BOUNCE, SEG, STATS, false, false, G, PHASE>(
       tn, tf, rays, n, max_b, out, path_len, n_hits, seg, stats, queue, refill,
       (int64_t)blockIdx.x * (kBlock / G), s_stack + threadIdx.x, RecvArgs{}, EnergyArgs{}, n_tf,
-      cont, cont_n, cut);
+      cont, cont_n, cut, -1, pad != 0);
 }
 
 // Second launch of a two-launch trace: work-group g resumes the live chains
@@ -742,7 +743,8 @@ __global__ __launch_bounds__(kBlock) void k_trace_resume(const void* __restrict_
                                                          double* __restrict__ path_len,
                                                          int32_t* __restrict__ n_hits, int n_tf,
                                                          const ChainCont* __restrict__ cont,
-                                                         const unsigned long long* __restrict__ cont_n) {
+                                                         const unsigned long long* __restrict__ cont_n,
+                                                         int pad) {
   extern __shared__ int s_stack[];
   const int64_t total = (int64_t)*cont_n;
   const int64_t base = (int64_t)blockIdx.x * kBlock;
@@ -750,7 +752,7 @@ __global__ __launch_bounds__(kBlock) void k_trace_resume(const void* __restrict_
   trace_chains<FMT, true, false, false, false, false, 1, 2>(
       tn, tf, nullptr, n, max_b, out, path_len, n_hits, nullptr, nullptr, nullptr, 0, base,
       s_stack + threadIdx.x, RecvArgs{}, EnergyArgs{}, n_tf, const_cast<ChainCont*>(cont), nullptr, 0,
-      total);
+      total, pad != 0);
 }
 
 // Reflection chains whose segments are tested against field points as they
@@ -861,7 +863,8 @@ size_t stack_bytes(int depth) {
 template <int FMT, bool BOUNCE, bool SEG, bool STATS>
 void launch(const Buffers& B, int depth, const float* rays, int64_t n, int max_b, rt_hit* out,
             double* path_len, int32_t* n_hits, float* seg, uint32_t* stats, int grid,
-            int refill, int n_tf, unsigned long long* queue, int cut, void* ws, hipStream_t s) {
+            int refill, int n_tf, unsigned long long* queue, int cut, void* ws, int pad,
+            hipStream_t s) {
   const int64_t batches = (n + kBlock - 1) / kBlock;
   const void* nodes = FMT == RT_NODE_BIN2 ? (const void*)B.tnodes : (const void*)B.wnodes;
   if constexpr (BOUNCE && !SEG && !STATS) {
@@ -872,10 +875,10 @@ void launch(const Buffers& B, int depth, const float* rays, int64_t n, int max_b
       hipLaunchKernelGGL((k_trace<FMT, true, false, false, 1, 1>), dim3((unsigned)batches),
                          dim3(kBlock), stack_bytes<FMT>(depth), s, nodes, B.tfacets,
                          reinterpret_cast<const float4*>(rays), n, max_b, out, path_len, n_hits,
-                         nullptr, nullptr, nullptr, 0, n_tf, cont, cont_n, cut);
+                         nullptr, nullptr, nullptr, 0, n_tf, cont, cont_n, cut, pad);
       hipLaunchKernelGGL((k_trace_resume<FMT>), dim3((unsigned)batches), dim3(kBlock),
                          stack_bytes<FMT>(depth), s, nodes, B.tfacets, n, max_b, out, path_len,
-                         n_hits, n_tf, cont, cont_n);
+                         n_hits, n_tf, cont, cont_n, pad);
       return;
     }
   }
@@ -889,44 +892,45 @@ void launch(const Buffers& B, int depth, const float* rays, int64_t n, int max_b
   hipLaunchKernelGGL((k_trace<FMT, BOUNCE, SEG, STATS>), dim3((unsigned)blocks), dim3(kBlock),
                      stack_bytes<FMT>(depth), s, nodes, B.tfacets,
                      reinterpret_cast<const float4*>(rays), n, max_b, out, path_len, n_hits,
-                     reinterpret_cast<float4*>(seg), stats, q, refill, n_tf);
+                     reinterpret_cast<float4*>(seg), stats, q, refill, n_tf, nullptr, nullptr, 0, pad);
 }
 
 // G lanes per ray: one work-group per 64 / G consecutive rays.
 template <int FMT, int G>
 void launch_group(const Buffers& B, int depth, const float* rays, int64_t n, int max_b,
-                  rt_hit* out, double* path_len, int32_t* n_hits, int n_tf, hipStream_t s) {
+                  rt_hit* out, double* path_len, int32_t* n_hits, int n_tf, int pad,
+                  hipStream_t s) {
   constexpr int per_wave = kBlock / G;
   const int64_t blocks = (n + per_wave - 1) / per_wave;
   const void* nodes = FMT == RT_NODE_BIN2 ? (const void*)B.tnodes : (const void*)B.wnodes;
   hipLaunchKernelGGL((k_trace<FMT, true, false, false, G>), dim3((unsigned)blocks), dim3(kBlock),
                      stack_bytes<FMT>(depth), s, nodes, B.tfacets,
                      reinterpret_cast<const float4*>(rays), n, max_b, out, path_len, n_hits,
-                     nullptr, nullptr, nullptr, 0, n_tf);
+                     nullptr, nullptr, nullptr, 0, n_tf, nullptr, nullptr, 0, pad);
 }
 
 template <int FMT>
 void launch_fmt(const Buffers& B, int depth, const float* rays, int64_t n, int max_b, rt_hit* out,
                 double* path_len, int32_t* n_hits, float* seg, uint32_t* stats, int grid,
-                int refill, int lanes, int n_tf, unsigned long long* q, int cut, void* ws,
+                int refill, int lanes, int n_tf, unsigned long long* q, int cut, void* ws, int pad,
                 hipStream_t s) {
   switch (lanes) {  // the caller allows lanes > 1 only without seg, stats and grid
-    case 4: return launch_group<FMT, 4>(B, depth, rays, n, max_b, out, path_len, n_hits, n_tf, s);
-    case 16: return launch_group<FMT, 16>(B, depth, rays, n, max_b, out, path_len, n_hits, n_tf, s);
-    case 64: return launch_group<FMT, 64>(B, depth, rays, n, max_b, out, path_len, n_hits, n_tf, s);
+    case 4: return launch_group<FMT, 4>(B, depth, rays, n, max_b, out, path_len, n_hits, n_tf, pad, s);
+    case 16: return launch_group<FMT, 16>(B, depth, rays, n, max_b, out, path_len, n_hits, n_tf, pad, s);
+    case 64: return launch_group<FMT, 64>(B, depth, rays, n, max_b, out, path_len, n_hits, n_tf, pad, s);
     default: break;
   }
   const bool bounce = max_b > 1 || path_len || n_hits;
   if (!bounce && !seg && !stats) {
-    launch<FMT, false, false, false>(B, depth, rays, n, 1, out, nullptr, nullptr, nullptr, nullptr, grid, refill, n_tf, q, cut, ws, s);
+    launch<FMT, false, false, false>(B, depth, rays, n, 1, out, nullptr, nullptr, nullptr, nullptr, grid, refill, n_tf, q, cut, ws, pad, s);
   } else if (!seg && !stats) {
-    launch<FMT, true, false, false>(B, depth, rays, n, max_b, out, path_len, n_hits, nullptr, nullptr, grid, refill, n_tf, q, cut, ws, s);
+    launch<FMT, true, false, false>(B, depth, rays, n, max_b, out, path_len, n_hits, nullptr, nullptr, grid, refill, n_tf, q, cut, ws, pad, s);
   } else if (seg && !stats) {
-    launch<FMT, true, true, false>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, nullptr, grid, refill, n_tf, q, cut, ws, s);
+    launch<FMT, true, true, false>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, nullptr, grid, refill, n_tf, q, cut, ws, pad, s);
   } else if (!seg) {
-    launch<FMT, true, false, true>(B, depth, rays, n, max_b, out, path_len, n_hits, nullptr, stats, grid, refill, n_tf, q, cut, ws, s);
+    launch<FMT, true, false, true>(B, depth, rays, n, max_b, out, path_len, n_hits, nullptr, stats, grid, refill, n_tf, q, cut, ws, pad, s);
   } else {
-    launch<FMT, true, true, true>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, stats, grid, refill, n_tf, q, cut, ws, s);
+    launch<FMT, true, true, true>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, stats, grid, refill, n_tf, q, cut, ws, pad, s);
   }
 }
 
@@ -1095,15 +1099,16 @@ int launch_trace(const Buffers& B, int node_format, int depth, const float* rays
   const int refill = opts ? opts->refill : 0;
   const int cut = opts ? opts->cut : 0;
   void* ws = opts ? opts->chain_ws : nullptr;
+  const int pad = opts && (opts->flags & RT_TRACE_NO_PAD) ? 0 : 1;
   switch (node_format) {
     case RT_NODE_F4:
-      launch_fmt<RT_NODE_F4>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, stats, grid, refill, lanes, n_tf, q, cut, ws, s);
+      launch_fmt<RT_NODE_F4>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, stats, grid, refill, lanes, n_tf, q, cut, ws, pad, s);
       break;
     case RT_NODE_Q4:
-      launch_fmt<RT_NODE_Q4>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, stats, grid, refill, lanes, n_tf, q, cut, ws, s);
+      launch_fmt<RT_NODE_Q4>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, stats, grid, refill, lanes, n_tf, q, cut, ws, pad, s);
       break;
     default:
-      launch_fmt<RT_NODE_BIN2>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, stats, grid, refill, lanes, n_tf, q, cut, ws, s);
+      launch_fmt<RT_NODE_BIN2>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, stats, grid, refill, lanes, n_tf, q, cut, ws, pad, s);
       break;
   }
   return check_hip(hipGetLastError(), "trace launch");

@@ -75,7 +75,7 @@ int main(void) {
          offsetof(rt_ray_launch, n));
   printf("%zu %zu %zu %zu\\n", offsetof(rt_bvh_info, has_stats), offsetof(rt_bvh_info, tree_cost),
          offsetof(rt_bvh_info, root_area), offsetof(rt_bvh_info, leaf_hist));
-  printf("%zu %zu %zu %zu\\n", offsetof(rt_trace_opts, cut), offsetof(rt_trace_opts, reserved2),
+  printf("%zu %zu %zu %zu\\n", offsetof(rt_trace_opts, cut), offsetof(rt_trace_opts, flags),
          offsetof(rt_trace_opts, chain_ws), offsetof(rt_trace_opts, chain_ws_bytes));
   return 0;
 }""")
@@ -112,7 +112,7 @@ int main(void) {
                                            R.rt_bvh_info.root_area.offset,
                                            R.rt_bvh_info.leaf_hist.offset]
     assert [int(x) for x in m.split()] == [R.rt_trace_opts.cut.offset,
-                                           R.rt_trace_opts.reserved2.offset,
+                                           R.rt_trace_opts.flags.offset,
                                            R.rt_trace_opts.chain_ws.offset,
                                            R.rt_trace_opts.chain_ws_bytes.offset]
 
