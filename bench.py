@@ -342,7 +342,8 @@ def main_step(args):
             "tx": list(w.tx), "alpha": args.alpha, "max_leaf": args.max_leaf,
             "node_format": args.node_format,
             "step": "rt_rebuild (Eq. 2 BVH for this Tx) + " + (
-                f"rt_trace_ex (two launches, cut {args.cut})" if args.cut > 0 else "rt_trace_bounces"),
+                f"rt_trace_ex (two launches, cut {args.cut})" if args.cut > 0 else
+                "rt_trace_ex (one launch)" if flags else "rt_trace_bounces"),
             "pipeline": depth,
             "miss_rows": "padded" if args.pad else "left (RT_TRACE_NO_PAD; n_hits ends each chain)",
         },
