@@ -359,6 +359,7 @@ def main_step(args):
         "tri_tests_per_ray": round(tests_total / segments, 3),
         "nodes_per_ray": round(nodes_total / segments, 3),
         "tri_tests_per_primary_p50_p99": [int(np.percentile(st[:, 1], 50)), int(np.percentile(st[:, 1], 99))],
+        "nodes_per_primary_p50_p99": [int(np.percentile(st[:, 0], 50)), int(np.percentile(st[:, 0], 99))],
         "bvh": {"nodes": info.n_nodes, "depth": info.depth, "trace_bytes": info.trace_bytes,
                 "tree_cost": round(tree_stats.tree_cost, 4),
                 "leaf_hist": list(tree_stats.leaf_hist)[:8]},
