@@ -1725,22 +1725,25 @@ __device__ inline float4 f4(float x, float y, float z, float w) { return make_fl
 // traversal index of an internal node: its child pair
 __device__ inline int pair_index(const BNode& nd) { return (nd.left - 1) >> 1; }
 
-// One used split boundary b (or, for the extra last index, the root): copies
-// its two children to their compact ids, writes its traversal node and the
-// leaf-ordered facets of its leaf children.
-__device__ inline void emit_leaf(const BNode& nd, const int32_t* __restrict__ perm,
-                                 const float* __restrict__ tris, TFacet* __restrict__ tf) {
-  for (int k = nd.first; k < nd.first + nd.count; ++k) {
-    const int f = perm[k];
-    const float* v = tris + 9 * (int64_t)f;
-    const uint32_t tag = (uint32_t)f | (k == nd.first + nd.count - 1 ? kLastFacet : 0u);
-    TFacet o;
-    o.p0 = f4(v[0], v[1], v[2], __uint_as_float(tag));
-    o.p1 = f4(v[3], v[4], v[5], 0.f);
-    o.p2 = f4(v[6], v[7], v[8], 0.f);
-    tf[k] = o;
-  }
+// The facet at leaf-ordered position k.  The leaves tile the positions, and
+// the boundary between two neighbouring leaves is the split position of some
+// internal node, so the facet at k ends its leaf exactly when boundary k is
+// used (or k is the last position).
+__device__ inline void emit_facet(int k, int n, const int32_t* __restrict__ used,
+                                  const int32_t* __restrict__ perm, const float* __restrict__ tris,
+                                  TFacet* __restrict__ tf) {
+  const int f = perm[k];
+  const float* v = tris + 9 * (int64_t)f;
+  const uint32_t tag = (uint32_t)f | (k == n - 1 || used[k] > 0 ? kLastFacet : 0u);
+  TFacet o;
+  o.p0 = f4(v[0], v[1], v[2], __uint_as_float(tag));
+  o.p1 = f4(v[3], v[4], v[5], 0.f);
+  o.p2 = f4(v[6], v[7], v[8], 0.f);
+  tf[k] = o;
 }
+// One split boundary b (or, for the extra last index, the root): the facet at
+// position b, and for a used boundary its two children copied to their
+// compact ids and its traversal node.
 // Traversal starts at index 0, so the root's pair swaps its rank with rank 0.
 __device__ inline int remap(int r, int rr) { return r == rr ? 0 : (r == 0 ? rr : r); }
 __device__ inline int compact_left(int left, const int32_t* __restrict__ rank, int rr) {
@@ -1754,6 +1757,7 @@ __device__ void emit_one(const BNode* __restrict__ nodes, const BuildState* __re
   const int n = st->n;
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (st->error || b >= n) return;
+  emit_facet(b, n, used, perm, tris, tf);
   const int root_left = nodes[0].left;
   const int rr = root_left < 0 ? 0 : rank[(root_left - 1) >> 1];
   if (b == n - 1) {  // the root (a boundary index that is never used)
@@ -1761,7 +1765,6 @@ __device__ void emit_one(const BNode* __restrict__ nodes, const BuildState* __re
     r.left = compact_left(r.left, rank, rr);
     cn[0] = r;
     if (r.left < 0) {  // the whole scene is one leaf: a root with one empty child
-      emit_leaf(r, perm, tris, tf);
       TNode t;
       t.a = f4(r.lo[0], r.hi[0], r.lo[1], r.hi[1]);
       // an empty volume: lo = hi = +inf gives an empty slab on every axis
@@ -1779,7 +1782,6 @@ __device__ void emit_one(const BNode* __restrict__ nodes, const BuildState* __re
     ch[side] = nodes[2 * b + 1 + side];
     ch[side].left = compact_left(ch[side].left, rank, rr);
     cn[2 * r + 1 + side] = ch[side];
-    if (ch[side].left < 0) emit_leaf(ch[side], perm, tris, tf);
   }
   const BNode& l = ch[0];
   const BNode& q = ch[1];
