@@ -9,7 +9,8 @@ formats, with the output pre-filled with a sentinel:
 
 * rows 0 .. min(h, max_bounces - 1) of a chain with h hits, its path length
   and its hit count are those of the padded trace of the same launch shape,
-  bit for bit for one launch (64 rays or 16 rays per wave); under the
+  bit for bit for one launch (64 rays or 16 rays per wave) and for persistent
+  work-groups taking 64 consecutive rays; with lane refill and under the
   two-launch trace (cut 2) they equal the one-launch trace or differ only as
   tests/_parity.py allows;
 * every later row still holds the sentinel;
@@ -30,6 +31,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 SENTINEL = 0x5A5A5A5A
+WAVES_PER_CU = 28  # resident trace waves per compute unit (7 per SIMD)
 
 
 def log(*a):
@@ -93,11 +95,16 @@ def test_no_pad_writes_only_the_traced_rows(city, fmt):
     ws = R.chain_workspace(n)
     tree = None
     one = host(*bvh.trace_bounces(rays, nb))
-    for kw in (dict(), dict(lanes_per_ray=4), dict(cut=2, chain_ws=ws)):
-        tag = f"{fmt} {kw.get('lanes_per_ray', 1)} lanes, cut {kw.get('cut', 0)}"
+    resident = torch.cuda.get_device_properties(0).multi_processor_count * WAVES_PER_CU
+    shapes = (dict(), dict(lanes_per_ray=4), dict(grid=resident, refill=0),
+              dict(grid=resident, refill=1), dict(cut=2, chain_ws=ws))
+    for kw in shapes:
+        tag = f"{fmt} " + (", ".join(f"{k} {v}" for k, v in kw.items() if k != "chain_ws") or "default")
         log("launch:", tag)
-        # the two-launch trace is held to the one-launch trace, as without the flag
-        base = one if "cut" in kw else host(*bvh.trace_bounces(rays, nb, **kw))
+        # launches that regroup chains (lane refill, two launches) are held to
+        # the one-launch trace, as without the flag
+        regroup = "cut" in kw or kw.get("refill") == 1
+        base = one if regroup else host(*bvh.trace_bounces(rays, nb, **kw))
         out = bvh.hits_buffer(n, nb)
         out.fill_(SENTINEL)
         got = host(*bvh.trace_bounces(rays, nb, out=out, pad=False, **kw))
@@ -107,7 +114,7 @@ def test_no_pad_writes_only_the_traced_rows(city, fmt):
         log(f"{tag}: {int(untouched.sum())} of {nb * n} rows left untouched")
         full = padded(got, base, written)
         differ = differing(base, full)
-        if "cut" not in kw:
+        if not regroup:
             assert differ.size == 0, tag
         elif differ.size:
             log(f"{tag}: {differ.size} of {n} chains differ from the one-launch trace")
