@@ -108,8 +108,7 @@ struct BuildState {
   int32_t error;       // an internal capacity check failed
   int32_t n;           // facets of the build
   int32_t prep_done;   // work-groups of the facet pass that have finished
-  int32_t emit_done;   // work-groups of the emit pass that have finished
-  int32_t pad;
+  int32_t pad[2];
   double inv_l2;       // 1 / squared root diagonal (0 if the root is a point)
   // per big-node level: (big nodes << 32) | chunk items, both taken by one
   // atomic add per parent
