@@ -6,11 +6,14 @@ the scene with the Eq. (2) split for that transmitter (Sec. II-B, II-C), then
 trace the launched rays with up to 6 specular bounces (Sec. III-B).  Scene and
 rays are seeded synthetic inputs already resident in HBM.  The value is
 traced segments (primary + every re-launched segment) per second of the timed
-steps, in millions.  Consecutive steps alternate between two trees, output
-sets and streams (--pipeline 2, the default), so one transmitter's build runs
-while the previous transmitter's rays are traced; every step still builds its
-whole tree and traces all its rays.  The serial rate (--pipeline 1: each step
-waits for the previous one) is reported beside it.
+steps, in millions.  Consecutive steps alternate between two trees and output
+sets (--pipeline 2, the default); builds run on a stream holding 48 of the 256
+compute units and traces on one holding the other 208 (rt_streams_split_cus),
+so one transmitter's build runs while the previous transmitter's rays are
+traced, and each step orders its ray batches most horizontal first
+(rt_rays_batch_order) before tracing them; every step still builds its whole
+tree, orders and traces all its rays.  The serial rate (--pipeline 1: each step
+waits for the previous one, on all compute units) is reported beside it.
 
 Prints one JSON line.  Extra fields: the trace kernel's roofline (vector
 instruction issue, from the committed SQ counters of the current kernel
@@ -75,6 +78,12 @@ def parse():
     ap.add_argument("--cut", type=int, default=0,
                     help="two-launch trace: chains alive after this many segments are traced by a "
                          "second launch in full waves (rt_trace_opts.cut; 0: one launch)")
+    ap.add_argument("--build-cus", type=int, default=48, choices=[0] + list(range(8, 129, 8)),
+                    help="pipelined steps: builds on this many compute units, traces on the rest "
+                         "(rt_streams_split_cus); 0: one stream per tree on all of them")
+    ap.add_argument("--order", default="elevation", choices=["elevation", "given"],
+                    help="trace batch order: most horizontal batches first (rt_rays_batch_order, "
+                         "computed in every step) or the rays' own order")
     ap.add_argument("--pad", action="store_true",
                     help="write the rows after each chain's miss as misses too (the library default; "
                          "the step leaves them, since n_hits says where every chain ends)")
@@ -244,27 +253,44 @@ def main_step(args):
     out, path_len, n_hits = outs[0]
     trees = [R.BVH(tris, params) for _ in range(depth)]
     bvh = trees[0]
-    streams = [torch.cuda.Stream() for _ in range(depth)]  # default priority
+    plain = torch.cuda.Stream()  # default priority, all compute units (serial steps)
+    split = R.SplitStreams(args.build_cus) if depth > 1 and args.build_cus > 0 else None
+    if split is not None:  # builds on build_cus compute units, traces on the rest
+        bstreams, tstreams = [split.small] * depth, [split.large] * depth
+    else:  # one stream per tree, build and trace of a step on it
+        bstreams = tstreams = [torch.cuda.Stream() for _ in range(depth)]
+    done = [torch.cuda.Event() for _ in range(depth)]  # tree i's last trace has ended
     wss = [R.chain_workspace(n) for _ in range(depth)] if args.cut > 0 else [None] * depth
+    nbat = (n + 63) // 64
+    orders = [torch.empty(nbat, dtype=torch.int32, device="cuda") for _ in range(depth)]
+    okeys = [torch.empty(R.rt_rays_batch_order_ws_bytes(n) // 4, dtype=torch.int32, device="cuda")
+             for _ in range(depth)]
 
     flags = 0 if args.pad else R.RT_TRACE_NO_PAD
 
     def step(k, p, d, ev=None, flags=flags):
-        """Step k on tree, outputs and stream k mod d: rebuild, then trace."""
+        """Step k on tree and outputs k mod d: rebuild, order the ray batches,
+        trace."""
         i = k % d
-        s = streams[i]
+        sb, st = (plain, plain) if d == 1 else (bstreams[i], tstreams[i])
+        sb.wait_event(done[i])  # the tree's previous trace has finished
         if ev is not None:
-            ev[0].record(s)
-        R.rt_rebuild(trees[i].handle, tris, p, stream=s)
+            ev[0].record(sb)
+        R.rt_rebuild(trees[i].handle, tris, p, stream=sb)
         if ev is not None:
-            ev[1].record(s)
-        if args.cut > 0 or flags:
+            ev[1].record(sb)
+        st.wait_stream(sb)
+        order = None
+        if args.order == "elevation":
+            order = R.rt_rays_batch_order(rays, axis=2, order=orders[i], keys=okeys[i], stream=st)
+        if args.cut > 0 or flags or order is not None:
             R.rt_trace_ex(trees[i].handle, rays, nb, *outs[i], cut=args.cut, chain_ws=wss[i],
-                          stream=s, flags=flags)
+                          stream=st, flags=flags, batch_order=order)
         else:
-            R.rt_trace_bounces(trees[i].handle, rays, nb, *outs[i], stream=s)
+            R.rt_trace_bounces(trees[i].handle, rays, nb, *outs[i], stream=st)
+        done[i].record(st)
         if ev is not None:
-            ev[2].record(s)
+            ev[2].record(st)
 
     def timed(p, steps, warmup, d=1, flags=flags):
         for k in range(warmup):
@@ -342,9 +368,12 @@ def main_step(args):
             "tx": list(w.tx), "alpha": args.alpha, "max_leaf": args.max_leaf,
             "node_format": args.node_format,
             "step": "rt_rebuild (Eq. 2 BVH for this Tx) + " + (
+                "rt_rays_batch_order + " if args.order == "elevation" else "") + (
                 f"rt_trace_ex (two launches, cut {args.cut})" if args.cut > 0 else
-                "rt_trace_ex (one launch)" if flags else "rt_trace_bounces"),
+                "rt_trace_ex (one launch)" if flags or args.order == "elevation" else "rt_trace_bounces"),
             "pipeline": depth,
+            "streams": (f"builds on {args.build_cus} compute units, traces on {256 - args.build_cus}"
+                        if split is not None else "one stream per tree, all compute units"),
             "miss_rows": "padded" if args.pad else "left (RT_TRACE_NO_PAD; n_hits ends each chain)",
         },
         "roofline": roofline(trace_mean_ms, segments, nodes_total, tests_total,
@@ -405,6 +434,8 @@ def main_step(args):
         step(0, params, 1)  # leave the improved tree in place
         torch.cuda.synchronize()
 
+    if split is not None:
+        split.close()
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(w, args.alpha, args.max_leaf)
 

@@ -224,6 +224,16 @@ typedef struct rt_trace_opts {
                           rt_trace_chain_ws_bytes(n) bytes, 256-byte aligned, used by this
                           call only (calls that overlap need workspaces of their own) */
   int64_t chain_ws_bytes;
+  const int32_t* batch_order; /* nullable, device [ceil(n / 64)]: the order in which the
+                          launch starts its batches of 64 consecutive rays (work-group g traces
+                          batch batch_order[g]); a permutation of 0 .. ceil(n / 64) - 1 (an
+                          entry outside that range traces nothing, a repeated one traces its
+                          batch again with the same results).  Results do not depend on it;
+                          the launch's duration does: the hardware starts work-groups in index
+                          order, and chains that run long but start late set the launch's
+                          end.  rt_rays_batch_order makes one from the ray directions.  With
+                          cut >= 1 it orders the first launch.  Needs grid 0 and one lane per
+                          ray (lanes_per_ray 0 then means 1). */
 } rt_trace_opts;
 
 /* Workspace of a two-launch trace (rt_trace_opts.cut >= 1) of n rays: a
@@ -236,9 +246,10 @@ int64_t rt_trace_chain_ws_bytes(int64_t n);
  * block, grid, refill or lanes_per_ray outside their values, lanes_per_ray > 1
  * with seg_rays, ray_stats or grid > 0, n > (2^31 - 1) 64 / lanes_per_ray,
  * cut < 0, flags other than 0 or RT_TRACE_NO_PAD, RT_TRACE_NO_PAD without
- * n_hits, or cut >= 1 with seg_rays, ray_stats, grid > 0,
+ * n_hits, cut >= 1 with seg_rays, ray_stats, grid > 0,
  * lanes_per_ray > 1, n >= 2^31, or chain_ws NULL, misaligned or smaller than
- * rt_trace_chain_ws_bytes(n). */
+ * rt_trace_chain_ws_bytes(n), or batch_order misaligned or with grid > 0 or
+ * lanes_per_ray > 1. */
 int rt_trace_ex(const rt_bvh* b, const float* rays, int64_t n, int32_t max_bounces,
                 rt_hit* out, double* path_len, int32_t* n_hits, const rt_trace_opts* opts,
                 hipStream_t s);
@@ -252,6 +263,31 @@ int rt_trace_ex(const rt_bvh* b, const float* rays, int64_t n, int32_t max_bounc
  * Errors: RT_EINVAL (NULL, misaligned, n < 0, tmin > tmax or not finite), RT_EHIP. */
 int rt_rays_from_directions(const float* dirs, int64_t n, float ox, float oy, float oz, float tmin,
                             float tmax, float* rays, hipStream_t s);
+
+/* Dispatch order for rt_trace_opts.batch_order from the ray directions.  Rays
+ * are taken in batches of 64 consecutive ones (the last may be shorter).  A
+ * ray's q = floor(1023 d_a^2 / |d|^2) in float32, each operation rounded on its
+ * own (a = axis: 0 x, 1 y, 2 z; q = 0 for a zero or non-finite direction); a
+ * batch's key is the smallest q among its rays, and its class c the number of
+ * k in 1..15 with key >= floor(1023 k^2 / 256), i.e. the smallest |d_a| / |d|
+ * in sixteenths.  order lists the batches by ascending class, in index order
+ * within a class: the batches holding a ray nearest the plane normal to the
+ * axis come first.  With the axis pointing up in an outdoor scene those rays
+ * reflect between facades and build the longest chains (Sec. III-B
+ * re-launch), and a wave lasts as long as its longest chain, so these batches
+ * start while the rest of the launch can still fill the device around them.
+ * rays: device float32 [n][8], 16-byte aligned; order: device int32
+ * [ceil(n / 64)]; keys: caller-owned device workspace of
+ * rt_rays_batch_order_ws_bytes(n) bytes, 4-byte aligned (its first
+ * ceil(n / 64) int32 are left holding the batch keys).  Three kernels enqueued
+ * on s.  n = 0 writes nothing.
+ * Errors: RT_EINVAL (NULL, misaligned, n < 0 or n >= 2^31, axis outside 0..2),
+ * RT_EHIP. */
+int rt_rays_batch_order(const float* rays, int64_t n, int32_t axis, int32_t* order,
+                        int32_t* keys, hipStream_t s);
+/* Workspace of rt_rays_batch_order for n rays: 4 (ceil(n / 64) + 16 ceil(n / 65536))
+ * bytes; n < 0: 0. */
+int64_t rt_rays_batch_order_ws_bytes(int64_t n);
 
 /* Many launches with one kernel (a serving batch): launch j writes n rays from
  * its source along the first n directions of dirs to rows first .. first + n - 1
@@ -472,6 +508,28 @@ int rt_bvh_download(const rt_bvh* b, rt_node_rec* nodes, int64_t node_cap, int32
 int rt_bvh_export_trace_nodes(const rt_bvh* b, void* host, int64_t* bytes);
 
 void rt_bvh_destroy(rt_bvh* b); /* NULL is a no-op; waits for the device */
+
+/* ---- streams on split compute units ----------------------------------------
+ * For overlapping one transmitter's build with another's trace: the trace's
+ * one-wave work-groups fill every compute unit as fast as earlier ones
+ * retire, so the build's larger work-groups start only once the trace has
+ * none left to dispatch.  These two streams divide the device's compute
+ * units instead: `small` gets k of them and `large` the rest, so work on
+ * `small` never waits for room.  The runtime may number an MI355X's 256 CUs
+ * by XCD (blocks of 32) or interleaved over its 8 XCDs (CU c on XCD c mod 8);
+ * `small` takes k / 8 CUs of every block, block b first those numbered b mod
+ * 8, then b + 1 mod 8, ..., so that either way every XCD gives k / 8 CUs to
+ * `small` and keeps the rest for `large` (a stream left with no CU on some
+ * XCD could not run the work-groups the hardware hands that XCD).  k: a
+ * multiple of 8 in 8..128.  Both are ordinary streams of default priority for
+ * the current device; free them with rt_stream_destroy.
+ * Errors: RT_EINVAL (NULL, k outside those values, a device without 256 CUs),
+ * RT_EHIP. */
+int rt_streams_split_cus(int32_t k, hipStream_t* small, hipStream_t* large);
+/* The mask `small` gets (host only, no device): bit c of word c / 32 set for
+ * each of its CUs; small_mask: host uint32 [8].  Errors: RT_EINVAL (NULL, k). */
+int rt_split_cus_mask(int32_t k, uint32_t* small_mask);
+int rt_stream_destroy(hipStream_t s); /* a stream from rt_streams_split_cus; RT_EHIP on failure */
 
 /* ---- batched trace (Sec. III-B for many transmitters and scenes) ---------
  * Many queries -- each a resident tree, a set of launched rays and a bounce

@@ -75,7 +75,8 @@ class rt_trace_opts(ctypes.Structure):
                 ("block", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("refill", ctypes.c_int32), ("lanes_per_ray", ctypes.c_int32),
                 ("cut", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("chain_ws", ctypes.c_void_p), ("chain_ws_bytes", ctypes.c_int64)]
+                ("chain_ws", ctypes.c_void_p), ("chain_ws_bytes", ctypes.c_int64),
+                ("batch_order", ctypes.c_void_p)]
 
 
 class rt_query(ctypes.Structure):
@@ -129,7 +130,9 @@ EXPORTS = ("rt_split_params_default", "rt_build", "rt_rebuild", "rt_trace",
            "rt_batch_autotune", "rt_batch_destroy", "rt_rays_from_directions",
            "rt_rays_from_directions_many", "rt_trace_receive", "rt_receive_segments", "rt_receive_dedup_workspace",
            "rt_receive_dedup", "rt_trace_energy", "rt_wedges", "rt_wedges_noalloc",
-           "rt_diffract_segments", "rt_trace_chain_ws_bytes")
+           "rt_diffract_segments", "rt_trace_chain_ws_bytes", "rt_rays_batch_order",
+           "rt_rays_batch_order_ws_bytes", "rt_split_cus_mask",
+           "rt_streams_split_cus", "rt_stream_destroy")
 PROBE_EXPORTS = ("rt_probe_read", "rt_probe_copy")  # include/rt_probe.h
 
 _lib = None
@@ -171,6 +174,12 @@ def load(path: str = LIB_PATH):
     f32 = ctypes.c_float
     lib.rt_rays_from_directions.argtypes = [P, i64, f32, f32, f32, f32, f32, P, P]
     lib.rt_rays_from_directions_many.argtypes = [P, i64, P, i32, f32, f32, P, i64, P]
+    lib.rt_rays_batch_order.argtypes = [P, i64, i32, P, P, P]
+    lib.rt_rays_batch_order_ws_bytes.argtypes = [i64]
+    lib.rt_rays_batch_order_ws_bytes.restype = i64
+    lib.rt_streams_split_cus.argtypes = [i32, ctypes.POINTER(P), ctypes.POINTER(P)]
+    lib.rt_stream_destroy.argtypes = [P]
+    lib.rt_split_cus_mask.argtypes = [i32, P]
     lib.rt_batch_destroy.argtypes = [P]
     lib.rt_batch_destroy.restype = None
     lib.rt_probe_copy.argtypes = [P, P, i64, P]
@@ -190,6 +199,8 @@ def load(path: str = LIB_PATH):
                  "rt_bvh_export_trace_nodes", "rt_probe_read", "rt_probe_copy", "rt_batch_create", "rt_batch_set",
                  "rt_batch_configure", "rt_batch_get_config", "rt_batch_launch",
                  "rt_batch_autotune", "rt_rays_from_directions", "rt_rays_from_directions_many",
+                 "rt_rays_batch_order", "rt_streams_split_cus", "rt_stream_destroy",
+                 "rt_split_cus_mask",
                  "rt_trace_receive",
                  "rt_receive_segments", "rt_receive_dedup", "rt_trace_energy", "rt_wedges",
                  "rt_wedges_noalloc", "rt_diffract_segments"):
@@ -286,9 +297,10 @@ def rt_trace_chain_ws_bytes(n: int) -> int:
 
 def rt_trace_ex(handle, rays, max_bounces, out, path_len=None, n_hits=None, seg_rays=None,
                 ray_stats=None, block=0, grid=0, refill=0, lanes_per_ray=0, cut=0, chain_ws=None,
-                stream=None, flags=0):
+                stream=None, flags=0, batch_order=None):
     lib = load()
     o = rt_trace_opts()
+    o.batch_order = None if batch_order is None else batch_order.data_ptr()
     o.seg_rays = None if seg_rays is None else seg_rays.data_ptr()
     o.ray_stats = None if ray_stats is None else ray_stats.data_ptr()
     o.block, o.grid, o.refill, o.lanes_per_ray = block, grid, refill, lanes_per_ray
@@ -298,6 +310,68 @@ def rt_trace_ex(handle, rays, max_bounces, out, path_len=None, n_hits=None, seg_
         o.chain_ws_bytes = chain_ws.numel() * chain_ws.element_size()
     _check(lib.rt_trace_ex(handle, _ptr(rays), rays.shape[0], max_bounces, _ptr(out),
                            _ptr(path_len), _ptr(n_hits), ctypes.byref(o), _stream(stream)))
+
+
+def rt_rays_batch_order_ws_bytes(n: int) -> int:
+    return int(load().rt_rays_batch_order_ws_bytes(n))
+
+
+def rt_rays_batch_order(rays, axis=2, order=None, keys=None, stream=None):
+    """Dispatch order of the rays' batches of 64 (rt_trace_opts.batch_order):
+    returns order, an int32 CUDA tensor of ceil(n / 64) batch indices.  keys:
+    int32 workspace of rt_rays_batch_order_ws_bytes(n) / 4 entries (its first
+    ceil(n / 64) are left holding the batch keys)."""
+    import torch
+    lib = load()
+    _dev(rays, torch.float32, 8, "rays")
+    n = rays.shape[0]
+    nb = (n + 63) // 64
+    nk = rt_rays_batch_order_ws_bytes(n) // 4
+    if order is None:
+        order = torch.empty(nb, dtype=torch.int32, device=rays.device)
+    if keys is None:
+        keys = torch.empty(nk, dtype=torch.int32, device=rays.device)
+    if order.numel() < nb or keys.numel() < nk or order.dtype != torch.int32 or keys.dtype != torch.int32:
+        raise RtError(RT_EINVAL, "order: int32 [ceil(n / 64)]; keys: int32 "
+                                 "[rt_rays_batch_order_ws_bytes(n) / 4]")
+    _check(lib.rt_rays_batch_order(_ptr(rays), rays.shape[0], axis, _ptr(order), _ptr(keys),
+                                   _stream(stream)))
+    return order
+
+
+def rt_split_cus_mask(k: int) -> np.ndarray:
+    """The CU mask rt_streams_split_cus gives its `small` stream (host only)."""
+    m = (ctypes.c_uint32 * 8)()
+    _check(load().rt_split_cus_mask(k, m))
+    return np.array(list(m), dtype=np.uint32)
+
+
+class SplitStreams:
+    """rt_streams_split_cus: `small` runs on k compute units, `large` on the
+    rest (torch external streams; close() or garbage collection frees them)."""
+
+    def __init__(self, k: int):
+        import torch
+        lib = load()
+        a, b = ctypes.c_void_p(), ctypes.c_void_p()
+        _check(lib.rt_streams_split_cus(k, ctypes.byref(a), ctypes.byref(b)))
+        self._raw = [a.value, b.value]
+        self.small = torch.cuda.ExternalStream(a.value)
+        self.large = torch.cuda.ExternalStream(b.value)
+
+    def close(self):
+        if self._raw:
+            import torch
+            torch.cuda.synchronize()
+            for h in self._raw:
+                _check(load().rt_stream_destroy(ctypes.c_void_p(h)))
+            self._raw = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def rt_trace_receive(handle, rays, max_bounces, out, path_len, n_hits, receivers: "Receivers",
@@ -565,7 +639,7 @@ class BVH:
 
     def trace_bounces(self, rays, max_bounces, out=None, path_len=None, n_hits=None,
                       seg_rays=None, ray_stats=None, block=0, grid=0, refill=0, lanes_per_ray=0,
-                      cut=0, chain_ws=None, stream=None, pad=True):
+                      cut=0, chain_ws=None, stream=None, pad=True, batch_order=None):
         """cut >= 1: two launches (see rt_trace_opts.cut); chain_ws is made
         (rt_trace_chain_ws_bytes(n) bytes) when not given.  pad=False sets
         RT_TRACE_NO_PAD: rows of ``out`` after each chain's miss keep what they
@@ -582,12 +656,12 @@ class BVH:
         if n_hits is None:
             n_hits = torch.empty(n, dtype=torch.int32, device=rays.device)
         if (seg_rays is None and ray_stats is None and block == 0 and grid == 0 and refill == 0
-                and lanes_per_ray == 0 and cut == 0 and pad):
+                and lanes_per_ray == 0 and cut == 0 and pad and batch_order is None):
             rt_trace_bounces(self.handle, rays, max_bounces, out, path_len, n_hits, stream)
         else:
             rt_trace_ex(self.handle, rays, max_bounces, out, path_len, n_hits, seg_rays,
                         ray_stats, block, grid, refill, lanes_per_ray, cut, chain_ws, stream,
-                        0 if pad else RT_TRACE_NO_PAD)
+                        0 if pad else RT_TRACE_NO_PAD, batch_order)
         return out, path_len, n_hits
 
     def trace_receive(self, rays, max_bounces, receivers: Receivers, out=None, path_len=None,

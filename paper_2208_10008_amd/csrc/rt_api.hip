@@ -194,6 +194,13 @@ int check_trace_args(const rt_bvh* b, const float* rays, int64_t n, int32_t max_
         return set_error(RT_EINVAL, "trace: cut >= 1 needs a 256-byte aligned chain_ws of "
                                     "rt_trace_chain_ws_bytes(n) bytes");
     }
+    if (opts->batch_order) {
+      if (!aligned(opts->batch_order, 4))
+        return set_error(RT_EINVAL, "trace: batch_order must be 4-byte aligned");
+      if (opts->grid > 0 || g > 1)
+        return set_error(RT_EINVAL, "trace: batch_order takes grid 0 and one lane per ray");
+      if ((n + 63) / 64 > INT32_MAX) return set_error(RT_EINVAL, "trace: too many batches for batch_order");
+    }
   }
   return RT_OK;
 }
@@ -219,7 +226,9 @@ int trace_lanes(int64_t n, int max_leaf) {
 // (one lane per ray whenever segments or statistics are recorded).
 int lanes_of(const rt_bvh* b, int64_t n, const rt_trace_opts* opts) {
   if (opts && opts->lanes_per_ray > 0) return opts->lanes_per_ray;
-  if (opts && (opts->seg_rays || opts->ray_stats || opts->grid > 0 || opts->cut > 0)) return 1;
+  if (opts && (opts->seg_rays || opts->ray_stats || opts->grid > 0 || opts->cut > 0 ||
+               opts->batch_order))
+    return 1;
   return trace_lanes(n, b->params.max_leaf);
 }
 
@@ -381,6 +390,55 @@ void rt_bvh_destroy(rt_bvh* b) {
   (void)hipDeviceSynchronize();
   free_buffers(b->buf);
   delete b;
+}
+
+int rt_split_cus_mask(int32_t k, uint32_t* small_mask) {
+  constexpr int kCUs = 256, kXcds = 8, kWords = kCUs / 32;
+  if (!small_mask) return set_error(RT_EINVAL, "rt_split_cus_mask: NULL mask");
+  if (k < 8 || k > 128 || k % 8 != 0)
+    return set_error(RT_EINVAL, "rt_split_cus_mask: k must be a multiple of 8 in 8..128");
+  for (int w = 0; w < kWords; ++w) small_mask[w] = 0;
+  // block b gives its CUs of residue b mod 8 first, then of residue b + 1, ...:
+  // block b's t-th CU has residue b + t / 4, so residue x collects one CU per t
+  // from block x - t / 4, k / 8 in all, as block b does
+  for (int b = 0; b < kXcds; ++b)
+    for (int t = 0; t < k / kXcds; ++t) {
+      const int cu = (kCUs / kXcds) * b + (b + t / 4) % kXcds + kXcds * (t % 4);
+      small_mask[cu / 32] |= 1u << (cu % 32);
+    }
+  return RT_OK;
+}
+
+int rt_streams_split_cus(int32_t k, hipStream_t* small, hipStream_t* large) {
+  if (!small || !large) return set_error(RT_EINVAL, "rt_streams_split_cus: NULL pointer");
+  uint32_t small_mask[8], large_mask[8];
+  int rc = rt_split_cus_mask(k, small_mask);
+  if (rc != RT_OK) return rc;
+  int dev = 0, ncu = 0;
+  rc = check_hip(hipGetDevice(&dev), "hipGetDevice");
+  if (rc != RT_OK) return rc;
+  rc = check_hip(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev),
+                 "hipDeviceGetAttribute");
+  if (rc != RT_OK) return rc;
+  constexpr int kWords = 8;
+  if (ncu != 32 * kWords) return set_error(RT_EINVAL, "rt_streams_split_cus: needs a device with 256 CUs");
+  for (int w = 0; w < kWords; ++w) large_mask[w] = ~small_mask[w];
+  hipStream_t a = nullptr, c = nullptr;
+  rc = check_hip(hipExtStreamCreateWithCUMask(&a, kWords, small_mask), "hipExtStreamCreateWithCUMask");
+  if (rc != RT_OK) return rc;
+  rc = check_hip(hipExtStreamCreateWithCUMask(&c, kWords, large_mask), "hipExtStreamCreateWithCUMask");
+  if (rc != RT_OK) {
+    (void)hipStreamDestroy(a);
+    return rc;
+  }
+  *small = a;
+  *large = c;
+  return RT_OK;
+}
+
+int rt_stream_destroy(hipStream_t s) {
+  if (!s) return set_error(RT_EINVAL, "rt_stream_destroy: NULL stream");
+  return check_hip(hipStreamDestroy(s), "hipStreamDestroy");
 }
 
 const char* rt_last_error(void) { return g_err.c_str(); }

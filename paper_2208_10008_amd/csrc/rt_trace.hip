@@ -726,11 +726,19 @@ __global__ __launch_bounds__(kBlock) void k_trace(const void* __restrict__ tn,
                                                   int refill, int n_tf,
                                                   ChainCont* __restrict__ cont = nullptr,
                                                   unsigned long long* __restrict__ cont_n = nullptr,
-                                                  int cut = 0, int pad = 1) {
+                                                  int cut = 0, int pad = 1,
+                                                  const int32_t* __restrict__ order = nullptr) {
   extern __shared__ int s_stack[];
+  // the batch this work-group traces: its own index, or the caller's order
+  // (an entry outside the launch's batches leaves the work-group idle)
+  int64_t batch = blockIdx.x;
+  if (order != nullptr) {
+    batch = order[blockIdx.x];
+    if (batch < 0 || batch * (kBlock / G) >= n) return;
+  }
   trace_chains<FMT, BOUNCE, SEG, STATS, false, false, G, PHASE>(
       tn, tf, rays, n, max_b, out, path_len, n_hits, seg, stats, queue, refill,
-      (int64_t)blockIdx.x * (kBlock / G), s_stack + threadIdx.x, RecvArgs{}, EnergyArgs{}, n_tf,
+      batch * (kBlock / G), s_stack + threadIdx.x, RecvArgs{}, EnergyArgs{}, n_tf,
       cont, cont_n, cut, -1, pad != 0);
 }
 
@@ -864,7 +872,7 @@ template <int FMT, bool BOUNCE, bool SEG, bool STATS>
 void launch(const Buffers& B, int depth, const float* rays, int64_t n, int max_b, rt_hit* out,
             double* path_len, int32_t* n_hits, float* seg, uint32_t* stats, int grid,
             int refill, int n_tf, unsigned long long* queue, int cut, void* ws, int pad,
-            hipStream_t s) {
+            const int32_t* order, hipStream_t s) {
   const int64_t batches = (n + kBlock - 1) / kBlock;
   const void* nodes = FMT == RT_NODE_BIN2 ? (const void*)B.tnodes : (const void*)B.wnodes;
   if constexpr (BOUNCE && !SEG && !STATS) {
@@ -875,7 +883,7 @@ void launch(const Buffers& B, int depth, const float* rays, int64_t n, int max_b
       hipLaunchKernelGGL((k_trace<FMT, true, false, false, 1, 1>), dim3((unsigned)batches),
                          dim3(kBlock), stack_bytes<FMT>(depth), s, nodes, B.tfacets,
                          reinterpret_cast<const float4*>(rays), n, max_b, out, path_len, n_hits,
-                         nullptr, nullptr, nullptr, 0, n_tf, cont, cont_n, cut, pad);
+                         nullptr, nullptr, nullptr, 0, n_tf, cont, cont_n, cut, pad, order);
       hipLaunchKernelGGL((k_trace_resume<FMT>), dim3((unsigned)batches), dim3(kBlock),
                          stack_bytes<FMT>(depth), s, nodes, B.tfacets, n, max_b, out, path_len,
                          n_hits, n_tf, cont, cont_n, pad);
@@ -892,7 +900,8 @@ void launch(const Buffers& B, int depth, const float* rays, int64_t n, int max_b
   hipLaunchKernelGGL((k_trace<FMT, BOUNCE, SEG, STATS>), dim3((unsigned)blocks), dim3(kBlock),
                      stack_bytes<FMT>(depth), s, nodes, B.tfacets,
                      reinterpret_cast<const float4*>(rays), n, max_b, out, path_len, n_hits,
-                     reinterpret_cast<float4*>(seg), stats, q, refill, n_tf, nullptr, nullptr, 0, pad);
+                     reinterpret_cast<float4*>(seg), stats, q, refill, n_tf, nullptr, nullptr, 0, pad,
+                     grid > 0 ? nullptr : order);
 }
 
 // G lanes per ray: one work-group per 64 / G consecutive rays.
@@ -913,7 +922,7 @@ template <int FMT>
 void launch_fmt(const Buffers& B, int depth, const float* rays, int64_t n, int max_b, rt_hit* out,
                 double* path_len, int32_t* n_hits, float* seg, uint32_t* stats, int grid,
                 int refill, int lanes, int n_tf, unsigned long long* q, int cut, void* ws, int pad,
-                hipStream_t s) {
+                const int32_t* order, hipStream_t s) {
   switch (lanes) {  // the caller allows lanes > 1 only without seg, stats and grid
     case 4: return launch_group<FMT, 4>(B, depth, rays, n, max_b, out, path_len, n_hits, n_tf, pad, s);
     case 16: return launch_group<FMT, 16>(B, depth, rays, n, max_b, out, path_len, n_hits, n_tf, pad, s);
@@ -922,15 +931,15 @@ void launch_fmt(const Buffers& B, int depth, const float* rays, int64_t n, int m
   }
   const bool bounce = max_b > 1 || path_len || n_hits;
   if (!bounce && !seg && !stats) {
-    launch<FMT, false, false, false>(B, depth, rays, n, 1, out, nullptr, nullptr, nullptr, nullptr, grid, refill, n_tf, q, cut, ws, pad, s);
+    launch<FMT, false, false, false>(B, depth, rays, n, 1, out, nullptr, nullptr, nullptr, nullptr, grid, refill, n_tf, q, cut, ws, pad, order, s);
   } else if (!seg && !stats) {
-    launch<FMT, true, false, false>(B, depth, rays, n, max_b, out, path_len, n_hits, nullptr, nullptr, grid, refill, n_tf, q, cut, ws, pad, s);
+    launch<FMT, true, false, false>(B, depth, rays, n, max_b, out, path_len, n_hits, nullptr, nullptr, grid, refill, n_tf, q, cut, ws, pad, order, s);
   } else if (seg && !stats) {
-    launch<FMT, true, true, false>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, nullptr, grid, refill, n_tf, q, cut, ws, pad, s);
+    launch<FMT, true, true, false>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, nullptr, grid, refill, n_tf, q, cut, ws, pad, order, s);
   } else if (!seg) {
-    launch<FMT, true, false, true>(B, depth, rays, n, max_b, out, path_len, n_hits, nullptr, stats, grid, refill, n_tf, q, cut, ws, pad, s);
+    launch<FMT, true, false, true>(B, depth, rays, n, max_b, out, path_len, n_hits, nullptr, stats, grid, refill, n_tf, q, cut, ws, pad, order, s);
   } else {
-    launch<FMT, true, true, true>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, stats, grid, refill, n_tf, q, cut, ws, pad, s);
+    launch<FMT, true, true, true>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, stats, grid, refill, n_tf, q, cut, ws, pad, order, s);
   }
 }
 
@@ -1100,15 +1109,16 @@ int launch_trace(const Buffers& B, int node_format, int depth, const float* rays
   const int cut = opts ? opts->cut : 0;
   void* ws = opts ? opts->chain_ws : nullptr;
   const int pad = opts && (opts->flags & RT_TRACE_NO_PAD) ? 0 : 1;
+  const int32_t* order = opts ? opts->batch_order : nullptr;
   switch (node_format) {
     case RT_NODE_F4:
-      launch_fmt<RT_NODE_F4>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, stats, grid, refill, lanes, n_tf, q, cut, ws, pad, s);
+      launch_fmt<RT_NODE_F4>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, stats, grid, refill, lanes, n_tf, q, cut, ws, pad, order, s);
       break;
     case RT_NODE_Q4:
-      launch_fmt<RT_NODE_Q4>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, stats, grid, refill, lanes, n_tf, q, cut, ws, pad, s);
+      launch_fmt<RT_NODE_Q4>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, stats, grid, refill, lanes, n_tf, q, cut, ws, pad, order, s);
       break;
     default:
-      launch_fmt<RT_NODE_BIN2>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, stats, grid, refill, lanes, n_tf, q, cut, ws, pad, s);
+      launch_fmt<RT_NODE_BIN2>(B, depth, rays, n, max_b, out, path_len, n_hits, seg, stats, grid, refill, lanes, n_tf, q, cut, ws, pad, order, s);
       break;
   }
   return check_hip(hipGetLastError(), "trace launch");

@@ -75,8 +75,9 @@ int main(void) {
          offsetof(rt_ray_launch, n));
   printf("%zu %zu %zu %zu\\n", offsetof(rt_bvh_info, has_stats), offsetof(rt_bvh_info, tree_cost),
          offsetof(rt_bvh_info, root_area), offsetof(rt_bvh_info, leaf_hist));
-  printf("%zu %zu %zu %zu\\n", offsetof(rt_trace_opts, cut), offsetof(rt_trace_opts, flags),
-         offsetof(rt_trace_opts, chain_ws), offsetof(rt_trace_opts, chain_ws_bytes));
+  printf("%zu %zu %zu %zu %zu\\n", offsetof(rt_trace_opts, cut), offsetof(rt_trace_opts, flags),
+         offsetof(rt_trace_opts, chain_ws), offsetof(rt_trace_opts, chain_ws_bytes),
+         offsetof(rt_trace_opts, batch_order));
   return 0;
 }""")
     exe = tmp_path / "sz"
@@ -114,7 +115,35 @@ int main(void) {
     assert [int(x) for x in m.split()] == [R.rt_trace_opts.cut.offset,
                                            R.rt_trace_opts.flags.offset,
                                            R.rt_trace_opts.chain_ws.offset,
-                                           R.rt_trace_opts.chain_ws_bytes.offset]
+                                           R.rt_trace_opts.chain_ws_bytes.offset,
+                                           R.rt_trace_opts.batch_order.offset]
+
+
+def test_split_cus_mask_gives_every_xcd_its_share():
+    # an MI355X numbers its 256 CUs either by XCD in blocks of 32 or
+    # interleaved over its 8 XCDs; the small set must hold k / 8 CUs of every
+    # XCD either way (and the large set the rest), so neither stream is ever
+    # left without a CU on some XCD
+    for k in range(8, 129, 8):
+        m = R.rt_split_cus_mask(k)
+        cus = [c for c in range(256) if (int(m[c // 32]) >> (c % 32)) & 1]
+        assert len(cus) == k
+        assert [sum(1 for c in cus if c // 32 == x) for x in range(8)] == [k // 8] * 8
+        assert [sum(1 for c in cus if c % 8 == x) for x in range(8)] == [k // 8] * 8
+    for k in (0, 4, 12, 136, -8):
+        with pytest.raises(R.RtError) as e:
+            R.rt_split_cus_mask(k)
+        assert e.value.code == R.RT_EINVAL
+
+
+def test_batch_order_workspace_size():
+    # ceil(n / 64) batch keys and 16 class counts per tile of 1024 batches
+    assert R.rt_rays_batch_order_ws_bytes(0) == 0
+    assert R.rt_rays_batch_order_ws_bytes(1) == 4 * (1 + 16)
+    assert R.rt_rays_batch_order_ws_bytes(65536) == 4 * (1024 + 16)
+    assert R.rt_rays_batch_order_ws_bytes(65537) == 4 * (1025 + 32)
+    assert R.rt_rays_batch_order_ws_bytes(2621442) == 4 * (40961 + 16 * 41)
+    assert R.rt_rays_batch_order_ws_bytes(-1) == 0
 
 
 def test_chain_workspace_size():
