@@ -280,9 +280,13 @@ def main_step(args):
         if ev is not None:
             ev[1].record(sb)
         st.wait_stream(sb)
+        if ev is not None:
+            ev[3].record(st)
         order = None
         if args.order == "elevation":
             order = R.rt_rays_batch_order(rays, axis=2, order=orders[i], keys=okeys[i], stream=st)
+        if ev is not None:
+            ev[4].record(st)
         if args.cut > 0 or flags or order is not None:
             R.rt_trace_ex(trees[i].handle, rays, nb, *outs[i], cut=args.cut, chain_ws=wss[i],
                           stream=st, flags=flags, batch_order=order)
@@ -292,11 +296,13 @@ def main_step(args):
         if ev is not None:
             ev[2].record(st)
 
+    order_ms = []  # the last timed() call's batch-order times
+
     def timed(p, steps, warmup, d=1, flags=flags):
         for k in range(warmup):
             step(k, p, d, flags=flags)
         torch.cuda.synchronize()
-        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(steps):
@@ -304,7 +310,9 @@ def main_step(args):
         torch.cuda.synchronize()
         total = time.perf_counter() - t0
         build_ms = [e[0].elapsed_time(e[1]) for e in evs]
-        trace_ms = [e[1].elapsed_time(e[2]) for e in evs]
+        # the trace launch on its own stream (after the batch order, which is timed apart)
+        trace_ms = [e[4].elapsed_time(e[2]) for e in evs]
+        order_ms[:] = [e[3].elapsed_time(e[4]) for e in evs]
         step_ms = [e[0].elapsed_time(e[2]) for e in evs]  # one step's latency on the device
         return total, step_ms, build_ms, trace_ms
 
@@ -320,6 +328,7 @@ def main_step(args):
         return st, segs
 
     total, step_lat, build_ms, trace_ms = timed(params, args.steps, args.warmup, depth)
+    main_order_ms = list(order_ms)
     serial = depth > 1 and not args.no_serial
     if serial:
         s_steps = max(5, args.steps // 3)
@@ -383,6 +392,7 @@ def main_step(args):
         "primary_mrays_s": round(n / (total / args.steps) / 1e6, 2),
         "build_ms": round(float(np.mean(build_ms)), 4),
         "trace_ms": round(trace_mean_ms, 4),
+        "batch_order_ms": round(float(np.mean(main_order_ms)), 4),
         "latency_ms_p50": round(float(np.percentile(step_lat, 50)), 4),
         "latency_ms_p99": round(float(np.percentile(step_lat, 99)), 4),
         "tri_tests_per_ray": round(tests_total / segments, 3),
