@@ -7,10 +7,11 @@ trace the launched rays with up to 6 specular bounces (Sec. III-B).  Scene and
 rays are seeded synthetic inputs already resident in HBM.  The value is
 traced segments (primary + every re-launched segment) per second of the timed
 steps, in millions.  Consecutive steps alternate between two trees and output
-sets (--pipeline 2, the default); builds run on a stream holding 48 of the 256
-compute units and traces on one holding the other 208 (rt_streams_split_cus),
-so one transmitter's build runs while the previous transmitter's rays are
-traced, and each step orders its ray batches most horizontal first
+sets (--pipeline 2, the default), so one transmitter's build runs while the
+previous transmitter's rays are traced; on city24k builds run on a stream
+holding 48 of the 256 compute units and traces on one holding the other 208
+(rt_streams_split_cus), on the dense city both share the device (one stream
+per tree).  Each step orders its ray batches most horizontal first
 (rt_rays_batch_order) before tracing them; every step still builds its whole
 tree, orders and traces all its rays.  The serial rate (--pipeline 1: each step
 waits for the previous one, on all compute units) is reported beside it.
@@ -63,6 +64,12 @@ ALU_PEAK_TOPS = VALU_ISSUE_PER_S * 64 / 1e12
 CPU_SHARE = 16
 
 
+# Compute units the pipelined steps give the builds (the traces get the rest),
+# measured per workload: the 24k-facet build fits beside the trace on 48 of
+# 256, while the 200k-facet build needs the whole device (its steps share it).
+BUILD_CUS = {"city24k": 48, "microcell": 0, "dense200k": 0}
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,9 +85,10 @@ def parse():
     ap.add_argument("--cut", type=int, default=0,
                     help="two-launch trace: chains alive after this many segments are traced by a "
                          "second launch in full waves (rt_trace_opts.cut; 0: one launch)")
-    ap.add_argument("--build-cus", type=int, default=48, choices=[0] + list(range(8, 129, 8)),
+    ap.add_argument("--build-cus", type=int, default=None, choices=[0] + list(range(8, 129, 8)),
                     help="pipelined steps: builds on this many compute units, traces on the rest "
-                         "(rt_streams_split_cus); 0: one stream per tree on all of them")
+                         "(rt_streams_split_cus); 0: one stream per tree on all of them; default "
+                         "per workload (BUILD_CUS)")
     ap.add_argument("--order", default="elevation", choices=["elevation", "given"],
                     help="trace batch order: most horizontal batches first (rt_rays_batch_order, "
                          "computed in every step) or the rays' own order")
@@ -254,6 +262,8 @@ def main_step(args):
     trees = [R.BVH(tris, params) for _ in range(depth)]
     bvh = trees[0]
     plain = torch.cuda.Stream()  # default priority, all compute units (serial steps)
+    if args.build_cus is None:
+        args.build_cus = BUILD_CUS.get(args.workload, 0)
     split = R.SplitStreams(args.build_cus) if depth > 1 and args.build_cus > 0 else None
     if split is not None:  # builds on build_cus compute units, traces on the rest
         bstreams, tstreams = [split.small] * depth, [split.large] * depth
