@@ -9,7 +9,7 @@ traced segments (primary + every re-launched segment) per second of the timed
 steps, in millions.  Consecutive steps alternate between two trees and output
 sets (--pipeline 2, the default), so one transmitter's build runs while the
 previous transmitter's rays are traced; on city24k builds run on a stream
-holding 48 of the 256 compute units and traces on one holding the other 208
+holding 32 of the 256 compute units and traces on one holding the other 224
 (rt_streams_split_cus), on the dense city both share the device (one stream
 per tree).  Each step orders its ray batches most horizontal first
 (rt_rays_batch_order) before tracing them; every step still builds its whole
@@ -65,9 +65,9 @@ CPU_SHARE = 16
 
 
 # Compute units the pipelined steps give the builds (the traces get the rest),
-# measured per workload: the 24k-facet build fits beside the trace on 48 of
+# measured per workload: the 24k-facet build fits beside the trace on 32 of
 # 256, while the 200k-facet build needs the whole device (its steps share it).
-BUILD_CUS = {"city24k": 48, "microcell": 0, "dense200k": 0}
+BUILD_CUS = {"city24k": 32, "microcell": 0, "dense200k": 0}
 
 
 def parse():

@@ -1313,7 +1313,16 @@ __device__ int wave_split_global(const Ctx& X, int id, const Bins& S, int& kc0, 
 // node (more than kRegNode facets) is filed under its first facet, so a
 // window holds at most one.
 constexpr int kMWindow = kRegNode + 1;
-constexpr int kWaveThreads = 256;  // four independent waves per work-group
+// The wave kernels (k_m, k_s) serve up to four independent waves per
+// work-group, each in its own LDS slice, and are launched with one: a wave
+// that finishes frees its slot and LDS at once instead of waiting for its
+// neighbours, which keeps the few compute units of a build that runs beside
+// a trace busy.  The slice is found from the lane's own wave index, so the
+// compiler sees the child-bound accumulators at lane-dependent LDS
+// addresses and keeps their min / max as single LDS atomics (with a uniform
+// address it expands each into a loop over the active lanes, which doubled
+// the build time).
+constexpr int kWaveThreads = 256;
 __global__ __launch_bounds__(kWaveThreads) void k_m(Ctx X, int pass) {
   extern __shared__ __align__(16) char lds[];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -2059,12 +2068,10 @@ int build_tree(Buffers& B, const float* tris, int64_t n64, const rt_split_params
   // one wave per window of facet positions
   const int m_windows = (n + kMWindow - 1) / kMWindow;
   for (int m = 0; m < lm; ++m)
-    hipLaunchKernelGGL(k_m, dim3((m_windows + 3) / 4), dim3(256), 4 * bins_bytes(Bn, true), s, X, m);
-  const int s_waves = (int)std::max<size_t>(1, std::min<size_t>(4, (60 * 1024) / s_wave_bytes(Bn)));
+    hipLaunchKernelGGL(k_m, dim3(m_windows), dim3(64), bins_bytes(Bn, true), s, X, m);
   const int s_win = std::min(64, 2 * (p.max_leaf + 1));
   const int s_windows = (n + s_win - 1) / s_win;
-  hipLaunchKernelGGL(k_s, dim3((s_windows + s_waves - 1) / s_waves), dim3(64 * s_waves),
-                     s_waves * s_wave_bytes(Bn), s, X);
+  hipLaunchKernelGGL(k_s, dim3(s_windows), dim3(64), s_wave_bytes(Bn), s, X);
   // compaction and traversal data
   const int nb = std::max(n - 1, 0);  // split boundaries
   const int nblk = std::max(1, (nb + kScanBlock - 1) / kScanBlock);
