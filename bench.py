@@ -13,8 +13,11 @@ holding 32 of the 256 compute units and traces on one holding the other 224
 (rt_streams_split_cus), on the dense city both share the device (one stream
 per tree).  Each step orders its ray batches most horizontal first
 (rt_rays_batch_order) before tracing them; every step still builds its whole
-tree, orders and traces all its rays.  The serial rate (--pipeline 1: each step
-waits for the previous one, on all compute units) is reported beside it.
+tree, orders and traces all its rays.  The trees' traversal nodes are 4-wide
+float32 on city24k and binary float32 on the dense city (NODE_FORMAT); the rate
+of the same step with each node format is reported beside it, and so is the
+serial rate (--pipeline 1: each step waits for the previous one, on all compute
+units).
 
 Prints one JSON line.  Extra fields: the trace kernel's roofline (vector
 instruction issue, from the committed SQ counters of the current kernel
@@ -47,7 +50,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "closest-hit Mrays/s (24k-tri scene, ≤6 bounces); tri tests/ray; p50/p99 latency"
 TRACE_SRC = os.path.join(ROOT, "paper_2208_10008_amd", "csrc", "rt_trace.hip")
-NODE_BYTES = 64      # binary node: both child boxes + references
+# bytes of one node visit: binary nodes hold both child boxes and references,
+# 4-wide float32 nodes four boxes, 8-bit nodes four quantised boxes
+NODE_BYTES = {"bin2": 64, "f4": 128, "q4": 64}
+CHILDREN = {"bin2": 2, "f4": 4, "q4": 4}  # child boxes tested per node visit
 FACET_BYTES = 36     # three float32 vertices
 RAY_BYTES = 32
 HIT_BYTES = 16
@@ -68,6 +74,11 @@ CPU_SHARE = 16
 # measured per workload: the 24k-facet build fits beside the trace on 32 of
 # 256, while the 200k-facet build needs the whole device (its steps share it).
 BUILD_CUS = {"city24k": 32, "microcell": 0, "dense200k": 0}
+# Traversal nodes of the benchmark's trees, measured per workload in the
+# pipelined step: on the 24k-facet city the 4-wide nodes' shorter traversal
+# pays for their longer build; the 200k-facet tree exceeds an XCD's L2, where
+# binary nodes trace fastest.
+NODE_FORMAT = {"city24k": "f4", "microcell": "bin2", "dense200k": "bin2"}
 
 
 def parse():
@@ -79,7 +90,10 @@ def parse():
     ap.add_argument("--workload", default="city24k", choices=["city24k", "microcell", "dense200k"])
     ap.add_argument("--alpha", type=float, default=0.4)
     ap.add_argument("--max-leaf", type=int, default=4)
-    ap.add_argument("--node-format", default="bin2", choices=["bin2", "f4", "q4"])
+    ap.add_argument("--node-format", default=None, choices=["bin2", "f4", "q4"],
+                    help="traversal nodes of the benchmark's trees: binary float32, 4-wide float32 "
+                         "or 4-wide 8-bit; default per workload (NODE_FORMAT); every format is "
+                         "also timed beside it")
     ap.add_argument("--pipeline", type=int, default=2, choices=[1, 2],
                     help="trees / streams that consecutive steps alternate between")
     ap.add_argument("--cut", type=int, default=0,
@@ -124,43 +138,47 @@ def kernel_source_hash():
     return source_sha1(TRACE_SRC)
 
 
-def _profile_record(name, workload_name):
+def _profile_record(name, workload_name, node_format):
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("kernel_source_sha1") != kernel_source_hash() or rec.get("workload") != workload_name:
+    if (rec.get("kernel_source_sha1") != kernel_source_hash() or rec.get("workload") != workload_name
+            or rec.get("node_format", "bin2") != node_format):
         return None
     return rec
 
 
-def load_traffic(workload_name):
+def load_traffic(workload_name, node_format):
     """HBM bytes per trace launch from committed counter runs, if they were
-    taken on the current kernel source."""
-    rec = _profile_record("trace_traffic.json", workload_name)
+    taken on the current kernel source with this node format."""
+    rec = _profile_record("trace_traffic.json", workload_name, node_format)
     return None if rec is None else rec.get("hbm_bytes_per_launch")
 
 
-def load_sq(workload_name):
-    """Vector instructions per trace launch (binary nodes, the benchmark's
-    tree) from a committed SQ counter run on the current kernel source."""
-    rec = _profile_record("trace_sq_counters.json", workload_name)
+def load_sq(workload_name, node_format):
+    """Vector instructions per trace launch (the benchmark's launch: its tree
+    and node format) from a committed SQ counter run on the current kernel
+    source."""
+    rec = _profile_record("trace_sq_counters.json", workload_name, node_format)
     if rec is None:
         return None
     g = rec["groups"][0]
     return {"valu_wave_instr": g["SQ_INSTS_VALU"], "vmem_rd_wave_instr": g["SQ_INSTS_VMEM_RD"]}
 
 
-def roofline(trace_ms, segments, nodes_total, tests_total, sq, traffic, ceilings):
+def roofline(trace_ms, segments, nodes_total, tests_total, sq, traffic, ceilings, node_format):
     """The trace kernel's roofline.  The bound is vector instruction issue: the
     kernel's VALU wave-instructions per launch (SQ counters) over its measured
     time against the chip's non-packed issue rate, in lane operations.  The
-    algorithmic operations and bytes (per segment: ray and hit record, 64 B
-    per node visited, 36 B per facet tested) are reported beside it."""
+    algorithmic operations and bytes (per segment: ray and hit record, the
+    node bytes per node visited, 36 B per facet tested) are reported beside
+    it."""
     sec = trace_ms * 1e-3
-    alg_bytes = segments * (RAY_BYTES + HIT_BYTES) + nodes_total * NODE_BYTES + tests_total * FACET_BYTES
-    alg_ops = nodes_total * 2 * OPS_PER_CHILD_TEST + tests_total * OPS_PER_FACET_TEST
+    alg_bytes = (segments * (RAY_BYTES + HIT_BYTES) + nodes_total * NODE_BYTES[node_format]
+                 + tests_total * FACET_BYTES)
+    alg_ops = nodes_total * CHILDREN[node_format] * OPS_PER_CHILD_TEST + tests_total * OPS_PER_FACET_TEST
     alg_gbs = alg_bytes / sec / 1e9
     r = {"bound": "alu", "achieved": None, "peak": round(ALU_PEAK_TOPS, 2),
          "unit": "TOP/s (VALU lane operations, packed FP32 off)", "frac": None,
@@ -248,6 +266,8 @@ def main_step(args):
     torch.cuda.set_device(0)
     w = {"city24k": workloads.city24k, "microcell": workloads.microcell,
          "dense200k": workloads.dense200k}[args.workload]()
+    if args.node_format is None:
+        args.node_format = NODE_FORMAT.get(args.workload, "bin2")
     params = R.SplitParams(alpha=args.alpha, src=w.tx, max_leaf=args.max_leaf,
                            node_format=args.node_format)
     nb = w.max_bounces
@@ -396,7 +416,8 @@ def main_step(args):
             "miss_rows": "padded" if args.pad else "left (RT_TRACE_NO_PAD; n_hits ends each chain)",
         },
         "roofline": roofline(trace_mean_ms, segments, nodes_total, tests_total,
-                             load_sq(w.name), load_traffic(w.name), ceilings),
+                             load_sq(w.name, args.node_format), load_traffic(w.name, args.node_format),
+                             ceilings, args.node_format),
         "segments_per_step": segments,
         "trace_only_mrays_s": round(segments / (trace_mean_ms * 1e-3) / 1e6, 2),
         "primary_mrays_s": round(n / (total / args.steps) / 1e6, 2),
@@ -429,12 +450,16 @@ def main_step(args):
             }
 
     if not args.no_compare:
-        fmts = {}
+        fmts, piped = {}, {}
         for fmt in ("bin2", "f4", "q4"):
             pf = R.SplitParams(alpha=args.alpha, src=w.tx, max_leaf=args.max_leaf, node_format=fmt)
             _, _, _, f_trace = timed(pf, 10, 2)
             fmts[fmt] = round(float(np.mean(f_trace)), 4)
+            # the benchmark's step (pipelined, same streams) with this format's trees
+            f_tot, _, _, _ = timed(pf, args.steps, args.warmup, depth)
+            piped[fmt] = round(segments / (f_tot / args.steps) / 1e6, 2)
         result["trace_ms_by_node_format"] = fmts
+        result["mrays_s_by_node_format"] = piped
         reps = max(5, args.steps // 3)
         trad = R.SplitParams(alpha=1.0, src=w.tx, max_leaf=args.max_leaf, node_format=args.node_format)
         t_tot, _, t_build, t_trace = timed(trad, reps, 1)

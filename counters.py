@@ -147,10 +147,13 @@ def main():
     a2.add_argument("--runs", default="", help="comma-separated dispatch counts of the runs, in order")
     for p in (a1, a2):
         p.add_argument("--workload", required=True)
+        p.add_argument("--node-format", default="bin2", choices=["bin2", "f4", "q4"],
+                       help="node format of the benchmark's launch (the record's first run)")
         p.add_argument("--command", default="")
         p.add_argument("--out", required=True)
     a = ap.parse_args()
-    head = {"workload": a.workload, "kernel": "k_trace", "kernel_source_sha1": source_sha1(),
+    head = {"workload": a.workload, "node_format": a.node_format, "kernel": "k_trace",
+            "kernel_source_sha1": source_sha1(),
             "command": a.command}
     if a.what == "traffic":
         rec = {**head, **trace_traffic(a.fetch, a.write, a.copy_mib)}

@@ -1877,73 +1877,83 @@ __device__ inline unsigned quant_hi(float v, float lo, float sc) {
   return (unsigned)q;
 }
 
+// Four lanes per binary node: lane c of a node's group gathers child slot c
+// of the wide node (and, for 8-bit nodes, encodes that child's six planes)
+// and stores its own parts of the record, so a lane encodes one child
+// instead of four and the launch has four times the waves (one lane per node
+// left most of the device idle behind long serial encodings).
 template <int FMT>
-__global__ void k_collapse(const BNode* __restrict__ nodes, const BuildState* __restrict__ st,
-                           FNode4* __restrict__ wn) {
-  const int id = blockIdx.x * blockDim.x + threadIdx.x;
-  if (st->error || id >= min(st->total, 2 * st->n - 1)) return;
-  const BNode nd = nodes[id];
-  const bool root_leaf = id == 0 && nd.left < 0;
-  if (!root_leaf && (nd.left < 0 || (nd.depth & 1))) return;
-  // gather up to four children
-  BNode ch[4];
-  int nc = 0;
+__global__ __launch_bounds__(256) void k_collapse(const BNode* __restrict__ nodes,
+                                                  const BuildState* __restrict__ st,
+                                                  FNode4* __restrict__ wn) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = (int)(gid & 3);
+  if (st->error || gid >> 2 >= min(st->total, 2 * st->n - 1)) return;
+  const int id = (int)(gid >> 2);
+  const BNode& nd = nodes[id];
+  const int left = nd.left;
+  const bool root_leaf = id == 0 && left < 0;
+  if (!root_leaf && (left < 0 || (nd.depth & 1))) return;
+  // the slots: each side's child if it is a leaf, else that child's two
+  // children, side 0 first
+  int src = -1, nc = 1;
   if (root_leaf) {
-    ch[nc++] = nd;
+    src = c == 0 ? id : -1;
   } else {
-    for (int side = 0; side < 2; ++side) {
-      const BNode c = nodes[nd.left + side];
-      if (c.left < 0) {
-        ch[nc++] = c;
-      } else {
-        ch[nc++] = nodes[c.left];
-        ch[nc++] = nodes[c.left + 1];
-      }
-    }
+    const int la = nodes[left].left, lb = nodes[left + 1].left;
+    const int na = la < 0 ? 1 : 2;
+    nc = na + (lb < 0 ? 1 : 2);
+    if (c < na)
+      src = la < 0 ? left : la + c;
+    else if (c < nc)
+      src = lb < 0 ? left + 1 : lb + (c - na);
   }
-  int ref[4] = {0, 0, 0, 0};
-  for (int c = 0; c < nc; ++c) ref[c] = ch[c].left < 0 ? ~ch[c].first : pair_index(ch[c]);
   const unsigned mask = (1u << nc) - 1u;
   const int slot = root_leaf ? 0 : pair_index(nd);
+  float lo[3], hi[3];
+  int ref = 0;
+  if (src >= 0) {
+    const BNode& ch = nodes[src];
+    ref = ch.left < 0 ? ~ch.first : pair_index(ch);
+    for (int q = 0; q < 3; ++q) {
+      lo[q] = ch.lo[q];
+      hi[q] = ch.hi[q];
+    }
+  }
   if (FMT == RT_NODE_F4) {
-    FNode4 o;
-    float v[6][4];
-    for (int c = 0; c < 4; ++c)
-      for (int q = 0; q < 3; ++q) {
-        // unused slots: lo = hi = +inf (never entered; also masked out)
-        v[2 * q][c] = c < nc ? ch[c].lo[q] : INFINITY;
-        v[2 * q + 1][c] = c < nc ? ch[c].hi[q] : INFINITY;
-      }
-    o.lox = make_float4(v[0][0], v[0][1], v[0][2], v[0][3]);
-    o.hix = make_float4(v[1][0], v[1][1], v[1][2], v[1][3]);
-    o.loy = make_float4(v[2][0], v[2][1], v[2][2], v[2][3]);
-    o.hiy = make_float4(v[3][0], v[3][1], v[3][2], v[3][3]);
-    o.loz = make_float4(v[4][0], v[4][1], v[4][2], v[4][3]);
-    o.hiz = make_float4(v[5][0], v[5][1], v[5][2], v[5][3]);
-    o.ref = make_int4(ref[0], ref[1], ref[2], ref[3]);
-    o.meta = make_uint4(mask, 0u, 0u, 0u);
-    wn[slot] = o;
+    // words: lox, hix, loy, hiy, loz, hiz (component c = slot c), ref, meta
+    uint32_t* w = reinterpret_cast<uint32_t*>(wn + slot);
+    for (int q = 0; q < 3; ++q) {
+      // unused slots: lo = hi = +inf (never entered; also masked out)
+      w[8 * q + c] = __float_as_uint(src >= 0 ? lo[q] : INFINITY);
+      w[8 * q + 4 + c] = __float_as_uint(src >= 0 ? hi[q] : INFINITY);
+    }
+    w[24 + c] = (uint32_t)ref;
+    w[28 + c] = c == 0 ? mask : 0u;
   } else {
-    QNode4 o;
+    // words: origin xyz and meta, then byte c of words 4-6 (qlo xyz) and 7-9
+    // (qhi xyz) for slot c, two zero words, ref
+    QNode4* o = reinterpret_cast<QNode4*>(wn) + slot;
+    uint32_t* w = reinterpret_cast<uint32_t*>(o);
+    unsigned char* b = reinterpret_cast<unsigned char*>(o);
     int e[3];
-    float sc[3];
     for (int q = 0; q < 3; ++q) {
       e[q] = quant_exp(nd.lo[q], nd.hi[q]);
-      sc[q] = pow2f(e[q]);
+      const float sc = pow2f(e[q]);
+      b[4 * (4 + q) + c] = (unsigned char)(src >= 0 ? quant_lo(lo[q], nd.lo[q], sc) : 0u);
+      b[4 * (7 + q) + c] = (unsigned char)(src >= 0 ? quant_hi(hi[q], nd.lo[q], sc) : 0u);
     }
-    unsigned ql[3] = {0u, 0u, 0u}, qh[3] = {0u, 0u, 0u};
-    for (int c = 0; c < nc; ++c)
-      for (int q = 0; q < 3; ++q) {
-        ql[q] |= quant_lo(ch[c].lo[q], nd.lo[q], sc[q]) << (8 * c);
-        qh[q] |= quant_hi(ch[c].hi[q], nd.lo[q], sc[q]) << (8 * c);
-      }
-    const unsigned meta = (unsigned)(e[0] + 127) | ((unsigned)(e[1] + 127) << 8) |
-                          ((unsigned)(e[2] + 127) << 16) | (mask << 24);
-    o.h = make_float4(nd.lo[0], nd.lo[1], nd.lo[2], __uint_as_float(meta));
-    o.qa = make_uint4(ql[0], ql[1], ql[2], qh[0]);
-    o.qb = make_uint4(qh[1], qh[2], 0u, 0u);
-    o.ref = make_int4(ref[0], ref[1], ref[2], ref[3]);
-    reinterpret_cast<QNode4*>(wn)[slot] = o;
+    w[12 + c] = (uint32_t)ref;
+    if (c == 0) {
+      const unsigned meta = (unsigned)(e[0] + 127) | ((unsigned)(e[1] + 127) << 8) |
+                            ((unsigned)(e[2] + 127) << 16) | (mask << 24);
+      w[0] = __float_as_uint(nd.lo[0]);
+      w[1] = __float_as_uint(nd.lo[1]);
+      w[2] = __float_as_uint(nd.lo[2]);
+      w[3] = meta;
+    } else if (c >= 2) {
+      w[8 + c] = 0u;  // words 10 and 11
+    }
   }
 }
 
@@ -2082,13 +2092,12 @@ int build_tree(Buffers& B, const float* tris, int64_t n64, const rt_split_params
   const int eb = 256;
   hipLaunchKernelGGL(k_emit, dim3((n + eb - 1) / eb), dim3(eb), 0, s, B.nodes, st, B.used, B.rank,
                      B.perm, tris, B.cnodes, B.tnodes, B.tfacets);
-  const int max_nodes = std::max(1, 2 * n - 1);
+  const int64_t max_nodes = std::max(1, 2 * n - 1);
+  const dim3 cgrid((unsigned)((4 * max_nodes + eb - 1) / eb));  // four lanes per node
   if (p.node_format == RT_NODE_F4)
-    hipLaunchKernelGGL(k_collapse<RT_NODE_F4>, dim3((max_nodes + eb - 1) / eb), dim3(eb), 0, s,
-                       B.cnodes, st, B.wnodes);
+    hipLaunchKernelGGL(k_collapse<RT_NODE_F4>, cgrid, dim3(eb), 0, s, B.cnodes, st, B.wnodes);
   else if (p.node_format == RT_NODE_Q4)
-    hipLaunchKernelGGL(k_collapse<RT_NODE_Q4>, dim3((max_nodes + eb - 1) / eb), dim3(eb), 0, s,
-                       B.cnodes, st, B.wnodes);
+    hipLaunchKernelGGL(k_collapse<RT_NODE_Q4>, cgrid, dim3(eb), 0, s, B.cnodes, st, B.wnodes);
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, st, B.root_box, B.cnodes, rec.dev, seq);
   HIPCHECK(hipGetLastError());
   {

@@ -88,18 +88,34 @@ def test_bench_reads_records_only_for_the_current_source(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     os.makedirs(tmp_path / "profiles")
     sha = bench.kernel_source_hash()
-    rec = {"workload": "w", "kernel_source_sha1": sha, "hbm_bytes_per_launch": 123,
-           "groups": [{"SQ_INSTS_VALU": 7.0, "SQ_INSTS_VMEM_RD": 3.0}]}
+    rec = {"workload": "w", "node_format": "f4", "kernel_source_sha1": sha,
+           "hbm_bytes_per_launch": 123, "groups": [{"SQ_INSTS_VALU": 7.0, "SQ_INSTS_VMEM_RD": 3.0}]}
     for name in ("trace_traffic.json", "trace_sq_counters.json"):
         with open(tmp_path / "profiles" / name, "w") as f:
             json.dump(rec, f)
-    assert bench.load_traffic("w") == 123
-    assert bench.load_sq("w") == {"valu_wave_instr": 7.0, "vmem_rd_wave_instr": 3.0}
-    assert bench.load_traffic("other") is None
+    assert bench.load_traffic("w", "f4") == 123
+    assert bench.load_sq("w", "f4") == {"valu_wave_instr": 7.0, "vmem_rd_wave_instr": 3.0}
+    assert bench.load_traffic("other", "f4") is None
+    # a record of another node format's launch is not this launch's
+    assert bench.load_sq("w", "bin2") is None and bench.load_traffic("w", "q4") is None
     rec["kernel_source_sha1"] = "0" * 12
     with open(tmp_path / "profiles" / "trace_traffic.json", "w") as f:
         json.dump(rec, f)
-    assert bench.load_traffic("w") is None
+    assert bench.load_traffic("w", "f4") is None
+
+
+def test_roofline_prices_node_visits_by_format():
+    import bench
+    # per segment: ray + hit 48 B; a binary visit reads 64 B and tests two
+    # boxes, a 4-wide visit 128 B (float32) or 64 B (8-bit) and four boxes
+    kw = dict(trace_ms=1.0, segments=10, nodes_total=100, tests_total=20, sq=None, traffic=None,
+              ceilings=None)
+    alg = {f: bench.roofline(**kw, node_format=f)["algorithmic"] for f in ("bin2", "f4", "q4")}
+    assert alg["bin2"]["bytes_per_launch"] == 10 * 48 + 100 * 64 + 20 * 36
+    assert alg["f4"]["bytes_per_launch"] == 10 * 48 + 100 * 128 + 20 * 36
+    assert alg["q4"]["bytes_per_launch"] == alg["bin2"]["bytes_per_launch"]
+    assert alg["bin2"]["ops_per_launch"] == 100 * 2 * 18 + 20 * 45
+    assert alg["f4"]["ops_per_launch"] == alg["q4"]["ops_per_launch"] == 100 * 4 * 18 + 20 * 45
 
 
 def test_bench_refuses_more_than_one_gpu():
