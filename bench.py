@@ -8,16 +8,15 @@ rays are seeded synthetic inputs already resident in HBM.  The value is
 traced segments (primary + every re-launched segment) per second of the timed
 steps, in millions.  Consecutive steps alternate between two trees and output
 sets (--pipeline 2, the default), so one transmitter's build runs while the
-previous transmitter's rays are traced; on city24k builds run on a stream
-holding 32 of the 256 compute units and traces on one holding the other 224
-(rt_streams_split_cus), on the dense city both share the device (one stream
-per tree).  Each step orders its ray batches most horizontal first
-(rt_rays_batch_order) before tracing them; every step still builds its whole
-tree, orders and traces all its rays.  The trees' traversal nodes are 4-wide
-float32 on city24k and binary float32 on the dense city (NODE_FORMAT); the rate
-of the same step with each node format is reported beside it, and so is the
-serial rate (--pipeline 1: each step waits for the previous one, on all compute
-units).
+previous transmitter's rays are traced; builds run on a stream holding some
+of the 256 compute units (32 on city24k, 64 on the dense city) and traces on
+one holding the rest (rt_streams_split_cus).  Each step orders its ray
+batches most horizontal first (rt_rays_batch_order) before tracing them;
+every step still builds its whole tree, orders and traces all its rays.  The
+trees' traversal nodes are 4-wide float32 on city24k and binary float32 on the
+dense city (NODE_FORMAT); the rate of the same step with each node format is
+reported beside it, and so is the serial rate (--pipeline 1: each step waits
+for the previous one, on all compute units).
 
 Prints one JSON line.  Extra fields: the trace kernel's roofline (vector
 instruction issue, from the committed SQ counters of the current kernel
@@ -72,8 +71,8 @@ CPU_SHARE = 16
 
 # Compute units the pipelined steps give the builds (the traces get the rest),
 # measured per workload: the 24k-facet build fits beside the trace on 32 of
-# 256, while the 200k-facet build needs the whole device (its steps share it).
-BUILD_CUS = {"city24k": 32, "microcell": 0, "dense200k": 0}
+# 256, the 200k-facet build on 64.
+BUILD_CUS = {"city24k": 32, "microcell": 0, "dense200k": 64}
 # Traversal nodes of the benchmark's trees, measured per workload in the
 # pipelined step: on the 24k-facet city the 4-wide nodes' shorter traversal
 # pays for their longer build; the 200k-facet tree exceeds an XCD's L2, where
