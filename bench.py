@@ -13,6 +13,9 @@ of the 256 compute units (32 on city24k, 64 on the dense city) and traces on
 one holding the rest (rt_streams_split_cus).  Each step orders its ray
 batches most horizontal first (rt_rays_batch_order) before tracing them;
 every step still builds its whole tree, orders and traces all its rays.  The
+value comes from a pass of the timed steps that records no events among them;
+a second pass of the same steps with HIP events around each stage gives the
+kernel, build and batch-order times and the step latency.  The
 trees' traversal nodes are 4-wide float32 on city24k and binary float32 on the
 dense city (NODE_FORMAT); the rate of the same step with each node format is
 reported beside it, and so is the serial rate (--pipeline 1: each step waits
@@ -327,17 +330,25 @@ def main_step(args):
 
     order_ms = []  # the last timed() call's batch-order times
 
-    def timed(p, steps, warmup, d=1, flags=flags):
+    def timed(p, steps, warmup, d=1, flags=flags, events=True):
+        """Wall time of `steps` steps after `warmup` untimed ones; with
+        events, HIP events around each step's build, batch order and trace
+        give their times and the step's latency.  events=False records none
+        inside the timed region (each event is a barrier packet on its
+        stream, about 1-3 % of a step): the rates come from such passes."""
         for k in range(warmup):
             step(k, p, d, flags=flags)
         torch.cuda.synchronize()
-        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)] \
+            if events else None
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(steps):
-            step(k, p, d, evs[k], flags=flags)
+            step(k, p, d, evs[k] if events else None, flags=flags)
         torch.cuda.synchronize()
         total = time.perf_counter() - t0
+        if not events:
+            return total, None, None, None
         build_ms = [e[0].elapsed_time(e[1]) for e in evs]
         # the trace launch on its own stream (after the batch order, which is timed apart)
         trace_ms = [e[4].elapsed_time(e[2]) for e in evs]
@@ -356,14 +367,19 @@ def main_step(args):
         segs = int(np.minimum(n_hits.cpu().numpy() + 1, nb).sum())
         return st, segs
 
-    total, step_lat, build_ms, trace_ms = timed(params, args.steps, args.warmup, depth)
+    # the value: the timed steps with no events among them; then the same
+    # steps with events (kernel, build and order times, step latency)
+    total, _, _, _ = timed(params, args.steps, args.warmup, depth, events=False)
+    _, step_lat, build_ms, trace_ms = timed(params, args.steps, args.warmup, depth)
     main_order_ms = list(order_ms)
     serial = depth > 1 and not args.no_serial
     if serial:
         s_steps = max(5, args.steps // 3)
-        s_tot, _, s_build, s_trace = timed(params, s_steps, 1, 1)
+        s_tot, _, _, _ = timed(params, s_steps, 1, 1, events=False)
+        _, _, s_build, s_trace = timed(params, s_steps, 1, 1)
         if flags:
-            p_tot, _, p_build, p_trace = timed(params, args.steps, 1, depth, flags=0)
+            p_tot, _, _, _ = timed(params, args.steps, 1, depth, flags=0, events=False)
+            _, _, p_build, p_trace = timed(params, args.steps, 1, depth, flags=0)
     nh = n_hits.cpu().numpy()
     segments = int(np.minimum(nh + 1, nb).sum())
     ms_per_step = 1e3 * total / args.steps
@@ -455,7 +471,7 @@ def main_step(args):
             _, _, _, f_trace = timed(pf, 10, 2)
             fmts[fmt] = round(float(np.mean(f_trace)), 4)
             # the benchmark's step (pipelined, same streams) with this format's trees
-            f_tot, _, _, _ = timed(pf, args.steps, args.warmup, depth)
+            f_tot, _, _, _ = timed(pf, args.steps, args.warmup, depth, events=False)
             piped[fmt] = round(segments / (f_tot / args.steps) / 1e6, 2)
         result["trace_ms_by_node_format"] = fmts
         result["mrays_s_by_node_format"] = piped
