@@ -13,7 +13,9 @@ of the 256 compute units (32 on city24k, 64 on the dense city) and traces on
 one holding the rest (rt_streams_split_cus).  Each step orders its ray
 batches most horizontal first (rt_rays_batch_order) before tracing them;
 every step still builds its whole tree, orders and traces all its rays.  The
-value comes from a pass of the timed steps that records no events among them;
+pipelined builds are queued with rt_rebuild_async, the next one before the host
+waits (rt_bvh_wait) for the current one, so the build stream does not wait for
+the host between builds.  The value comes from a pass of the timed steps that records no events among them;
 a second pass of the same steps with HIP events around each stage gives the
 kernel, build and batch-order times and the step latency.  The
 trees' traversal nodes are 4-wide float32 on city24k and binary float32 on the
@@ -300,18 +302,33 @@ def main_step(args):
 
     flags = 0 if args.pad else R.RT_TRACE_NO_PAD
 
-    def step(k, p, d, ev=None, flags=flags):
-        """Step k on tree and outputs k mod d: rebuild, order the ray batches,
-        trace."""
+    built = [torch.cuda.Event() for _ in range(depth)]  # tree i's last queued build has ended
+
+    def queue_build(k, p, d, ev=None):
+        """Step k's build, tree k mod d, queued without waiting for it (the
+        host reads its record in finish_step)."""
         i = k % d
-        sb, st = (plain, plain) if d == 1 else (bstreams[i], tstreams[i])
+        sb = bstreams[i]
         sb.wait_event(done[i])  # the tree's previous trace has finished
         if ev is not None:
             ev[0].record(sb)
-        R.rt_rebuild(trees[i].handle, tris, p, stream=sb)
+        R.rt_rebuild_async(trees[i].handle, tris, p, stream=sb)
         if ev is not None:
             ev[1].record(sb)
-        st.wait_stream(sb)
+        built[i].record(sb)
+
+    def finish_step(k, p, d, ev=None, flags=flags):
+        """Step k after its build: order the ray batches (they need the rays
+        only), wait for the build's record, trace once the build has ended.
+        With one tree (d = 1) the build is synchronous, on the same stream."""
+        i = k % d
+        sb, st = (plain, plain) if d == 1 else (bstreams[i], tstreams[i])
+        if d == 1:
+            if ev is not None:
+                ev[0].record(sb)
+            R.rt_rebuild(trees[i].handle, tris, p, stream=sb)
+            if ev is not None:
+                ev[1].record(sb)
         if ev is not None:
             ev[3].record(st)
         order = None
@@ -319,6 +336,11 @@ def main_step(args):
             order = R.rt_rays_batch_order(rays, axis=2, order=orders[i], keys=okeys[i], stream=st)
         if ev is not None:
             ev[4].record(st)
+        if d > 1:
+            R.rt_bvh_wait(trees[i].handle)
+            st.wait_event(built[i])
+        if ev is not None:
+            ev[5].record(st)
         if args.cut > 0 or flags or order is not None:
             R.rt_trace_ex(trees[i].handle, rays, nb, *outs[i], cut=args.cut, chain_ws=wss[i],
                           stream=st, flags=flags, batch_order=order)
@@ -328,6 +350,17 @@ def main_step(args):
         if ev is not None:
             ev[2].record(st)
 
+    def run_steps(steps, p, d, evs=None, flags=flags):
+        """Steps 0 .. steps - 1.  Pipelined (d > 1): step k + 1's build is
+        queued before the host waits for step k's, so the build stream goes
+        from one build to the next without waiting for the host."""
+        if d > 1 and steps > 0:
+            queue_build(0, p, d, evs[0] if evs else None)
+        for k in range(steps):
+            if d > 1 and k + 1 < steps:
+                queue_build(k + 1, p, d, evs[k + 1] if evs else None)
+            finish_step(k, p, d, evs[k] if evs else None, flags=flags)
+
     order_ms = []  # the last timed() call's batch-order times
 
     def timed(p, steps, warmup, d=1, flags=flags, events=True):
@@ -336,22 +369,20 @@ def main_step(args):
         give their times and the step's latency.  events=False records none
         inside the timed region (each event is a barrier packet on its
         stream, about 1-3 % of a step): the rates come from such passes."""
-        for k in range(warmup):
-            step(k, p, d, flags=flags)
+        run_steps(warmup, p, d, flags=flags)
         torch.cuda.synchronize()
-        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)] \
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(steps)] \
             if events else None
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for k in range(steps):
-            step(k, p, d, evs[k] if events else None, flags=flags)
+        run_steps(steps, p, d, evs, flags=flags)
         torch.cuda.synchronize()
         total = time.perf_counter() - t0
         if not events:
             return total, None, None, None
         build_ms = [e[0].elapsed_time(e[1]) for e in evs]
-        # the trace launch on its own stream (after the batch order, which is timed apart)
-        trace_ms = [e[4].elapsed_time(e[2]) for e in evs]
+        # the trace launch on its own stream, from the end of its wait for the build
+        trace_ms = [e[5].elapsed_time(e[2]) for e in evs]
         order_ms[:] = [e[3].elapsed_time(e[4]) for e in evs]
         step_ms = [e[0].elapsed_time(e[2]) for e in evs]  # one step's latency on the device
         return total, step_ms, build_ms, trace_ms
@@ -421,7 +452,8 @@ def main_step(args):
             "workload": w.name, "tris": w.n_tris, "rays": n, "max_bounces": nb,
             "tx": list(w.tx), "alpha": args.alpha, "max_leaf": args.max_leaf,
             "node_format": args.node_format,
-            "step": "rt_rebuild (Eq. 2 BVH for this Tx) + " + (
+            "step": ("rt_rebuild_async + rt_bvh_wait" if depth > 1 else "rt_rebuild")
+                    + " (Eq. 2 BVH for this Tx) + " + (
                 "rt_rays_batch_order + " if args.order == "elevation" else "") + (
                 f"rt_trace_ex (two launches, cut {args.cut})" if args.cut > 0 else
                 "rt_trace_ex (one launch)" if flags or args.order == "elevation" else "rt_trace_bounces"),
@@ -491,7 +523,7 @@ def main_step(args):
         }
         if not args.no_sweep:
             result["split_sweep"] = split_sweep(R, w, args, timed, launch_counts, bvh)
-        step(0, params, 1)  # leave the improved tree in place
+        finish_step(0, params, 1)  # leave the improved tree in place
         torch.cuda.synchronize()
 
     if split is not None:

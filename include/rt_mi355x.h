@@ -160,6 +160,28 @@ int rt_build(const float* tris, int64_t n, const rt_split_params* p, rt_bvh** ou
 int rt_rebuild(rt_bvh* b, const float* tris, int64_t n, const rt_split_params* p,
                hipStream_t s);
 
+/* The same build as rt_rebuild (Sec. II-B, II-C), queued on stream s without
+ * waiting for it: returns once its kernels are queued, so the host can queue
+ * other work (another handle's trace, the next handle's build) while it runs.
+ * The handle is unusable (every call that reads the tree returns RT_EINVAL,
+ * rt_bvh_info_get reports n_tris = 0) until rt_bvh_wait(b) has read the
+ * build's record; errors found on the device (a non-finite vertex, a capacity
+ * check) are returned by rt_bvh_wait.  Work queued on other streams that uses
+ * the tree must wait for s (an event recorded on s after this call).  tris
+ * must stay valid until the build has run.  rt_rebuild, rt_rebuild_async and
+ * rt_bvh_destroy on a handle with a build in flight end that build first.
+ * Errors returned at once: RT_EINVAL (as rt_rebuild's arguments), RT_ENOMEM,
+ * RT_EHIP; the handle is then unusable until rebuilt. */
+int rt_rebuild_async(rt_bvh* b, const float* tris, int64_t n, const rt_split_params* p,
+                     hipStream_t s);
+
+/* Waits for the build rt_rebuild_async queued on b (host spin on the build's
+ * record, then a synchronisation of its stream if the record is late) and
+ * makes the tree usable.  RT_OK at once if no build is in flight.  Errors:
+ * RT_EINVAL (NULL, or a non-finite vertex), RT_EHIP (device error, capacity
+ * check); the handle then stays unusable until rebuilt. */
+int rt_bvh_wait(rt_bvh* b);
+
 /* ---- trace (Sec. III-B) -------------------------------------------------
  * Closest hit of each ray: out[i] for rays[i].  n = 0 is a no-op.  The handle
  * may be traced concurrently from several streams.

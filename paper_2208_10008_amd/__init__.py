@@ -123,7 +123,8 @@ NODE_DTYPE = np.dtype([("lo", "<f4", 3), ("hi", "<f4", 3), ("left", "<i4"), ("fi
                        ("flags", "<i4"), ("reserved", "<i4"), ("cost", "<f8")])
 assert NODE_DTYPE.itemsize == 64
 
-EXPORTS = ("rt_split_params_default", "rt_build", "rt_rebuild", "rt_trace",
+EXPORTS = ("rt_split_params_default", "rt_build", "rt_rebuild", "rt_rebuild_async", "rt_bvh_wait",
+           "rt_trace",
            "rt_trace_bounces", "rt_trace_ex", "rt_bvh_info_get", "rt_bvh_stats", "rt_bvh_download",
            "rt_bvh_export_trace_nodes", "rt_bvh_destroy", "rt_last_error", "rt_batch_create",
            "rt_batch_set", "rt_batch_configure", "rt_batch_get_config", "rt_batch_launch",
@@ -151,6 +152,8 @@ def load(path: str = LIB_PATH):
     lib.rt_split_params_default.restype = None
     lib.rt_build.argtypes = [P, i64, ctypes.POINTER(rt_split_params), ctypes.POINTER(P), P]
     lib.rt_rebuild.argtypes = [P, P, i64, ctypes.POINTER(rt_split_params), P]
+    lib.rt_rebuild_async.argtypes = [P, P, i64, ctypes.POINTER(rt_split_params), P]
+    lib.rt_bvh_wait.argtypes = [P]
     lib.rt_trace.argtypes = [P, P, i64, P, P]
     lib.rt_trace_bounces.argtypes = [P, P, i64, i32, P, P, P, P]
     lib.rt_trace_ex.argtypes = [P, P, i64, i32, P, P, P, ctypes.POINTER(rt_trace_opts), P]
@@ -194,7 +197,8 @@ def load(path: str = LIB_PATH):
     lib.rt_wedges_noalloc.argtypes = [P, i64, P, P]
     lib.rt_diffract_segments.argtypes = [P, i64, P, P, P, i64, i32, ctypes.c_double, P, i32, P,
                                          i64, P, P]
-    for name in ("rt_build", "rt_rebuild", "rt_trace", "rt_trace_bounces", "rt_trace_ex",
+    for name in ("rt_build", "rt_rebuild", "rt_rebuild_async", "rt_bvh_wait", "rt_trace",
+                 "rt_trace_bounces", "rt_trace_ex",
                  "rt_bvh_info_get", "rt_bvh_stats", "rt_bvh_download",
                  "rt_bvh_export_trace_nodes", "rt_probe_read", "rt_probe_copy", "rt_batch_create", "rt_batch_set",
                  "rt_batch_configure", "rt_batch_get_config", "rt_batch_launch",
@@ -277,6 +281,20 @@ def rt_rebuild(handle, tris, params, stream=None):
     _dev(tris, __import__("torch").float32, 9, "tris")
     cp = params.c() if isinstance(params, SplitParams) else params
     _check(lib.rt_rebuild(handle, _ptr(tris), tris.shape[0], ctypes.byref(cp), _stream(stream)))
+
+
+def rt_rebuild_async(handle, tris, params, stream=None):
+    """Queues the build on `stream` and returns; the tree is usable after
+    rt_bvh_wait(handle).  tris must stay alive until the build has run."""
+    lib = load()
+    _dev(tris, __import__("torch").float32, 9, "tris")
+    cp = params.c() if isinstance(params, SplitParams) else params
+    _check(lib.rt_rebuild_async(handle, _ptr(tris), tris.shape[0], ctypes.byref(cp),
+                                _stream(stream)))
+
+
+def rt_bvh_wait(handle):
+    _check(load().rt_bvh_wait(handle))
 
 
 def rt_trace(handle, rays, out, stream=None):
@@ -613,6 +631,15 @@ class BVH:
         if params is not None:
             self.params = params
         rt_rebuild(self.handle, tris, self.params, stream)
+
+    def rebuild_async(self, tris, params: SplitParams | None = None, stream=None):
+        """rt_rebuild_async: the tree is usable after wait()."""
+        if params is not None:
+            self.params = params
+        rt_rebuild_async(self.handle, tris, self.params, stream)
+
+    def wait(self):
+        rt_bvh_wait(self.handle)
 
     def info(self) -> rt_bvh_info:
         return rt_bvh_info_get(self.handle)

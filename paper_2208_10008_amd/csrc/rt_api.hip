@@ -38,6 +38,7 @@ void free_buffers(Buffers& B) {
                   B.stat_work};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
+  if (B.rec_host) (void)hipHostFree(B.rec_host);
   B = Buffers();
 }
 
@@ -133,7 +134,24 @@ int check_build_args(const float* tris, int64_t n, const rt_split_params* p) {
   return RT_OK;
 }
 
+// Reads the record of a build queued by rt_rebuild_async and makes the tree
+// usable (or leaves it unusable with the build's error).
+int complete_pending(rt_bvh* b) {
+  if (!b->pending) return RT_OK;
+  b->pending = false;
+  rt_bvh_info info;
+  std::memset(&info, 0, sizeof(info));
+  int rc = build_complete(b->buf, b->pending_n, b->pending_params, b->pending_seq,
+                          b->pending_stream, &info);
+  if (rc != RT_OK) return rc;
+  info.device_bytes = b->buf.bytes;
+  b->info = info;
+  b->params = b->pending_params;
+  return RT_OK;
+}
+
 int do_build(rt_bvh* b, const float* tris, int64_t n, const rt_split_params* p, hipStream_t s) {
+  (void)complete_pending(b);  // a build still in flight on the handle ends first
   int rc = check_build_args(tris, n, p);
   if (rc != RT_OK) return rc;
   rc = ensure_buffers(b->buf, n);
@@ -285,6 +303,30 @@ int rt_rebuild(rt_bvh* b, const float* tris, int64_t n, const rt_split_params* p
   int rc = do_build(b, tris, n, p, s);
   if (rc != RT_OK) b->info.n_tris = 0;  // unusable until rebuilt
   return rc;
+}
+
+int rt_rebuild_async(rt_bvh* b, const float* tris, int64_t n, const rt_split_params* p,
+                     hipStream_t s) {
+  if (!b) return set_error(RT_EINVAL, "rt_rebuild_async: handle is NULL");
+  (void)complete_pending(b);
+  int rc = check_build_args(tris, n, p);
+  if (rc == RT_OK) rc = ensure_buffers(b->buf, n);
+  b->info.n_tris = 0;  // unusable until rt_bvh_wait has read the build's record
+  if (rc != RT_OK) return rc;
+  int seq = 0;
+  rc = build_enqueue(b->buf, tris, n, *p, s, &seq);
+  if (rc != RT_OK) return rc;
+  b->pending = true;
+  b->pending_seq = seq;
+  b->pending_n = n;
+  b->pending_params = *p;
+  b->pending_stream = s;
+  return RT_OK;
+}
+
+int rt_bvh_wait(rt_bvh* b) {
+  if (!b) return set_error(RT_EINVAL, "rt_bvh_wait: handle is NULL");
+  return complete_pending(b);
 }
 
 int rt_trace(const rt_bvh* b, const float* rays, int64_t n, rt_hit* out, hipStream_t s) {

@@ -1973,16 +1973,23 @@ struct HostRecord {
   int32_t* dev = nullptr;
 };
 
-int host_record(HostRecord& r) {
-  static thread_local HostRecord rec;
-  if (!rec.host) {
-    int rc = check_hip(hipHostMalloc((void**)&rec.host, 64, hipHostMallocMapped), "hipHostMalloc");
+// The handle's record, made on its first build (freed with its buffers).
+int host_record(Buffers& B, HostRecord& r) {
+  if (!B.rec_host) {
+    int rc = check_hip(hipHostMalloc((void**)&B.rec_host, 64, hipHostMallocMapped), "hipHostMalloc");
     if (rc != RT_OK) return rc;
-    rc = check_hip(hipHostGetDevicePointer((void**)&rec.dev, rec.host, 0), "hipHostGetDevicePointer");
-    if (rc != RT_OK) return rc;
-    rec.host[0] = 0;
+    rc = check_hip(hipHostGetDevicePointer((void**)&B.rec_dev, B.rec_host, 0),
+                   "hipHostGetDevicePointer");
+    if (rc != RT_OK) {
+      (void)hipHostFree(B.rec_host);
+      B.rec_host = nullptr;
+      return rc;
+    }
+    B.rec_host[0] = 0;
+    B.rec_seq = 0;
   }
-  r = rec;
+  r.host = B.rec_host;
+  r.dev = B.rec_dev;
   return RT_OK;
 }
 
@@ -2005,14 +2012,22 @@ int wait_record(const HostRecord& r, int seq, hipStream_t s) {
 
 int build_tree(Buffers& B, const float* tris, int64_t n64, const rt_split_params& p,
                hipStream_t s, rt_bvh_info* info) {
+  int seq = 0;
+  int rc = build_enqueue(B, tris, n64, p, s, &seq);
+  if (rc != RT_OK) return rc;
+  return build_complete(B, n64, p, seq, s, info);
+}
+
+int build_enqueue(Buffers& B, const float* tris, int64_t n64, const rt_split_params& p,
+                  hipStream_t s, int* seq_out) {
   const int n = (int)n64;
   HostRecord rec;
   {
-    int rc = host_record(rec);
+    int rc = host_record(B, rec);
     if (rc != RT_OK) return rc;
   }
-  static thread_local int seq = 0;
-  ++seq;
+  const int seq = ++B.rec_seq;
+  *seq_out = seq;
   BuildState* st = reinterpret_cast<BuildState*>(B.counters);
 
   Ctx X;
@@ -2100,6 +2115,13 @@ int build_tree(Buffers& B, const float* tris, int64_t n64, const rt_split_params
     hipLaunchKernelGGL(k_collapse<RT_NODE_Q4>, cgrid, dim3(eb), 0, s, B.cnodes, st, B.wnodes);
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, st, B.root_box, B.cnodes, rec.dev, seq);
   HIPCHECK(hipGetLastError());
+  return RT_OK;
+}
+
+int build_complete(Buffers& B, int64_t n64, const rt_split_params& p, int seq, hipStream_t s,
+                   rt_bvh_info* info) {
+  const int n = (int)n64;
+  const HostRecord rec{B.rec_host, B.rec_dev};
   {
     int rc = wait_record(rec, seq, s);
     if (rc != RT_OK) return rc;

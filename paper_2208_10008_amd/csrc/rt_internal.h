@@ -144,6 +144,12 @@ struct Buffers {
   // BuildState and root bounds hold their starting values (set once after
   // allocation; every build's last kernel sets them again for the next one)
   bool state_ready = false;
+  // pinned, device-mapped record that the last kernel of every build fills
+  // (sequence number, tree size, errors, root box); one per handle, so builds
+  // of different handles may be in flight at once
+  int32_t* rec_host = nullptr;
+  int32_t* rec_dev = nullptr;
+  int rec_seq = 0;          // sequence number of the handle's last build
   int64_t cap_n = 0;        // facets the buffers can hold
   int64_t bytes = 0;
 };
@@ -339,6 +345,12 @@ int check_trace_args(const rt_bvh* b, const float* rays, int64_t n, int32_t max_
 // build.hip
 int build_tree(Buffers& B, const float* tris, int64_t n, const rt_split_params& p,
                hipStream_t s, rt_bvh_info* info);
+// build_tree in two halves: queue the build's kernels on s (*seq: the record
+// its last kernel writes), then wait for that record and fill info.
+int build_enqueue(Buffers& B, const float* tris, int64_t n, const rt_split_params& p,
+                  hipStream_t s, int* seq);
+int build_complete(Buffers& B, int64_t n, const rt_split_params& p, int seq, hipStream_t s,
+                   rt_bvh_info* info);
 // Eq. (1) tree cost and leaf histogram of the built tree into info (synchronous).
 int tree_stats(const Buffers& B, int64_t n_nodes, double t_isect, double t_trav,
                rt_bvh_info* info);
@@ -391,4 +403,11 @@ struct rt_bvh {
   // the handle, whatever its kernel variant or node format, takes the next
   // one, so calls in flight on different streams never share a head.
   mutable std::atomic<unsigned> queue_slot{0};
+  // a build queued by rt_rebuild_async whose record has not been read yet
+  // (info.n_tris stays 0 meanwhile, so no call uses the tree)
+  bool pending = false;
+  int pending_seq = 0;
+  int64_t pending_n = 0;
+  rt_split_params pending_params;
+  hipStream_t pending_stream = nullptr;
 };

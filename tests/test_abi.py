@@ -215,6 +215,8 @@ def test_null_handles():
     assert lib.rt_bvh_export_trace_nodes(None, None, None) == R.RT_EINVAL
     lib.rt_bvh_destroy(None)
     assert lib.rt_rebuild(None, None, 0, None, None) == R.RT_EINVAL
+    assert lib.rt_rebuild_async(None, None, 0, None, None) == R.RT_EINVAL
+    assert lib.rt_bvh_wait(None) == R.RT_EINVAL
 
 
 def test_binding_rejects_host_tensors():
