@@ -11,6 +11,7 @@ usable.  Checked:
   n_tris = 0;
 * an error found on the device (a non-finite vertex) comes back from
   rt_bvh_wait, the handle stays refused, and a valid rebuild restores it;
+  an argument error comes back at once, with the same effect;
 * two handles driven as a transmitter sweep that queues the next build before
   waiting for the current one (builds on one stream, traces on another,
   ordered by events) give every step the hits, path lengths and hit counts
@@ -118,6 +119,25 @@ def test_device_error_comes_back_from_wait(city):
         b.trace(dev(city.rays[:64]))
     b.rebuild(dev(tris), p)
     assert b.info().n_tris == tris.shape[0]
+    b.close()
+
+
+def test_argument_errors_return_at_once(city):
+    """An argument rt_rebuild refuses is refused by rt_rebuild_async before
+    anything is queued; the handle is then unusable (as after a failed
+    rt_rebuild) until a valid rebuild, synchronous or not."""
+    tris = dev(city.tris)
+    p = R.SplitParams(alpha=0.4, src=city.tx)
+    b = R.BVH(tris, p)
+    with pytest.raises(R.RtError):
+        b.rebuild_async(tris, R.SplitParams(alpha=0.4, src=city.tx, max_leaf=0))
+    assert b.info().n_tris == 0
+    b.wait()                         # nothing in flight
+    with pytest.raises(R.RtError):
+        b.trace(dev(city.rays[:64]))
+    b.rebuild_async(tris, p)
+    b.wait()
+    assert b.info().n_tris == city.tris.shape[0]
     b.close()
 
 
